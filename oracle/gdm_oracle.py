@@ -1,0 +1,555 @@
+"""Plain FP64 CPU oracle for the Green's Dyadic Method (GDM) hot path.
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+baseline leg of the benchmark may import or run this module.  The product
+(the HIP library and its Python binding) never calls it and shares no code
+with it.
+
+What it computes, each function citing the passage of arXiv:2505.09545 it
+follows (sections / equations of the paper):
+
+* Green's dyad blocks G^Ep, G^Hp, G^Em, G^Hm of a homogeneous lossless medium
+  (Sec. "Formalism and implementation", Eq. superprop_G).  The paper defers
+  their explicit form to its pyGDM reference; the forms used here follow from
+  Maxwell's equations in Gaussian units with exp(-i w t) and are pinned in the
+  tests by the vector Helmholtz equation, the curl relations between blocks,
+  the static dipole limit and the radiative limit.
+* cubic-cell polarisability alpha = (eps - eps_env) d^3 / (4 pi) (Sec. "Volume
+  discretization polarizabilities") and the cubic self-term
+  S^Ep = -4 pi / (3 eps_env d^3) I (Eq. selfterm_SEp_cubic); zero self-terms for
+  effective point dipoles (same section, last paragraph).
+* the discretised coupled system F_i = F0_i + sum_j G(r_i, r_j) alpha_j F_j
+  (Eq. LPS_6by6_discrete) written as M F = F0 with M = I - G~ A
+  (Eq. GDM_system_of_equations, read as in the design notes), with electric and
+  magnetic unknowns separated and the magnetic unknowns of mesh cells removed
+  (Sec. "Hybrid discretization GDM", Fig. coupling_matrix).
+* solution by LU decomposition (Sec. "Numerical solution"): LAPACK zgetrf /
+  zgetrs through SciPy.
+* scattered fields by re-propagation of the dipole moments (Sec.
+  "Observables", first item).
+* extinction / absorption / scattering cross sections (Sec. "Observables"),
+  plus the far-field scattering cross section by the exact double sum and by
+  quadrature of the far-field amplitude.
+* gradients of a scalar loss by a hand-written FP64 adjoint (the paper obtains
+  them by automatic differentiation, Sec. "Example: Autograd for resonance
+  search").
+
+Units: nm, nm^2.  Complex values are numpy complex128.
+"""
+from __future__ import annotations
+
+import math
+from typing import Dict
+
+import numpy as np
+import scipy.linalg as sla
+
+FOUR_PI = 4.0 * math.pi
+
+
+# ----------------------------------------------------------------------------
+# wave numbers and Green's tensors  (Eq. superprop_G)
+# ----------------------------------------------------------------------------
+def wavenumbers(wavelength: float, n_env: float):
+    """k0 = 2 pi / lambda0 (Sec. "Effective polarizabilities ..."), k = n_env k0."""
+    k0 = 2.0 * math.pi / wavelength
+    return k0, n_env * k0, n_env * n_env
+
+
+def cross_matrix(v: np.ndarray) -> np.ndarray:
+    """[v]_x such that [v]_x @ w = v x w, for v of shape (..., 3)."""
+    z = np.zeros(v.shape[:-1])
+    return np.stack([np.stack([z, -v[..., 2], v[..., 1]], -1),
+                     np.stack([v[..., 2], z, -v[..., 0]], -1),
+                     np.stack([-v[..., 1], v[..., 0], z], -1)], -2)
+
+
+def green_ep(R: np.ndarray, k0: float, n_env: float) -> np.ndarray:
+    """Electric field at r from an electric dipole at r', R = r - r' (..., 3).
+
+    G^Ep = exp(ikR)/eps_env [ (k^2/R + ik/R^2 - 1/R^3) I
+                              + (-k^2/R - 3ik/R^2 + 3/R^3) Rhat Rhat^T ]."""
+    k = n_env * k0
+    eps = n_env * n_env
+    Rn = np.linalg.norm(R, axis=-1)
+    Rh = R / Rn[..., None]
+    ph = np.exp(1j * k * Rn) / eps
+    a = (k * k / Rn + 1j * k / Rn ** 2 - 1.0 / Rn ** 3) * ph
+    b = (-k * k / Rn - 3j * k / Rn ** 2 + 3.0 / Rn ** 3) * ph
+    return a[..., None, None] * np.eye(3) + b[..., None, None] * (Rh[..., :, None] * Rh[..., None, :])
+
+
+def green_hp(R: np.ndarray, k0: float, n_env: float) -> np.ndarray:
+    """Magnetic field at r from an electric dipole at r':
+    G^Hp = k0 k exp(ikR)/R (1 + i/(kR)) [Rhat]_x."""
+    k = n_env * k0
+    Rn = np.linalg.norm(R, axis=-1)
+    Rh = R / Rn[..., None]
+    h = k0 * k * np.exp(1j * k * Rn) / Rn * (1.0 + 1j / (k * Rn))
+    return h[..., None, None] * cross_matrix(Rh)
+
+
+def green6(R: np.ndarray, k0: float, n_env: float) -> np.ndarray:
+    """6x6 dyad [[G^Ep, G^Em], [G^Hp, G^Hm]] with G^Em = -G^Hp and
+    G^Hm = eps_env G^Ep (duality of the magnetic-dipole fields, mu = 1)."""
+    eps = n_env * n_env
+    gep = green_ep(R, k0, n_env)
+    ghp = green_hp(R, k0, n_env)
+    top = np.concatenate([gep, -ghp], axis=-1)
+    bot = np.concatenate([ghp, eps * gep], axis=-1)
+    return np.concatenate([top, bot], axis=-2)
+
+
+def dgreen6_dR(R: np.ndarray, k0: float, n_env: float) -> np.ndarray:
+    """Analytic derivative d G6(R) / d R_a, returned with shape (..., 3[a], 6, 6)."""
+    k = n_env * k0
+    eps = n_env * n_env
+    Rn = np.linalg.norm(R, axis=-1)
+    Rh = R / Rn[..., None]
+    phi = np.exp(1j * k * Rn)
+    # G^Ep = phi/eps (A I + Bq R R^T)
+    A = k * k / Rn + 1j * k / Rn ** 2 - 1.0 / Rn ** 3
+    A_R = -k * k / Rn ** 2 - 2j * k / Rn ** 3 + 3.0 / Rn ** 4
+    Bq = -k * k / Rn ** 3 - 3j * k / Rn ** 4 + 3.0 / Rn ** 5
+    Bq_R = 3 * k * k / Rn ** 4 + 12j * k / Rn ** 5 - 15.0 / Rn ** 6
+    phi_R = 1j * k * phi
+    I3 = np.eye(3)
+    RR = R[..., :, None] * R[..., None, :]
+    shp = R.shape[:-1]
+    dE = np.zeros(shp + (3, 3, 3), dtype=np.complex128)
+    dH = np.zeros(shp + (3, 3, 3), dtype=np.complex128)
+    u = k0 * k * phi * (1.0 / Rn ** 2 + 1j / (k * Rn ** 3))
+    u_R = k0 * k * (phi_R * (1.0 / Rn ** 2 + 1j / (k * Rn ** 3))
+                    + phi * (-2.0 / Rn ** 3 - 3j / (k * Rn ** 4)))
+    cx = cross_matrix(R)
+    for a in range(3):
+        ea = np.zeros(3)
+        ea[a] = 1.0
+        dRR = ea[:, None] * R[..., None, :] + R[..., :, None] * ea[None, :]
+        termA = ((phi_R * A + phi * A_R) * Rh[..., a])[..., None, None] * I3
+        termB = ((phi_R * Bq + phi * Bq_R) * Rh[..., a])[..., None, None] * RR
+        termC = (phi * Bq)[..., None, None] * dRR
+        dE[..., a, :, :] = (termA + termB + termC) / eps
+        dH[..., a, :, :] = (u_R * Rh[..., a])[..., None, None] * cx + u[..., None, None] * cross_matrix(ea)
+    top = np.concatenate([dE, -dH], axis=-1)
+    bot = np.concatenate([dH, eps * dE], axis=-1)
+    return np.concatenate([top, bot], axis=-2)
+
+
+def dgreen6_dk0(R: np.ndarray, k0: float, n_env: float) -> np.ndarray:
+    """Analytic derivative d G6 / d k0 at fixed R and n_env (k = n_env k0)."""
+    k = n_env * k0
+    eps = n_env * n_env
+    Rn = np.linalg.norm(R, axis=-1)
+    phi = np.exp(1j * k * Rn)
+    dphi = 1j * n_env * Rn * phi
+    A = k * k / Rn + 1j * k / Rn ** 2 - 1.0 / Rn ** 3
+    dA = n_env * (2 * k / Rn + 1j / Rn ** 2)
+    Bq = -k * k / Rn ** 3 - 3j * k / Rn ** 4 + 3.0 / Rn ** 5
+    dBq = n_env * (-2 * k / Rn ** 3 - 3j / Rn ** 4)
+    RR = R[..., :, None] * R[..., None, :]
+    dE = ((dphi * A + phi * dA)[..., None, None] * np.eye(3)
+          + (dphi * Bq + phi * dBq)[..., None, None] * RR) / eps
+    # G^Hp = u(R) [R]_x with u = phi (n k0^2 / R^2 + i k0 / R^3)
+    w = n_env * k0 * k0 / Rn ** 2 + 1j * k0 / Rn ** 3
+    dw = 2 * n_env * k0 / Rn ** 2 + 1j / Rn ** 3
+    du = dphi * w + phi * dw
+    dH = du[..., None, None] * cross_matrix(R)
+    top = np.concatenate([dE, -dH], axis=-1)
+    bot = np.concatenate([dH, eps * dE], axis=-1)
+    return np.concatenate([top, bot], axis=-2)
+
+
+# ----------------------------------------------------------------------------
+# dipoles: polarisabilities, self-terms, unknown layout
+# ----------------------------------------------------------------------------
+def cell_alpha(eps_cell, step: float, n_env: float):
+    """alpha_pE = chi_ee d^3 / (4 pi) with chi_ee = eps - eps_env
+    (Sec. "Volume discretization polarizabilities")."""
+    return (np.asarray(eps_cell, dtype=np.complex128) - n_env * n_env) * step ** 3 / FOUR_PI
+
+
+def cell_selfterm(step: float, n_env: float, k0: float, mode: str = "static") -> complex:
+    """S^Ep = -I 4 pi / (3 eps_env d^3) (Eq. selfterm_SEp_cubic).  mode
+    'radiative' adds i (2/3) k^3 / eps_env (radiation reaction; an option, not
+    the paper's method)."""
+    eps = n_env * n_env
+    s = -FOUR_PI / (3.0 * eps * step ** 3) + 0j
+    if mode == "radiative":
+        k = n_env * k0
+        s += 1j * (2.0 / 3.0) * k ** 3 / eps
+    return s
+
+
+class Dipoles:
+    """All point dipoles of a simulation: N_c mesh cells then N_e effective
+    ED+MD dipoles.  Unknown layout (Sec. "Hybrid discretization GDM"):
+    [E of all N_c + N_e dipoles | H of the N_e effective dipoles]."""
+
+    def __init__(self, wl: Dict, wavelength: float = None, mode: str = "static",
+                 eps_cell=None, r_cell=None, r_eff=None):
+        self.n_env = float(wl["n_env"])
+        self.eps_env = self.n_env ** 2
+        self.wavelength = float(wl["wavelength"] if wavelength is None else wavelength)
+        self.k0, self.k, _ = wavenumbers(self.wavelength, self.n_env)
+        self.step = float(wl["step"])
+        self.mode = mode
+        rc = np.asarray(wl["r_cell"] if r_cell is None else r_cell, dtype=np.float64)
+        re = np.asarray(wl["r_eff"] if r_eff is None else r_eff, dtype=np.float64).reshape(-1, 3)
+        self.nc, self.ne = len(rc), len(re)
+        self.N = self.nc + self.ne
+        self.pos = np.concatenate([rc, re], axis=0)
+        eps_c = wl["eps_cell"] if eps_cell is None else eps_cell
+        self.eps_cell = np.asarray(eps_c, dtype=np.complex128)
+        a_c = cell_alpha(self.eps_cell, self.step, self.n_env)
+        self.alpha6 = np.zeros((self.N, 6, 6), dtype=np.complex128)
+        for a in range(3):
+            self.alpha6[: self.nc, a, a] = a_c
+        if self.ne:
+            self.alpha6[self.nc:] = np.asarray(wl["alpha_eff"], dtype=np.complex128)
+        self.S6 = np.zeros((self.N, 6, 6), dtype=np.complex128)
+        s = cell_selfterm(self.step, self.n_env, self.k0, mode)
+        for a in range(3):
+            self.S6[: self.nc, a, a] = s
+        # unknown index of (dipole, 6-component); -1 where the unknown is removed
+        self.idx = -np.ones((self.N, 6), dtype=np.int64)
+        self.idx[:, 0:3] = 3 * np.arange(self.N)[:, None] + np.arange(3)[None, :]
+        self.idx[self.nc:, 3:6] = 3 * self.N + 3 * np.arange(self.ne)[:, None] + np.arange(3)[None, :]
+        self.n = 3 * self.N + 3 * self.ne
+        self.rho = np.concatenate([np.zeros(self.nc), np.ones(self.ne)])  # radiative reaction in alpha
+
+    def comps(self, d: int):
+        return np.arange(6) if d >= self.nc else np.arange(3)
+
+    def alpha_matrix(self) -> np.ndarray:
+        """Block-diagonal A in the reduced layout (q = A F)."""
+        A = np.zeros((self.n, self.n), dtype=np.complex128)
+        for d in range(self.N):
+            c = self.comps(d)
+            ii = self.idx[d, c]
+            A[np.ix_(ii, ii)] = self.alpha6[d][np.ix_(c, c)]
+        return A
+
+    def to6(self, x: np.ndarray) -> np.ndarray:
+        """Reduced vector(s) [n, ...] -> per-dipole 6-vectors [N, 6, ...] (zeros where removed)."""
+        out = np.zeros((self.N, 6) + x.shape[1:], dtype=np.complex128)
+        out[:, 0:3] = x[: 3 * self.N].reshape((self.N, 3) + x.shape[1:])
+        if self.ne:
+            out[self.nc:, 3:6] = x[3 * self.N:].reshape((self.ne, 3) + x.shape[1:])
+        return out
+
+    def from6(self, y: np.ndarray) -> np.ndarray:
+        x = np.zeros((self.n,) + y.shape[2:], dtype=np.complex128)
+        x[: 3 * self.N] = y[:, 0:3].reshape((3 * self.N,) + y.shape[2:])
+        if self.ne:
+            x[3 * self.N:] = y[self.nc:, 3:6].reshape((3 * self.ne,) + y.shape[2:])
+        return x
+
+
+# ----------------------------------------------------------------------------
+# the coupled system  (Eq. LPS_6by6_discrete, Eq. GDM_system_of_equations)
+# ----------------------------------------------------------------------------
+def coupling_greens(D: Dipoles, chunk: int = 64) -> np.ndarray:
+    """G~ in the reduced layout: G~[idx(i,a), idx(j,b)] = G6(r_i - r_j)[a, b]
+    for i != j and S6_i[a, b] for i == j."""
+    n, N = D.n, D.N
+    G = np.zeros((n, n), dtype=np.complex128)
+    rows_all = D.idx  # [N, 6]
+    for i0 in range(0, N, chunk):
+        i1 = min(N, i0 + chunk)
+        R = D.pos[i0:i1, None, :] - D.pos[None, :, :]
+        same = np.all(R == 0.0, axis=-1)
+        Rs = np.where(same[..., None], 1.0, R)
+        g6 = green6(Rs, D.k0, D.n_env)  # [c, N, 6, 6]
+        for li, i in enumerate(range(i0, i1)):
+            g6[li, i] = D.S6[i]
+        # electric rows of the chunk
+        for a_lo, a_hi, row_sel in ((0, 3, slice(i0, i1)), (3, 6, slice(max(i0, D.nc), i1))):
+            r_d = np.arange(N)[row_sel]
+            if len(r_d) == 0:
+                continue
+            rr = rows_all[r_d, a_lo:a_hi].reshape(-1)
+            blk = g6[r_d - i0, :, a_lo:a_hi, :]  # [ri, N, 3, 6]
+            # electric columns of all dipoles
+            ce = rows_all[:, 0:3].reshape(-1)
+            G[np.ix_(rr, ce)] = blk[:, :, :, 0:3].transpose(0, 2, 1, 3).reshape(len(rr), 3 * N)
+            if D.ne:
+                cm = rows_all[D.nc:, 3:6].reshape(-1)
+                G[np.ix_(rr, cm)] = blk[:, D.nc:, :, 3:6].transpose(0, 2, 1, 3).reshape(len(rr), 3 * D.ne)
+    return G
+
+
+def apply_alpha_right(D: Dipoles, G: np.ndarray) -> np.ndarray:
+    """G~ A for the block-diagonal A (column mixing within each dipole)."""
+    out = np.empty_like(G)
+    # cells: alpha_pE is scalar times I
+    a_c = D.alpha6[: D.nc, 0, 0]
+    out[:, : 3 * D.nc] = G[:, : 3 * D.nc] * np.repeat(a_c, 3)[None, :]
+    for d in range(D.nc, D.N):
+        c = D.idx[d]
+        out[:, c] = G[:, c] @ D.alpha6[d]
+    return out
+
+
+def assemble(D: Dipoles) -> np.ndarray:
+    """M = I - G~ A (n x n, complex128)."""
+    G = coupling_greens(D)
+    M = -apply_alpha_right(D, G)
+    M[np.diag_indices(D.n)] += 1.0
+    return M
+
+
+# ----------------------------------------------------------------------------
+# illumination  (Appendix, 3D illuminations: plane wave)
+# ----------------------------------------------------------------------------
+def planewave(r: np.ndarray, khat: np.ndarray, e0: np.ndarray, k0: float, n_env: float):
+    """E0(r) = e0 exp(i k khat.r), H0 = n_env khat x E0; returns E, H [n_pw, P, 3]."""
+    k = n_env * k0
+    khat = np.atleast_2d(khat)
+    e0 = np.atleast_2d(e0)
+    ph = np.exp(1j * k * (r @ khat.T)).T  # [n_pw, P]
+    E = ph[:, :, None] * e0[:, None, :]
+    H = n_env * np.cross(khat[:, None, :], E)
+    return E, H
+
+
+def incident_at_dipoles(D: Dipoles, khat, e0) -> np.ndarray:
+    """F0 in the reduced layout, [n, n_pw]."""
+    E, H = planewave(D.pos, khat, e0, D.k0, D.n_env)
+    F6 = np.concatenate([E, H], axis=-1).transpose(1, 2, 0)  # [N, 6, n_pw]
+    return D.from6(F6)
+
+
+# ----------------------------------------------------------------------------
+# solve  (Sec. "Numerical solution": LU decomposition)
+# ----------------------------------------------------------------------------
+def solve(M: np.ndarray, F0: np.ndarray):
+    lu = sla.lu_factor(M, check_finite=False)
+    return sla.lu_solve(lu, F0, check_finite=False), lu
+
+
+def simulate(wl: Dict, mode: str = "static", wavelength: float = None, eps_cell=None,
+             r_cell=None, keep_matrix: bool = False) -> Dict:
+    """Full forward pass: dipoles, assembly, LU solve, q = A F, cross sections."""
+    D = Dipoles(wl, wavelength, mode, eps_cell=eps_cell, r_cell=r_cell)
+    M = assemble(D)
+    F0 = incident_at_dipoles(D, wl["khat"], wl["e0"])
+    F, lu = solve(M, F0)
+    q = D.from6(np.einsum("dab,dbr->dar", D.alpha6, D.to6(F)))
+    out = dict(D=D, F0=F0, F=F, q=q, lu=lu)
+    out.update(cross_sections(D, F0, F, q, np.sum(np.abs(np.atleast_2d(wl["e0"])) ** 2, axis=1)))
+    if keep_matrix:
+        out["M"] = M
+    return out
+
+
+# ----------------------------------------------------------------------------
+# observables  (Sec. "Observables")
+# ----------------------------------------------------------------------------
+def cross_sections(D: Dipoles, F0, F, q, e0_norm2) -> Dict:
+    """Per RHS: ext = C sum Im(F0^* . q); abs = C sum [Im(F^* . q) - rho (2/3) k^3
+    (|p|^2/eps_env + |m|^2)]; sca = ext - abs; rad = C sum (2/3) k^3 (|p|^2/eps_env + |m|^2);
+    with C = 4 pi k0 / (n_env |E0|^2)."""
+    C = FOUR_PI * D.k0 / (D.n_env * np.asarray(e0_norm2, dtype=np.float64))
+    q6 = D.to6(q)
+    w = np.concatenate([np.full(3, 1.0 / D.eps_env), np.ones(3)])
+    prad = (2.0 / 3.0) * D.k ** 3 * np.einsum("c,dcr->dr", w, np.abs(q6) ** 2)  # [N, rhs]
+    ext = C * np.sum(np.imag(np.conj(F0) * q), axis=0)
+    absr = C * (np.sum(np.imag(np.conj(F) * q), axis=0) - np.sum(D.rho[:, None] * prad, axis=0))
+    rad = C * np.sum(prad, axis=0)
+    return dict(ext=ext, abs=absr, sca=ext - absr, rad=rad)
+
+
+def sca_farfield_doublesum(D: Dipoles, q, e0_norm2, chunk: int = 256) -> np.ndarray:
+    """sigma_sca,ff = C Im sum_{i,j} q_i^H G^_ij q_j, G^_ij = G6(r_i - r_j) (i != j),
+    G^_ii = i (2/3) k^3 diag(I/eps_env, I): the exact power radiated by the dipoles."""
+    C = FOUR_PI * D.k0 / (D.n_env * np.asarray(e0_norm2, dtype=np.float64))
+    q6 = D.to6(q)  # [N, 6, rhs]
+    tot = np.zeros(q6.shape[2])
+    diag = 1j * (2.0 / 3.0) * D.k ** 3 * np.concatenate([np.full(3, 1.0 / D.eps_env), np.ones(3)])
+    for i0 in range(0, D.N, chunk):
+        i1 = min(D.N, i0 + chunk)
+        R = D.pos[i0:i1, None, :] - D.pos[None, :, :]
+        same = np.all(R == 0.0, axis=-1)
+        g6 = green6(np.where(same[..., None], 1.0, R), D.k0, D.n_env)
+        g6[same] = 0.0
+        s = np.einsum("iar,ijab,jbr->r", np.conj(q6[i0:i1]), g6, q6)
+        s += np.einsum("iar,a,iar->r", np.conj(q6[i0:i1]), diag, q6[i0:i1])
+        tot += np.imag(s)
+    return C * tot
+
+
+def farfield_amplitude(D: Dipoles, q, nhat: np.ndarray) -> np.ndarray:
+    """A(n) with E_sca -> exp(ikR)/R A(n): sum_j exp(-ik n.r_j) [(k^2/eps)(n x p_j) x n
+    - k0 k (n x m_j)]; returns [n_dir, 3, rhs]."""
+    q6 = D.to6(q)
+    p, m = q6[:, 0:3], q6[:, 3:6]
+    ph = np.exp(-1j * D.k * (nhat @ D.pos.T))  # [dir, N]
+    P = np.einsum("dj,jar->dar", ph, p)
+    Mm = np.einsum("dj,jar->dar", ph, m)
+    n3 = nhat[:, :, None]
+    nxp = np.cross(n3, P, axis=1)
+    return (D.k ** 2 / D.eps_env) * np.cross(nxp, n3, axis=1) - D.k0 * D.k * np.cross(n3, Mm, axis=1)
+
+
+def sca_farfield_quadrature(D: Dipoles, q, e0_norm2, n_theta: int = 96, n_phi: int = 192):
+    """sigma_sca = (1/|E0|^2) \\oint |A(n)|^2 dOmega by Gauss-Legendre in cos(theta)
+    times the uniform rule in phi."""
+    x, wx = np.polynomial.legendre.leggauss(n_theta)
+    phi = 2 * math.pi * np.arange(n_phi) / n_phi
+    ct, ph = np.meshgrid(x, phi, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    nhat = np.stack([st * np.cos(ph), st * np.sin(ph), ct], axis=-1).reshape(-1, 3)
+    w = (wx[:, None] * np.full(n_phi, 2 * math.pi / n_phi)[None, :]).reshape(-1)
+    A = farfield_amplitude(D, q, nhat)
+    return np.einsum("d,dar->r", w, np.abs(A) ** 2) / np.asarray(e0_norm2, dtype=np.float64)
+
+
+def scattered_fields(D: Dipoles, q, r_probe: np.ndarray, chunk: int = 512):
+    """E_sca, H_sca at probes by re-propagation sum_j G6(r_p - r_j) q_j
+    (Sec. "Observables"); returns E, H [rhs, P, 3]."""
+    q6 = D.to6(q)  # [N, 6, rhs]
+    P = len(r_probe)
+    out = np.zeros((q6.shape[2], P, 6), dtype=np.complex128)
+    for p0 in range(0, P, chunk):
+        p1 = min(P, p0 + chunk)
+        R = r_probe[p0:p1, None, :] - D.pos[None, :, :]
+        g6 = green6(R, D.k0, D.n_env)
+        out[:, p0:p1, :] = np.einsum("pjab,jbr->rpa", g6, q6)
+    return out[..., 0:3], out[..., 3:6]
+
+
+# ----------------------------------------------------------------------------
+# adjoint gradient of a scalar loss (FP64 reference gradient)
+# ----------------------------------------------------------------------------
+def loss_sca_plus_nearfield(wl: Dict, w_sca: float = 1.0, w_nf: float = None,
+                            wavelength=None, eps_cell=None, r_cell=None, mode="static") -> float:
+    """L = w_sca sigma_sca + w_nf sum_p |E_tot(r_p)|^2 / |E0|^2, summed over RHS
+    (default w_nf = 1 / number of probes)."""
+    sim = simulate(wl, mode, wavelength, eps_cell, r_cell)
+    D = sim["D"]
+    P = len(wl["r_probe"])
+    w_nf = (1.0 / P if P else 0.0) if w_nf is None else w_nf
+    L = w_sca * float(np.sum(sim["sca"]))
+    if P and w_nf:
+        E_inc, _ = planewave(wl["r_probe"], wl["khat"], wl["e0"], D.k0, D.n_env)
+        Es, _ = scattered_fields(D, sim["q"], wl["r_probe"])
+        e2 = np.sum(np.abs(np.atleast_2d(wl["e0"])) ** 2, axis=1)
+        L += w_nf * float(np.sum(np.sum(np.abs(E_inc + Es) ** 2, axis=(1, 2)) / e2))
+    return L
+
+
+def adjoint_gradient(wl: Dict, w_sca: float = 1.0, w_nf: float = None, mode="static") -> Dict:
+    """Gradient of ``loss_sca_plus_nearfield`` w.r.t. every dipole position,
+    Re/Im of every cell permittivity and the wavelength.
+
+    Adjoint identity (M F = F0, q = A F, dL = 2 Re[g . dz] for Wirtinger
+    partials g of the real loss):
+      M^T lam = g_F + A^T g_qe,   g_qe = g_q + sum_p g_Ep G_pj,
+      dL = 2 Re[(lam + g_F0) . dF0 + lam . dG~ q + (lam^T G~ + g_qe) dA F
+                + g_Ep . (dE0_p + dG_p q)] + explicit dependence through C(k0)."""
+    D = Dipoles(wl, None, mode)
+    M = assemble(D)
+    Gt = coupling_greens(D)
+    F0 = incident_at_dipoles(D, wl["khat"], wl["e0"])
+    F, lu = solve(M, F0)
+    q = D.from6(np.einsum("dab,dbr->dar", D.alpha6, D.to6(F)))
+    e2 = np.sum(np.abs(np.atleast_2d(wl["e0"])) ** 2, axis=1)  # [rhs]
+    C = FOUR_PI * D.k0 / (D.n_env * e2)  # [rhs]
+    nrhs = F0.shape[1]
+    rp = np.asarray(wl["r_probe"], dtype=np.float64).reshape(-1, 3)
+    P = len(rp)
+    w_nf = (1.0 / P if P else 0.0) if w_nf is None else w_nf
+    wq = np.concatenate([np.full(3, 1.0 / D.eps_env), np.ones(3)])
+    q6 = D.to6(q)
+    # Wirtinger partials of sigma_sca = ext - abs
+    g_q = w_sca * C[None, :] * (np.conj(F0) / 2j - np.conj(F) / 2j)
+    g_q6 = D.to6(g_q) + w_sca * C[None, None, :] * (2.0 / 3.0) * D.k ** 3 * (
+        D.rho[:, None, None] * wq[None, :, None] * np.conj(q6))
+    g_q = D.from6(g_q6)
+    g_F = w_sca * C[None, :] * (np.conj(q) / 2j)
+    g_F0 = w_sca * C[None, :] * (-np.conj(q) / 2j)
+    # probes
+    if P and w_nf:
+        E_inc, H_inc = planewave(rp, wl["khat"], wl["e0"], D.k0, D.n_env)
+        Es, _ = scattered_fields(D, q, rp)
+        Etot = E_inc + Es  # [rhs, P, 3]
+        g_Ep = w_nf * np.conj(Etot) / e2[:, None, None]
+        # g_qe contribution: sum_p g_Ep[r,p,a] G6(r_p - r_j)[a, b]
+        acc = np.zeros((D.N, 6, nrhs), dtype=np.complex128)
+        for p0 in range(0, P, 256):
+            p1 = min(P, p0 + 256)
+            g6 = green6(rp[p0:p1, None, :] - D.pos[None, :, :], D.k0, D.n_env)
+            acc += np.einsum("rpa,pjab->jbr", g_Ep[:, p0:p1], g6[:, :, 0:3, :])
+        g_qe = g_q + D.from6(acc)
+    else:
+        g_Ep = None
+        g_qe = g_q
+    A = D.alpha_matrix()
+    lam = sla.lu_solve(lu, g_F + A.T @ g_qe, trans=1, check_finite=False)
+    v = Gt.T @ lam + g_qe  # (lam^T G~ + g_qe)^T
+    # permittivity of cells: dA_j = d^3/(4 pi) deps I3
+    v6 = D.to6(v)
+    F6 = D.to6(F)
+    s = np.sum(v6[: D.nc, 0:3] * F6[: D.nc, 0:3], axis=(1, 2)) * D.step ** 3 / FOUR_PI
+    g_eps_re = 2.0 * np.real(s)
+    g_eps_im = 2.0 * np.real(1j * s)
+    # positions
+    lam6 = D.to6(lam)
+    lg6 = D.to6(lam + g_F0)
+    F06 = D.to6(F0)
+    g_r = np.zeros((D.N, 3))
+    khat = np.atleast_2d(wl["khat"])
+    # incident phase: dF0_m / dr_m,a = i k khat_a F0_m
+    for a in range(3):
+        g_r[:, a] += 2.0 * np.real(np.einsum("dcr,dcr,r->d", lg6, F06, 1j * D.k * khat[:, a]))
+    # pair terms
+    for i0 in range(0, D.N, 64):
+        i1 = min(D.N, i0 + 64)
+        R = D.pos[i0:i1, None, :] - D.pos[None, :, :]
+        same = np.all(R == 0.0, axis=-1)
+        dg = dgreen6_dR(np.where(same[..., None], 1.0, R), D.k0, D.n_env)  # [c, N, 3, 6, 6]
+        dg[same] = 0.0
+        # rows i in chunk (m = i): lam_i^T dG(r_i - r_j) q_j
+        t1 = np.einsum("iar,ijxab,jbr->ix", lam6[i0:i1], dg, q6)
+        g_r[i0:i1] += 2.0 * np.real(t1)
+        # columns j (m = j): - lam_i^T dG(r_i - r_j) q_j
+        t2 = np.einsum("iar,ijxab,jbr->jx", lam6[i0:i1], dg, q6)
+        g_r -= 2.0 * np.real(t2)
+    if g_Ep is not None:
+        for p0 in range(0, P, 128):
+            p1 = min(P, p0 + 128)
+            dg = dgreen6_dR(rp[p0:p1, None, :] - D.pos[None, :, :], D.k0, D.n_env)
+            t = np.einsum("rpa,pjxab,jbr->jx", g_Ep[:, p0:p1], dg[:, :, :, 0:3, :], q6)
+            g_r -= 2.0 * np.real(t)
+    # wavelength through k0
+    dLdk0 = 0.0
+    for i0 in range(0, D.N, 64):
+        i1 = min(D.N, i0 + 64)
+        R = D.pos[i0:i1, None, :] - D.pos[None, :, :]
+        same = np.all(R == 0.0, axis=-1)
+        dg = dgreen6_dk0(np.where(same[..., None], 1.0, R), D.k0, D.n_env)
+        dg[same] = 0.0
+        dLdk0 += 2.0 * np.real(np.einsum("iar,ijab,jbr->", lam6[i0:i1], dg, q6))
+    if D.mode == "radiative":
+        dS = 1j * 2.0 * D.k ** 2 * D.n_env / D.eps_env
+        dLdk0 += 2.0 * np.real(dS * np.sum(lam6[: D.nc, 0:3] * q6[: D.nc, 0:3]))
+    kr = D.pos @ khat.T  # [N, rhs]
+    dLdk0 += 2.0 * np.real(np.sum(lg6 * (1j * D.n_env * kr)[:, None, :] * F06))
+    # explicit dependence through C(k0) (sigma proportional to k0) and (2/3) k^3
+    sig = cross_sections(D, F0, F, q, e2)
+    prad_eff = (2.0 / 3.0) * D.k ** 3 * np.einsum("c,dcr->r", wq, D.rho[:, None, None] * np.abs(q6) ** 2)
+    dLdk0 += w_sca * float(np.sum(sig["sca"] / D.k0))
+    dLdk0 += w_sca * float(np.sum(C * prad_eff * 3.0 / D.k0))
+    if g_Ep is not None:
+        E_inc, _ = planewave(rp, wl["khat"], wl["e0"], D.k0, D.n_env)
+        dEinc = E_inc * (1j * D.n_env * (rp @ khat.T)).T[:, :, None]
+        dLdk0 += 2.0 * np.real(np.sum(g_Ep * dEinc))
+        for p0 in range(0, P, 256):
+            p1 = min(P, p0 + 256)
+            dg = dgreen6_dk0(rp[p0:p1, None, :] - D.pos[None, :, :], D.k0, D.n_env)
+            dLdk0 += 2.0 * np.real(np.einsum("rpa,pjab,jbr->", g_Ep[:, p0:p1], dg[:, :, 0:3, :], q6))
+    g_wl = dLdk0 * (-D.k0 / D.wavelength)
+    return dict(r=g_r, eps_re=g_eps_re, eps_im=g_eps_im, wavelength=g_wl,
+                loss=w_sca * float(np.sum(sig["sca"])) + (
+                    w_nf * float(np.sum(np.sum(np.abs(Etot) ** 2, axis=(1, 2)) / e2)) if g_Ep is not None else 0.0))

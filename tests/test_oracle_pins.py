@@ -1,0 +1,452 @@
+"""Pins of the FP64 oracle against what physics and mathematics fix, independent
+of the oracle's own formulas (arXiv:2505.09545; sections cited per test).
+
+Each check is chosen so that a plausible slip in the oracle (a dropped term of
+a Green's tensor, a wrong sign, a transposed block, a wrong normalisation of
+alpha, of the self-term or of the cross-section prefactor) fails one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.special as sp
+
+import gdm_inputs as gi
+from oracle import gdm_oracle as O
+
+RNG = np.random.default_rng(1234)
+
+
+def _fd_grad(f, r, h):
+    """Central differences of a vector field f(r) -> (..., 3) complex; returns d_a f_b [a, b]."""
+    out = []
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        out.append((f(r + e) - f(r - e)) / (2 * h))
+    return np.stack(out)
+
+
+def _curl(f, r, h):
+    J = _fd_grad(f, r, h)  # J[a, b] = d_a f_b
+    return np.array([J[1, 2] - J[2, 1], J[2, 0] - J[0, 2], J[0, 1] - J[1, 0]])
+
+
+def _laplacian(f, r, h):
+    """Fourth-order central-difference Laplacian."""
+    acc = -90.0 * f(r)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        acc = acc + 16.0 * (f(r + e) + f(r - e)) - (f(r + 2 * e) + f(r - 2 * e))
+    return acc / (12.0 * h * h)
+
+
+# ---------------------------------------------------------------------------
+# Green's dyad (Eq. superprop_G): Maxwell's equations fix every block
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n_env,wl,R", [(1.0, 600.0, 37.0), (1.33, 550.0, 180.0), (1.5, 700.0, 900.0)])
+def test_green_ep_solves_vector_helmholtz(n_env, wl, R):
+    """Away from the source E = G^Ep p is divergence free and obeys
+    lap E + k^2 E = 0 (homogeneous medium, k = n_env k0)."""
+    k0, k, _ = O.wavenumbers(wl, n_env)
+    p = RNG.standard_normal(3) + 1j * RNG.standard_normal(3)
+    d = RNG.standard_normal(3)
+    r = R * d / np.linalg.norm(d)
+    f = lambda x: O.green_ep(x, k0, n_env) @ p
+    J = _fd_grad(f, r, 1e-4 * R)
+    div = J[0, 0] + J[1, 1] + J[2, 2]
+    scale = np.linalg.norm(J)
+    assert abs(div) < 1e-6 * scale
+    lap = _laplacian(f, r, 1e-2 * R)
+    resid = lap + k * k * f(r)
+    assert np.linalg.norm(resid) < 1e-4 * np.linalg.norm(k * k * f(r))
+
+
+def test_green_ep_static_and_far_limits():
+    """k -> 0: the static dipole field (3 Rh Rh - I)/(eps R^3);
+    kR >> 1: the radiation field k^2 exp(ikR)/(eps R) (I - Rh Rh)."""
+    n_env = 1.4
+    R = np.array([13.0, -7.0, 22.0])
+    Rn = np.linalg.norm(R)
+    Rh = R / Rn
+    k0 = 1e-9
+    G = O.green_ep(R, k0, n_env)
+    static = (3 * np.outer(Rh, Rh) - np.eye(3)) / (n_env ** 2 * Rn ** 3)
+    assert np.max(np.abs(G - static)) < 1e-12 * np.max(np.abs(static))
+    k0 = 2 * math.pi / 500.0
+    k = n_env * k0
+    Rfar = Rh * 5e6
+    G = O.green_ep(Rfar, k0, n_env)
+    far = k * k * np.exp(1j * k * 5e6) / (n_env ** 2 * 5e6) * (np.eye(3) - np.outer(Rh, Rh))
+    assert np.max(np.abs(G - far)) < 1e-4 * np.max(np.abs(far))
+
+
+@pytest.mark.parametrize("n_env", [1.0, 1.33])
+def test_curl_relations_between_blocks(n_env):
+    """Faraday: curl(G^Ep p) = i k0 G^Hp p.  Ampere: curl(G^Hm m) = -i k0 eps G^Em m."""
+    k0 = 2 * math.pi / 633.0
+    eps = n_env ** 2
+    v = RNG.standard_normal(3) + 1j * RNG.standard_normal(3)
+    r = np.array([40.0, -25.0, 61.0])
+    h = 1e-3
+    g = lambda x: O.green6(x, k0, n_env)
+    cE = _curl(lambda x: g(x)[0:3, 0:3] @ v, r, h)
+    assert np.allclose(cE, 1j * k0 * (g(r)[3:6, 0:3] @ v), rtol=1e-7, atol=0)
+    cH = _curl(lambda x: g(x)[3:6, 3:6] @ v, r, h)
+    assert np.allclose(cH, -1j * k0 * eps * (g(r)[0:3, 3:6] @ v), rtol=1e-7, atol=0)
+
+
+def test_radiative_limit():
+    """Im G^Ep(R -> 0) = (2/3) k^3 / eps I and Im G^Hm(R -> 0) = (2/3) k^3 I."""
+    n_env = 1.33
+    k0 = 2 * math.pi / 550.0
+    k = n_env * k0
+    G = O.green6(np.array([1e-2, 2e-2, -1.5e-2]), k0, n_env)
+    assert np.allclose(np.imag(G[0:3, 0:3]), (2 / 3) * k ** 3 / n_env ** 2 * np.eye(3), rtol=1e-6, atol=1e-12)
+    assert np.allclose(np.imag(G[3:6, 3:6]), (2 / 3) * k ** 3 * np.eye(3), rtol=1e-6, atol=1e-12)
+
+
+def test_green_derivatives_match_finite_differences():
+    """The analytic dG/dR and dG/dk0 used by the oracle adjoint."""
+    n_env = 1.2
+    k0 = 2 * math.pi / 640.0
+    R = np.array([21.0, -9.0, 14.0])
+    dR = O.dgreen6_dR(R, k0, n_env)
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = 1e-4
+        fd = (O.green6(R + e, k0, n_env) - O.green6(R - e, k0, n_env)) / 2e-4
+        assert np.max(np.abs(dR[a] - fd)) < 1e-7 * np.max(np.abs(fd))
+    h = 1e-7 * k0
+    fd = (O.green6(R, k0 + h, n_env) - O.green6(R, k0 - h, n_env)) / (2 * h)
+    assert np.max(np.abs(O.dgreen6_dk0(R, k0, n_env) - fd)) < 1e-6 * np.max(np.abs(fd))
+
+
+# ---------------------------------------------------------------------------
+# polarisability, self-term and solve
+# ---------------------------------------------------------------------------
+def _single(eps, step=10.0, n_env=1.0, wl=600.0, pos=(0.0, 0.0, 0.0)):
+    return dict(r_cell=np.array([pos]), step=step, eps_cell=np.array([eps]), n_env=n_env,
+                wavelength=wl, khat=np.array([[0.0, 0.0, 1.0]]),
+                e0=np.array([[1.0, 0.0, 0.0]], dtype=complex), r_probe=np.zeros((0, 3)),
+                r_eff=np.zeros((0, 3)), alpha_eff=np.zeros((0, 6, 6), complex))
+
+
+@pytest.mark.parametrize("eps,n_env", [(12 + 0.1j, 1.0), (2.5 + 1j, 1.33), (-3 + 0.4j, 1.5)])
+def test_single_cell_clausius_mossotti(eps, n_env):
+    """One cubic cell (Sec. "Volume discretization polarizabilities" with the cubic
+    self-term, Eq. selfterm_SEp_cubic) is the quasistatic sphere of equal volume:
+    p = eps_env a^3 (eps - eps_env)/(eps + 2 eps_env) E0 with a^3 = 3 d^3/(4 pi)."""
+    d = 7.0
+    s = O.simulate(_single(eps, d, n_env))
+    a3 = 3 * d ** 3 / (4 * math.pi)
+    eenv = n_env ** 2
+    expect = eenv * a3 * (eps - eenv) / (eps + 2 * eenv)
+    assert abs(s["q"][0, 0] - expect) < 1e-14 * abs(expect)
+    assert np.max(np.abs(s["q"][1:3, 0])) == 0.0
+
+
+@pytest.mark.parametrize("pol", ["parallel", "perpendicular"])
+def test_two_cells_closed_form(pol):
+    """Two cells on the x axis, plane wave along z: by symmetry p1 = p2 = p and
+    p = alpha E0 / (1 - S alpha - G alpha), with G the textbook on-axis field of a
+    dipole, 2 (1/s^3 - ik/s^2) exp(iks)/eps, or its broadside field,
+    (k^2/s + ik/s^2 - 1/s^3) exp(iks)/eps."""
+    eps, n_env, d, s, wl = 9 + 0.3j, 1.2, 8.0, 8.0, 500.0
+    k0 = 2 * math.pi / wl
+    k = n_env * k0
+    eenv = n_env ** 2
+    w = _single(eps, d, n_env, wl)
+    w["r_cell"] = np.array([[-s / 2, 0, 0], [s / 2, 0, 0]])
+    w["eps_cell"] = np.array([eps, eps])
+    w["e0"] = np.array([[1, 0, 0]] if pol == "parallel" else [[0, 1, 0]], dtype=complex)
+    out = O.simulate(w)
+    alpha = (eps - eenv) * d ** 3 / (4 * math.pi)
+    S = -4 * math.pi / (3 * eenv * d ** 3)
+    if pol == "parallel":
+        G = 2 * (1 / s ** 3 - 1j * k / s ** 2) * np.exp(1j * k * s) / eenv
+        comp = 0
+    else:
+        G = (k * k / s + 1j * k / s ** 2 - 1 / s ** 3) * np.exp(1j * k * s) / eenv
+        comp = 1
+    expect = alpha / (1 - S * alpha - G * alpha)
+    for cell in range(2):
+        assert abs(out["q"][3 * cell + comp, 0] - expect) < 1e-13 * abs(expect)
+
+
+def test_lu_solution_equals_explicit_inverse_and_discrete_equation():
+    """Brute force on a tiny mixed system: LU solution == inv(M) @ F0, and the
+    solution satisfies the discrete Lippmann-Schwinger equation
+    F_i = F0_i + sum_j G~_ij alpha_j F_j (Eq. LPS_6by6_discrete) evaluated by
+    plain loops over dipoles in the full 6-component form."""
+    w = gi.small_mixed(seed=3, n_cell_side=1, n_eff=3)
+    sim = O.simulate(w, keep_matrix=True)
+    D = sim["D"]
+    Minv = np.linalg.inv(sim["M"])
+    assert np.allclose(Minv @ sim["F0"], sim["F"], rtol=0, atol=1e-13 * np.abs(sim["F"]).max())
+    F6 = D.to6(sim["F"])
+    E0, H0 = O.planewave(D.pos, w["khat"], w["e0"], D.k0, D.n_env)
+    for i in range(D.N):
+        acc = np.concatenate([E0[:, i, :], H0[:, i, :]], axis=1).T.astype(complex)  # [6, rhs]
+        for j in range(D.N):
+            G = D.S6[i] if i == j else O.green6(D.pos[i] - D.pos[j], D.k0, D.n_env)
+            acc = acc + G @ (D.alpha6[j] @ F6[j])
+        c = D.comps(i)
+        assert np.allclose(acc[c], F6[i][c], rtol=0, atol=1e-12 * np.abs(F6).max())
+
+
+def test_reciprocity_of_assembled_matrix():
+    """G6(r_j, r_i) = P G6(r_i, r_j)^T P with P = diag(I3, -I3); on M = I - G~ A this
+    reads (I - M)_ij alpha_j^-1 = P [(I - M)_ji alpha_i^-1]^T P."""
+    w = gi.small_mixed(seed=5, n_cell_side=2, n_eff=3)
+    D = O.Dipoles(w)
+    M = O.assemble(D)
+    Pm = np.diag([1, 1, 1, -1, -1, -1]).astype(float)
+    K = np.eye(D.n) - M
+    for i in range(D.N):
+        for j in range(D.N):
+            if i == j:
+                continue
+            ci, cj = D.comps(i), D.comps(j)
+            ai = np.linalg.inv(D.alpha6[i][np.ix_(ci, ci)])
+            aj = np.linalg.inv(D.alpha6[j][np.ix_(cj, cj)])
+            bij = K[np.ix_(D.idx[i, ci], D.idx[j, cj])] @ aj
+            bji = K[np.ix_(D.idx[j, cj], D.idx[i, ci])] @ ai
+            Pi, Pj = Pm[np.ix_(ci, ci)], Pm[np.ix_(cj, cj)]
+            assert np.allclose(bij, Pi @ bji.T @ Pj, rtol=1e-12, atol=1e-14 * np.abs(bij).max())
+
+
+# ---------------------------------------------------------------------------
+# cross sections (Sec. "Observables")
+# ---------------------------------------------------------------------------
+def _mie_ab1(m, x):
+    """Mie coefficients a1, b1 of a sphere (mu = 1) from Riccati-Bessel functions."""
+    def psi(z):
+        return z * sp.spherical_jn(1, z), sp.spherical_jn(1, z) + z * sp.spherical_jn(1, z, derivative=True)
+
+    def xi(z):
+        h = sp.spherical_jn(1, z) + 1j * sp.spherical_yn(1, z)
+        dh = sp.spherical_jn(1, z, derivative=True) + 1j * sp.spherical_yn(1, z, derivative=True)
+        return z * h, h + z * dh
+    px, dpx = psi(x)
+    pmx, dpmx = psi(m * x)
+    xx, dxx = xi(x)
+    a1 = (m * pmx * dpx - px * dpmx) / (m * pmx * dxx - xx * dpmx)
+    b1 = (pmx * dpx - m * px * dpmx) / (pmx * dxx - m * xx * dpmx)
+    return a1, b1
+
+
+@pytest.mark.parametrize("n_s,n_env,a,wl", [(3.5, 1.0, 60.0, 700.0), (2.0 + 0.1j, 1.33, 80.0, 600.0)])
+def test_mie_dipole_limit(n_s, n_env, a, wl):
+    """A single effective ED+MD dipole with the Mie polarisabilities of Sec.
+    "Effective polarizabilities of spherical ... particles" (alpha_pE = (3i/2) a1 /
+    (k0^3 n_env), alpha_mH = (3i/2) b1 / (k0^3 n_env^3)) must give the textbook dipolar
+    Mie cross sections sigma_ext = 6 pi/k^2 Re(a1 + b1), sigma_sca = 6 pi/k^2 (|a1|^2 + |b1|^2)."""
+    k0 = 2 * math.pi / wl
+    k = n_env * k0
+    a1, b1 = _mie_ab1(n_s / n_env, k * a)
+    A6 = np.zeros((1, 6, 6), complex)
+    A6[0, 0:3, 0:3] = np.eye(3) * 1.5j * a1 / (k0 ** 3 * n_env)
+    A6[0, 3:6, 3:6] = np.eye(3) * 1.5j * b1 / (k0 ** 3 * n_env ** 3)
+    w = dict(r_cell=np.zeros((0, 3)), step=1.0, eps_cell=np.zeros(0, complex), n_env=n_env,
+             wavelength=wl, khat=np.array([[0.0, 0.0, 1.0], [0.6, 0.0, 0.8]]),
+             e0=np.array([[1.0, 0, 0], [0.8, 0.0, -0.6]], dtype=complex),
+             r_probe=np.zeros((0, 3)), r_eff=np.array([[3.0, -4.0, 5.0]]), alpha_eff=A6)
+    s = O.simulate(w)
+    D = s["D"]
+    ext = 6 * math.pi / k ** 2 * np.real(a1 + b1)
+    sca = 6 * math.pi / k ** 2 * (abs(a1) ** 2 + abs(b1) ** 2)
+    assert np.allclose(s["ext"], ext, rtol=1e-12)
+    assert np.allclose(s["sca"], sca, rtol=1e-12)
+    assert np.allclose(O.sca_farfield_doublesum(D, s["q"], np.ones(2)), sca, rtol=1e-12)
+    if np.imag(n_s) == 0:
+        assert np.allclose(s["abs"], 0.0, atol=1e-12 * ext)
+
+
+def test_mie_small_sphere_reduces_to_clausius_mossotti():
+    """Small-particle limit of a1 gives the quasistatic alpha of the single-cell pin."""
+    n_env, wl, a = 1.2, 1e6, 10.0
+    k0 = 2 * math.pi / wl
+    eps_s = 6.0 + 0.5j
+    a1, _ = _mie_ab1(np.sqrt(eps_s) / n_env, n_env * k0 * a)
+    alpha = 1.5j * a1 / (k0 ** 3 * n_env)
+    cm = n_env ** 2 * a ** 3 * (eps_s - n_env ** 2) / (eps_s + 2 * n_env ** 2)
+    assert abs(alpha - cm) < 1e-6 * abs(cm)
+
+
+def test_passivity_and_lossless():
+    """Im eps >= 0 => sigma_abs >= 0; Im eps = 0 => sigma_abs = 0 and ext = sca."""
+    w = gi.config1()
+    s = O.simulate(w)
+    assert np.all(s["abs"] > 0)
+    w2 = dict(w, eps_cell=np.full(len(w["r_cell"]), 12.0 + 0j))
+    s2 = O.simulate(w2)
+    assert np.allclose(s2["abs"], 0.0, atol=1e-12 * np.max(s2["ext"]))
+    assert np.allclose(s2["ext"], s2["sca"], rtol=1e-12)
+
+
+@pytest.mark.parametrize("mode", ["static", "radiative"])
+def test_optical_theorem_identity(mode):
+    """Energy balance of the solved system (any self-term):
+    ext = sca_ff + C sum Im(F^* q) - rad + C sum Im(q^* S q).
+    In radiative mode this is ext = sca_ff + abs, and lossless => ext = sca_ff."""
+    for w in (gi.small_mixed(seed=2), gi.config1()):
+        s = O.simulate(w, mode)
+        D = s["D"]
+        e2 = np.sum(np.abs(w["e0"]) ** 2, axis=1)
+        C = 4 * math.pi * D.k0 / (D.n_env * e2)
+        ff = O.sca_farfield_doublesum(D, s["q"], e2)
+        q6 = D.to6(s["q"])
+        Sq = np.einsum("dab,dbr->dar", D.S6, q6)
+        selfw = C * np.sum(np.imag(np.conj(q6) * Sq), axis=(0, 1))
+        fq = C * np.sum(np.imag(np.conj(s["F"]) * s["q"]), axis=0)
+        assert np.allclose(s["ext"], ff + fq - s["rad"] + selfw, rtol=1e-12)
+        if mode == "radiative":
+            assert np.allclose(s["ext"], ff + s["abs"], rtol=1e-12)
+    w = gi.config1()
+    w = dict(w, eps_cell=np.full(len(w["r_cell"]), 12.0 + 0j))
+    s = O.simulate(w, "radiative")
+    assert np.allclose(s["ext"], O.sca_farfield_doublesum(s["D"], s["q"], np.ones(2)), rtol=1e-12)
+
+
+def test_farfield_quadrature_equals_double_sum():
+    """sca_ff (closed-form double sum) = (1/|E0|^2) \\oint |A|^2 dOmega by quadrature."""
+    w = gi.small_mixed(seed=7)
+    s = O.simulate(w)
+    e2 = np.sum(np.abs(w["e0"]) ** 2, axis=1)
+    a = O.sca_farfield_doublesum(s["D"], s["q"], e2)
+    b = O.sca_farfield_quadrature(s["D"], s["q"], e2, 64, 128)
+    assert np.allclose(a, b, rtol=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# fields and symmetries
+# ---------------------------------------------------------------------------
+def test_fields_reproduce_solved_local_field():
+    """Re-propagated field at dipole i from all other dipoles, plus the incident
+    field, equals the solved F_i minus the self-field S_i q_i."""
+    w = gi.small_mixed(seed=9)
+    s = O.simulate(w)
+    D = s["D"]
+    q6 = D.to6(s["q"])
+    F6 = D.to6(s["F"])
+    E0, H0 = O.planewave(D.pos, w["khat"], w["e0"], D.k0, D.n_env)
+    for i in (0, 5, D.nc, D.N - 1):
+        others = [j for j in range(D.N) if j != i]
+        Dm = O.Dipoles(w)
+        Dm.pos = D.pos[others]
+        Dm.N = len(others)
+        Dm.nc = D.nc - (1 if i < D.nc else 0)
+        Dm.ne = Dm.N - Dm.nc
+        Dm.n = 3 * Dm.N + 3 * Dm.ne
+        q_o = Dm.from6(q6[others])
+        E, H = O.scattered_fields(Dm, q_o, D.pos[i:i + 1])
+        tot = np.concatenate([E0[:, i] + E[:, 0], H0[:, i] + H[:, 0]], axis=1).T  # [6, rhs]
+        expect = F6[i] - D.S6[i] @ q6[i]
+        c = D.comps(i)
+        assert np.allclose(tot[c], expect[c], rtol=0, atol=1e-12 * np.abs(expect).max())
+
+
+def test_far_field_of_probe_sum_matches_amplitude():
+    """At kR >> 1 the re-propagated field tends to exp(ikR)/R A(n)."""
+    w = gi.small_mixed(seed=4)
+    s = O.simulate(w)
+    D = s["D"]
+    nhat = np.array([[0.3, -0.5, 0.8124038404635961]])
+    nhat /= np.linalg.norm(nhat)
+    Rf = 4e7
+    E, _ = O.scattered_fields(D, s["q"], nhat * Rf)
+    A = O.farfield_amplitude(D, s["q"], nhat)[0]  # [3, rhs]
+    expect = (np.exp(1j * D.k * Rf) / Rf * A).T
+    assert np.allclose(E[:, 0], expect, rtol=0, atol=1e-4 * np.abs(expect).max())
+
+
+def test_sphere_symmetries_and_linearity():
+    """C4 symmetry of the gridded sphere: sigma(x-pol) == sigma(y-pol) and the
+    y-pol moments are the x-pol moments rotated by 90 deg about z; translating
+    the structure leaves the cross sections unchanged; the solve is linear in F0."""
+    w = gi.config1()
+    s = O.simulate(w)
+    assert abs(s["ext"][0] - s["ext"][1]) < 1e-12 * s["ext"][0]
+    D = s["D"]
+    pos = D.pos
+    p = s["q"].reshape(D.N, 3, 2)
+    # rotation Rz(90): (x, y, z) -> (-y, x, z)
+    rot = np.array([[0, -1, 0], [1, 0, 0], [0, 0, 1]], float)
+    key = {tuple(np.round(r, 6)): i for i, r in enumerate(pos)}
+    for i in range(0, D.N, 17):
+        j = key[tuple(np.round(rot @ pos[i], 6))]
+        assert np.allclose(p[j, :, 1], rot @ p[i, :, 0], rtol=0, atol=1e-12 * np.abs(p).max())
+    wt = dict(w, r_cell=w["r_cell"] + np.array([13.0, -4.0, 27.0]))
+    st = O.simulate(wt)
+    assert np.allclose(st["ext"], s["ext"], rtol=1e-12)
+    assert np.allclose(st["abs"], s["abs"], rtol=1e-12)
+    w3 = dict(w, e0=np.array([[2.0 - 1j, 0.5j, 0]]), khat=np.array([[0, 0, 1.0]]))
+    s3 = O.simulate(w3)
+    assert np.allclose(s3["q"][:, 0], (2 - 1j) * s["q"][:, 0] + 0.5j * s["q"][:, 1], rtol=0,
+                       atol=1e-12 * np.abs(s3["q"]).max())
+
+
+# ---------------------------------------------------------------------------
+# adjoint gradient (FP64 reference) vs central finite differences
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["cells", "mixed"])
+def test_adjoint_matches_central_differences(which):
+    if which == "cells":
+        w = dict(gi.config4())
+        w["r_cell"] = gi.cuboid_cells(2, 2, 3, 8.0)
+        w["eps_cell"] = np.full(12, 10 + 0.05j) + np.linspace(0, 1, 12)
+        w["r_probe"] = gi.probe_plane(4, 4, 60.0, 60.0, -50.0)
+    else:
+        w = dict(gi.small_mixed(seed=13, n_cell_side=2, n_eff=2))
+        w["khat"], w["e0"] = w["khat"][:1], w["e0"][:1]
+        w["r_probe"] = w["r_probe"][:10]
+    g = O.adjoint_gradient(w)
+    L0 = O.loss_sca_plus_nearfield(w)
+    assert abs(L0 - g["loss"]) < 1e-12 * abs(L0)
+    nc = len(w["r_cell"])
+    # positions (cells and effective dipoles)
+    h = 1e-4
+    for d, a in ((0, 0), (3, 2), (nc - 1, 1)) + (((nc, 0), (nc + 1, 2)) if which == "mixed" else ()):
+        def L(sgn):
+            rc = np.array(w["r_cell"], dtype=float)
+            re = np.array(w["r_eff"], dtype=float).reshape(-1, 3)
+            if d < nc:
+                rc[d, a] += sgn * h
+            else:
+                re[d - nc, a] += sgn * h
+            return O.loss_sca_plus_nearfield(dict(w, r_cell=rc, r_eff=re))
+        fd = (L(1) - L(-1)) / (2 * h)
+        assert abs(g["r"][d, a] - fd) <= 1e-6 * np.max(np.abs(g["r"])) + 1e-7 * abs(fd)
+    # permittivity
+    he = 1e-4
+    for c in (0, nc // 2):
+        for part, key in ((1.0, "eps_re"), (1j, "eps_im")):
+            def L(sgn):
+                e = np.array(w["eps_cell"], dtype=complex)
+                e[c] += sgn * he * part
+                return O.loss_sca_plus_nearfield(dict(w, eps_cell=e))
+            fd = (L(1) - L(-1)) / (2 * he)
+            assert abs(g[key][c] - fd) <= 1e-6 * np.max(np.abs(g[key])) + 1e-6 * abs(fd)
+    # wavelength
+    hw = 1e-4
+    fd = (O.loss_sca_plus_nearfield(w, wavelength=w["wavelength"] + hw)
+          - O.loss_sca_plus_nearfield(w, wavelength=w["wavelength"] - hw)) / (2 * hw)
+    assert abs(g["wavelength"] - fd) <= 1e-6 * abs(fd)
+
+
+def test_planewave_obeys_maxwell():
+    """Incident plane wave (Appendix, 3D illuminations): Faraday curl E0 = i k0 H0,
+    Ampere curl H0 = -i k0 eps_env E0, and |H0| = n_env |E0|."""
+    n_env, wl = 1.33, 550.0
+    k0 = 2 * math.pi / wl
+    khat = np.array([[0.48, -0.6, 0.64]])
+    e0 = np.array([[0.8, 0.64, 0.0]], dtype=complex)
+    e0 = e0 - (e0 @ khat.T) * khat
+    r = np.array([31.0, 17.0, -44.0])
+    E = lambda x: O.planewave(x[None, :], khat, e0, k0, n_env)[0][0, 0]
+    H = lambda x: O.planewave(x[None, :], khat, e0, k0, n_env)[1][0, 0]
+    assert np.allclose(_curl(E, r, 1e-3), 1j * k0 * H(r), rtol=1e-7)
+    assert np.allclose(_curl(H, r, 1e-3), -1j * k0 * n_env ** 2 * E(r), rtol=1e-7)
+    assert abs(np.linalg.norm(H(r)) - n_env * np.linalg.norm(E(r))) < 1e-14
