@@ -1,0 +1,165 @@
+/* libgdm: Green's Dyadic Method hot path on an MI355X (gfx950) GPU.
+ *
+ * The library solves the coupled electric/magnetic dipole scattering problem of
+ * arXiv:2505.09545 (TorchGDM):
+ *   (a) assembly of the dense coupling matrix M = I - G~ A of the discretised
+ *       Lippmann-Schwinger equation (Sec. "Formalism and implementation", Eq.
+ *       LPS_6by6_discrete and Eq. GDM_system_of_equations), with electric and
+ *       magnetic unknowns separated and the magnetic unknowns of mesh cells
+ *       removed (Sec. "Hybrid discretization GDM");
+ *   (b) LU decomposition with partial pivoting and a multi-RHS solve (Sec.
+ *       "Numerical solution"), in FP64 or in FP32 with FP64 iterative refinement;
+ *   (c) matrix-free re-propagation of the dipole moments to probe points (Sec.
+ *       "Observables") and the extinction / absorption / scattering cross
+ *       sections.
+ *
+ * Conventions shared by every call
+ *  - Units: nm for lengths and wavelengths, nm^2 for cross sections; Gaussian
+ *    units, time factor exp(-i w t), Im(eps) > 0 is absorbing.
+ *  - Complex numbers are interleaved (re, im) pairs of double.  Every array
+ *    argument is a DEVICE pointer on the context's device (e.g. a torch tensor's
+ *    data_ptr()), C order as written in the comments.  Work is enqueued on the
+ *    context's HIP stream: buffers must stay alive until that stream reaches the
+ *    call; calls that return a status derived from device results (factorize,
+ *    solve, fields) synchronise the stream before returning.
+ *  - Unknown layout (n = 3 (n_cell + n_eff) + 3 n_eff): the electric field of
+ *    every dipole (cells first, then effective dipoles), then the magnetic field
+ *    of every effective dipole.  Vectors "in the unknown layout" are [n_rhs][n].
+ *  - Ownership: the caller owns every buffer it passes; the context owns copies
+ *    of the structure, the factors and all workspaces.  Nothing allocated by the
+ *    library is handed to the caller.
+ *  - Errors: every call returns a gdm_status; arguments are validated before any
+ *    work is enqueued (outputs untouched on GDM_E_ARG); gdm_last_error() gives
+ *    a message.  A context is not thread-safe; several contexts may coexist.
+ */
+#ifndef GDM_H
+#define GDM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gdm_ctx gdm_ctx;
+
+typedef enum {
+  GDM_OK = 0,
+  GDM_E_ARG = 1,             /* invalid argument */
+  GDM_E_OOM = 2,             /* device allocation failed */
+  GDM_E_DEVICE = 3,          /* HIP runtime / kernel failure */
+  GDM_E_SINGULAR = 4,        /* exactly zero pivot; gdm_info.bad_index = its column */
+  GDM_E_NOCONV = 5,          /* refinement did not reach tol; best iterate written */
+  GDM_E_PROBE_AT_DIPOLE = 6, /* a probe lies on a dipole (|R| < 1e-9 step) */
+  GDM_E_STATE = 7            /* call order violated (e.g. solve before factorize) */
+} gdm_status;
+
+typedef enum { GDM_PREC_FP64 = 0, GDM_PREC_FP32_IR = 1 } gdm_precision;
+
+/* Self-term of the cubic mesh cells.  STATIC is the paper's
+ * S^Ep = -4 pi / (3 eps_env d^3) I (Eq. selfterm_SEp_cubic); RADIATIVE adds the
+ * radiation-reaction term i (2/3) k^3 / eps_env (an option, not the paper's).
+ * Effective dipoles have zero self-term (Sec. "Self-terms", last paragraph). */
+typedef enum { GDM_SELF_STATIC = 0, GDM_SELF_RADIATIVE = 1 } gdm_selfterm;
+
+typedef struct {
+  int32_t ir_iters;    /* refinement corrections applied after the first solve */
+  double backward_err; /* max over RHS of |r|_inf / (|M|_inf |x|_inf + |F0|_inf) */
+  int64_t bad_index;   /* zero-pivot column for GDM_E_SINGULAR, else -1 */
+  float ms_assemble, ms_factor, ms_solve, ms_ir; /* stage times of the last calls */
+} gdm_info;
+
+/* Create a context on HIP device `device`.  `hip_stream` (a hipStream_t, may be
+ * NULL for a context-owned stream) is used for all work of the context. */
+gdm_status gdm_create(int device, void* hip_stream, gdm_ctx** out);
+void gdm_destroy(gdm_ctx* ctx);
+/* Message of the last failing call (never NULL; owned by the context). */
+const char* gdm_last_error(const gdm_ctx* ctx);
+
+/* Real refractive index of the lossless homogeneous host (Appendix, tg.env
+ * EnvHomogeneous3D).  Must be > 0.  Invalidates the factors. */
+gdm_status gdm_set_environment(gdm_ctx* ctx, double n_env);
+
+/* Structure: n_cell cubic mesh cells of side step_nm at r_cell [n_cell][3] with
+ * complex permittivity eps_cell [n_cell] (polarisability (eps - eps_env) d^3 /
+ * (4 pi), Sec. "Volume discretization polarizabilities"), plus n_eff effective
+ * electric+magnetic point dipoles at r_eff [n_eff][3] with 6x6 polarisability
+ * tensors alpha_eff [n_eff][6][6] (row-major, mapping (E, H) to (p, m); Eq.
+ * after LPS_6by6_discrete).  Either count may be 0 (not both).  The arrays are
+ * copied; the caller may free them after the stream reaches the call.
+ * Invalidates the factors. */
+gdm_status gdm_set_structure(gdm_ctx* ctx, int64_t n_cell, const double* r_cell, double step_nm,
+                             const double* eps_cell, int64_t n_eff, const double* r_eff,
+                             const double* alpha_eff, gdm_selfterm selfterm);
+
+/* Number of unknowns n of the current structure (0 if none). */
+int64_t gdm_num_unknowns(const gdm_ctx* ctx);
+
+/* Step (a) alone: write M = I - G~ A at `wavelength_nm` into the caller's
+ * column-major buffer M_out (n x n, leading dimension ld >= n), as complex
+ * double (dtype 0) or complex float (dtype 1; FP64 arithmetic, rounded once). */
+gdm_status gdm_assemble(gdm_ctx* ctx, double wavelength_nm, int dtype, void* M_out, int64_t ld);
+
+/* Steps (a) + (b1): assemble M at `wavelength_nm` and LU-factorise it in the
+ * context, in FP64 (prec 0) or FP32 (prec 1, keeping an FP64 copy of M for the
+ * refinement residual).  Sets the context wavelength.  GDM_E_SINGULAR on an
+ * exactly zero pivot (info->bad_index, info may be NULL). */
+gdm_status gdm_factorize(gdm_ctx* ctx, double wavelength_nm, gdm_precision prec, gdm_info* info);
+
+/* Incident plane waves at the dipoles in the unknown layout: f0 [n_pw][n] with
+ * E0 = e0 exp(i k khat.r), H0 = n_env khat x E0 (Appendix, 3D illuminations);
+ * khat [n_pw][3] unit vectors, e0 [n_pw][3] complex.  Uses the context
+ * wavelength. */
+gdm_status gdm_incident_planewave(gdm_ctx* ctx, int64_t n_pw, const double* khat, const double* e0, double* f0);
+
+/* Step (b2): solve M F = F0 for n_rhs right-hand sides f0 [n_rhs][n]; writes the
+ * dipole moments q = A F [n_rhs][n] and, if f_out is not NULL, the field F.
+ * FP64 factors: one solve.  FP32 factors: FP64 iterative refinement
+ * (residual and update in FP64) until the normwise backward error of every RHS
+ * is <= tol (tol <= 0 selects 1e-14) or max_iter corrections (max_iter < 0
+ * selects 10); GDM_E_NOCONV if not reached (best iterate written). */
+gdm_status gdm_solve(gdm_ctx* ctx, int64_t n_rhs, const double* f0, double tol, int32_t max_iter,
+                     double* q_out, double* f_out, gdm_info* info);
+
+/* Plane waves at arbitrary points: E, H [n_pw][n_pts][3] (H may be NULL). */
+gdm_status gdm_planewave(gdm_ctx* ctx, int64_t n_pw, const double* khat, const double* e0, int64_t n_pts,
+                         const double* r, double* E, double* H);
+
+/* Step (c): scattered fields of the moments q [n_rhs][n] at n_probe points
+ * r_probe [n_probe][3]: E_sca, H_sca [n_rhs][n_probe][3] (H_sca may be NULL),
+ * FP64, matrix-free.  GDM_E_PROBE_AT_DIPOLE if a probe is within 1e-9 step of
+ * a dipole (its contribution is then skipped).  Uses the context wavelength. */
+gdm_status gdm_fields(gdm_ctx* ctx, int64_t n_rhs, const double* q, int64_t n_probe, const double* r_probe,
+                      double* E_sca, double* H_sca);
+
+/* Cross sections per RHS (Sec. "Observables"), FP64: out [n_rhs][5] =
+ * (extinction, scattering = ext - abs, absorption, radiated-by-dipoles,
+ * far-field scattering by the exact double sum or NaN unless want_ff).
+ * f0, q, f: [n_rhs][n] incident field, moments and solved field at the dipoles;
+ * e0_norm2: |E0|^2 per RHS [n_rhs] (device). */
+gdm_status gdm_cross_sections(gdm_ctx* ctx, int64_t n_rhs, const double* f0, const double* q, const double* f,
+                              const double* e0_norm2, int32_t want_ff, double* out);
+
+/* Dense LU of a caller matrix (dtype 0: complex double, 1: complex float),
+ * column-major n x n, leading dimension lda, factored in place; ipiv [n]
+ * receives 0-based pivot rows.  The factors are in the library's factored form
+ * (row interchanges applied right of each block only) and are meant for
+ * gdm_getrs with the same context, which keeps the block permutations. */
+gdm_status gdm_getrf(gdm_ctx* ctx, int dtype, int64_t n, void* A, int64_t lda, int32_t* ipiv, gdm_info* info);
+/* Solve op(A) X = B in place with the factors of the last gdm_getrf on this
+ * context (trans 0: A, 1: A^T without conjugation); B n x nrhs, ldb >= n. */
+gdm_status gdm_getrs(gdm_ctx* ctx, int dtype, int trans, int64_t n, int64_t nrhs, const void* A, int64_t lda,
+                     void* B, int64_t ldb);
+
+/* Complex GEMM used by the trailing update: C = C - op(A) B (mode 0) or
+ * C = op(A) B (mode 1); dtype 0/1 as above; column-major. */
+gdm_status gdm_gemm(gdm_ctx* ctx, int dtype, int mode, int transA, int64_t m, int64_t n, int64_t k,
+                    const void* A, int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc);
+
+/* Synchronise the context stream. */
+gdm_status gdm_sync(gdm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GDM_H */

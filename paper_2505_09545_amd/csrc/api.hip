@@ -1,0 +1,568 @@
+// C-ABI of libgdm (declared in include/gdm.h): context, device buffers, argument
+// validation and the host drivers that chain the kernels of the hot path.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/gdm.h"
+#include "gdm_common.hpp"
+#include "gdm_kernels.hpp"
+#include "gdm_misc.hpp"
+
+using namespace gdm;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= cap && p) return hipSuccess;
+    if (p) {
+      hipError_t e = hipFree(p);
+      if (e != hipSuccess) return e;
+      p = nullptr;
+      cap = 0;
+    }
+    if (bytes == 0) bytes = 256;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();
+      return e;
+    }
+    cap = bytes;
+    return hipSuccess;
+  }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+__global__ void fill_i32_kernel(int* a, int n, int v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+}  // namespace
+
+struct gdm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int num_cu = 256;
+  int lds_bytes = 160 * 1024;
+  std::string err = "";
+  double n_env = 1.0;
+  // structure
+  int64_t nc = 0, ne = 0, N = 0, n = 0;
+  double step = 0.0;
+  gdm_selfterm self_mode = GDM_SELF_STATIC;
+  DevBuf pos, eps, alpha_c, alpha6;
+  // factorisation state
+  double wavelength = 0.0;
+  bool factored = false;
+  gdm_precision prec = GDM_PREC_FP64;
+  DevBuf M, M64, ipiv, luws, rows;
+  LUPlan plan;
+  int64_t ld = 0;
+  double Minf = 0.0;
+  // standalone getrf state
+  LUPlan ext_plan;
+  int ext_dtype = -1;
+  DevBuf ext_ws;
+  // solve / fields scratch
+  DevBuf X, Rr, C32, small, scratch, flag;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  float ms_assemble = 0, ms_factor = 0;
+};
+
+#define FAIL(ctx, code, ...)                                     \
+  do {                                                           \
+    char _b[512];                                                \
+    snprintf(_b, sizeof(_b), __VA_ARGS__);                       \
+    (ctx)->err = _b;                                             \
+    return code;                                                 \
+  } while (0)
+
+#define HIPCHK(ctx, expr)                                                                                   \
+  do {                                                                                                      \
+    hipError_t _e = (expr);                                                                                 \
+    if (_e != hipSuccess) {                                                                                 \
+      if (_e == hipErrorOutOfMemory || _e == hipErrorMemoryAllocation)                                      \
+        FAIL(ctx, GDM_E_OOM, "device allocation failed in %s: %s", #expr, hipGetErrorString(_e));           \
+      FAIL(ctx, GDM_E_DEVICE, "HIP error in %s: %s", #expr, hipGetErrorString(_e));                         \
+    }                                                                                                       \
+  } while (0)
+
+static DipoleView view_of(const gdm_ctx* c, double2 self_c) {
+  DipoleView d;
+  d.pos = c->pos.as<double>();
+  d.alpha_c = c->alpha_c.as<double2>();
+  d.alpha6 = c->alpha6.as<double2>();
+  d.N = c->N;
+  d.nc = c->nc;
+  d.ne = c->ne;
+  d.self_c = self_c;
+  return d;
+}
+
+static Wave wave_of(const gdm_ctx* c, double wl) {
+  Wave w;
+  w.k0 = 2.0 * M_PI / wl;
+  w.k = c->n_env * w.k0;
+  w.eps_env = c->n_env * c->n_env;
+  return w;
+}
+
+static double2 self_term(const gdm_ctx* c, const Wave& w) {
+  const double eps = w.eps_env;
+  double2 s = make_double2(-4.0 * M_PI / (3.0 * eps * c->step * c->step * c->step), 0.0);
+  if (c->self_mode == GDM_SELF_RADIATIVE) s.y = (2.0 / 3.0) * w.k * w.k * w.k / eps;
+  return s;
+}
+
+static gdm_status prepare_alpha(gdm_ctx* c) {
+  HIPCHK(c, launch_cell_alpha(c->eps.as<double2>(), c->nc, c->n_env * c->n_env, c->step, c->alpha_c.as<double2>(),
+                              c->stream));
+  return GDM_OK;
+}
+
+static gdm_status check_wavelength(gdm_ctx* c, double wl) {
+  if (!(wl > 0.0) || !std::isfinite(wl)) FAIL(c, GDM_E_ARG, "wavelength must be finite and > 0 (got %g)", wl);
+  if (c->N == 0) FAIL(c, GDM_E_STATE, "no structure set");
+  return GDM_OK;
+}
+
+template <typename T>
+static gdm_status run_lu(gdm_ctx* c, void* A, int64_t n, int64_t ld, LUPlan& plan, DevBuf& ws, DevBuf& ipiv,
+                         int32_t* ipiv_out, gdm_info* info) {
+  plan = lu_plan(n, (int)sizeof(T), c->num_cu, c->lds_bytes);
+  const size_t wsb = lu_workspace_bytes(plan, (int)sizeof(T), c->num_cu);
+  HIPCHK(c, ws.ensure(wsb));
+  LUWork w;
+  lu_workspace_carve(ws.p, plan, (int)sizeof(T), c->num_cu, w);
+  int32_t* piv = ipiv_out;
+  if (!piv) {
+    HIPCHK(c, ipiv.ensure(sizeof(int32_t) * n));
+    piv = ipiv.as<int32_t>();
+  }
+  HIPCHK(c, lu_factor<T>(A, ld, plan, w, piv, c->stream));
+  int32_t err[2] = {0, 0};
+  HIPCHK(c, hipMemcpyAsync(err, w.err, sizeof(err), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (info) info->bad_index = -1;
+  if (err[0] != 0) FAIL(c, GDM_E_DEVICE, "LU panel barrier timed out (workgroups not co-resident?)");
+  if (err[1] != INT32_MAX) {
+    if (info) info->bad_index = err[1];
+    FAIL(c, GDM_E_SINGULAR, "exactly zero pivot in column %d", err[1]);
+  }
+  return GDM_OK;
+}
+
+
+extern "C" {
+
+gdm_status gdm_create(int device, void* hip_stream, gdm_ctx** out) {
+  if (!out) return GDM_E_ARG;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return GDM_E_DEVICE;
+  if (device < 0 || device >= ndev) return GDM_E_ARG;
+  if (hipSetDevice(device) != hipSuccess) return GDM_E_DEVICE;
+  gdm_ctx* c = new gdm_ctx();
+  c->device = device;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+    c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+    size_t lds = prop.maxSharedMemoryPerMultiProcessor;
+    if (lds == 0 || lds > 160 * 1024) lds = 160 * 1024;
+    c->lds_bytes = (int)lds;
+  }
+  if (hip_stream) {
+    c->stream = static_cast<hipStream_t>(hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return GDM_E_DEVICE;
+    }
+    c->own_stream = true;
+  }
+  for (auto& e : c->ev) (void)hipEventCreate(&e);
+  *out = c;
+  return GDM_OK;
+}
+
+void gdm_destroy(gdm_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  for (DevBuf* b : {&c->pos, &c->eps, &c->alpha_c, &c->alpha6, &c->M, &c->M64, &c->ipiv, &c->luws, &c->rows,
+                    &c->ext_ws, &c->X, &c->Rr, &c->C32, &c->small, &c->scratch, &c->flag})
+    b->release();
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+const char* gdm_last_error(const gdm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+gdm_status gdm_sync(gdm_ctx* c) {
+  if (!c) return GDM_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return GDM_OK;
+}
+
+gdm_status gdm_set_environment(gdm_ctx* c, double n_env) {
+  if (!c) return GDM_E_ARG;
+  if (!(n_env > 0.0) || !std::isfinite(n_env)) FAIL(c, GDM_E_ARG, "n_env must be finite and > 0 (got %g)", n_env);
+  c->n_env = n_env;
+  c->factored = false;
+  return GDM_OK;
+}
+
+gdm_status gdm_set_structure(gdm_ctx* c, int64_t n_cell, const double* r_cell, double step_nm, const double* eps_cell,
+                             int64_t n_eff, const double* r_eff, const double* alpha_eff, gdm_selfterm selfterm) {
+  if (!c) return GDM_E_ARG;
+  if (n_cell < 0 || n_eff < 0 || n_cell + n_eff == 0)
+    FAIL(c, GDM_E_ARG, "need n_cell >= 0, n_eff >= 0 and at least one dipole (got %lld, %lld)", (long long)n_cell,
+         (long long)n_eff);
+  if (n_cell > 0 && (!r_cell || !eps_cell)) FAIL(c, GDM_E_ARG, "r_cell and eps_cell are required when n_cell > 0");
+  if (n_cell > 0 && !(step_nm > 0.0 && std::isfinite(step_nm))) FAIL(c, GDM_E_ARG, "step_nm must be > 0");
+  if (n_eff > 0 && (!r_eff || !alpha_eff)) FAIL(c, GDM_E_ARG, "r_eff and alpha_eff are required when n_eff > 0");
+  if (selfterm != GDM_SELF_STATIC && selfterm != GDM_SELF_RADIATIVE) FAIL(c, GDM_E_ARG, "unknown self-term mode");
+  const int64_t N = n_cell + n_eff;
+  if (3 * N + 3 * n_eff > (int64_t)INT32_MAX) FAIL(c, GDM_E_ARG, "too many unknowns");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, c->pos.ensure(sizeof(double) * 3 * N));
+  HIPCHK(c, c->eps.ensure(sizeof(double2) * std::max<int64_t>(n_cell, 1)));
+  HIPCHK(c, c->alpha_c.ensure(sizeof(double2) * std::max<int64_t>(n_cell, 1)));
+  HIPCHK(c, c->alpha6.ensure(sizeof(double2) * 36 * std::max<int64_t>(n_eff, 1)));
+  if (n_cell > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->pos.p, r_cell, sizeof(double) * 3 * n_cell, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->eps.p, eps_cell, sizeof(double2) * n_cell, hipMemcpyDeviceToDevice, c->stream));
+  }
+  if (n_eff > 0) {
+    HIPCHK(c, hipMemcpyAsync(c->pos.as<double>() + 3 * n_cell, r_eff, sizeof(double) * 3 * n_eff,
+                             hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->alpha6.p, alpha_eff, sizeof(double2) * 36 * n_eff, hipMemcpyDeviceToDevice,
+                             c->stream));
+  }
+  c->nc = n_cell;
+  c->ne = n_eff;
+  c->N = N;
+  c->n = 3 * N + 3 * n_eff;
+  c->step = n_cell > 0 ? step_nm : 1.0;
+  c->self_mode = selfterm;
+  c->factored = false;
+  return GDM_OK;
+}
+
+int64_t gdm_num_unknowns(const gdm_ctx* c) { return c ? c->n : 0; }
+
+gdm_status gdm_assemble(gdm_ctx* c, double wl, int dtype, void* M_out, int64_t ld) {
+  if (!c) return GDM_E_ARG;
+  gdm_status s = check_wavelength(c, wl);
+  if (s != GDM_OK) return s;
+  if (!M_out) FAIL(c, GDM_E_ARG, "M_out is NULL");
+  if (dtype != 0 && dtype != 1) FAIL(c, GDM_E_ARG, "dtype must be 0 (complex double) or 1 (complex float)");
+  if (ld < c->n) FAIL(c, GDM_E_ARG, "ld (%lld) < n (%lld)", (long long)ld, (long long)c->n);
+  HIPCHK(c, hipSetDevice(c->device));
+  if ((s = prepare_alpha(c)) != GDM_OK) return s;
+  const Wave w = wave_of(c, wl);
+  const DipoleView d = view_of(c, self_term(c, w));
+  if (dtype == 0) HIPCHK(c, launch_assemble<double>(d, w, M_out, ld, c->stream));
+  else HIPCHK(c, launch_assemble<float>(d, w, M_out, ld, c->stream));
+  return GDM_OK;
+}
+
+gdm_status gdm_factorize(gdm_ctx* c, double wl, gdm_precision prec, gdm_info* info) {
+  if (!c) return GDM_E_ARG;
+  gdm_status s = check_wavelength(c, wl);
+  if (s != GDM_OK) return s;
+  if (prec != GDM_PREC_FP64 && prec != GDM_PREC_FP32_IR) FAIL(c, GDM_E_ARG, "unknown precision");
+  HIPCHK(c, hipSetDevice(c->device));
+  c->factored = false;
+  const int64_t n = c->n;
+  c->ld = n;
+  if ((s = prepare_alpha(c)) != GDM_OK) return s;
+  const Wave w = wave_of(c, wl);
+  const DipoleView d = view_of(c, self_term(c, w));
+  HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+  if (prec == GDM_PREC_FP64) {
+    HIPCHK(c, c->M.ensure(sizeof(double2) * n * n));
+    HIPCHK(c, launch_assemble<double>(d, w, c->M.p, n, c->stream));
+  } else {
+    HIPCHK(c, c->M64.ensure(sizeof(double2) * n * n));
+    HIPCHK(c, c->M.ensure(sizeof(float2) * n * n));
+    HIPCHK(c, launch_assemble<double>(d, w, c->M64.p, n, c->stream));
+    HIPCHK(c, launch_assemble<float>(d, w, c->M.p, n, c->stream));
+    HIPCHK(c, c->rows.ensure(sizeof(double) * n));
+    HIPCHK(c, launch_rowsum_abs(c->M64.as<double2>(), n, n, c->rows.as<double>(), c->stream));
+  }
+  HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+  if (prec == GDM_PREC_FP64) s = run_lu<double>(c, c->M.p, n, n, c->plan, c->luws, c->ipiv, nullptr, info);
+  else s = run_lu<float>(c, c->M.p, n, n, c->plan, c->luws, c->ipiv, nullptr, info);
+  if (s != GDM_OK) return s;
+  HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
+  HIPCHK(c, hipEventSynchronize(c->ev[2]));
+  (void)hipEventElapsedTime(&c->ms_assemble, c->ev[0], c->ev[1]);
+  (void)hipEventElapsedTime(&c->ms_factor, c->ev[1], c->ev[2]);
+  if (prec == GDM_PREC_FP32_IR) {
+    std::vector<double> rows(n);
+    HIPCHK(c, hipMemcpy(rows.data(), c->rows.p, sizeof(double) * n, hipMemcpyDeviceToHost));
+    c->Minf = *std::max_element(rows.begin(), rows.end());
+  }
+  if (info) {
+    info->ms_assemble = c->ms_assemble;
+    info->ms_factor = c->ms_factor;
+    info->bad_index = -1;
+  }
+  c->wavelength = wl;
+  c->prec = prec;
+  c->factored = true;
+  return GDM_OK;
+}
+
+gdm_status gdm_incident_planewave(gdm_ctx* c, int64_t n_pw, const double* khat, const double* e0, double* f0) {
+  if (!c) return GDM_E_ARG;
+  if (c->wavelength <= 0) FAIL(c, GDM_E_STATE, "no wavelength set (call gdm_factorize first)");
+  if (n_pw < 0 || (n_pw > 0 && (!khat || !e0 || !f0))) FAIL(c, GDM_E_ARG, "bad plane-wave arguments");
+  if (n_pw > 65535) FAIL(c, GDM_E_ARG, "at most 65535 plane waves per call");
+  HIPCHK(c, hipSetDevice(c->device));
+  const Wave w = wave_of(c, c->wavelength);
+  const DipoleView d = view_of(c, make_double2(0, 0));
+  HIPCHK(c, launch_incident(d, w, c->n_env, n_pw, khat, reinterpret_cast<const double2*>(e0),
+                            reinterpret_cast<double2*>(f0), c->n, c->stream));
+  return GDM_OK;
+}
+
+gdm_status gdm_planewave(gdm_ctx* c, int64_t n_pw, const double* khat, const double* e0, int64_t n_pts,
+                         const double* r, double* E, double* H) {
+  if (!c) return GDM_E_ARG;
+  if (c->wavelength <= 0) FAIL(c, GDM_E_STATE, "no wavelength set (call gdm_factorize first)");
+  if (n_pw < 0 || n_pts < 0 || (n_pw > 0 && n_pts > 0 && (!khat || !e0 || !r || !E)))
+    FAIL(c, GDM_E_ARG, "bad plane-wave arguments");
+  if (n_pw > 65535) FAIL(c, GDM_E_ARG, "at most 65535 plane waves per call");
+  HIPCHK(c, hipSetDevice(c->device));
+  const Wave w = wave_of(c, c->wavelength);
+  HIPCHK(c, launch_planewave_points(w, c->n_env, n_pw, khat, reinterpret_cast<const double2*>(e0), r, n_pts,
+                                    reinterpret_cast<double2*>(E), reinterpret_cast<double2*>(H), c->stream));
+  return GDM_OK;
+}
+
+gdm_status gdm_solve(gdm_ctx* c, int64_t nrhs, const double* f0, double tol, int32_t max_iter, double* q_out,
+                     double* f_out, gdm_info* info) {
+  if (!c) return GDM_E_ARG;
+  if (!c->factored) FAIL(c, GDM_E_STATE, "gdm_solve before gdm_factorize");
+  if (nrhs <= 0 || !f0 || !q_out) FAIL(c, GDM_E_ARG, "need n_rhs > 0, f0 and q_out");
+  if (nrhs > 65535) FAIL(c, GDM_E_ARG, "at most 65535 right-hand sides per call");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int64_t n = c->n;
+  const double2* F0 = reinterpret_cast<const double2*>(f0);
+  HIPCHK(c, c->X.ensure(sizeof(double2) * n * nrhs));
+  double2* X = c->X.as<double2>();
+  const DipoleView d = view_of(c, make_double2(0, 0));
+  HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+  LUWork w;
+  const int eb = c->prec == GDM_PREC_FP64 ? 8 : 4;
+  lu_workspace_carve(c->luws.p, c->plan, eb, c->num_cu, w);
+  int iters = 0;
+  double be_max = 0.0;
+  gdm_status status = GDM_OK;
+  float ms_ir = 0.f;
+  if (c->prec == GDM_PREC_FP64) {
+    HIPCHK(c, launch_copy_d(F0, n, X, n, n, nrhs, c->stream));
+    HIPCHK(c, lu_solve<double>(0, c->M.p, c->ld, c->plan, w, X, n, nrhs, c->stream));
+  } else {
+    if (tol <= 0) tol = 1e-14;
+    if (max_iter < 0) max_iter = 10;
+    HIPCHK(c, c->Rr.ensure(sizeof(double2) * n * nrhs));
+    HIPCHK(c, c->C32.ensure(sizeof(float2) * n * nrhs));
+    HIPCHK(c, c->small.ensure(sizeof(double) * 4 * nrhs));
+    double2* Rr = c->Rr.as<double2>();
+    float2* C32 = c->C32.as<float2>();
+    double* sm = c->small.as<double>();  // [0..nrhs): |r|, [nrhs..2nrhs): |x|, [2nrhs..): |F0|, [3nrhs..): |c|
+    // first solve from F0 in FP32
+    HIPCHK(c, launch_convert_d2f(F0, n, C32, n, n, nrhs, c->stream));
+    HIPCHK(c, lu_solve<float>(0, c->M.p, c->ld, c->plan, w, C32, n, nrhs, c->stream));
+    HIPCHK(c, launch_convert_f2d(C32, n, X, n, n, nrhs, c->stream));
+    HIPCHK(c, launch_colmax(F0, n, n, nrhs, sm + 2 * nrhs, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+    std::vector<double> h(4 * nrhs);
+    std::vector<double> prev_c(nrhs, INFINITY);
+    for (int it = 0;; ++it) {
+      // r = F0 - M x  (FP64, stored FP64 matrix)
+      HIPCHK(c, launch_copy_d(F0, n, Rr, n, n, nrhs, c->stream));
+      HIPCHK(c, launch_gemm<double>(0, 0, n, nrhs, n, c->M64.p, n, X, n, Rr, n, c->stream));
+      HIPCHK(c, launch_colmax(Rr, n, n, nrhs, sm, c->stream));
+      HIPCHK(c, launch_colmax(X, n, n, nrhs, sm + nrhs, c->stream));
+      HIPCHK(c, hipMemcpyAsync(h.data(), sm, sizeof(double) * 4 * nrhs, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      be_max = 0.0;
+      for (int64_t r = 0; r < nrhs; ++r) {
+        const double den = c->Minf * h[nrhs + r] + h[2 * nrhs + r];
+        const double be = den > 0 ? h[r] / den : 0.0;
+        be_max = std::max(be_max, be);
+      }
+      if (be_max <= tol) break;
+      if (it >= max_iter) {
+        status = GDM_E_NOCONV;
+        break;
+      }
+      if (it > 0) {
+        bool stagnated = true;
+        for (int64_t r = 0; r < nrhs; ++r)
+          if (!(h[3 * nrhs + r] > 0.5 * prev_c[r])) stagnated = false;
+        if (stagnated) {
+          status = GDM_E_NOCONV;
+          break;
+        }
+        for (int64_t r = 0; r < nrhs; ++r) prev_c[r] = h[3 * nrhs + r];
+      }
+      HIPCHK(c, launch_convert_d2f(Rr, n, C32, n, n, nrhs, c->stream));
+      HIPCHK(c, lu_solve<float>(0, c->M.p, c->ld, c->plan, w, C32, n, nrhs, c->stream));
+      HIPCHK(c, launch_axpy_f2d(C32, n, X, n, n, nrhs, sm + 3 * nrhs, c->stream));
+      ++iters;
+    }
+    HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
+  }
+  HIPCHK(c, launch_apply_alpha(d, X, n, reinterpret_cast<double2*>(q_out), n, nrhs, c->stream));
+  if (f_out) HIPCHK(c, launch_copy_d(X, n, reinterpret_cast<double2*>(f_out), n, n, nrhs, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
+  HIPCHK(c, hipEventSynchronize(c->ev[3]));
+  float ms_total = 0.f;
+  (void)hipEventElapsedTime(&ms_total, c->ev[0], c->ev[3]);
+  if (c->prec == GDM_PREC_FP32_IR) (void)hipEventElapsedTime(&ms_ir, c->ev[1], c->ev[2]);
+  if (info) {
+    info->ir_iters = iters;
+    info->backward_err = be_max;
+    info->bad_index = -1;
+    info->ms_assemble = c->ms_assemble;
+    info->ms_factor = c->ms_factor;
+    info->ms_solve = ms_total - ms_ir;
+    info->ms_ir = ms_ir;
+  }
+  if (status == GDM_E_NOCONV) FAIL(c, GDM_E_NOCONV, "refinement stopped at backward error %.3e > tol %.3e", be_max, tol);
+  return GDM_OK;
+}
+
+gdm_status gdm_fields(gdm_ctx* c, int64_t nrhs, const double* q, int64_t P, const double* rp, double* E, double* H) {
+  if (!c) return GDM_E_ARG;
+  if (c->wavelength <= 0) FAIL(c, GDM_E_STATE, "no wavelength set (call gdm_factorize first)");
+  if (nrhs <= 0 || P < 0 || !q || (P > 0 && (!rp || !E))) FAIL(c, GDM_E_ARG, "bad field arguments");
+  if (P == 0) return GDM_OK;
+  if ((P + 255) / 256 > (int64_t)INT32_MAX) FAIL(c, GDM_E_ARG, "too many probes");
+  HIPCHK(c, hipSetDevice(c->device));
+  const Wave w = wave_of(c, c->wavelength);
+  const DipoleView d = view_of(c, make_double2(0, 0));
+  const int nsplit = fields_num_splits(P, c->N, c->num_cu);
+  if (nsplit > 1) HIPCHK(c, c->scratch.ensure(sizeof(double2) * 2 * (size_t)nsplit * nrhs * P * 3));
+  HIPCHK(c, c->flag.ensure(sizeof(int) * 4));
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, c->stream, c->flag.as<int>(), 4, 0);
+  const double rmin = 1e-9 * c->step;
+  HIPCHK(c, launch_fields(d, w, reinterpret_cast<const double2*>(q), c->n, nrhs, rp, P, reinterpret_cast<double2*>(E),
+                          reinterpret_cast<double2*>(H), c->scratch.as<double2>(), nsplit, rmin * rmin,
+                          c->flag.as<int>(), c->stream));
+  int flag = 0;
+  HIPCHK(c, hipMemcpyAsync(&flag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (flag) FAIL(c, GDM_E_PROBE_AT_DIPOLE, "a probe point lies on a dipole (|R| < 1e-9 step)");
+  return GDM_OK;
+}
+
+gdm_status gdm_cross_sections(gdm_ctx* c, int64_t nrhs, const double* f0, const double* q, const double* f,
+                              const double* e0_norm2, int32_t want_ff, double* out) {
+  if (!c) return GDM_E_ARG;
+  if (c->wavelength <= 0) FAIL(c, GDM_E_STATE, "no wavelength set (call gdm_factorize first)");
+  if (nrhs <= 0 || !f0 || !q || !f || !e0_norm2 || !out) FAIL(c, GDM_E_ARG, "bad cross-section arguments");
+  if (nrhs > 65535) FAIL(c, GDM_E_ARG, "at most 65535 right-hand sides per call");
+  HIPCHK(c, hipSetDevice(c->device));
+  const Wave w = wave_of(c, c->wavelength);
+  const DipoleView d = view_of(c, make_double2(0, 0));
+  const int64_t nblk = sca_ff_blocks(c->N);
+  HIPCHK(c, c->small.ensure(sizeof(double) * std::max<int64_t>(5 * nrhs + nrhs * nblk, 4 * nrhs)));
+  double* sums = c->small.as<double>();
+  double* part = sums + 5 * nrhs;
+  HIPCHK(c, launch_cs_sums(d, reinterpret_cast<const double2*>(f0), reinterpret_cast<const double2*>(q),
+                           reinterpret_cast<const double2*>(f), c->n, nrhs, sums, c->stream));
+  if (want_ff)
+    HIPCHK(c, launch_sca_ff(d, w, reinterpret_cast<const double2*>(q), c->n, nrhs, part, nblk, c->stream));
+  std::vector<double> h(5 * nrhs + (want_ff ? nrhs * nblk : 0)), e2(nrhs);
+  HIPCHK(c, hipMemcpyAsync(h.data(), sums, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(e2.data(), e0_norm2, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::vector<double> o(5 * nrhs);
+  const double k3 = (2.0 / 3.0) * w.k * w.k * w.k;
+  for (int64_t r = 0; r < nrhs; ++r) {
+    if (!(e2[r] > 0)) FAIL(c, GDM_E_ARG, "|E0|^2 of RHS %lld is not > 0", (long long)r);
+    const double C = 4.0 * M_PI * w.k0 / (c->n_env * e2[r]);
+    const double* s = &h[5 * r];
+    const double ext = C * s[0];
+    const double ab = C * (s[1] - k3 * (s[3] / w.eps_env + s[4]));
+    const double rad = C * k3 * ((s[2] + s[3]) / w.eps_env + s[4]);
+    o[5 * r + 0] = ext;
+    o[5 * r + 1] = ext - ab;
+    o[5 * r + 2] = ab;
+    o[5 * r + 3] = rad;
+    if (want_ff) {
+      double off = 0;
+      for (int64_t b = 0; b < nblk; ++b) off += h[5 * nrhs + r * nblk + b];
+      o[5 * r + 4] = C * off + rad;
+    } else {
+      o[5 * r + 4] = NAN;
+    }
+  }
+  HIPCHK(c, hipMemcpyAsync(out, o.data(), sizeof(double) * o.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return GDM_OK;
+}
+
+gdm_status gdm_getrf(gdm_ctx* c, int dtype, int64_t n, void* A, int64_t lda, int32_t* ipiv, gdm_info* info) {
+  if (!c) return GDM_E_ARG;
+  if (dtype != 0 && dtype != 1) FAIL(c, GDM_E_ARG, "dtype must be 0 or 1");
+  if (n <= 0 || n > (int64_t)INT32_MAX / 4 || !A || !ipiv || lda < n) FAIL(c, GDM_E_ARG, "bad getrf arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  DevBuf dummy;
+  gdm_status s = dtype == 0 ? run_lu<double>(c, A, n, lda, c->ext_plan, c->ext_ws, dummy, ipiv, info)
+                            : run_lu<float>(c, A, n, lda, c->ext_plan, c->ext_ws, dummy, ipiv, info);
+  c->ext_dtype = (s == GDM_OK || s == GDM_E_SINGULAR) ? dtype : -1;
+  return s;
+}
+
+gdm_status gdm_getrs(gdm_ctx* c, int dtype, int trans, int64_t n, int64_t nrhs, const void* A, int64_t lda, void* B,
+                     int64_t ldb) {
+  if (!c) return GDM_E_ARG;
+  if (c->ext_dtype != dtype || c->ext_plan.n != n) FAIL(c, GDM_E_STATE, "gdm_getrs without a matching gdm_getrf");
+  if (nrhs < 0 || !A || (nrhs > 0 && !B) || lda < n || ldb < n || (trans != 0 && trans != 1))
+    FAIL(c, GDM_E_ARG, "bad getrs arguments");
+  if (nrhs > 65535) FAIL(c, GDM_E_ARG, "at most 65535 right-hand sides per call");
+  HIPCHK(c, hipSetDevice(c->device));
+  LUWork w;
+  lu_workspace_carve(c->ext_ws.p, c->ext_plan, dtype == 0 ? 8 : 4, c->num_cu, w);
+  if (dtype == 0) HIPCHK(c, lu_solve<double>(trans, A, lda, c->ext_plan, w, B, ldb, nrhs, c->stream));
+  else HIPCHK(c, lu_solve<float>(trans, A, lda, c->ext_plan, w, B, ldb, nrhs, c->stream));
+  return GDM_OK;
+}
+
+gdm_status gdm_gemm(gdm_ctx* c, int dtype, int mode, int transA, int64_t m, int64_t n, int64_t k, const void* A,
+                    int64_t lda, const void* B, int64_t ldb, void* C, int64_t ldc) {
+  if (!c) return GDM_E_ARG;
+  if ((dtype != 0 && dtype != 1) || (mode != 0 && mode != 1) || (transA != 0 && transA != 1))
+    FAIL(c, GDM_E_ARG, "bad gemm mode");
+  if (m < 0 || n < 0 || k < 0 || !A || !B || !C) FAIL(c, GDM_E_ARG, "bad gemm arguments");
+  if (ldc < m || ldb < k || lda < (transA ? k : m)) FAIL(c, GDM_E_ARG, "bad gemm leading dimensions");
+  HIPCHK(c, hipSetDevice(c->device));
+  if (dtype == 0) HIPCHK(c, launch_gemm<double>(mode, transA, m, n, k, A, lda, B, ldb, C, ldc, c->stream));
+  else HIPCHK(c, launch_gemm<float>(mode, transA, m, n, k, A, lda, B, ldb, C, ldc, c->stream));
+  return GDM_OK;
+}
+
+}  // extern "C"

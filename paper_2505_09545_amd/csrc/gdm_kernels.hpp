@@ -1,0 +1,67 @@
+// Host-side launch declarations shared by the kernel files and the C-ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <vector>
+
+namespace gdm {
+
+// Dipoles in device memory: N = nc cells followed by ne effective ED+MD dipoles.
+struct DipoleView {
+  const double* pos;       // [N][3] nm
+  const double2* alpha_c;  // [nc] cell polarisability (times I3)
+  const double2* alpha6;   // [ne][6][6] row-major effective polarisability
+  int64_t N, nc, ne;
+  double2 self_c;          // S^Ep of a cell (times I3)
+};
+
+template <typename T>
+hipError_t launch_assemble(const DipoleView& d, const struct Wave& w, void* M, int64_t ld, hipStream_t st);
+
+// C (m x n) = C - op(A) B   (mode 0)   or   C = op(A) B   (mode 1);
+// complex interleaved, column-major; op(A) = A (transA 0) or A^T (transA 1, no conjugation).
+template <typename T>
+hipError_t launch_gemm(int mode, int transA, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st);
+
+// ---------------------------------------------------------------------------
+// blocked LU with partial pivoting
+// ---------------------------------------------------------------------------
+struct LUBlock {
+  int64_t k0;  // first row/column of the block
+  int w;       // block width
+  int R;       // panel rows per workgroup
+  int G;       // panel workgroups
+};
+
+struct LUPlan {
+  int64_t n = 0;
+  int nb = 0;
+  int max_wg = 0;  // number of CUs: upper bound on panel workgroups
+  std::vector<LUBlock> blocks;
+};
+
+// Device workspace of the factorisation; sized by lu_workspace_bytes().
+struct LUWork {
+  uint32_t* cnt;   // [nb] barrier arrival counters
+  uint64_t* key;   // [nb] pivot keys
+  void* slot;      // [2][Gmax][nb] complex candidate rows
+  void* dslot;     // [2][nb] complex diagonal rows
+  int32_t* err;    // [2]: barrier timeout flag, first zero pivot (INT32_MAX if none)
+  int32_t* pairs;  // [nblocks][2][2 nb]: destination rows then source rows
+  int32_t* npairs; // [nblocks]
+};
+
+LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes);
+size_t lu_workspace_bytes(const LUPlan& p, int elem_bytes, int num_cu);
+void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu, LUWork& w);
+
+template <typename T>
+hipError_t lu_factor(void* A, int64_t ld, const LUPlan& plan, const LUWork& ws, int32_t* ipiv, hipStream_t st);
+
+// Solve op(M) X = B in place for B (n x nrhs, ld ldb) with the factors of lu_factor.
+template <typename T>
+hipError_t lu_solve(int trans, const void* A, int64_t ld, const LUPlan& plan, const LUWork& ws, void* B,
+                    int64_t ldb, int64_t nrhs, hipStream_t st);
+
+}  // namespace gdm

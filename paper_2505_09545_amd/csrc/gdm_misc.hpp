@@ -1,0 +1,55 @@
+// Launch declarations of the small kernels (incident field, polarisation,
+// cross sections, refinement helpers, probe fields).
+#pragma once
+#include "gdm_common.hpp"
+#include "gdm_kernels.hpp"
+
+namespace gdm {
+
+// alpha_c[i] = (eps[i] - eps_env) d^3 / (4 pi)
+hipError_t launch_cell_alpha(const double2* eps, int64_t nc, double eps_env, double step, double2* alpha,
+                             hipStream_t st);
+
+// F0 at the dipoles in the unknown layout, [n_pw][n] (ld n): plane wave
+// E0 = e0 exp(i k khat.r), H0 = n_env khat x E0.
+hipError_t launch_incident(const DipoleView& d, const Wave& w, double n_env, int64_t n_pw, const double* khat,
+                           const double2* e0, double2* f0, int64_t n, hipStream_t st);
+
+// Plane wave at arbitrary points: E, H [n_pw][P][3] (H nullable).
+hipError_t launch_planewave_points(const Wave& w, double n_env, int64_t n_pw, const double* khat, const double2* e0,
+                                   const double* r, int64_t P, double2* E, double2* H, hipStream_t st);
+
+// q = A F in the unknown layout (cells: alpha F; effective: alpha6 (E, H)).
+hipError_t launch_apply_alpha(const DipoleView& d, const double2* F, int64_t ldf, double2* q, int64_t ldq,
+                              int64_t nrhs, hipStream_t st);
+
+// Five FP64 sums per RHS: Im(F0^* q), Im(F^* q), sum |q|^2 over cell E,
+// effective E and effective H unknowns.
+hipError_t launch_cs_sums(const DipoleView& d, const double2* f0, const double2* q, const double2* f, int64_t n,
+                          int64_t nrhs, double* sums5, hipStream_t st);
+
+// sum_{i != j} q_i^H G6_ij q_j per RHS (partial sums per workgroup, [nrhs][nblk]).
+hipError_t launch_sca_ff(const DipoleView& d, const Wave& w, const double2* q, int64_t ldq, int64_t nrhs,
+                         double* partial, int64_t nblk, hipStream_t st);
+int64_t sca_ff_blocks(int64_t N);
+
+// conversions and refinement helpers
+hipError_t launch_convert_d2f(const double2* a, int64_t lda, float2* b, int64_t ldb, int64_t m, int64_t n,
+                              hipStream_t st);
+hipError_t launch_convert_f2d(const float2* a, int64_t lda, double2* b, int64_t ldb, int64_t m, int64_t n,
+                              hipStream_t st);
+hipError_t launch_copy_d(const double2* a, int64_t lda, double2* b, int64_t ldb, int64_t m, int64_t n, hipStream_t st);
+// x += c (c in float), and per-column max |c| into cmax[col]
+hipError_t launch_axpy_f2d(const float2* c, int64_t ldc, double2* x, int64_t ldx, int64_t m, int64_t n,
+                           double* cmax, hipStream_t st);
+// per-column max |a| (modulus)
+hipError_t launch_colmax(const double2* a, int64_t lda, int64_t m, int64_t n, double* out, hipStream_t st);
+// row sums of |M| (infinity norm = max row sum), out[m] (zeroed by the kernel driver)
+hipError_t launch_rowsum_abs(const double2* M, int64_t ld, int64_t n, double* rows, hipStream_t st);
+
+int fields_num_splits(int64_t P, int64_t N, int num_cu);
+hipError_t launch_fields(const DipoleView& d, const Wave& w, const double2* q, int64_t ldq, int64_t nrhs,
+                         const double* rp, int64_t P, double2* E, double2* H, double2* scratch, int nsplit,
+                         double min_r2, int* flag, hipStream_t st);
+
+}  // namespace gdm

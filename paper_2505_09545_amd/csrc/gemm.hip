@@ -1,0 +1,187 @@
+// Complex GEMM on the CDNA matrix cores, used for the trailing update of the
+// blocked right-looking LU (arXiv:2505.09545, Sec. "Numerical solution": the
+// coupled system is solved by LU decomposition), for the blocked triangular
+// solves and for the FP64 residual of iterative refinement.
+//
+// Storage: column-major, interleaved complex.  Viewed as real matrices, an
+// m x k complex A is a 2m x k real matrix whose rows alternate (re, im).  The
+// product C = A B is then the real product  C^ = A~ B^  with
+//   A~ (2m x 2k):  each complex a becomes the 2x2 block [[a_r, -a_i], [a_i, a_r]]
+//   B^ (2k x n) :  the real view of B (rows alternate re, im)
+// so one real 16x16x4 MFMA covers 8 complex rows x 16 complex columns x 2
+// complex k, and the accumulators already hold interleaved complex C.  The
+// expansion of A costs one LDS load per lane (the lane picks re or im and the
+// sign from its (row, k) parity); no extra storage and no 3M/4M bookkeeping.
+//
+// Tile: 64 complex rows x 64 columns per 256-thread workgroup (2 x 2 waves, each
+// 64 real rows x 32 columns = 4 x 2 MFMA blocks), 8 complex k per stage,
+// double-buffered LDS.  Workgroups are remapped so that each of the 8 XCDs works
+// on a contiguous range of tiles (their operands then share that XCD's L2).
+#include "gdm_common.hpp"
+#include "gdm_kernels.hpp"
+
+namespace gdm {
+
+template <typename T> struct acc_of;
+template <> struct acc_of<double> { using type = v4d; };
+template <> struct acc_of<float> { using type = v4f; };
+
+__device__ inline v4d mfma16(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+__device__ inline v4f mfma16(float a, float b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+
+constexpr int GBM = 64;  // complex rows per tile
+constexpr int GBN = 64;  // columns per tile
+constexpr int GBK = 8;   // complex k per stage
+
+template <typename T, int MODE, int TRANSA>
+__global__ void __launch_bounds__(256) cgemm_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict__ A,
+                                                     int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb,
+                                                     cplx<T>* __restrict__ C, int64_t ldc, int tiles_m, int tiles) {
+  using CT = cplx<T>;
+  using ACC = typename acc_of<T>::type;
+  __shared__ T As[2][GBK * GBM * 2];   // [kc][mc] complex
+  __shared__ T Bs[2][2 * GBK * GBN];   // [kk][nc] real view
+  // XCD-aware remap: hardware places workgroup b on XCD b % 8.
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7, loc = bid >> 3;
+  const int per = tiles >> 3, rem = tiles & 7;
+  const int tile = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + loc;
+  const int tm = tile % tiles_m, tn = tile / tiles_m;
+  const int64_t m0 = (int64_t)tm * GBM, n0 = (int64_t)tn * GBN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wrow = (wave & 1) * 64;  // real-row offset of the wave inside the tile
+  const int wcol = (wave >> 1) * 32;
+
+  ACC acc[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = ACC{0, 0, 0, 0};
+
+  CT ra[2], rb[2];
+  auto gload = [&](int64_t kb) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int idx = tid + 256 * i;
+      int mc, kc;
+      if (TRANSA == 0) { mc = idx % GBM; kc = idx / GBM; } else { kc = idx % GBK; mc = idx / GBK; }
+      const int64_t gm = m0 + mc, gk = kb + kc;
+      CT v;
+      v.x = 0; v.y = 0;
+      if (gm < m && gk < k) v = TRANSA == 0 ? A[gm + gk * lda] : A[gk + gm * lda];
+      ra[i] = v;
+      const int kc2 = idx % GBK, nc = idx / GBK;
+      const int64_t gn = n0 + nc, gk2 = kb + kc2;
+      CT u;
+      u.x = 0; u.y = 0;
+      if (gn < n && gk2 < k) u = B[gk2 + gn * ldb];
+      rb[i] = u;
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int idx = tid + 256 * i;
+      int mc, kc;
+      if (TRANSA == 0) { mc = idx % GBM; kc = idx / GBM; } else { kc = idx % GBK; mc = idx / GBK; }
+      As[buf][(kc * GBM + mc) * 2 + 0] = ra[i].x;
+      As[buf][(kc * GBM + mc) * 2 + 1] = ra[i].y;
+      const int kc2 = idx % GBK, nc = idx / GBK;
+      Bs[buf][(2 * kc2 + 0) * GBN + nc] = rb[i].x;
+      Bs[buf][(2 * kc2 + 1) * GBN + nc] = rb[i].y;
+    }
+  };
+
+  const int64_t ktiles = (k + GBK - 1) / GBK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  const int lr = lane & 15;   // row (A) / column (B) inside a 16-block
+  const int lk = lane >> 4;   // k index inside a 4-step
+  // Output rows of the 16x16 accumulator held by a lane: f32 MFMA gives rows
+  // 4*lk + reg, f64 MFMA gives rows lk + 4*reg.  For f64 the A-fragment rows are
+  // loaded through the transpose pi(x) = 4*(x & 3) + (x >> 2) of the 4x4 index
+  // grid, so that in both cases the lane ends up with real rows 4*lk .. 4*lk+3,
+  // i.e. (re, im) of two consecutive complex rows.
+  const int arow = sizeof(T) == 8 ? (4 * (lr & 3) + (lr >> 2)) : lr;
+  for (int64_t kt = 0; kt < ktiles; ++kt) {
+    const int buf = (int)(kt & 1);
+    if (kt + 1 < ktiles) gload((kt + 1) * GBK);
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int kk = 4 * s + lk;       // real k inside the stage
+      const int kc = kk >> 1, sb = kk & 1;
+      T a[4], b[2];
+#pragma unroll
+      for (int bm = 0; bm < 4; ++bm) {
+        const int r = wrow + bm * 16 + arow;  // real row inside the tile
+        const int t = r & 1;
+        T v = As[buf][(kc * GBM + (r >> 1)) * 2 + (sb ^ t)];
+        a[bm] = (sb == 1 && t == 0) ? -v : v;
+      }
+#pragma unroll
+      for (int bn = 0; bn < 2; ++bn) b[bn] = Bs[buf][kk * GBN + wcol + bn * 16 + lr];
+#pragma unroll
+      for (int bm = 0; bm < 4; ++bm)
+#pragma unroll
+        for (int bn = 0; bn < 2; ++bn) acc[bm][bn] = mfma16(a[bm], b[bn], acc[bm][bn]);
+    }
+    if (kt + 1 < ktiles) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  // epilogue: lane holds real rows 4*lk + {0..3} = two complex rows of column lane%16
+#pragma unroll
+  for (int bm = 0; bm < 4; ++bm)
+#pragma unroll
+    for (int bn = 0; bn < 2; ++bn) {
+      const int64_t col = n0 + wcol + bn * 16 + lr;
+      const int64_t crow = m0 + ((wrow + bm * 16) >> 1) + 2 * lk;
+      if (col >= n) continue;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int64_t row = crow + h;
+        if (row >= m) continue;
+        CT* p = C + row + col * ldc;
+        const T vr = acc[bm][bn][2 * h], vi = acc[bm][bn][2 * h + 1];
+        if (MODE == 0) {
+          CT c = *p;
+          c.x -= vr;
+          c.y -= vi;
+          *p = c;
+        } else {
+          CT c;
+          c.x = vr;
+          c.y = vi;
+          *p = c;
+        }
+      }
+    }
+}
+
+template <typename T>
+hipError_t launch_gemm(int mode, int transA, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
+                       const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const int64_t tm = (m + GBM - 1) / GBM, tn = (n + GBN - 1) / GBN;
+  if (tm * tn > INT32_MAX) return hipErrorInvalidValue;
+  const int tiles = (int)(tm * tn);
+  const auto* a = static_cast<const cplx<T>*>(A);
+  const auto* b = static_cast<const cplx<T>*>(B);
+  auto* c = static_cast<cplx<T>*>(C);
+  if (k <= 0) {
+    if (mode == 0) return hipSuccess;  // C - 0
+  }
+  const dim3 grid(tiles), blk(256);
+  if (mode == 0 && transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
+  else if (mode == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 1>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
+  else if (transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 1, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
+  else hipLaunchKernelGGL((cgemm_kernel<T, 1, 1>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
+  return hipGetLastError();
+}
+
+template hipError_t launch_gemm<double>(int, int, int64_t, int64_t, int64_t, const void*, int64_t, const void*,
+                                        int64_t, void*, int64_t, hipStream_t);
+template hipError_t launch_gemm<float>(int, int, int64_t, int64_t, int64_t, const void*, int64_t, const void*,
+                                       int64_t, void*, int64_t, hipStream_t);
+
+}  // namespace gdm

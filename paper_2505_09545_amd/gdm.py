@@ -1,0 +1,272 @@
+"""Thin ctypes binding of libgdm (include/gdm.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP kernels
+of libgdm.so.  Torch tensors are used as device buffers; the library works on
+the stream that is current when the context is created.  There is no CPU
+fallback: importing this module without the built library raises.
+
+Layouts follow the C header: complex arrays are torch.complex128 tensors
+(interleaved re/im doubles); vectors in the unknown layout are [n_rhs, n];
+dense matrices are column-major, i.e. returned as the transpose of a
+row-major tensor.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgdm.so")
+
+GDM_OK, GDM_E_ARG, GDM_E_OOM, GDM_E_DEVICE, GDM_E_SINGULAR, GDM_E_NOCONV, GDM_E_PROBE_AT_DIPOLE, GDM_E_STATE = range(8)
+STATUS_NAMES = ["OK", "E_ARG", "E_OOM", "E_DEVICE", "E_SINGULAR", "E_NOCONV", "E_PROBE_AT_DIPOLE", "E_STATE"]
+PREC_FP64, PREC_FP32_IR = 0, 1
+SELF_STATIC, SELF_RADIATIVE = 0, 1
+
+EXPORTED = ["gdm_create", "gdm_destroy", "gdm_last_error", "gdm_set_environment", "gdm_set_structure",
+            "gdm_num_unknowns", "gdm_assemble", "gdm_factorize", "gdm_incident_planewave", "gdm_solve",
+            "gdm_planewave", "gdm_fields", "gdm_cross_sections", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync"]
+
+
+class GDMInfo(ctypes.Structure):
+    _fields_ = [("ir_iters", ctypes.c_int32), ("backward_err", ctypes.c_double), ("bad_index", ctypes.c_int64),
+                ("ms_assemble", ctypes.c_float), ("ms_factor", ctypes.c_float), ("ms_solve", ctypes.c_float),
+                ("ms_ir", ctypes.c_float)]
+
+
+class GDMError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES[status] if 0 <= status < len(STATUS_NAMES) else status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libgdm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libgdm.so not found at {path}; build it with python -m paper_2505_09545_amd.build")
+    lib = ctypes.CDLL(path)
+    P, I64, I32, D = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+    sig = {
+        "gdm_create": ([ctypes.c_int, P, ctypes.POINTER(P)], ctypes.c_int),
+        "gdm_destroy": ([P], None),
+        "gdm_last_error": ([P], ctypes.c_char_p),
+        "gdm_set_environment": ([P, D], ctypes.c_int),
+        "gdm_set_structure": ([P, I64, P, D, P, I64, P, P, ctypes.c_int], ctypes.c_int),
+        "gdm_num_unknowns": ([P], I64),
+        "gdm_assemble": ([P, D, ctypes.c_int, P, I64], ctypes.c_int),
+        "gdm_factorize": ([P, D, ctypes.c_int, ctypes.POINTER(GDMInfo)], ctypes.c_int),
+        "gdm_incident_planewave": ([P, I64, P, P, P], ctypes.c_int),
+        "gdm_solve": ([P, I64, P, D, I32, P, P, ctypes.POINTER(GDMInfo)], ctypes.c_int),
+        "gdm_planewave": ([P, I64, P, P, I64, P, P, P], ctypes.c_int),
+        "gdm_fields": ([P, I64, P, I64, P, P, P], ctypes.c_int),
+        "gdm_cross_sections": ([P, I64, P, P, P, P, I32, P], ctypes.c_int),
+        "gdm_getrf": ([P, ctypes.c_int, I64, P, I64, P, ctypes.POINTER(GDMInfo)], ctypes.c_int),
+        "gdm_getrs": ([P, ctypes.c_int, ctypes.c_int, I64, I64, P, I64, P, I64], ctypes.c_int),
+        "gdm_gemm": ([P, ctypes.c_int, ctypes.c_int, ctypes.c_int, I64, I64, I64, P, I64, P, I64, P, I64],
+                     ctypes.c_int),
+        "gdm_sync": ([P], ctypes.c_int),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclass
+class Structure:
+    r_cell: torch.Tensor  # [nc, 3] float64
+    step: float
+    eps_cell: torch.Tensor  # [nc] complex128
+    r_eff: torch.Tensor = None  # [ne, 3] float64
+    alpha_eff: torch.Tensor = None  # [ne, 6, 6] complex128
+
+
+class Context:
+    """One libgdm context on a CUDA (HIP) device, bound to the current stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self.lib = load_library()
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        self._check(self.lib.gdm_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)), None)
+        self.h = h
+        self.info = GDMInfo()
+        self._keep = []
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.gdm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, h="self"):
+        if st != GDM_OK:
+            msg = self.lib.gdm_last_error(self.h if h == "self" else None).decode()
+            raise GDMError(st, msg)
+
+    def _dev(self, t, dtype, shape=None, name="array"):
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor):
+            t = torch.as_tensor(t)
+        t = t.to(device=self.device, dtype=dtype).contiguous()
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
+        return t
+
+    # -- structure / environment ------------------------------------------------
+    def set_environment(self, n_env: float):
+        self._check(self.lib.gdm_set_environment(self.h, float(n_env)))
+
+    def set_structure(self, r_cell, step, eps_cell, r_eff=None, alpha_eff=None, selfterm=SELF_STATIC):
+        nc = 0 if r_cell is None else len(r_cell)
+        ne = 0 if r_eff is None else len(r_eff)
+        rc = self._dev(r_cell, torch.float64, (nc, 3), "r_cell") if nc else None
+        ec = self._dev(eps_cell, torch.complex128, (nc,), "eps_cell") if nc else None
+        re = self._dev(r_eff, torch.float64, (ne, 3), "r_eff") if ne else None
+        ae = self._dev(alpha_eff, torch.complex128, (ne, 6, 6), "alpha_eff") if ne else None
+        self._keep = [rc, ec, re, ae]
+        self._check(self.lib.gdm_set_structure(self.h, nc, _ptr(rc), float(step), _ptr(ec), ne, _ptr(re), _ptr(ae),
+                                               int(selfterm)))
+        self.n_cell, self.n_eff = nc, ne
+
+    @property
+    def n(self) -> int:
+        return int(self.lib.gdm_num_unknowns(self.h))
+
+    # -- steps ------------------------------------------------------------------------
+    def assemble(self, wavelength, dtype=torch.complex128):
+        n = self.n
+        out = torch.empty((n, n), dtype=dtype, device=self.device)
+        self._check(self.lib.gdm_assemble(self.h, float(wavelength), 0 if dtype == torch.complex128 else 1,
+                                          _ptr(out), n))
+        return out.t()  # column-major storage -> M[i, j]
+
+    def factorize(self, wavelength, prec=PREC_FP64):
+        self._check(self.lib.gdm_factorize(self.h, float(wavelength), int(prec), ctypes.byref(self.info)))
+        return self.info
+
+    def incident_planewave(self, khat, e0):
+        k = self._dev(khat, torch.float64, None, "khat").reshape(-1, 3)
+        e = self._dev(e0, torch.complex128, None, "e0").reshape(-1, 3)
+        if len(k) != len(e):
+            raise ValueError("khat and e0 must have the same number of plane waves")
+        f0 = torch.empty((len(k), self.n), dtype=torch.complex128, device=self.device)
+        self._check(self.lib.gdm_incident_planewave(self.h, len(k), _ptr(k), _ptr(e), _ptr(f0)))
+        return f0
+
+    def solve(self, f0, tol=0.0, max_iter=-1, want_field=True):
+        f0 = self._dev(f0, torch.complex128, None, "f0")
+        if f0.dim() != 2 or f0.shape[1] != self.n:
+            raise ValueError(f"f0 must be [n_rhs, {self.n}]")
+        q = torch.empty_like(f0)
+        f = torch.empty_like(f0) if want_field else None
+        st = self.lib.gdm_solve(self.h, f0.shape[0], _ptr(f0), float(tol), int(max_iter), _ptr(q), _ptr(f),
+                                ctypes.byref(self.info))
+        self._check(st)
+        return q, f
+
+    def planewave(self, khat, e0, r, want_h=True):
+        k = self._dev(khat, torch.float64, None, "khat").reshape(-1, 3)
+        e = self._dev(e0, torch.complex128, None, "e0").reshape(-1, 3)
+        r = self._dev(r, torch.float64, None, "r").reshape(-1, 3)
+        E = torch.empty((len(k), len(r), 3), dtype=torch.complex128, device=self.device)
+        H = torch.empty_like(E) if want_h else None
+        self._check(self.lib.gdm_planewave(self.h, len(k), _ptr(k), _ptr(e), len(r), _ptr(r), _ptr(E), _ptr(H)))
+        return E, H
+
+    def fields(self, q, r_probe, want_h=True):
+        q = self._dev(q, torch.complex128, None, "q")
+        r = self._dev(r_probe, torch.float64, None, "r_probe").reshape(-1, 3)
+        E = torch.empty((q.shape[0], len(r), 3), dtype=torch.complex128, device=self.device)
+        H = torch.empty_like(E) if want_h else None
+        self._check(self.lib.gdm_fields(self.h, q.shape[0], _ptr(q), len(r), _ptr(r), _ptr(E), _ptr(H)))
+        return E, H
+
+    def cross_sections(self, f0, q, f, e0_norm2, want_ff=False):
+        f0 = self._dev(f0, torch.complex128, None, "f0")
+        q = self._dev(q, torch.complex128, None, "q")
+        f = self._dev(f, torch.complex128, None, "f")
+        e2 = self._dev(e0_norm2, torch.float64, (f0.shape[0],), "e0_norm2")
+        out = torch.empty((f0.shape[0], 5), dtype=torch.float64, device=self.device)
+        self._check(self.lib.gdm_cross_sections(self.h, f0.shape[0], _ptr(f0), _ptr(q), _ptr(f), _ptr(e2),
+                                                int(bool(want_ff)), _ptr(out)))
+        return out
+
+    # -- dense linear algebra entry points ---------------------------------------------
+    def getrf(self, A_colmajor_storage: torch.Tensor):
+        """LU of the matrix whose column-major storage is the row-major tensor
+        A_colmajor_storage (i.e. the matrix is A_colmajor_storage.T); in place."""
+        t = A_colmajor_storage
+        n = t.shape[0]
+        dtype = 0 if t.dtype == torch.complex128 else 1
+        ipiv = torch.empty(n, dtype=torch.int32, device=self.device)
+        self._check(self.lib.gdm_getrf(self.h, dtype, n, _ptr(t), t.shape[1], _ptr(ipiv), ctypes.byref(self.info)))
+        return ipiv
+
+    def getrs(self, A_storage: torch.Tensor, B_storage: torch.Tensor, trans: int = 0):
+        """B_storage: [nrhs, n] row-major = column-major n x nrhs; solved in place."""
+        dtype = 0 if A_storage.dtype == torch.complex128 else 1
+        n = A_storage.shape[0]
+        self._check(self.lib.gdm_getrs(self.h, dtype, int(trans), n, B_storage.shape[0], _ptr(A_storage),
+                                       A_storage.shape[1], _ptr(B_storage), B_storage.shape[1]))
+
+    def gemm(self, mode, transA, m, n, k, A, lda, B, ldb, C, ldc):
+        dtype = 0 if C.dtype == torch.complex128 else 1
+        self._check(self.lib.gdm_gemm(self.h, dtype, int(mode), int(transA), m, n, k, _ptr(A), lda, _ptr(B), ldb,
+                                      _ptr(C), ldc))
+
+    def sync(self):
+        self._check(self.lib.gdm_sync(self.h))
+
+
+def plane_wave_inputs(workload: dict, device):
+    khat = torch.as_tensor(workload["khat"], dtype=torch.float64, device=device)
+    e0 = torch.as_tensor(workload["e0"], dtype=torch.complex128, device=device)
+    e2 = (e0.abs() ** 2).sum(dim=1)
+    return khat, e0, e2
+
+
+def run_forward(ctx: Context, workload: dict, prec=PREC_FP64, tol=0.0, probes=True, want_ff=False):
+    """Set up a workload dict (see gdm_inputs) and run the whole forward hot path:
+    assembly + LU, incident field, solve, cross sections, probe fields."""
+    dev = ctx.device
+    r_eff = workload.get("r_eff")
+    ne = 0 if r_eff is None else len(r_eff)
+    ctx.set_environment(workload["n_env"])
+    ctx.set_structure(torch.as_tensor(workload["r_cell"]), workload["step"], torch.as_tensor(workload["eps_cell"]),
+                      torch.as_tensor(r_eff) if ne else None,
+                      torch.as_tensor(workload["alpha_eff"]) if ne else None)
+    ctx.factorize(workload["wavelength"], prec)
+    khat, e0, e2 = plane_wave_inputs(workload, dev)
+    f0 = ctx.incident_planewave(khat, e0)
+    q, f = ctx.solve(f0, tol=tol)
+    out = dict(f0=f0, q=q, f=f, cs=ctx.cross_sections(f0, q, f, e2, want_ff=want_ff), info=ctx.info)
+    rp = workload.get("r_probe")
+    if probes and rp is not None and len(rp):
+        E, H = ctx.fields(q, torch.as_tensor(rp))
+        out["E_sca"], out["H_sca"] = E, H
+    return out
