@@ -159,6 +159,17 @@ gdm_status gdm_gemm(gdm_ctx* ctx, int dtype, int mode, int transA, int64_t m, in
 /* Synchronise the context stream. */
 gdm_status gdm_sync(gdm_ctx* ctx);
 
+/* Per-kernel timing with HIP events recorded on the context stream around each
+ * launch (for benchmarks; adds a few microseconds per launch).  enable != 0
+ * clears the counters and starts recording; 0 stops. */
+gdm_status gdm_profile(gdm_ctx* ctx, int enable);
+/* Counters accumulated since gdm_profile(ctx, 1), written to the HOST array
+ * out (n_out >= 15): out[3 t + 0..2] = (milliseconds, work, launches) for
+ * t = 0 LU trailing-update GEMM (work = real flops 8 m n k), 1 LU panel (work =
+ * columns), 2 assembly (work = bytes written), 3 block triangular solve of the
+ * factorisation (work = real flops), 4 row permutation of the trailing columns. */
+gdm_status gdm_profile_read(gdm_ctx* ctx, double* out, int32_t n_out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -81,6 +81,7 @@ struct gdm_ctx {
   DevBuf X, Rr, C32, small, scratch, flag;
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   float ms_assemble = 0, ms_factor = 0;
+  Prof prof;
 };
 
 #define FAIL(ctx, code, ...)                                     \
@@ -153,10 +154,11 @@ static gdm_status run_lu(gdm_ctx* c, void* A, int64_t n, int64_t ld, LUPlan& pla
     HIPCHK(c, ipiv.ensure(sizeof(int32_t) * n));
     piv = ipiv.as<int32_t>();
   }
-  HIPCHK(c, lu_factor<T>(A, ld, plan, w, piv, c->stream));
+  HIPCHK(c, lu_factor<T>(A, ld, plan, w, piv, c->stream, &c->prof));
   int32_t err[2] = {0, 0};
   HIPCHK(c, hipMemcpyAsync(err, w.err, sizeof(err), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->prof.collect();
   if (info) info->bad_index = -1;
   if (err[0] != 0) FAIL(c, GDM_E_DEVICE, "LU panel barrier timed out (workgroups not co-resident?)");
   if (err[1] != INT32_MAX) {
@@ -296,14 +298,21 @@ gdm_status gdm_factorize(gdm_ctx* c, double wl, gdm_precision prec, gdm_info* in
   const Wave w = wave_of(c, wl);
   const DipoleView d = view_of(c, self_term(c, w));
   HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+  const double nn = (double)n * (double)n;
   if (prec == GDM_PREC_FP64) {
     HIPCHK(c, c->M.ensure(sizeof(double2) * n * n));
+    HIPCHK(c, c->prof.begin(c->stream, PROF_ASSEMBLE, 16.0 * nn));
     HIPCHK(c, launch_assemble<double>(d, w, c->M.p, n, c->stream));
+    HIPCHK(c, c->prof.end(c->stream));
   } else {
     HIPCHK(c, c->M64.ensure(sizeof(double2) * n * n));
     HIPCHK(c, c->M.ensure(sizeof(float2) * n * n));
+    HIPCHK(c, c->prof.begin(c->stream, PROF_ASSEMBLE, 16.0 * nn));
     HIPCHK(c, launch_assemble<double>(d, w, c->M64.p, n, c->stream));
+    HIPCHK(c, c->prof.end(c->stream));
+    HIPCHK(c, c->prof.begin(c->stream, PROF_ASSEMBLE, 8.0 * nn));
     HIPCHK(c, launch_assemble<float>(d, w, c->M.p, n, c->stream));
+    HIPCHK(c, c->prof.end(c->stream));
     HIPCHK(c, c->rows.ensure(sizeof(double) * n));
     HIPCHK(c, launch_rowsum_abs(c->M64.as<double2>(), n, n, c->rows.as<double>(), c->stream));
   }
@@ -562,6 +571,28 @@ gdm_status gdm_gemm(gdm_ctx* c, int dtype, int mode, int transA, int64_t m, int6
   HIPCHK(c, hipSetDevice(c->device));
   if (dtype == 0) HIPCHK(c, launch_gemm<double>(mode, transA, m, n, k, A, lda, B, ldb, C, ldc, c->stream));
   else HIPCHK(c, launch_gemm<float>(mode, transA, m, n, k, A, lda, B, ldb, C, ldc, c->stream));
+  return GDM_OK;
+}
+
+gdm_status gdm_profile(gdm_ctx* c, int enable) {
+  if (!c) return GDM_E_ARG;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->prof.collect();
+  c->prof.reset();
+  c->prof.on = enable != 0;
+  return GDM_OK;
+}
+
+gdm_status gdm_profile_read(gdm_ctx* c, double* out, int32_t n_out) {
+  if (!c) return GDM_E_ARG;
+  if (!out || n_out < 3 * PROF_NTAGS) FAIL(c, GDM_E_ARG, "need a host array of at least %d doubles", 3 * PROF_NTAGS);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->prof.collect();
+  for (int t = 0; t < PROF_NTAGS; ++t) {
+    out[3 * t + 0] = c->prof.ms[t];
+    out[3 * t + 1] = c->prof.wsum[t];
+    out[3 * t + 2] = c->prof.cnt[t];
+  }
   return GDM_OK;
 }
 

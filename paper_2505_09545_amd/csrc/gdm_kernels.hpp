@@ -23,6 +23,30 @@ hipError_t launch_assemble(const DipoleView& d, const struct Wave& w, void* M, i
 template <typename T>
 hipError_t launch_gemm(int mode, int transA, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
                        const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st);
+// The LU trailing update A22 -= L21 U12: same kernel body, separate symbol so
+// that profilers report it on its own.
+template <typename T>
+hipError_t launch_gemm_update(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
+                              int64_t ldb, void* C, int64_t ldc, hipStream_t st);
+
+// Optional per-launch timing with HIP events on the launch stream.
+enum ProfTag { PROF_UPDATE = 0, PROF_PANEL = 1, PROF_ASSEMBLE = 2, PROF_TRSM = 3, PROF_PERM = 4, PROF_NTAGS = 5 };
+struct Prof {
+  bool on = false;
+  std::vector<hipEvent_t> ev;
+  std::vector<int> tag;
+  std::vector<double> work;
+  size_t used = 0;
+  double ms[PROF_NTAGS] = {0, 0, 0, 0, 0};
+  double wsum[PROF_NTAGS] = {0, 0, 0, 0, 0};
+  double cnt[PROF_NTAGS] = {0, 0, 0, 0, 0};
+  hipError_t begin(hipStream_t st, int t, double w);
+  hipError_t end(hipStream_t st);
+  // after the stream is synchronised: fold the recorded pairs into ms/wsum/cnt
+  void collect();
+  void reset();
+  ~Prof();
+};
 
 // ---------------------------------------------------------------------------
 // blocked LU with partial pivoting
@@ -43,13 +67,14 @@ struct LUPlan {
 
 // Device workspace of the factorisation; sized by lu_workspace_bytes().
 struct LUWork {
-  uint32_t* cnt;   // [nb] barrier arrival counters
-  uint64_t* key;   // [nb] pivot keys
-  void* slot;      // [2][Gmax][nb] complex candidate rows
-  void* dslot;     // [2][nb] complex diagonal rows
-  int32_t* err;    // [2]: barrier timeout flag, first zero pivot (INT32_MAX if none)
-  int32_t* pairs;  // [nblocks][2][2 nb]: destination rows then source rows
-  int32_t* npairs; // [nblocks]
+  unsigned long long* cand;  // [2][gmax][2] epoch-tagged pivot keys (value, row)
+  unsigned long long* rows;  // [2][gmax][wwmax] epoch-tagged candidate rows
+  unsigned long long* drow;  // [2][wwmax] epoch-tagged copy of the diagonal row
+  int gmax;                  // max panel workgroups
+  int wwmax;                 // payload words per row (nb * words per complex)
+  int32_t* err;              // [2]: exchange timeout flag, first zero pivot (INT32_MAX if none)
+  int32_t* pairs;            // [nblocks][2][2 nb]: destination rows then source rows
+  int32_t* npairs;           // [nblocks]
 };
 
 LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes);
@@ -57,7 +82,8 @@ size_t lu_workspace_bytes(const LUPlan& p, int elem_bytes, int num_cu);
 void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu, LUWork& w);
 
 template <typename T>
-hipError_t lu_factor(void* A, int64_t ld, const LUPlan& plan, const LUWork& ws, int32_t* ipiv, hipStream_t st);
+hipError_t lu_factor(void* A, int64_t ld, const LUPlan& plan, const LUWork& ws, int32_t* ipiv, hipStream_t st,
+                     Prof* prof = nullptr);
 
 // Solve op(M) X = B in place for B (n x nrhs, ld ldb) with the factors of lu_factor.
 template <typename T>

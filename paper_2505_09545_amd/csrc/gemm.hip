@@ -33,7 +33,7 @@ constexpr int GBM = 64;  // complex rows per tile
 constexpr int GBN = 64;  // columns per tile
 constexpr int GBK = 8;   // complex k per stage
 
-template <typename T, int MODE, int TRANSA>
+template <typename T, int MODE, int TRANSA, int ROLE>
 __global__ void __launch_bounds__(256) cgemm_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict__ A,
                                                      int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb,
                                                      cplx<T>* __restrict__ C, int64_t ldc, int tiles_m, int tiles) {
@@ -172,11 +172,70 @@ hipError_t launch_gemm(int mode, int transA, int64_t m, int64_t n, int64_t k, co
     if (mode == 0) return hipSuccess;  // C - 0
   }
   const dim3 grid(tiles), blk(256);
-  if (mode == 0 && transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
-  else if (mode == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 1>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
-  else if (transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 1, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
-  else hipLaunchKernelGGL((cgemm_kernel<T, 1, 1>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
+  if (mode == 0 && transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 0, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
+  else if (mode == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 1, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
+  else if (transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 1, 0, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
+  else hipLaunchKernelGGL((cgemm_kernel<T, 1, 1, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gemm_update(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
+                              int64_t ldb, void* C, int64_t ldc, hipStream_t st) {
+  if (m <= 0 || n <= 0 || k <= 0) return hipSuccess;
+  const int64_t tm = (m + GBM - 1) / GBM, tn = (n + GBN - 1) / GBN;
+  if (tm * tn > INT32_MAX) return hipErrorInvalidValue;
+  const int tiles = (int)(tm * tn);
+  hipLaunchKernelGGL((cgemm_kernel<T, 0, 0, 1>), dim3(tiles), dim3(256), 0, st, m, n, k,
+                     static_cast<const cplx<T>*>(A), lda, static_cast<const cplx<T>*>(B), ldb,
+                     static_cast<cplx<T>*>(C), ldc, (int)tm, tiles);
+  return hipGetLastError();
+}
+template hipError_t launch_gemm_update<double>(int64_t, int64_t, int64_t, const void*, int64_t, const void*, int64_t,
+                                               void*, int64_t, hipStream_t);
+template hipError_t launch_gemm_update<float>(int64_t, int64_t, int64_t, const void*, int64_t, const void*, int64_t,
+                                              void*, int64_t, hipStream_t);
+
+// ---- per-launch event timing -------------------------------------------------
+hipError_t Prof::begin(hipStream_t st, int t, double w) {
+  if (!on) return hipSuccess;
+  if (2 * used + 2 > ev.size()) {
+    for (int i = 0; i < 2; ++i) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      ev.push_back(e);
+    }
+    tag.push_back(0);
+    work.push_back(0);
+  }
+  tag[used] = t;
+  work[used] = w;
+  return hipEventRecord(ev[2 * used], st);
+}
+hipError_t Prof::end(hipStream_t st) {
+  if (!on) return hipSuccess;
+  hipError_t r = hipEventRecord(ev[2 * used + 1], st);
+  ++used;
+  return r;
+}
+void Prof::collect() {
+  for (size_t i = 0; i < used; ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) == hipSuccess) {
+      ms[tag[i]] += t;
+      wsum[tag[i]] += work[i];
+      cnt[tag[i]] += 1;
+    }
+  }
+  used = 0;
+}
+void Prof::reset() {
+  used = 0;
+  for (int i = 0; i < PROF_NTAGS; ++i) ms[i] = wsum[i] = cnt[i] = 0;
+}
+Prof::~Prof() {
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
 }
 
 template hipError_t launch_gemm<double>(int, int, int64_t, int64_t, int64_t, const void*, int64_t, const void*,

@@ -28,7 +28,8 @@ SELF_STATIC, SELF_RADIATIVE = 0, 1
 
 EXPORTED = ["gdm_create", "gdm_destroy", "gdm_last_error", "gdm_set_environment", "gdm_set_structure",
             "gdm_num_unknowns", "gdm_assemble", "gdm_factorize", "gdm_incident_planewave", "gdm_solve",
-            "gdm_planewave", "gdm_fields", "gdm_cross_sections", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync"]
+            "gdm_planewave", "gdm_fields", "gdm_cross_sections", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
+            "gdm_profile", "gdm_profile_read"]
 
 
 class GDMInfo(ctypes.Structure):
@@ -74,6 +75,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gdm_gemm": ([P, ctypes.c_int, ctypes.c_int, ctypes.c_int, I64, I64, I64, P, I64, P, I64, P, I64],
                      ctypes.c_int),
         "gdm_sync": ([P], ctypes.c_int),
+        "gdm_profile": ([P, ctypes.c_int], ctypes.c_int),
+        "gdm_profile_read": ([P, ctypes.POINTER(ctypes.c_double), I32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -241,6 +244,17 @@ class Context:
 
     def sync(self):
         self._check(self.lib.gdm_sync(self.h))
+
+    PROF_TAGS = ("update", "panel", "assemble", "trsm", "perm")
+
+    def profile(self, enable: bool):
+        self._check(self.lib.gdm_profile(self.h, int(bool(enable))))
+
+    def profile_read(self) -> dict:
+        buf = (ctypes.c_double * 15)()
+        self._check(self.lib.gdm_profile_read(self.h, buf, 15))
+        return {t: dict(ms=buf[3 * i], work=buf[3 * i + 1], launches=int(buf[3 * i + 2]))
+                for i, t in enumerate(self.PROF_TAGS)}
 
 
 def plane_wave_inputs(workload: dict, device):
