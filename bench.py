@@ -161,6 +161,11 @@ def main() -> int:
             "trsm_ms_per_step": prof["trsm"]["ms"] / args.steps,
             "perm_ms_per_step": prof["perm"]["ms"] / args.steps,
             "update_ms_per_step": up["ms"] / args.steps,
+            "solve_ms_per_step": prof["solve"]["ms"] / args.steps,
+            "solve_calls_per_step": prof["solve"]["launches"] / args.steps,
+            "resid_ms_per_step": prof["resid"]["ms"] / args.steps,
+            "resid_fp64_tflops": prof["resid"]["work"] / (prof["resid"]["ms"] * 1e-3) / 1e12
+            if prof["resid"]["ms"] > 0 else None,
         },
     }
     if not args.no_cpu_baseline:

@@ -164,10 +164,12 @@ gdm_status gdm_sync(gdm_ctx* ctx);
  * clears the counters and starts recording; 0 stops. */
 gdm_status gdm_profile(gdm_ctx* ctx, int enable);
 /* Counters accumulated since gdm_profile(ctx, 1), written to the HOST array
- * out (n_out >= 15): out[3 t + 0..2] = (milliseconds, work, launches) for
+ * out (n_out >= 21): out[3 t + 0..2] = (milliseconds, work, launches) for
  * t = 0 LU trailing-update GEMM (work = real flops 8 m n k), 1 LU panel (work =
  * columns), 2 assembly (work = bytes written), 3 block triangular solve of the
- * factorisation (work = real flops), 4 row permutation of the trailing columns. */
+ * factorisation (work = real flops), 4 row permutation of the trailing columns,
+ * 5 forward + backward substitution of gdm_solve (work = 8 n^2 n_rhs),
+ * 6 FP64 refinement residual (work = 8 n^2 n_rhs). */
 gdm_status gdm_profile_read(gdm_ctx* ctx, double* out, int32_t n_out);
 
 #ifdef __cplusplus

@@ -55,6 +55,7 @@ __global__ void fill_i32_kernel(int* a, int n, int v) {
 struct gdm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;  // look-ahead stream of the factorisation (default priority)
   bool own_stream = false;
   int num_cu = 256;
   int lds_bytes = 160 * 1024;
@@ -82,6 +83,8 @@ struct gdm_ctx {
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   float ms_assemble = 0, ms_factor = 0;
   Prof prof;
+  bool lookahead = true;
+  std::vector<hipEvent_t> lu_events;
 };
 
 #define FAIL(ctx, code, ...)                                     \
@@ -149,12 +152,13 @@ static gdm_status run_lu(gdm_ctx* c, void* A, int64_t n, int64_t ld, LUPlan& pla
   HIPCHK(c, ws.ensure(wsb));
   LUWork w;
   lu_workspace_carve(ws.p, plan, (int)sizeof(T), c->num_cu, w);
+  w.events = &c->lu_events;
   int32_t* piv = ipiv_out;
   if (!piv) {
     HIPCHK(c, ipiv.ensure(sizeof(int32_t) * n));
     piv = ipiv.as<int32_t>();
   }
-  HIPCHK(c, lu_factor<T>(A, ld, plan, w, piv, c->stream, &c->prof));
+  HIPCHK(c, lu_factor<T>(A, ld, plan, w, piv, c->stream, &c->prof, c->lookahead ? c->side : nullptr));
   int32_t err[2] = {0, 0};
   HIPCHK(c, hipMemcpyAsync(err, w.err, sizeof(err), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -197,6 +201,7 @@ gdm_status gdm_create(int device, void* hip_stream, gdm_ctx** out) {
     c->own_stream = true;
   }
   for (auto& e : c->ev) (void)hipEventCreate(&e);
+  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) c->side = nullptr;
   *out = c;
   return GDM_OK;
 }
@@ -210,6 +215,11 @@ void gdm_destroy(gdm_ctx* c) {
     b->release();
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->lu_events) (void)hipEventDestroy(e);
+  if (c->side) {
+    (void)hipStreamSynchronize(c->side);
+    (void)hipStreamDestroy(c->side);
+  }
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -387,9 +397,12 @@ gdm_status gdm_solve(gdm_ctx* c, int64_t nrhs, const double* f0, double tol, int
   double be_max = 0.0;
   gdm_status status = GDM_OK;
   float ms_ir = 0.f;
+  const double solve_flops = 8.0 * (double)n * (double)n * (double)nrhs;
   if (c->prec == GDM_PREC_FP64) {
     HIPCHK(c, launch_copy_d(F0, n, X, n, n, nrhs, c->stream));
+    HIPCHK(c, c->prof.begin(c->stream, PROF_SOLVE, solve_flops));
     HIPCHK(c, lu_solve<double>(0, c->M.p, c->ld, c->plan, w, X, n, nrhs, c->stream));
+    HIPCHK(c, c->prof.end(c->stream));
   } else {
     if (tol <= 0) tol = 1e-14;
     if (max_iter < 0) max_iter = 10;
@@ -401,7 +414,9 @@ gdm_status gdm_solve(gdm_ctx* c, int64_t nrhs, const double* f0, double tol, int
     double* sm = c->small.as<double>();  // [0..nrhs): |r|, [nrhs..2nrhs): |x|, [2nrhs..): |F0|, [3nrhs..): |c|
     // first solve from F0 in FP32
     HIPCHK(c, launch_convert_d2f(F0, n, C32, n, n, nrhs, c->stream));
+    HIPCHK(c, c->prof.begin(c->stream, PROF_SOLVE, solve_flops));
     HIPCHK(c, lu_solve<float>(0, c->M.p, c->ld, c->plan, w, C32, n, nrhs, c->stream));
+    HIPCHK(c, c->prof.end(c->stream));
     HIPCHK(c, launch_convert_f2d(C32, n, X, n, n, nrhs, c->stream));
     HIPCHK(c, launch_colmax(F0, n, n, nrhs, sm + 2 * nrhs, c->stream));
     HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
@@ -410,7 +425,9 @@ gdm_status gdm_solve(gdm_ctx* c, int64_t nrhs, const double* f0, double tol, int
     for (int it = 0;; ++it) {
       // r = F0 - M x  (FP64, stored FP64 matrix)
       HIPCHK(c, launch_copy_d(F0, n, Rr, n, n, nrhs, c->stream));
+      HIPCHK(c, c->prof.begin(c->stream, PROF_RESID, solve_flops));
       HIPCHK(c, launch_gemm<double>(0, 0, n, nrhs, n, c->M64.p, n, X, n, Rr, n, c->stream));
+      HIPCHK(c, c->prof.end(c->stream));
       HIPCHK(c, launch_colmax(Rr, n, n, nrhs, sm, c->stream));
       HIPCHK(c, launch_colmax(X, n, n, nrhs, sm + nrhs, c->stream));
       HIPCHK(c, hipMemcpyAsync(h.data(), sm, sizeof(double) * 4 * nrhs, hipMemcpyDeviceToHost, c->stream));
@@ -437,7 +454,9 @@ gdm_status gdm_solve(gdm_ctx* c, int64_t nrhs, const double* f0, double tol, int
         for (int64_t r = 0; r < nrhs; ++r) prev_c[r] = h[3 * nrhs + r];
       }
       HIPCHK(c, launch_convert_d2f(Rr, n, C32, n, n, nrhs, c->stream));
+      HIPCHK(c, c->prof.begin(c->stream, PROF_SOLVE, solve_flops));
       HIPCHK(c, lu_solve<float>(0, c->M.p, c->ld, c->plan, w, C32, n, nrhs, c->stream));
+      HIPCHK(c, c->prof.end(c->stream));
       HIPCHK(c, launch_axpy_f2d(C32, n, X, n, n, nrhs, sm + 3 * nrhs, c->stream));
       ++iters;
     }
@@ -450,6 +469,7 @@ gdm_status gdm_solve(gdm_ctx* c, int64_t nrhs, const double* f0, double tol, int
   float ms_total = 0.f;
   (void)hipEventElapsedTime(&ms_total, c->ev[0], c->ev[3]);
   if (c->prec == GDM_PREC_FP32_IR) (void)hipEventElapsedTime(&ms_ir, c->ev[1], c->ev[2]);
+  c->prof.collect();
   if (info) {
     info->ir_iters = iters;
     info->backward_err = be_max;
@@ -586,6 +606,7 @@ gdm_status gdm_profile(gdm_ctx* c, int enable) {
 gdm_status gdm_profile_read(gdm_ctx* c, double* out, int32_t n_out) {
   if (!c) return GDM_E_ARG;
   if (!out || n_out < 3 * PROF_NTAGS) FAIL(c, GDM_E_ARG, "need a host array of at least %d doubles", 3 * PROF_NTAGS);
+  for (int i = 0; i < n_out; ++i) out[i] = 0.0;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->prof.collect();
   for (int t = 0; t < PROF_NTAGS; ++t) {

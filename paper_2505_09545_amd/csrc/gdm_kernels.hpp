@@ -18,11 +18,23 @@ struct DipoleView {
 template <typename T>
 hipError_t launch_assemble(const DipoleView& d, const struct Wave& w, void* M, int64_t ld, hipStream_t st);
 
+// Optional operand masks: rows [ar0, ar0 + adw) of op(A) are a square block
+// (row r - ar0, column k) of which only one triangle is read (kind below); a
+// B mask keeps the triangle of B (row k, column j).  Masked-out elements read
+// as zero.
+enum { GEMM_MASK_NONE = 0, GEMM_MASK_STRICT_LOWER = 1, GEMM_MASK_UPPER = 2, GEMM_MASK_LOWER = 3,
+       GEMM_MASK_STRICT_UPPER = 4 };
+struct GemmMask {
+  int akind = 0;
+  int64_t ar0 = 0, adw = 0;
+  int bkind = 0;
+};
+
 // C (m x n) = C - op(A) B   (mode 0)   or   C = op(A) B   (mode 1);
 // complex interleaved, column-major; op(A) = A (transA 0) or A^T (transA 1, no conjugation).
 template <typename T>
 hipError_t launch_gemm(int mode, int transA, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
-                       const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st);
+                       const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st, GemmMask mk = GemmMask{});
 // The LU trailing update A22 -= L21 U12: same kernel body, separate symbol so
 // that profilers report it on its own.
 template <typename T>
@@ -30,16 +42,25 @@ hipError_t launch_gemm_update(int64_t m, int64_t n, int64_t k, const void* A, in
                               int64_t ldb, void* C, int64_t ldc, hipStream_t st);
 
 // Optional per-launch timing with HIP events on the launch stream.
-enum ProfTag { PROF_UPDATE = 0, PROF_PANEL = 1, PROF_ASSEMBLE = 2, PROF_TRSM = 3, PROF_PERM = 4, PROF_NTAGS = 5 };
+enum ProfTag {
+  PROF_UPDATE = 0,
+  PROF_PANEL = 1,
+  PROF_ASSEMBLE = 2,
+  PROF_TRSM = 3,
+  PROF_PERM = 4,
+  PROF_SOLVE = 5,
+  PROF_RESID = 6,
+  PROF_NTAGS = 7
+};
 struct Prof {
   bool on = false;
   std::vector<hipEvent_t> ev;
   std::vector<int> tag;
   std::vector<double> work;
   size_t used = 0;
-  double ms[PROF_NTAGS] = {0, 0, 0, 0, 0};
-  double wsum[PROF_NTAGS] = {0, 0, 0, 0, 0};
-  double cnt[PROF_NTAGS] = {0, 0, 0, 0, 0};
+  double ms[PROF_NTAGS] = {};
+  double wsum[PROF_NTAGS] = {};
+  double cnt[PROF_NTAGS] = {};
   hipError_t begin(hipStream_t st, int t, double w);
   hipError_t end(hipStream_t st);
   // after the stream is synchronised: fold the recorded pairs into ms/wsum/cnt
@@ -75,16 +96,27 @@ struct LUWork {
   int32_t* err;              // [2]: exchange timeout flag, first zero pivot (INT32_MAX if none)
   int32_t* pairs;            // [nblocks][2][2 nb]: destination rows then source rows
   int32_t* npairs;           // [nblocks]
+  void* tmp;                 // [n * nb] complex scratch (operand copies)
+  void* dinv;                // [nblocks][nb][nb] complex inverses of the diagonal triangles
+  void* tmp2;                // [nb * nb] complex scratch of the main stream
+  std::vector<hipEvent_t>* events;  // host-side pool of reusable events (look-ahead)
+  int64_t tmp_elems;         // capacity of tmp in complex elements
 };
 
 LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes);
 size_t lu_workspace_bytes(const LUPlan& p, int elem_bytes, int num_cu);
 void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu, LUWork& w);
 
+// `side` (may be null): second stream for the look-ahead; all work is joined
+// back into `st` before return.
 template <typename T>
 hipError_t lu_factor(void* A, int64_t ld, const LUPlan& plan, const LUWork& ws, int32_t* ipiv, hipStream_t st,
-                     Prof* prof = nullptr);
+                     Prof* prof = nullptr, hipStream_t side = nullptr);
 
+// Factors are left in a solve-ready form: for every block the diagonal block
+// holds I - L11^-1 (strict lower part) and I - U11^-1 (upper part), the block
+// column below holds L21 L11^-1 and the block column above holds U01 U11^-1, so
+// that every step of a (transposed) solve is one GEMM.
 // Solve op(M) X = B in place for B (n x nrhs, ld ldb) with the factors of lu_factor.
 template <typename T>
 hipError_t lu_solve(int trans, const void* A, int64_t ld, const LUPlan& plan, const LUWork& ws, void* B,

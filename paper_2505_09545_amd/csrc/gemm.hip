@@ -33,10 +33,23 @@ constexpr int GBM = 64;  // complex rows per tile
 constexpr int GBN = 64;  // columns per tile
 constexpr int GBK = 8;   // complex k per stage
 
+// Operand masks (used by the triangular-block solves): an element (r, c) of a
+// masked square block is kept iff the relation holds, else read as zero.
+__device__ inline bool mask_keep(int kind, int64_t r, int64_t c) {
+  switch (kind) {
+    case GEMM_MASK_STRICT_LOWER: return r > c;
+    case GEMM_MASK_UPPER: return r <= c;
+    case GEMM_MASK_LOWER: return r >= c;
+    case GEMM_MASK_STRICT_UPPER: return r < c;
+    default: return true;
+  }
+}
+
 template <typename T, int MODE, int TRANSA, int ROLE>
 __global__ void __launch_bounds__(256) cgemm_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict__ A,
                                                      int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb,
-                                                     cplx<T>* __restrict__ C, int64_t ldc, int tiles_m, int tiles) {
+                                                     cplx<T>* __restrict__ C, int64_t ldc, int tiles_m, int tiles,
+                                                     GemmMask mk) {
   using CT = cplx<T>;
   using ACC = typename acc_of<T>::type;
   __shared__ T As[2][GBK * GBM * 2];   // [kc][mc] complex
@@ -68,13 +81,17 @@ __global__ void __launch_bounds__(256) cgemm_kernel(int64_t m, int64_t n, int64_
       const int64_t gm = m0 + mc, gk = kb + kc;
       CT v;
       v.x = 0; v.y = 0;
-      if (gm < m && gk < k) v = TRANSA == 0 ? A[gm + gk * lda] : A[gk + gm * lda];
+      bool keep = gm < m && gk < k;
+      if (mk.akind && gm >= mk.ar0 && gm < mk.ar0 + mk.adw) keep = keep && mask_keep(mk.akind, gm - mk.ar0, gk);
+      if (keep) v = TRANSA == 0 ? A[gm + gk * lda] : A[gk + gm * lda];
       ra[i] = v;
       const int kc2 = idx % GBK, nc = idx / GBK;
       const int64_t gn = n0 + nc, gk2 = kb + kc2;
       CT u;
       u.x = 0; u.y = 0;
-      if (gn < n && gk2 < k) u = B[gk2 + gn * ldb];
+      bool keepb = gn < n && gk2 < k;
+      if (mk.bkind) keepb = keepb && mask_keep(mk.bkind, gk2, gn);
+      if (keepb) u = B[gk2 + gn * ldb];
       rb[i] = u;
     }
   };
@@ -160,7 +177,7 @@ __global__ void __launch_bounds__(256) cgemm_kernel(int64_t m, int64_t n, int64_
 
 template <typename T>
 hipError_t launch_gemm(int mode, int transA, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
-                       const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st) {
+                       const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st, GemmMask mk) {
   if (m <= 0 || n <= 0) return hipSuccess;
   const int64_t tm = (m + GBM - 1) / GBM, tn = (n + GBN - 1) / GBN;
   if (tm * tn > INT32_MAX) return hipErrorInvalidValue;
@@ -168,14 +185,12 @@ hipError_t launch_gemm(int mode, int transA, int64_t m, int64_t n, int64_t k, co
   const auto* a = static_cast<const cplx<T>*>(A);
   const auto* b = static_cast<const cplx<T>*>(B);
   auto* c = static_cast<cplx<T>*>(C);
-  if (k <= 0) {
-    if (mode == 0) return hipSuccess;  // C - 0
-  }
+  if (k <= 0 && mode == 0) return hipSuccess;  // C - 0
   const dim3 grid(tiles), blk(256);
-  if (mode == 0 && transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 0, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
-  else if (mode == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 1, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
-  else if (transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 1, 0, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
-  else hipLaunchKernelGGL((cgemm_kernel<T, 1, 1, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles);
+  if (mode == 0 && transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 0, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk);
+  else if (mode == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 1, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk);
+  else if (transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 1, 0, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk);
+  else hipLaunchKernelGGL((cgemm_kernel<T, 1, 1, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk);
   return hipGetLastError();
 }
 
@@ -188,7 +203,7 @@ hipError_t launch_gemm_update(int64_t m, int64_t n, int64_t k, const void* A, in
   const int tiles = (int)(tm * tn);
   hipLaunchKernelGGL((cgemm_kernel<T, 0, 0, 1>), dim3(tiles), dim3(256), 0, st, m, n, k,
                      static_cast<const cplx<T>*>(A), lda, static_cast<const cplx<T>*>(B), ldb,
-                     static_cast<cplx<T>*>(C), ldc, (int)tm, tiles);
+                     static_cast<cplx<T>*>(C), ldc, (int)tm, tiles, GemmMask{});
   return hipGetLastError();
 }
 template hipError_t launch_gemm_update<double>(int64_t, int64_t, int64_t, const void*, int64_t, const void*, int64_t,
@@ -239,8 +254,8 @@ Prof::~Prof() {
 }
 
 template hipError_t launch_gemm<double>(int, int, int64_t, int64_t, int64_t, const void*, int64_t, const void*,
-                                        int64_t, void*, int64_t, hipStream_t);
+                                        int64_t, void*, int64_t, hipStream_t, GemmMask);
 template hipError_t launch_gemm<float>(int, int, int64_t, int64_t, int64_t, const void*, int64_t, const void*,
-                                       int64_t, void*, int64_t, hipStream_t);
+                                       int64_t, void*, int64_t, hipStream_t, GemmMask);
 
 }  // namespace gdm

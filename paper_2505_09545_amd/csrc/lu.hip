@@ -21,6 +21,7 @@
 // 0-based global row indices (LAPACK semantics otherwise).
 #include <algorithm>
 #include <climits>
+#include <vector>
 
 #include "gdm_common.hpp"
 #include "gdm_kernels.hpp"
@@ -102,6 +103,42 @@ template <typename CT> __device__ inline uint32_t cword(const CT& v, int k) {
   return reinterpret_cast<const uint32_t*>(&v)[k];
 }
 
+// Rows never move between workgroups inside the panel: each local row carries a
+// label, the position it will be written back to.  The interchange of column j
+// (positions gj <-> p) swaps the labels of the two rows involved, which their
+// owners do locally; the pivot row's values are the only data exchanged.
+template <typename CT>
+__device__ inline u64 pivot_key(const CT& v, uint32_t label) {
+  const float a = (float)(fabs(v.x) + fabs(v.y));
+  return ((u64)__float_as_uint(a) << 32) | (0xffffffffu - label);
+}
+
+// Workgroup-wide argmax of (key, idx); one barrier.  Keys are unique (they end
+// with the row label), so only the key is reduced across lanes and the lane that
+// holds the winning key publishes its idx.  skey/sidx: LDS arrays (4 entries)
+// that the caller does not touch again before the next barrier.
+__device__ inline void block_argmax(u64& key, int& idx, u64* skey, int* sidx) {
+  u64 k = key;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const u64 o = shfl_xor_u64(k, off);
+    k = o > k ? o : k;
+  }
+  const int wv = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) skey[wv] = k;
+  if (key == k && k != 0) sidx[wv] = idx;
+  __syncthreads();
+  key = skey[0];
+  int wbest = 0;
+#pragma unroll
+  for (int i = 1; i < 4; ++i)
+    if (skey[i] > key) {
+      key = skey[i];
+      wbest = i;
+    }
+  idx = key ? sidx[wbest] : -1;
+}
+
 template <typename T>
 __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int64_t ld, int64_t n, int64_t k0, int w,
                                                      int R, int G, int32_t* __restrict__ ipiv, LUWork ws,
@@ -109,9 +146,11 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
   using CT = cplx<T>;
   constexpr int NW = sizeof(CT) / 4;  // payload words per complex
   extern __shared__ unsigned char smem_raw[];
-  CT* tile = reinterpret_cast<CT*>(smem_raw);  // [w][R], column c at tile + c*R
-  CT* prow = tile + (size_t)w * R;             // [w] pivot row
-  __shared__ u64 red[4];
+  CT* tile = reinterpret_cast<CT*>(smem_raw);           // [w][R], column c at tile + c*R
+  CT* prow = tile + (size_t)w * R;                      // [w] pivot row
+  int32_t* lab = reinterpret_cast<int32_t*>(prow + w);  // [R] row labels (final positions)
+  __shared__ u64 skey1[4], skey2[4];
+  __shared__ int sidx1[4], sidx2[4];
   __shared__ int bad;
   const int g = blockIdx.x, tid = threadIdx.x;
   const int64_t rbase = k0 + (int64_t)g * R;
@@ -120,125 +159,117 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
   if (tid == 0) bad = 0;
   for (int c = 0; c < w; ++c)
     for (int lr = tid; lr < myR; lr += 256) tile[c * R + lr] = A[(rbase + lr) + (k0 + c) * ld];
+  for (int lr = tid; lr < myR; lr += 256) lab[lr] = (int32_t)(rbase + lr);
   // 2D mapping for the rank-1 update: RP rows x CG column groups
   int RP = 1;
   while (RP < myR && RP < 256) RP <<= 1;
   const int CG = 256 / RP;
   const int ulr0 = tid & (RP - 1), ucg = tid / RP;
   __syncthreads();
-
+  // candidate of column 0
+  u64 best = 0;
+  int brow = -1;
+  for (int lr = tid; lr < myR; lr += 256) {
+    const u64 kk = pivot_key(tile[lr], (uint32_t)lab[lr]);
+    if (kk > best) {
+      best = kk;
+      brow = lr;
+    }
+  }
   for (int j = 0; j < w; ++j) {
     const int64_t gj = k0 + j;
     const uint32_t E = epoch0 + (uint32_t)j;
     const int par = j & 1;
     u64* cand = ws.cand + (size_t)par * ws.gmax * 2;
     u64* rows = ws.rows + (size_t)par * ws.gmax * ws.wwmax;
-    u64* drow = ws.drow + (size_t)par * ws.wwmax;
-    // local pivot candidate: key = (|re|+|im| as float bits) << 32 | ~row
-    u64 best = 0;
-    for (int lr = tid; lr < myR; lr += 256) {
-      const int64_t gr = rbase + lr;
-      if (gr >= gj) {
-        const CT v = tile[j * R + lr];
-        const float a = (float)(fabs(v.x) + fabs(v.y));
-        const u64 kk = ((u64)__float_as_uint(a) << 32) | (0xffffffffu - (uint32_t)gr);
-        best = kk > best ? kk : best;
-      }
-    }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const u64 o = shfl_xor_u64(best, off);
-      best = o > best ? o : best;
-    }
-    if ((tid & 63) == 0) red[tid >> 6] = best;
-    __syncthreads();
-    u64 mybest = red[0];
-    for (int i = 1; i < 4; ++i) mybest = red[i] > mybest ? red[i] : mybest;
-    __syncthreads();
-    const int gd = j / R;  // owner of global row gj
-    // publish: candidate key, candidate row, and (owner only) row gj
+    // workgroup candidate over its active rows (labels >= gj); the tile is final
+    block_argmax(best, brow, skey1, sidx1);
+    const u64 mybest = best;
+    const int lrow = best ? brow : -1;
+    // publish key (value, label) and the candidate row
     if (tid == 0) {
-      const uint32_t val = mybest ? (uint32_t)(mybest >> 32) : 0u;
-      const uint32_t row = mybest ? (0xffffffffu - (uint32_t)(mybest & 0xffffffffu)) : 0xffffffffu;
-      ll_put(&cand[2 * g + 0], E, val);
-      ll_put(&cand[2 * g + 1], E, row);
+      ll_put(&cand[2 * g + 0], E, mybest ? (uint32_t)(mybest >> 32) : 0u);
+      ll_put(&cand[2 * g + 1], E, mybest ? (0xffffffffu - (uint32_t)(mybest & 0xffffffffu)) : 0xffffffffu);
     }
-    if (mybest) {
-      const int lrow = (int)((int64_t)(0xffffffffu - (uint32_t)(mybest & 0xffffffffu)) - rbase);
-      for (int t = tid; t < WW; t += 256) ll_put(&rows[(size_t)g * ws.wwmax + t], E, cword(tile[(t / NW) * R + lrow], t % NW));
-    }
-    if (g == gd) {
-      const int ldr = j - gd * R;
-      for (int t = tid; t < WW; t += 256) ll_put(&drow[t], E, cword(tile[(t / NW) * R + ldr], t % NW));
-    }
-    // gather every workgroup's key; winner = largest |re|+|im|, lowest row on ties
+    if (lrow >= 0)
+      for (int t = tid; t < WW; t += 256)
+        ll_put(&rows[(size_t)g * ws.wwmax + t], E, cword(tile[(t / NW) * R + lrow], t % NW));
+    // gather all keys; winner = largest |re|+|im|, lowest label on ties
     u64 k = 0;
+    int owner = -1;
     if (tid < G) {
       const uint32_t val = ll_get(&cand[2 * tid + 0], E, &bad);
-      const uint32_t row = ll_get(&cand[2 * tid + 1], E, &bad);
-      k = ((u64)val << 32) | (0xffffffffu - row);
+      const uint32_t label = ll_get(&cand[2 * tid + 1], E, &bad);
+      k = ((u64)val << 32) | (0xffffffffu - label);
+      owner = tid;
     }
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-      const u64 o = shfl_xor_u64(k, off);
-      k = o > k ? o : k;
-    }
-    if ((tid & 63) == 0) red[tid >> 6] = k;
-    __syncthreads();
-    u64 win = red[0];
-    for (int i = 1; i < 4; ++i) win = red[i] > win ? red[i] : win;
-    const int64_t p = (int64_t)(0xffffffffu - (uint32_t)(win & 0xffffffffu));
-    const int gp = (int)((p - k0) / R);
-    const int lp = (int)((p - k0) - (int64_t)gp * R);
+    block_argmax(k, owner, skey2, sidx2);
+    const int gp = owner;
+    const uint32_t plabel = 0xffffffffu - (uint32_t)(k & 0xffffffffu);
     // pivot row
-    for (int t = tid; t < WW; t += 256)
-      reinterpret_cast<uint32_t*>(prow)[t] = ll_get(&rows[(size_t)gp * ws.wwmax + t], E, &bad);
+    if (gp >= 0)
+      for (int t = tid; t < WW; t += 256)
+        reinterpret_cast<uint32_t*>(prow)[t] = ll_get(&rows[(size_t)gp * ws.wwmax + t], E, &bad);
     __syncthreads();
-    if (bad) {
+    if (bad || gp < 0) {
       if (tid == 0) __hip_atomic_store(&ws.err[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
-    if (p != gj && (g == gd || g == gp)) {
-      const int ldr = j - gd * R;
-      for (int c = tid; c < w; c += 256) {
-        CT dv;
-        if (g == gd) {
-          dv = tile[c * R + ldr];
-        } else {
-          for (int q = 0; q < NW; ++q) reinterpret_cast<uint32_t*>(&dv)[q] = ll_get(&drow[c * NW + q], E, &bad);
-        }
-        if (g == gp) tile[c * R + lp] = dv;
-        if (g == gd) tile[c * R + ldr] = prow[c];
-      }
-    }
-    if (g == 0 && tid == 0) ipiv[gj] = (int32_t)p;
-    __syncthreads();
-    if (bad) {
-      if (tid == 0) __hip_atomic_store(&ws.err[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      return;
-    }
+    if (g == 0 && tid == 0) ipiv[gj] = (int32_t)plabel;
     const CT piv = prow[j];
     const bool zero = piv.x == 0 && piv.y == 0;
     if (zero && g == 0 && tid == 0) atomicMin(&ws.err[1], (int)gj);
     CT inv;
     if (zero) { inv.x = 0; inv.y = 0; } else inv = cinv_t(piv);
-    for (int lr = tid; lr < myR; lr += 256)
-      if (rbase + lr > gj) tile[j * R + lr] = cmul_t(tile[j * R + lr], inv);
-    __syncthreads();
-    for (int lr = ulr0; lr < myR; lr += RP) {
-      if (rbase + lr <= gj) continue;
-      const CT l = tile[j * R + lr];
-      for (int c = j + 1 + ucg; c < w; c += CG) {
-        const CT u = prow[c];
-        CT& t = tile[c * R + lr];
-        t.x -= l.x * u.x - l.y * u.y;
-        t.y -= l.x * u.y + l.y * u.x;
+    // interchange of positions gj <-> plabel (label swap), then the multipliers
+    // of the rows below (labels > gj); each row is handled by one thread
+    for (int lr = tid; lr < myR; lr += 256) {
+      int32_t lb = lab[lr];
+      if (plabel != (uint32_t)gj) {
+        if (lb == (int32_t)gj) lb = (int32_t)plabel;
+        else if (g == gp && lr == lrow) lb = (int32_t)gj;
+        lab[lr] = lb;
       }
+      if (lb > (int32_t)gj) tile[j * R + lr] = cmul_t(tile[j * R + lr], inv);
     }
     __syncthreads();
+    // rank-1 update, and the candidate of column j + 1 on the fly: the threads of
+    // column group 0 own column j + 1; the remaining columns are updated with
+    // independent (unrolled) LDS read-modify-writes
+    best = 0;
+    brow = -1;
+    for (int lr = ulr0; lr < myR; lr += RP) {
+      const int32_t lb = lab[lr];
+      if (lb <= (int32_t)gj) continue;
+      const CT l = tile[j * R + lr];
+      int c = j + 1 + ucg;
+      if (ucg == 0 && c < w) {
+        const CT u = prow[c];
+        CT t = tile[c * R + lr];
+        t.x -= l.x * u.x - l.y * u.y;
+        t.y -= l.x * u.y + l.y * u.x;
+        tile[c * R + lr] = t;
+        const u64 kk = pivot_key(t, (uint32_t)lb);
+        if (kk > best) {
+          best = kk;
+          brow = lr;
+        }
+        c += CG;
+      }
+#pragma unroll 8
+      for (; c < w; c += CG) {
+        const CT u = prow[c];
+        CT t = tile[c * R + lr];
+        t.x -= l.x * u.x - l.y * u.y;
+        t.y -= l.x * u.y + l.y * u.x;
+        tile[c * R + lr] = t;
+      }
+    }
+    // (the barrier inside the next block_argmax orders the update before any read)
   }
+  __syncthreads();
   for (int c = 0; c < w; ++c)
-    for (int lr = tid; lr < myR; lr += 256) A[(rbase + lr) + (k0 + c) * ld] = tile[c * R + lr];
+    for (int lr = tid; lr < myR; lr += 256) A[lab[lr] + (k0 + c) * ld] = tile[c * R + lr];
 }
 
 // ---------------------------------------------------------------------------
@@ -350,35 +381,33 @@ __global__ void __launch_bounds__(256) row_permute_inv_kernel(cplx<T>* __restric
 // ---------------------------------------------------------------------------
 // KIND 0: L unit lower (forward)        KIND 1: U upper non-unit (backward)
 // KIND 2: U^T lower non-unit (forward)  KIND 3: L^T upper unit (backward)
-// Each workgroup owns TRSM_CB columns of B (in LDS) and sweeps the w steps of
-// the substitution; the needed columns of op(Tri) are staged in LDS, PW
-// columns at a time, so a step costs one LDS read per element and one barrier.
-constexpr int TRSM_CB = 16;
-constexpr int TRSM_LS_BYTES = 48 * 1024;
+// Wave-synchronous substitution (w <= 128): each wave owns CPW columns of B in
+// registers, lane l holding rows l and l + 64; x_j is broadcast from its owner
+// lane with readlane, so the w sequential steps need no workgroup barrier.  The
+// columns of op(Tri) are staged in LDS, PW at a time, shared by the 4 waves.
+constexpr int TRSM_LS_BYTES = 64 * 1024;
 
-template <typename T, int KIND>
-__global__ void __launch_bounds__(256) trsm_kernel(const cplx<T>* __restrict__ Tri, int64_t ldt, int w,
-                                                   cplx<T>* __restrict__ B, int64_t ldb, int64_t ncols, int PW) {
+__device__ inline float2 readlane_c(float2 v, int l) {
+  return make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), l)),
+                     __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), l)));
+}
+__device__ inline double readlane_d(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ inline double2 readlane_c(double2 v, int l) { return make_double2(readlane_d(v.x, l), readlane_d(v.y, l)); }
+
+// Substitution sweep on register-resident columns b (lane l holds rows l, l+64).
+template <typename T, int KIND, int CPW>
+__device__ inline void trsm_sweep(const cplx<T>* __restrict__ Tri, int64_t ldt, int w, cplx<T> (&b)[2][CPW],
+                                  cplx<T>* Ls, int PW) {
   using CT = cplx<T>;
-  extern __shared__ unsigned char smem_raw[];
-  CT* Bs = reinterpret_cast<CT*>(smem_raw);  // [w][CB] row-major
-  CT* Ls = Bs + (size_t)w * TRSM_CB;         // [PW][w]: Ls[c*w + i] = op(Tri)[i][jbase + c]
-  const int tid = threadIdx.x;
-  const int64_t c0 = (int64_t)blockIdx.x * TRSM_CB;
-  const int nc = (int)(ncols - c0 < TRSM_CB ? ncols - c0 : TRSM_CB);
-  for (int idx = tid; idx < w * TRSM_CB; idx += 256) {
-    const int i = idx % w, c = idx / w;
-    CT v;
-    v.x = 0;
-    v.y = 0;
-    if (c < nc) v = B[i + (c0 + c) * ldb];
-    Bs[i * TRSM_CB + c] = v;
-  }
+  const int tid = threadIdx.x, lane = tid & 63;
   constexpr bool forward = (KIND == 0 || KIND == 2);
   constexpr bool unit = (KIND == 0 || KIND == 3);
   constexpr bool transposed = (KIND >= 2);
-  const int c = tid % TRSM_CB, i0 = tid / TRSM_CB;
-  constexpr int ISTEP = 256 / TRSM_CB;
   for (int ph = 0; ph < w; ph += PW) {
     const int pw = w - ph < PW ? w - ph : PW;
     // columns of op(Tri) handled in this phase: [jb, jb + pw); rows needed: [lo, hi)
@@ -398,52 +427,136 @@ __global__ void __launch_bounds__(256) trsm_kernel(const cplx<T>* __restrict__ T
     for (int s = 0; s < pw; ++s) {
       const int j = forward ? jb + s : jb + pw - 1 - s;
       const CT* lcol = Ls + (j - jb) * w;
+      const int jl = j & 63;
+      CT x[CPW];
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) x[c] = readlane_c(j < 64 ? b[0][c] : b[1][c], jl);
       if (!unit) {
-        if (tid < TRSM_CB) Bs[j * TRSM_CB + tid] = cmul_t(Bs[j * TRSM_CB + tid], cinv_t(lcol[j]));
-        __syncthreads();
-      }
-      const CT xj = Bs[j * TRSM_CB + c];
-      if (forward) {
-        for (int i = j + 1 + i0; i < w; i += ISTEP) {
-          const CT t = lcol[i];
-          CT& b = Bs[i * TRSM_CB + c];
-          b.x -= t.x * xj.x - t.y * xj.y;
-          b.y -= t.x * xj.y + t.y * xj.x;
-        }
-      } else {
-        for (int i = i0; i < j; i += ISTEP) {
-          const CT t = lcol[i];
-          CT& b = Bs[i * TRSM_CB + c];
-          b.x -= t.x * xj.x - t.y * xj.y;
-          b.y -= t.x * xj.y + t.y * xj.x;
+        const CT inv = cinv_t(lcol[j]);
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          x[c] = cmul_t(x[c], inv);
+          if (lane == jl) {
+            if (j < 64) b[0][c] = x[c];
+            else b[1][c] = x[c];
+          }
         }
       }
-      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = lane + 64 * h;
+        const bool act = forward ? (i > j && i < w) : (i < j);
+        if (act) {
+          const CT t = lcol[i];
+#pragma unroll
+          for (int c = 0; c < CPW; ++c) {
+            b[h][c].x -= t.x * x[c].x - t.y * x[c].y;
+            b[h][c].y -= t.x * x[c].y + t.y * x[c].x;
+          }
+        }
+      }
     }
-  }
-  for (int idx = tid; idx < w * TRSM_CB; idx += 256) {
-    const int i = idx % w, cc = idx / w;
-    if (cc < nc) B[i + (c0 + cc) * ldb] = Bs[i * TRSM_CB + cc];
   }
 }
 
-template <typename T, int KIND>
-static hipError_t launch_trsm(const cplx<T>* Tri, int64_t ldt, int w, cplx<T>* B, int64_t ldb, int64_t ncols,
-                              hipStream_t st) {
-  if (ncols <= 0 || w <= 0) return hipSuccess;
-  int PW = TRSM_LS_BYTES / (w * (int)sizeof(cplx<T>));
+// Inverse of the diagonal triangle of blocks b0 + blockIdx.y (UPPER 0: unit lower
+// L11, 1: non-unit upper U11) by substitution on identity columns; written to
+// Dinv[b] (nb x nb column-major, zeros in the other triangle).
+template <typename T, int UPPER>
+__global__ void __launch_bounds__(256) block_inv_kernel(const cplx<T>* __restrict__ A, int64_t ld, int64_t n, int nb,
+                                                        int b0, cplx<T>* __restrict__ Dinv, int PW) {
+  using CT = cplx<T>;
+  constexpr int CPW = 4;
+  extern __shared__ unsigned char smem_raw[];
+  CT* Ls = reinterpret_cast<CT*>(smem_raw);
+  const int bb = b0 + blockIdx.y;
+  const int64_t k0 = (int64_t)bb * nb;
+  const int w = (int)(n - k0 < nb ? n - k0 : nb);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col0 = blockIdx.x * (4 * CPW) + wave * CPW;
+  CT b[2][CPW];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      b[h][c].x = (lane + 64 * h == col0 + c) ? 1 : 0;
+      b[h][c].y = 0;
+    }
+  trsm_sweep<T, UPPER ? 1 : 0, CPW>(A + k0 + k0 * ld, ld, w, b, Ls, PW);
+  CT* D = Dinv + (size_t)bb * nb * nb;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int i = lane + 64 * h;
+      if (i < w && col0 + c < w) D[i + (int64_t)(col0 + c) * nb] = b[h][c];
+    }
+}
+
+// Diagonal block of block b0 + blockIdx.y: strict lower <- -Linv (UPPER 0), or
+// upper incl. diagonal <- I - Uinv (UPPER 1).
+template <typename T, int UPPER>
+__global__ void __launch_bounds__(256) diag_store_kernel(cplx<T>* __restrict__ A, int64_t ld, int64_t n, int nb, int b0,
+                                                         const cplx<T>* __restrict__ Dinv) {
+  using CT = cplx<T>;
+  const int bb = b0 + blockIdx.y;
+  const int64_t k0 = (int64_t)bb * nb;
+  const int w = (int)(n - k0 < nb ? n - k0 : nb);
+  const CT* D = Dinv + (size_t)bb * nb * nb;
+  for (int idx = blockIdx.x * 256 + threadIdx.x; idx < w * w; idx += gridDim.x * 256) {
+    const int i = idx % w, j = idx / w;
+    const CT d = D[i + (int64_t)j * nb];
+    CT v;
+    if (!UPPER) {
+      if (i <= j) continue;
+      v.x = -d.x;
+      v.y = -d.y;
+    } else {
+      if (i > j) continue;
+      v.x = (i == j ? 1 : 0) - d.x;
+      v.y = -d.y;
+    }
+    A[(k0 + i) + (k0 + j) * ld] = v;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) copy_block_kernel(const cplx<T>* __restrict__ S, int64_t lds,
+                                                         cplx<T>* __restrict__ D, int64_t ldd, int64_t m, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= m) return;
+  for (int64_t j = blockIdx.y; j < n; j += gridDim.y) D[i + j * ldd] = S[i + j * lds];
+}
+
+template <typename T>
+static hipError_t launch_copy_block(const cplx<T>* S, int64_t lds, cplx<T>* D, int64_t ldd, int64_t m, int64_t n,
+                                    hipStream_t st) {
+  if (m <= 0 || n <= 0) return hipSuccess;
+  const unsigned gy = (unsigned)(n < 65535 ? n : 65535);
+  hipLaunchKernelGGL(copy_block_kernel<T>, dim3((unsigned)((m + 255) / 256), gy), dim3(256), 0, st, S, lds, D, ldd, m,
+                     n);
+  return hipGetLastError();
+}
+
+static int trsm_pw(int w, int elem) {
+  int PW = TRSM_LS_BYTES / (w * 2 * elem);
   if (PW < 1) PW = 1;
   if (PW > w) PW = w;
-  const size_t lds = ((size_t)w * TRSM_CB + (size_t)PW * w) * sizeof(cplx<T>);
-  static size_t set = 0;
-  if (lds > 64 * 1024 && lds > set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&trsm_kernel<T, KIND>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    set = lds;
-  }
-  const int64_t nblk = (ncols + TRSM_CB - 1) / TRSM_CB;
-  hipLaunchKernelGGL((trsm_kernel<T, KIND>), dim3((unsigned)nblk), dim3(256), lds, st, Tri, ldt, w, B, ldb, ncols, PW);
+  return PW;
+}
+
+template <typename T, int UPPER>
+static hipError_t launch_block_inv(const cplx<T>* A, int64_t ld, int64_t n, int nb, int b0, int nblocks, cplx<T>* Dinv,
+                                   hipStream_t st) {
+  if (nblocks <= 0) return hipSuccess;
+  const int PW = trsm_pw(nb, (int)sizeof(T));
+  const size_t lds = (size_t)PW * nb * sizeof(cplx<T>);
+  hipLaunchKernelGGL((block_inv_kernel<T, UPPER>), dim3((unsigned)((nb + 15) / 16), (unsigned)nblocks), dim3(256), lds,
+                     st, A, ld, n, nb, b0, Dinv, PW);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((diag_store_kernel<T, UPPER>), dim3(16, (unsigned)nblocks), dim3(256), 0, st,
+                     const_cast<cplx<T>*>(A), ld, n, nb, b0, Dinv);
   return hipGetLastError();
 }
 
@@ -461,7 +574,7 @@ LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes) {
   // the panel must fit: ceil(n / num_cu) rows x nb columns in LDS
   while (nb > 16) {
     const int64_t R = (n + num_cu - 1) / num_cu;
-    if ((int64_t)(R + 1) * nb * cbytes + LDS_RESERVE <= lds_bytes) break;
+    if ((int64_t)(R + 1) * nb * cbytes + 4 * R + LDS_RESERVE <= lds_bytes) break;
     nb /= 2;
   }
   p.nb = nb;
@@ -472,7 +585,7 @@ LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes) {
     const int64_t m = n - k0;
     int64_t R = (m + num_cu - 1) / num_cu;
     if (R < 32) R = 32;
-    const int64_t Rmax = (lds_bytes - LDS_RESERVE) / ((int64_t)b.w * cbytes) - 1;
+    const int64_t Rmax = (lds_bytes - LDS_RESERVE - (int64_t)b.w * cbytes) / ((int64_t)b.w * cbytes + 4);
     if (R > Rmax) R = Rmax;
     b.R = (int)R;
     b.G = (int)((m + R - 1) / R);
@@ -491,6 +604,9 @@ size_t lu_workspace_bytes(const LUPlan& p, int elem_bytes, int num_cu) {
   s += 64 + 256;
   s += nblk * 2 * 2 * nb * 4 + 256;
   s += nblk * 4 + 256;
+  s += (size_t)p.n * nb * 2 * elem_bytes + 256;
+  s += nblk * nb * nb * 2 * elem_bytes + 256;
+  s += nb * nb * 2 * elem_bytes + 256;
   return s + 8 * 256;
 }
 
@@ -511,6 +627,11 @@ void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu,
   w.err = reinterpret_cast<int32_t*>(take(64));
   w.pairs = reinterpret_cast<int32_t*>(take(nblk * 2 * 2 * nb * 4));
   w.npairs = reinterpret_cast<int32_t*>(take(nblk * 4));
+  w.tmp = take((size_t)p.n * nb * 2 * elem_bytes);
+  w.tmp_elems = (int64_t)p.n * nb;
+  w.dinv = take(nblk * nb * nb * 2 * elem_bytes);
+  w.tmp2 = take(nb * nb * 2 * elem_bytes);
+  w.events = nullptr;
 }
 
 // ---------------------------------------------------------------------------
@@ -518,13 +639,14 @@ void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu,
 // ---------------------------------------------------------------------------
 template <typename T>
 hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws, int32_t* ipiv, hipStream_t st,
-                     Prof* prof) {
+                     Prof* prof, hipStream_t side) {
   Prof noprof;
   Prof& P = prof ? *prof : noprof;
   using CT = cplx<T>;
   CT* A = static_cast<CT*>(Av);
   const int64_t n = plan.n;
   const int nb = plan.nb;
+  const int nblk = (int)plan.blocks.size();
   hipError_t e;
   hipLaunchKernelGGL(init_err_kernel, dim3(1), dim3(64), 0, st, ws.err);
   // exchange buffers start from zero (epoch 0 is never used), so epochs 1, 2, ...
@@ -537,7 +659,8 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
   uint32_t epoch = 1;
   // panels may need more than the default 64 KB of dynamic LDS
   size_t lds_need = 0;
-  for (const LUBlock& b : plan.blocks) lds_need = std::max(lds_need, ((size_t)b.w * b.R + b.w) * sizeof(CT));
+  for (const LUBlock& b : plan.blocks)
+    lds_need = std::max(lds_need, ((size_t)b.w * b.R + b.w) * sizeof(CT) + (size_t)b.R * 4);
   static size_t lds_set[2] = {0, 0};
   size_t& cur = lds_set[sizeof(T) == 8 ? 0 : 1];
   if (lds_need > 64 * 1024 && lds_need > cur) {
@@ -546,40 +669,132 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
       return e;
     cur = lds_need;
   }
-  for (size_t bi = 0; bi < plan.blocks.size(); ++bi) {
+  // Look-ahead: the main stream runs the panels and the update of the next
+  // panel's columns; the side stream runs the bulk of each trailing update (and
+  // the solve-ready transform of L21), overlapping the next panel.
+  const bool la = side != nullptr && side != st && ws.events != nullptr;
+  // events come from a pool owned by the caller and reused across calls (the
+  // caller synchronises the stream before the next factorisation)
+  size_t ev_used = 0;
+  auto new_event = [&](hipEvent_t& ev) -> hipError_t {
+    if (!ws.events) return hipErrorInvalidValue;
+    if (ev_used == ws.events->size()) {
+      hipEvent_t x;
+      hipError_t r = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+      if (r != hipSuccess) return r;
+      ws.events->push_back(x);
+    }
+    ev = (*ws.events)[ev_used++];
+    return hipSuccess;
+  };
+  auto cleanup = [&]() {};
+#define LUCHK(x)            \
+  do {                      \
+    if ((e = (x)) != hipSuccess) { \
+      cleanup();            \
+      return e;             \
+    }                       \
+  } while (0)
+  CT* tmpB = static_cast<CT*>(ws.tmp);   // side-stream operand copies (n x nb)
+  CT* tmpA = static_cast<CT*>(ws.tmp2);  // main-stream operand copies (nb x nb)
+  CT* dinv = static_cast<CT*>(ws.dinv);
+  hipEvent_t bulk_done = nullptr;  // side stream finished the previous block's bulk update
+  for (int bi = 0; bi < nblk; ++bi) {
     const LUBlock& b = plan.blocks[bi];
     const int64_t k0 = b.k0;
     const int w = b.w;
     // the panel's workgroups must all be resident at once (one per CU at most)
-    if (b.G > plan.max_wg || b.G > ws.gmax || b.w > nb || (int64_t)b.G * b.R < n - k0) return hipErrorInvalidValue;
-    const size_t lds = ((size_t)w * b.R + w) * sizeof(CT);
-    if ((e = P.begin(st, PROF_PANEL, (double)w)) != hipSuccess) return e;
+    if (b.G > plan.max_wg || b.G > ws.gmax || b.w > nb || (int64_t)b.G * b.R < n - k0) {
+      cleanup();
+      return hipErrorInvalidValue;
+    }
+    const size_t lds = ((size_t)w * b.R + w) * sizeof(CT) + (size_t)b.R * 4;
+    LUCHK(P.begin(st, PROF_PANEL, (double)w));
     hipLaunchKernelGGL(panel_kernel<T>, dim3(b.G), dim3(256), lds, st, A, ld, n, k0, w, b.R, b.G, ipiv, ws, epoch);
     epoch += (uint32_t)w;
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    if ((e = P.end(st)) != hipSuccess) return e;
+    LUCHK(hipGetLastError());
+    LUCHK(P.end(st));
     int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;
     int32_t* src = dst + 2 * nb;
     hipLaunchKernelGGL(block_perm_kernel, dim3(1), dim3(64), 0, st, ipiv, k0, w, dst, src, ws.npairs + bi);
     const int64_t c1 = k0 + w;
     const int64_t nr = n - c1;
-    if (nr > 0) {
-      if ((e = P.begin(st, PROF_PERM, 0.0)) != hipSuccess) return e;
-      hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)nr), dim3(256), 0, st, A, ld, c1, dst, src,
+    CT* diag = A + k0 + k0 * ld;
+    // L11^-1 -> strict lower part of the diagonal block holds I - L11^-1
+    LUCHK(P.begin(st, PROF_TRSM, 0.0));
+    LUCHK((launch_block_inv<T, 0>(A, ld, n, nb, bi, 1, dinv, st)));
+    LUCHK(P.end(st));
+    if (bulk_done) LUCHK(hipStreamWaitEvent(st, bulk_done, 0));  // columns of this step were in the bulk
+    if (nr <= 0) break;
+    hipEvent_t factored = nullptr;
+    if (la) {
+      LUCHK(new_event(factored));
+      LUCHK(hipEventRecord(factored, st));
+    }
+    GemmMask ml;
+    ml.akind = GEMM_MASK_STRICT_LOWER;
+    ml.ar0 = 0;
+    ml.adw = w;
+    // columns [c1, c1 + wa) on the main stream, [c1 + wa, n) on the side stream
+    const int64_t wa = la ? std::min<int64_t>(nr, nb) : nr;
+    auto update_cols = [&](hipStream_t s, int64_t cb, int64_t ncols, CT* tmp) -> hipError_t {
+      hipError_t r;
+      if (ncols <= 0) return hipSuccess;
+      if ((r = P.begin(s, PROF_PERM, 0.0)) != hipSuccess) return r;
+      hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)ncols), dim3(256), 0, s, A, ld, cb, dst, src,
                          ws.npairs + bi);
-      if ((e = P.end(st)) != hipSuccess) return e;
-      if ((e = P.begin(st, PROF_TRSM, 4.0 * w * w * (double)nr)) != hipSuccess) return e;
-      if ((e = launch_trsm<T, 0>(A + k0 + k0 * ld, ld, w, A + k0 + c1 * ld, ld, nr, st)) != hipSuccess) return e;
-      if ((e = P.end(st)) != hipSuccess) return e;
-      // A22 -= L21 U12: 8 nr^2 w real flops
-      if ((e = P.begin(st, PROF_UPDATE, 8.0 * (double)nr * (double)nr * w)) != hipSuccess) return e;
-      if ((e = launch_gemm_update<T>(nr, nr, w, A + c1 + k0 * ld, ld, A + k0 + c1 * ld, ld, A + c1 + c1 * ld, ld,
-                                     st)) != hipSuccess)
-        return e;
-      if ((e = P.end(st)) != hipSuccess) return e;
+      if ((r = P.end(s)) != hipSuccess) return r;
+      // U12 = L11^-1 A12 = A12 - (I - L11^-1) A12
+      if ((r = P.begin(s, PROF_TRSM, 8.0 * w * w * (double)ncols)) != hipSuccess) return r;
+      if ((r = launch_copy_block<T>(A + k0 + cb * ld, ld, tmp, w, w, ncols, s)) != hipSuccess) return r;
+      if ((r = launch_gemm<T>(0, 0, w, ncols, w, diag, ld, tmp, w, A + k0 + cb * ld, ld, s, ml)) != hipSuccess)
+        return r;
+      if ((r = P.end(s)) != hipSuccess) return r;
+      // A22[:, cols] -= L21 U12[:, cols]
+      if ((r = P.begin(s, PROF_UPDATE, 8.0 * (double)nr * (double)ncols * w)) != hipSuccess) return r;
+      if ((r = launch_gemm_update<T>(nr, ncols, w, A + c1 + k0 * ld, ld, A + k0 + cb * ld, ld, A + c1 + cb * ld, ld,
+                                     s)) != hipSuccess)
+        return r;
+      return P.end(s);
+    };
+    LUCHK(update_cols(st, c1, wa, la ? tmpA : tmpB));
+    hipEvent_t main_updated = nullptr;
+    if (la) {
+      LUCHK(new_event(main_updated));
+      LUCHK(hipEventRecord(main_updated, st));
+    }
+    hipStream_t sb = la ? side : st;
+    if (la) LUCHK(hipStreamWaitEvent(sb, factored, 0));
+    LUCHK(update_cols(sb, c1 + wa, nr - wa, tmpB));
+    // L21 is read by both parts of this step's update: transform it after both
+    if (la) LUCHK(hipStreamWaitEvent(sb, main_updated, 0));
+    // solve-ready form: L21 <- L21 L11^-1 = L21 - L21 (I - L11^-1)
+    LUCHK(P.begin(sb, PROF_TRSM, 8.0 * w * w * (double)nr));
+    LUCHK(launch_copy_block<T>(A + c1 + k0 * ld, ld, tmpB, nr, nr, w, sb));
+    GemmMask mb;
+    mb.bkind = GEMM_MASK_STRICT_LOWER;
+    LUCHK(launch_gemm<T>(0, 0, nr, w, w, tmpB, nr, diag, ld, A + c1 + k0 * ld, ld, sb, mb));
+    LUCHK(P.end(sb));
+    if (la) {
+      LUCHK(new_event(bulk_done));
+      LUCHK(hipEventRecord(bulk_done, sb));
     }
   }
+  if (bulk_done) LUCHK(hipStreamWaitEvent(st, bulk_done, 0));
+  // upper parts: diagonal blocks hold I - U11^-1, block columns above hold U01 U11^-1
+  LUCHK(P.begin(st, PROF_TRSM, 0.0));
+  LUCHK((launch_block_inv<T, 1>(A, ld, n, nb, 0, nblk, dinv, st)));
+  for (int bi = 1; bi < nblk; ++bi) {
+    const LUBlock& b = plan.blocks[bi];
+    const int64_t k0 = b.k0;
+    LUCHK(launch_copy_block<T>(A + k0 * ld, ld, tmpB, k0, k0, b.w, st));
+    GemmMask mu;
+    mu.bkind = GEMM_MASK_UPPER;
+    LUCHK(launch_gemm<T>(0, 0, k0, b.w, b.w, tmpB, k0, A + k0 + k0 * ld, ld, A + k0 * ld, ld, st, mu));
+  }
+  LUCHK(P.end(st));
   return hipGetLastError();
+#undef LUCHK
 }
 
 template <typename T>
@@ -587,65 +802,92 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
                     int64_t ldb, int64_t nrhs, hipStream_t st) {
   using CT = cplx<T>;
   const CT* A = static_cast<const CT*>(Av);
-  CT* B = static_cast<CT*>(Bv);
+  CT* Ball = static_cast<CT*>(Bv);
   const int64_t n = plan.n;
   const int nb = plan.nb;
   const int nblk = (int)plan.blocks.size();
+  CT* X = static_cast<CT*>(ws.tmp);
   hipError_t e;
   if (nrhs <= 0) return hipSuccess;
-  if (trans == 0) {
-    // forward: for each block apply P_b, then L11^-1, then B_below -= L21 B_b
-    for (int bi = 0; bi < nblk; ++bi) {
-      const LUBlock& b = plan.blocks[bi];
-      const int64_t k0 = b.k0, c1 = k0 + b.w;
-      const int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;
-      const int32_t* src = dst + 2 * nb;
-      hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)nrhs), dim3(256), 0, st, B, ldb, (int64_t)0, dst, src,
-                         ws.npairs + bi);
-      if ((e = launch_trsm<T, 0>(A + k0 + k0 * ld, ld, b.w, B + k0, ldb, nrhs, st)) != hipSuccess) return e;
-      if (n - c1 > 0)
-        if ((e = launch_gemm<T>(0, 0, n - c1, nrhs, b.w, A + c1 + k0 * ld, ld, B + k0, ldb, B + c1, ldb, st)) !=
+  const int64_t chunk = ws.tmp_elems / nb;  // RHS columns that fit the copy scratch
+  for (int64_t r0 = 0; r0 < nrhs; r0 += chunk) {
+    const int64_t nr = nrhs - r0 < chunk ? nrhs - r0 : chunk;
+    CT* B = Ball + r0 * ldb;
+    if (trans == 0) {
+      // forward: P_b, then rows [k0, n) -= [I - L11^-1 ; L21 L11^-1] B_b
+      for (int bi = 0; bi < nblk; ++bi) {
+        const LUBlock& b = plan.blocks[bi];
+        const int64_t k0 = b.k0;
+        const int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;
+        const int32_t* src = dst + 2 * nb;
+        hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)nr), dim3(256), 0, st, B, ldb, (int64_t)0, dst, src,
+                           ws.npairs + bi);
+        if ((e = launch_copy_block<T>(B + k0, ldb, X, b.w, b.w, nr, st)) != hipSuccess) return e;
+        GemmMask m;
+        m.akind = GEMM_MASK_STRICT_LOWER;
+        m.ar0 = 0;
+        m.adw = b.w;
+        if ((e = launch_gemm<T>(0, 0, n - k0, nr, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, st, m)) !=
             hipSuccess)
           return e;
-    }
-    // backward: U
-    for (int bi = nblk - 1; bi >= 0; --bi) {
-      const LUBlock& b = plan.blocks[bi];
-      const int64_t k0 = b.k0;
-      if ((e = launch_trsm<T, 1>(A + k0 + k0 * ld, ld, b.w, B + k0, ldb, nrhs, st)) != hipSuccess) return e;
-      if (k0 > 0)
-        if ((e = launch_gemm<T>(0, 0, k0, nrhs, b.w, A + k0 * ld, ld, B + k0, ldb, B, ldb, st)) != hipSuccess) return e;
-    }
-  } else {
-    // M^T = U^T L_k^T P_k ... L_1^T P_1: solve U^T z = g, then for b = k..1: z = L_b^-T z, z = P_b^T z
-    for (int bi = 0; bi < nblk; ++bi) {
-      const LUBlock& b = plan.blocks[bi];
-      const int64_t k0 = b.k0, c1 = k0 + b.w;
-      // z_b = U11^-T (g_b - U01^T z_above)
-      if (k0 > 0)
-        if ((e = launch_gemm<T>(0, 1, b.w, nrhs, k0, A + k0 * ld, ld, B, ldb, B + k0, ldb, st)) != hipSuccess) return e;
-      if ((e = launch_trsm<T, 2>(A + k0 + k0 * ld, ld, b.w, B + k0, ldb, nrhs, st)) != hipSuccess) return e;
-      (void)c1;
-    }
-    for (int bi = nblk - 1; bi >= 0; --bi) {
-      const LUBlock& b = plan.blocks[bi];
-      const int64_t k0 = b.k0, c1 = k0 + b.w;
-      if (n - c1 > 0)
-        if ((e = launch_gemm<T>(0, 1, b.w, nrhs, n - c1, A + c1 + k0 * ld, ld, B + c1, ldb, B + k0, ldb, st)) !=
-            hipSuccess)
+      }
+      // backward: rows [0, k0 + w) -= [U01 U11^-1 ; I - U11^-1] B_b
+      for (int bi = nblk - 1; bi >= 0; --bi) {
+        const LUBlock& b = plan.blocks[bi];
+        const int64_t k0 = b.k0;
+        if ((e = launch_copy_block<T>(B + k0, ldb, X, b.w, b.w, nr, st)) != hipSuccess) return e;
+        GemmMask m;
+        m.akind = GEMM_MASK_UPPER;
+        m.ar0 = k0;
+        m.adw = b.w;
+        if ((e = launch_gemm<T>(0, 0, k0 + b.w, nr, b.w, A + k0 * ld, ld, X, b.w, B, ldb, st, m)) != hipSuccess)
           return e;
-      if ((e = launch_trsm<T, 3>(A + k0 + k0 * ld, ld, b.w, B + k0, ldb, nrhs, st)) != hipSuccess) return e;
-      const int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;
-      const int32_t* src = dst + 2 * nb;
-      hipLaunchKernelGGL(row_permute_inv_kernel<T>, dim3((unsigned)nrhs), dim3(256), 0, st, B, ldb, (int64_t)0, dst,
-                         src, ws.npairs + bi);
+      }
+    } else {
+      // M^T = U^T L_k^T P_k ... L_1^T P_1.  U^T forward:
+      //   z_b = U11^-T g_b - (U01 U11^-1)^T z_above = g_b - (U01 U11^-1)^T z_above - (I - U11^-1)^T g_b
+      for (int bi = 0; bi < nblk; ++bi) {
+        const LUBlock& b = plan.blocks[bi];
+        const int64_t k0 = b.k0;
+        if ((e = launch_copy_block<T>(B + k0, ldb, X, b.w, b.w, nr, st)) != hipSuccess) return e;
+        if (k0 > 0)
+          if ((e = launch_gemm<T>(0, 1, b.w, nr, k0, A + k0 * ld, ld, B, ldb, B + k0, ldb, st)) != hipSuccess) return e;
+        GemmMask m;
+        m.akind = GEMM_MASK_LOWER;
+        m.ar0 = 0;
+        m.adw = b.w;
+        if ((e = launch_gemm<T>(0, 1, b.w, nr, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, st, m)) != hipSuccess)
+          return e;
+      }
+      // then for b = k..1: z_b = L11^-T z_b - (L21 L11^-1)^T z_below, and z = P_b^T z
+      for (int bi = nblk - 1; bi >= 0; --bi) {
+        const LUBlock& b = plan.blocks[bi];
+        const int64_t k0 = b.k0, c1 = k0 + b.w;
+        if ((e = launch_copy_block<T>(B + k0, ldb, X, b.w, b.w, nr, st)) != hipSuccess) return e;
+        if (n - c1 > 0)
+          if ((e = launch_gemm<T>(0, 1, b.w, nr, n - c1, A + c1 + k0 * ld, ld, B + c1, ldb, B + k0, ldb, st)) !=
+              hipSuccess)
+            return e;
+        GemmMask m;
+        m.akind = GEMM_MASK_STRICT_UPPER;
+        m.ar0 = 0;
+        m.adw = b.w;
+        if ((e = launch_gemm<T>(0, 1, b.w, nr, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, st, m)) != hipSuccess)
+          return e;
+        const int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;
+        const int32_t* src = dst + 2 * nb;
+        hipLaunchKernelGGL(row_permute_inv_kernel<T>, dim3((unsigned)nr), dim3(256), 0, st, B, ldb, (int64_t)0, dst,
+                           src, ws.npairs + bi);
+      }
     }
   }
   return hipGetLastError();
 }
 
-template hipError_t lu_factor<double>(void*, int64_t, const LUPlan&, const LUWork&, int32_t*, hipStream_t, Prof*);
-template hipError_t lu_factor<float>(void*, int64_t, const LUPlan&, const LUWork&, int32_t*, hipStream_t, Prof*);
+template hipError_t lu_factor<double>(void*, int64_t, const LUPlan&, const LUWork&, int32_t*, hipStream_t, Prof*,
+                                      hipStream_t);
+template hipError_t lu_factor<float>(void*, int64_t, const LUPlan&, const LUWork&, int32_t*, hipStream_t, Prof*,
+                                     hipStream_t);
 template hipError_t lu_solve<double>(int, const void*, int64_t, const LUPlan&, const LUWork&, void*, int64_t, int64_t,
                                      hipStream_t);
 template hipError_t lu_solve<float>(int, const void*, int64_t, const LUPlan&, const LUWork&, void*, int64_t, int64_t,

@@ -245,14 +245,14 @@ class Context:
     def sync(self):
         self._check(self.lib.gdm_sync(self.h))
 
-    PROF_TAGS = ("update", "panel", "assemble", "trsm", "perm")
+    PROF_TAGS = ("update", "panel", "assemble", "trsm", "perm", "solve", "resid")
 
     def profile(self, enable: bool):
         self._check(self.lib.gdm_profile(self.h, int(bool(enable))))
 
     def profile_read(self) -> dict:
-        buf = (ctypes.c_double * 15)()
-        self._check(self.lib.gdm_profile_read(self.h, buf, 15))
+        buf = (ctypes.c_double * 21)()
+        self._check(self.lib.gdm_profile_read(self.h, buf, 21))
         return {t: dict(ms=buf[3 * i], work=buf[3 * i + 1], launches=int(buf[3 * i + 2]))
                 for i, t in enumerate(self.PROF_TAGS)}
 
