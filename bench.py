@@ -30,6 +30,22 @@ PEAK_FP64_MFMA = 78.6    # TFLOP/s, MI355X dense FP64 matrix
 PEAK_HBM = 8000.0        # GB/s
 
 
+def update_gemm_traffic():
+    """HBM bytes per launch of the trailing-update GEMM from the committed
+    rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or None if the GEMM source has
+    changed since those counters were taken."""
+    import hashlib
+    here = os.path.dirname(os.path.abspath(__file__))
+    try:
+        rec = json.load(open(os.path.join(here, "profiles", "update_gemm_fp32_n12000_traffic.json")))
+        src = open(os.path.join(here, "paper_2505_09545_amd", "csrc", "gemm.hip"), "rb").read()
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("gemm_source_sha256"):
+        return None
+    return rec["bytes_per_launch"]
+
+
 def lu_solve_flops(n: int, nrhs: int) -> float:
     return 8.0 / 3.0 * n ** 3 + 8.0 * n * n * nrhs
 
@@ -65,6 +81,9 @@ def main() -> int:
     ap.add_argument("--cpu-sample-cells", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the plain FP64 path")
+    ap.add_argument("--copy-calib-mb", type=int, default=0,
+                    help="after the timed region, run one device copy of this many MiB (a known-size kernel "
+                         "for calibrating hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (got --gpus {args.gpus}); "
@@ -148,7 +167,7 @@ def main() -> int:
         "backward_err": be,
         **res,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_MFMA, "traffic": None,
+                     "frac": achieved / PEAK_FP32_MFMA, "traffic": update_gemm_traffic(),
                      "kernel": "cgemm_kernel<float,0,0,1> (LU trailing update)",
                      "launches_per_step": up["launches"] / args.steps,
                      "avg_launch_ms": up["ms"] / max(up["launches"], 1),
@@ -168,6 +187,17 @@ def main() -> int:
             if prof["resid"]["ms"] > 0 else None,
         },
     }
+    if args.copy_calib_mb > 0:
+        nbytes = args.copy_calib_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        flush = torch.empty(2 << 28, dtype=torch.float32, device=dev)  # 2 GiB: evicts the 256 MB last-level cache
+        flush.fill_(2.0)
+        del flush
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)  # elementwise copy kernel (16-byte vector loads and stores)
+        torch.cuda.synchronize()
+        line["copy_calib_bytes"] = nbytes
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample_cells)
     print(json.dumps(line), flush=True)

@@ -80,6 +80,9 @@ __global__ void init_err_kernel(int32_t* err) {
 // parity j%2 at column j+2, after every other workgroup has published its
 // column j+1 key, i.e. after they all finished reading column j.
 typedef unsigned long long u64;
+// each workgroup's key words get their own 128-byte line (no false sharing
+// between the atomic stores of different workgroups)
+constexpr int KEY_STRIDE = 16;
 
 __device__ inline void ll_put(u64* p, uint32_t epoch, uint32_t payload) {
   __hip_atomic_store(p, ((u64)epoch << 32) | payload, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -95,6 +98,30 @@ __device__ inline uint32_t ll_get(const u64* p, uint32_t epoch, int* bad) {
       return 0;
     }
   }
+}
+// Several words at once: all loads are in flight together (one round trip when
+// the data is already there); only words not yet carrying `epoch` are re-read.
+template <int K>
+__device__ inline void ll_get_n(const u64* const (&p)[K], uint32_t epoch, uint32_t (&out)[K], int* bad) {
+  u64 v[K];
+#pragma unroll
+  for (int i = 0; i < K; ++i) v[i] = __hip_atomic_load(p[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  uint32_t it = 0;
+  while (true) {
+    bool all = true;
+#pragma unroll
+    for (int i = 0; i < K; ++i) all = all && (uint32_t)(v[i] >> 32) == epoch;
+    if (all) break;
+    if (++it > SPIN_LIMIT) {
+      *bad = 1;
+      break;
+    }
+#pragma unroll
+    for (int i = 0; i < K; ++i)
+      if ((uint32_t)(v[i] >> 32) != epoch) v[i] = __hip_atomic_load(p[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+#pragma unroll
+  for (int i = 0; i < K; ++i) out[i] = (uint32_t)v[i];
 }
 
 // complex values travel as their 32-bit words (2 for complex float, 4 for
@@ -113,17 +140,42 @@ __device__ inline u64 pivot_key(const CT& v, uint32_t label) {
   return ((u64)__float_as_uint(a) << 32) | (0xffffffffu - label);
 }
 
-// Workgroup-wide argmax of (key, idx); one barrier.  Keys are unique (they end
-// with the row label), so only the key is reduced across lanes and the lane that
-// holds the winning key publishes its idx.  skey/sidx: LDS arrays (4 entries)
-// that the caller does not touch again before the next barrier.
-__device__ inline void block_argmax(u64& key, int& idx, u64* skey, int* sidx) {
-  u64 k = key;
+// Wave-wide max of a 64-bit key with DPP moves: xor-1 and xor-2 within quads,
+// then mirrors within 8 and 16 lanes leave every lane with the max of its row
+// of 16; the four row maxima are combined with readlane.
+template <int CTRL>
+__device__ inline u64 dpp_u64(u64 v) {
+  const int lo = __builtin_amdgcn_mov_dpp((int)(uint32_t)v, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(uint32_t)(v >> 32), CTRL, 0xf, 0xf, false);
+  return ((u64)(uint32_t)hi << 32) | (uint32_t)lo;
+}
+__device__ inline u64 wave_max_u64(u64 v) {
+  u64 o;
+  o = dpp_u64<0xb1>(v);  // quad_perm [1,0,3,2]
+  v = o > v ? o : v;
+  o = dpp_u64<0x4e>(v);  // quad_perm [2,3,0,1]
+  v = o > v ? o : v;
+  o = dpp_u64<0x141>(v);  // row_half_mirror
+  v = o > v ? o : v;
+  o = dpp_u64<0x140>(v);  // row_mirror
+  v = o > v ? o : v;
+  u64 r = 0;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const u64 o = shfl_xor_u64(k, off);
-    k = o > k ? o : k;
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 16 * q);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), 16 * q);
+    const u64 x = ((u64)hi << 32) | lo;
+    r = x > r ? x : r;
   }
+  return r;
+}
+
+// Workgroup-wide argmax of (key, idx); one barrier.  Keys are unique (they end
+// with the row label), so only the key is reduced and the lane holding the
+// winning key publishes its idx.  skey/sidx: LDS arrays (4 entries) that the
+// caller does not touch again before the next barrier.
+__device__ inline void block_argmax(u64& key, int& idx, u64* skey, int* sidx) {
+  const u64 k = wave_max_u64(key);
   const int wv = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) skey[wv] = k;
   if (key == k && k != 0) sidx[wv] = idx;
@@ -148,14 +200,15 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
   extern __shared__ unsigned char smem_raw[];
   CT* tile = reinterpret_cast<CT*>(smem_raw);           // [w][R], column c at tile + c*R
   CT* prow = tile + (size_t)w * R;                      // [w] pivot row
-  int32_t* lab = reinterpret_cast<int32_t*>(prow + w);  // [R] row labels (final positions)
+  CT* lst = prow + w;                                   // [R] multipliers of the current column
+  int32_t* lab = reinterpret_cast<int32_t*>(lst + R);   // [R] row labels (final positions)
+  int32_t* pl = lab + R;                                // [w] pivot positions of this panel
   __shared__ u64 skey1[4], skey2[4];
   __shared__ int sidx1[4], sidx2[4];
   __shared__ int bad;
   const int g = blockIdx.x, tid = threadIdx.x;
   const int64_t rbase = k0 + (int64_t)g * R;
   const int myR = (int)(n - rbase < (int64_t)R ? (n - rbase > 0 ? n - rbase : 0) : R);
-  const int WW = w * NW;  // payload words per row
   if (tid == 0) bad = 0;
   for (int c = 0; c < w; ++c)
     for (int lr = tid; lr < myR; lr += 256) tile[c * R + lr] = A[(rbase + lr) + (k0 + c) * ld];
@@ -176,72 +229,86 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
       brow = lr;
     }
   }
+  int zero_col = -1;
   for (int j = 0; j < w; ++j) {
     const int64_t gj = k0 + j;
     const uint32_t E = epoch0 + (uint32_t)j;
     const int par = j & 1;
-    u64* cand = ws.cand + (size_t)par * ws.gmax * 2;
+    u64* cand = ws.cand + (size_t)par * ws.gmax * KEY_STRIDE;
     u64* rows = ws.rows + (size_t)par * ws.gmax * ws.wwmax;
     // workgroup candidate over its active rows (labels >= gj); the tile is final
     block_argmax(best, brow, skey1, sidx1);
     const u64 mybest = best;
     const int lrow = best ? brow : -1;
-    // publish key (value, label) and the candidate row
+    // the multipliers of the previous column enter the tile now (nobody reads
+    // column j - 1 of the tile again inside the panel)
+    if (j > 0)
+      for (int lr = tid; lr < myR; lr += 256)
+        if (lab[lr] > (int32_t)(gj - 1)) tile[(j - 1) * R + lr] = lst[lr];
+    // publish key (value, label) and columns j.. of the candidate row
     if (tid == 0) {
-      ll_put(&cand[2 * g + 0], E, mybest ? (uint32_t)(mybest >> 32) : 0u);
-      ll_put(&cand[2 * g + 1], E, mybest ? (0xffffffffu - (uint32_t)(mybest & 0xffffffffu)) : 0xffffffffu);
+      ll_put(&cand[KEY_STRIDE * g + 0], E, mybest ? (uint32_t)(mybest >> 32) : 0u);
+      ll_put(&cand[KEY_STRIDE * g + 1], E, mybest ? (0xffffffffu - (uint32_t)(mybest & 0xffffffffu)) : 0xffffffffu);
     }
+    const int WW = (w - j) * NW;  // payload words still needed by the others
     if (lrow >= 0)
       for (int t = tid; t < WW; t += 256)
-        ll_put(&rows[(size_t)g * ws.wwmax + t], E, cword(tile[(t / NW) * R + lrow], t % NW));
+        ll_put(&rows[(size_t)g * ws.wwmax + t], E, cword(tile[(j + t / NW) * R + lrow], t % NW));
     // gather all keys; winner = largest |re|+|im|, lowest label on ties
     u64 k = 0;
     int owner = -1;
     if (tid < G) {
-      const uint32_t val = ll_get(&cand[2 * tid + 0], E, &bad);
-      const uint32_t label = ll_get(&cand[2 * tid + 1], E, &bad);
-      k = ((u64)val << 32) | (0xffffffffu - label);
+      const u64* const pk[2] = {&cand[KEY_STRIDE * tid + 0], &cand[KEY_STRIDE * tid + 1]};
+      uint32_t vk[2];
+      ll_get_n<2>(pk, E, vk, &bad);
+      k = ((u64)vk[0] << 32) | (0xffffffffu - vk[1]);
       owner = tid;
     }
     block_argmax(k, owner, skey2, sidx2);
     const int gp = owner;
     const uint32_t plabel = 0xffffffffu - (uint32_t)(k & 0xffffffffu);
-    // pivot row
-    if (gp >= 0)
-      for (int t = tid; t < WW; t += 256)
-        reinterpret_cast<uint32_t*>(prow)[t] = ll_get(&rows[(size_t)gp * ws.wwmax + t], E, &bad);
+    // pivot row, columns j..
+    if (gp >= 0) {
+      const u64* src = rows + (size_t)gp * ws.wwmax;
+      uint32_t* dstw = reinterpret_cast<uint32_t*>(prow + j);
+      int t = tid;
+      for (; t + 256 < WW; t += 512) {
+        const u64* const pw[2] = {src + t, src + t + 256};
+        uint32_t vw[2];
+        ll_get_n<2>(pw, E, vw, &bad);
+        dstw[t] = vw[0];
+        dstw[t + 256] = vw[1];
+      }
+      if (t < WW) dstw[t] = ll_get(src + t, E, &bad);
+    }
+    // interchange of positions gj <-> plabel: swap labels (each row by one thread)
+    if (plabel != (uint32_t)gj) {
+      for (int lr = tid; lr < myR; lr += 256) {
+        const int32_t lb = lab[lr];
+        if (lb == (int32_t)gj) lab[lr] = (int32_t)plabel;
+        else if (g == gp && lr == lrow) lab[lr] = (int32_t)gj;
+      }
+    }
+    if (tid == 0) pl[j] = (int32_t)plabel;
     __syncthreads();
     if (bad || gp < 0) {
       if (tid == 0) __hip_atomic_store(&ws.err[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       return;
     }
-    if (g == 0 && tid == 0) ipiv[gj] = (int32_t)plabel;
     const CT piv = prow[j];
     const bool zero = piv.x == 0 && piv.y == 0;
-    if (zero && g == 0 && tid == 0) atomicMin(&ws.err[1], (int)gj);
+    if (zero && zero_col < 0) zero_col = j;
     CT inv;
     if (zero) { inv.x = 0; inv.y = 0; } else inv = cinv_t(piv);
-    // interchange of positions gj <-> plabel (label swap), then the multipliers
-    // of the rows below (labels > gj); each row is handled by one thread
-    for (int lr = tid; lr < myR; lr += 256) {
-      int32_t lb = lab[lr];
-      if (plabel != (uint32_t)gj) {
-        if (lb == (int32_t)gj) lb = (int32_t)plabel;
-        else if (g == gp && lr == lrow) lb = (int32_t)gj;
-        lab[lr] = lb;
-      }
-      if (lb > (int32_t)gj) tile[j * R + lr] = cmul_t(tile[j * R + lr], inv);
-    }
-    __syncthreads();
-    // rank-1 update, and the candidate of column j + 1 on the fly: the threads of
-    // column group 0 own column j + 1; the remaining columns are updated with
-    // independent (unrolled) LDS read-modify-writes
+    // rank-1 update of the rows below (labels > gj) with multipliers computed on
+    // the fly; column group 0 owns column j + 1 and its pivot candidate
     best = 0;
     brow = -1;
     for (int lr = ulr0; lr < myR; lr += RP) {
       const int32_t lb = lab[lr];
       if (lb <= (int32_t)gj) continue;
-      const CT l = tile[j * R + lr];
+      const CT l = cmul_t(tile[j * R + lr], inv);
+      if (ucg == 0) lst[lr] = l;
       int c = j + 1 + ucg;
       if (ucg == 0 && c < w) {
         const CT u = prow[c];
@@ -268,6 +335,13 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
     // (the barrier inside the next block_argmax orders the update before any read)
   }
   __syncthreads();
+  for (int lr = tid; lr < myR; lr += 256)
+    if (lab[lr] > (int32_t)(k0 + w - 1)) tile[(w - 1) * R + lr] = lst[lr];
+  __syncthreads();
+  if (g == 0) {
+    for (int j = tid; j < w; j += 256) ipiv[k0 + j] = pl[j];
+    if (tid == 0 && zero_col >= 0) atomicMin(&ws.err[1], (int)(k0 + zero_col));
+  }
   for (int c = 0; c < w; ++c)
     for (int lr = tid; lr < myR; lr += 256) A[lab[lr] + (k0 + c) * ld] = tile[c * R + lr];
 }
@@ -565,6 +639,11 @@ static hipError_t launch_block_inv(const cplx<T>* A, int64_t ld, int64_t n, int 
 // ---------------------------------------------------------------------------
 static const int LDS_RESERVE = 2048;
 
+// dynamic LDS of a panel workgroup: tile, pivot row, multipliers, labels, pivots
+static size_t panel_lds_bytes(int w, int R, size_t cbytes) {
+  return ((size_t)w * R + w + R) * cbytes + (size_t)(R + w) * 4;
+}
+
 LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes) {
   LUPlan p;
   p.n = n;
@@ -574,7 +653,7 @@ LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes) {
   // the panel must fit: ceil(n / num_cu) rows x nb columns in LDS
   while (nb > 16) {
     const int64_t R = (n + num_cu - 1) / num_cu;
-    if ((int64_t)(R + 1) * nb * cbytes + 4 * R + LDS_RESERVE <= lds_bytes) break;
+    if ((int64_t)panel_lds_bytes(nb, (int)R, cbytes) + LDS_RESERVE <= lds_bytes) break;
     nb /= 2;
   }
   p.nb = nb;
@@ -585,7 +664,7 @@ LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes) {
     const int64_t m = n - k0;
     int64_t R = (m + num_cu - 1) / num_cu;
     if (R < 32) R = 32;
-    const int64_t Rmax = (lds_bytes - LDS_RESERVE - (int64_t)b.w * cbytes) / ((int64_t)b.w * cbytes + 4);
+    const int64_t Rmax = (lds_bytes - LDS_RESERVE - (int64_t)b.w * (cbytes + 4)) / ((int64_t)(b.w + 1) * cbytes + 4);
     if (R > Rmax) R = Rmax;
     b.R = (int)R;
     b.G = (int)((m + R - 1) / R);
@@ -598,7 +677,7 @@ size_t lu_workspace_bytes(const LUPlan& p, int elem_bytes, int num_cu) {
   const size_t nb = (size_t)p.nb, nblk = p.blocks.size();
   const size_t ww = nb * (2 * (size_t)elem_bytes / 4);
   size_t s = 0;
-  s += 2 * (size_t)num_cu * 2 * 8 + 256;
+  s += 2 * (size_t)num_cu * KEY_STRIDE * 8 + 256;
   s += 2 * (size_t)num_cu * ww * 8 + 256;
   s += 2 * ww * 8 + 256;
   s += 64 + 256;
@@ -621,7 +700,7 @@ void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu,
   };
   w.gmax = num_cu;
   w.wwmax = (int)ww;
-  w.cand = reinterpret_cast<unsigned long long*>(take(2 * (size_t)num_cu * 2 * 8));
+  w.cand = reinterpret_cast<unsigned long long*>(take(2 * (size_t)num_cu * KEY_STRIDE * 8));
   w.rows = reinterpret_cast<unsigned long long*>(take(2 * (size_t)num_cu * ww * 8));
   w.drow = reinterpret_cast<unsigned long long*>(take(2 * ww * 8));
   w.err = reinterpret_cast<int32_t*>(take(64));
@@ -652,15 +731,16 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
   // exchange buffers start from zero (epoch 0 is never used), so epochs 1, 2, ...
   // of this factorisation are unique
   {
-    const size_t nc = (size_t)ws.gmax * 4, nr = (size_t)2 * ws.gmax * ws.wwmax, nd = (size_t)2 * ws.wwmax;
-    hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, st, ws.cand, nc, ws.rows, nr,
+    const size_t nc = (size_t)ws.gmax * 2 * KEY_STRIDE, nr = (size_t)2 * ws.gmax * ws.wwmax, nd = (size_t)2 * ws.wwmax;
+    const size_t nmax = std::max(nc, std::max(nr, nd));
+    hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)((nmax + 255) / 256)), dim3(256), 0, st, ws.cand, nc, ws.rows, nr,
                        ws.drow, nd);
   }
   uint32_t epoch = 1;
   // panels may need more than the default 64 KB of dynamic LDS
   size_t lds_need = 0;
   for (const LUBlock& b : plan.blocks)
-    lds_need = std::max(lds_need, ((size_t)b.w * b.R + b.w) * sizeof(CT) + (size_t)b.R * 4);
+    lds_need = std::max(lds_need, panel_lds_bytes(b.w, b.R, sizeof(CT)));
   static size_t lds_set[2] = {0, 0};
   size_t& cur = lds_set[sizeof(T) == 8 ? 0 : 1];
   if (lds_need > 64 * 1024 && lds_need > cur) {
@@ -708,7 +788,7 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
       cleanup();
       return hipErrorInvalidValue;
     }
-    const size_t lds = ((size_t)w * b.R + w) * sizeof(CT) + (size_t)b.R * 4;
+    const size_t lds = panel_lds_bytes(w, b.R, sizeof(CT));
     LUCHK(P.begin(st, PROF_PANEL, (double)w));
     hipLaunchKernelGGL(panel_kernel<T>, dim3(b.G), dim3(256), lds, st, A, ld, n, k0, w, b.R, b.G, ipiv, ws, epoch);
     epoch += (uint32_t)w;
