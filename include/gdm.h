@@ -140,6 +140,33 @@ gdm_status gdm_fields(gdm_ctx* ctx, int64_t n_rhs, const double* q, int64_t n_pr
 gdm_status gdm_cross_sections(gdm_ctx* ctx, int64_t n_rhs, const double* f0, const double* q, const double* f,
                               const double* e0_norm2, int32_t want_ff, double* out);
 
+/* Reverse mode (the paper differentiates the solver with automatic
+ * differentiation, Sec. "Example: Autograd for resonance search"; here the
+ * adjoint is written out).  For a real loss L that depends on the cross sections
+ * of the last solve and on the TOTAL electric field at probe points, given
+ *   g_sigma [n_rhs][3] : dL/d(extinction, scattering, absorption) per RHS (real;
+ *                        the cross sections of gdm_cross_sections, columns 0-2),
+ *                        may be NULL (no cross-section term);
+ *   g_e [n_rhs][n_probe][3] complex : Wirtinger partial dL/dE of the total field
+ *                        E = E_inc + E_sca at r_probe [n_probe][3] (so that
+ *                        dL = 2 Re sum g_e dE), may be NULL (no field term),
+ * writes dL/d(every dipole position) grad_r [N][3] (cells then effective
+ * dipoles), dL/d(Re eps, Im eps) of every cell grad_eps [n_cell][2], and
+ * dL/d(wavelength) grad_wl [1] (through k0 in the dyad, the plane waves, the
+ * radiative self-term if selected and the cross-section prefactors; the cell
+ * permittivities and the effective polarisabilities are held fixed).  All
+ * arrays are device pointers.  The illumination must be the plane waves khat
+ * [n_rhs][3], e0 [n_rhs][3] complex, and f0, q, f [n_rhs][n] the incident field,
+ * moments and solved field of the last gdm_solve with the current factors,
+ * which are reused for the transposed solve M^T lam = g_F + A^T g_q (FP32
+ * factors: FP64 refinement of the transposed system to tol / max_iter as in
+ * gdm_solve).  GDM_E_STATE without factors; GDM_E_PROBE_AT_DIPOLE as in
+ * gdm_fields; GDM_E_NOCONV if the refinement stalls (gradients still written). */
+gdm_status gdm_adjoint(gdm_ctx* ctx, int64_t n_rhs, const double* khat, const double* e0, const double* f0,
+                       const double* q, const double* f, const double* g_sigma, int64_t n_probe,
+                       const double* r_probe, const double* g_e, double tol, int32_t max_iter, double* grad_r,
+                       double* grad_eps, double* grad_wl, gdm_info* info);
+
 /* Dense LU of a caller matrix (dtype 0: complex double, 1: complex float),
  * column-major n x n, leading dimension lda, factored in place; ipiv [n]
  * receives 0-based pivot rows.  The factors are in the library's factored form
@@ -164,12 +191,15 @@ gdm_status gdm_sync(gdm_ctx* ctx);
  * clears the counters and starts recording; 0 stops. */
 gdm_status gdm_profile(gdm_ctx* ctx, int enable);
 /* Counters accumulated since gdm_profile(ctx, 1), written to the HOST array
- * out (n_out >= 21): out[3 t + 0..2] = (milliseconds, work, launches) for
+ * out (n_out >= 30): out[3 t + 0..2] = (milliseconds, work, launches) for
  * t = 0 LU trailing-update GEMM (work = real flops 8 m n k), 1 LU panel (work =
  * columns), 2 assembly (work = bytes written), 3 block triangular solve of the
  * factorisation (work = real flops), 4 row permutation of the trailing columns,
- * 5 forward + backward substitution of gdm_solve (work = 8 n^2 n_rhs),
- * 6 FP64 refinement residual (work = 8 n^2 n_rhs). */
+ * 5 forward + backward substitution of gdm_solve / gdm_adjoint (work =
+ * 8 n^2 n_rhs), 6 FP64 refinement residual (work = 8 n^2 n_rhs), 7 adjoint
+ * dipole-pair kernel (work = ordered pairs x n_rhs), 8 adjoint probe kernel
+ * (work = probe-dipole pairs x n_rhs), 9 probe fields (work = probe-dipole
+ * pairs x n_rhs). */
 gdm_status gdm_profile_read(gdm_ctx* ctx, double* out, int32_t n_out);
 
 #ifdef __cplusplus

@@ -11,6 +11,7 @@
 #include "gdm_common.hpp"
 #include "gdm_kernels.hpp"
 #include "gdm_misc.hpp"
+#include "gdm_adjoint.hpp"
 
 using namespace gdm;
 
@@ -74,12 +75,14 @@ struct gdm_ctx {
   LUPlan plan;
   int64_t ld = 0;
   double Minf = 0.0;
+  double M1 = -1.0;  // 1-norm of the FP64 matrix, computed on first transposed refinement
   // standalone getrf state
   LUPlan ext_plan;
   int ext_dtype = -1;
   DevBuf ext_ws;
   // solve / fields scratch
   DevBuf X, Rr, C32, small, scratch, flag;
+  DevBuf Lam, adj;  // adjoint field and adjoint workspace
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   float ms_assemble = 0, ms_factor = 0;
   Prof prof;
@@ -173,6 +176,110 @@ static gdm_status run_lu(gdm_ctx* c, void* A, int64_t n, int64_t ld, LUPlan& pla
 }
 
 
+struct SolveStats {
+  int iters = 0;
+  double be = 0.0;
+  double tol = 0.0;
+  float ms_ir = 0.f;
+};
+
+// X = op(M)^{-1} B for nrhs columns (op = M for trans 0, M^T for trans 1) with
+// the context's factors.  FP64 factors: one solve.  FP32 factors: FP64
+// iterative refinement on the stored FP64 matrix until the normwise backward
+// error |r|_inf / (|op(M)|_inf |x|_inf + |b|_inf) of every column is <= tol, or
+// stagnation, or max_iter corrections (GDM_E_NOCONV, best iterate kept in X).
+static gdm_status solve_core(gdm_ctx* c, int trans, int64_t nrhs, const double2* B, double2* X, double tol,
+                             int32_t max_iter, SolveStats& ss) {
+  const int64_t n = c->n;
+  LUWork w;
+  const int eb = c->prec == GDM_PREC_FP64 ? 8 : 4;
+  lu_workspace_carve(c->luws.p, c->plan, eb, c->num_cu, w);
+  const double solve_flops = 8.0 * (double)n * (double)n * (double)nrhs;
+  gdm_status status = GDM_OK;
+  if (c->prec == GDM_PREC_FP64) {
+    HIPCHK(c, launch_copy_d(B, n, X, n, n, nrhs, c->stream));
+    HIPCHK(c, c->prof.begin(c->stream, PROF_SOLVE, solve_flops));
+    HIPCHK(c, lu_solve<double>(trans, c->M.p, c->ld, c->plan, w, X, n, nrhs, c->stream));
+    HIPCHK(c, c->prof.end(c->stream));
+    return GDM_OK;
+  }
+  if (tol <= 0) tol = 1e-14;
+  if (max_iter < 0) max_iter = 10;
+  ss.tol = tol;
+  double Mnorm = c->Minf;
+  if (trans) {
+    if (c->M1 < 0) {
+      HIPCHK(c, c->rows.ensure(sizeof(double) * n));
+      HIPCHK(c, launch_colsum_abs(c->M64.as<double2>(), n, n, c->rows.as<double>(), c->stream));
+      std::vector<double> cols(n);
+      HIPCHK(c, hipMemcpyAsync(cols.data(), c->rows.p, sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      c->M1 = *std::max_element(cols.begin(), cols.end());
+    }
+    Mnorm = c->M1;
+  }
+  HIPCHK(c, c->Rr.ensure(sizeof(double2) * n * nrhs));
+  HIPCHK(c, c->C32.ensure(sizeof(float2) * n * nrhs));
+  HIPCHK(c, c->small.ensure(sizeof(double) * 4 * nrhs));
+  double2* Rr = c->Rr.as<double2>();
+  float2* C32 = c->C32.as<float2>();
+  double* sm = c->small.as<double>();  // [0..nrhs): |r|, [nrhs..2nrhs): |x|, [2nrhs..): |b|, [3nrhs..): |c|
+  // first solve from B in FP32
+  HIPCHK(c, launch_convert_d2f(B, n, C32, n, n, nrhs, c->stream));
+  HIPCHK(c, c->prof.begin(c->stream, PROF_SOLVE, solve_flops));
+  HIPCHK(c, lu_solve<float>(trans, c->M.p, c->ld, c->plan, w, C32, n, nrhs, c->stream));
+  HIPCHK(c, c->prof.end(c->stream));
+  HIPCHK(c, launch_convert_f2d(C32, n, X, n, n, nrhs, c->stream));
+  HIPCHK(c, launch_colmax(B, n, n, nrhs, sm + 2 * nrhs, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
+  std::vector<double> h(4 * nrhs);
+  std::vector<double> prev_c(nrhs, INFINITY);
+  for (int it = 0;; ++it) {
+    // r = b - op(M) x  (FP64, stored FP64 matrix)
+    HIPCHK(c, launch_copy_d(B, n, Rr, n, n, nrhs, c->stream));
+    HIPCHK(c, c->prof.begin(c->stream, PROF_RESID, solve_flops));
+    HIPCHK(c, launch_gemm<double>(0, trans, n, nrhs, n, c->M64.p, n, X, n, Rr, n, c->stream));
+    HIPCHK(c, c->prof.end(c->stream));
+    HIPCHK(c, launch_colmax(Rr, n, n, nrhs, sm, c->stream));
+    HIPCHK(c, launch_colmax(X, n, n, nrhs, sm + nrhs, c->stream));
+    HIPCHK(c, hipMemcpyAsync(h.data(), sm, sizeof(double) * 4 * nrhs, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    double be_max = 0.0;
+    for (int64_t r = 0; r < nrhs; ++r) {
+      const double den = Mnorm * h[nrhs + r] + h[2 * nrhs + r];
+      const double be = den > 0 ? h[r] / den : 0.0;
+      be_max = std::max(be_max, be);
+    }
+    ss.be = be_max;
+    if (be_max <= tol) break;
+    if (it >= max_iter) {
+      status = GDM_E_NOCONV;
+      break;
+    }
+    if (it > 0) {
+      bool stagnated = true;
+      for (int64_t r = 0; r < nrhs; ++r)
+        if (!(h[3 * nrhs + r] > 0.5 * prev_c[r])) stagnated = false;
+      if (stagnated) {
+        status = GDM_E_NOCONV;
+        break;
+      }
+      for (int64_t r = 0; r < nrhs; ++r) prev_c[r] = h[3 * nrhs + r];
+    }
+    HIPCHK(c, launch_convert_d2f(Rr, n, C32, n, n, nrhs, c->stream));
+    HIPCHK(c, c->prof.begin(c->stream, PROF_SOLVE, solve_flops));
+    HIPCHK(c, lu_solve<float>(trans, c->M.p, c->ld, c->plan, w, C32, n, nrhs, c->stream));
+    HIPCHK(c, c->prof.end(c->stream));
+    HIPCHK(c, launch_axpy_f2d(C32, n, X, n, n, nrhs, sm + 3 * nrhs, c->stream));
+    ++ss.iters;
+  }
+  HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
+  HIPCHK(c, hipEventSynchronize(c->ev[2]));
+  (void)hipEventElapsedTime(&ss.ms_ir, c->ev[1], c->ev[2]);
+  return status;
+}
+
+
 extern "C" {
 
 gdm_status gdm_create(int device, void* hip_stream, gdm_ctx** out) {
@@ -211,7 +318,7 @@ void gdm_destroy(gdm_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (DevBuf* b : {&c->pos, &c->eps, &c->alpha_c, &c->alpha6, &c->M, &c->M64, &c->ipiv, &c->luws, &c->rows,
-                    &c->ext_ws, &c->X, &c->Rr, &c->C32, &c->small, &c->scratch, &c->flag})
+                    &c->ext_ws, &c->X, &c->Rr, &c->C32, &c->small, &c->scratch, &c->flag, &c->Lam, &c->adj})
     b->release();
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
@@ -346,6 +453,7 @@ gdm_status gdm_factorize(gdm_ctx* c, double wl, gdm_precision prec, gdm_info* in
   }
   c->wavelength = wl;
   c->prec = prec;
+  c->M1 = -1.0;
   c->factored = true;
   return GDM_OK;
 }
@@ -385,101 +493,119 @@ gdm_status gdm_solve(gdm_ctx* c, int64_t nrhs, const double* f0, double tol, int
   if (nrhs > 65535) FAIL(c, GDM_E_ARG, "at most 65535 right-hand sides per call");
   HIPCHK(c, hipSetDevice(c->device));
   const int64_t n = c->n;
-  const double2* F0 = reinterpret_cast<const double2*>(f0);
   HIPCHK(c, c->X.ensure(sizeof(double2) * n * nrhs));
   double2* X = c->X.as<double2>();
   const DipoleView d = view_of(c, make_double2(0, 0));
   HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
-  LUWork w;
-  const int eb = c->prec == GDM_PREC_FP64 ? 8 : 4;
-  lu_workspace_carve(c->luws.p, c->plan, eb, c->num_cu, w);
-  int iters = 0;
-  double be_max = 0.0;
-  gdm_status status = GDM_OK;
-  float ms_ir = 0.f;
-  const double solve_flops = 8.0 * (double)n * (double)n * (double)nrhs;
-  if (c->prec == GDM_PREC_FP64) {
-    HIPCHK(c, launch_copy_d(F0, n, X, n, n, nrhs, c->stream));
-    HIPCHK(c, c->prof.begin(c->stream, PROF_SOLVE, solve_flops));
-    HIPCHK(c, lu_solve<double>(0, c->M.p, c->ld, c->plan, w, X, n, nrhs, c->stream));
-    HIPCHK(c, c->prof.end(c->stream));
-  } else {
-    if (tol <= 0) tol = 1e-14;
-    if (max_iter < 0) max_iter = 10;
-    HIPCHK(c, c->Rr.ensure(sizeof(double2) * n * nrhs));
-    HIPCHK(c, c->C32.ensure(sizeof(float2) * n * nrhs));
-    HIPCHK(c, c->small.ensure(sizeof(double) * 4 * nrhs));
-    double2* Rr = c->Rr.as<double2>();
-    float2* C32 = c->C32.as<float2>();
-    double* sm = c->small.as<double>();  // [0..nrhs): |r|, [nrhs..2nrhs): |x|, [2nrhs..): |F0|, [3nrhs..): |c|
-    // first solve from F0 in FP32
-    HIPCHK(c, launch_convert_d2f(F0, n, C32, n, n, nrhs, c->stream));
-    HIPCHK(c, c->prof.begin(c->stream, PROF_SOLVE, solve_flops));
-    HIPCHK(c, lu_solve<float>(0, c->M.p, c->ld, c->plan, w, C32, n, nrhs, c->stream));
-    HIPCHK(c, c->prof.end(c->stream));
-    HIPCHK(c, launch_convert_f2d(C32, n, X, n, n, nrhs, c->stream));
-    HIPCHK(c, launch_colmax(F0, n, n, nrhs, sm + 2 * nrhs, c->stream));
-    HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
-    std::vector<double> h(4 * nrhs);
-    std::vector<double> prev_c(nrhs, INFINITY);
-    for (int it = 0;; ++it) {
-      // r = F0 - M x  (FP64, stored FP64 matrix)
-      HIPCHK(c, launch_copy_d(F0, n, Rr, n, n, nrhs, c->stream));
-      HIPCHK(c, c->prof.begin(c->stream, PROF_RESID, solve_flops));
-      HIPCHK(c, launch_gemm<double>(0, 0, n, nrhs, n, c->M64.p, n, X, n, Rr, n, c->stream));
-      HIPCHK(c, c->prof.end(c->stream));
-      HIPCHK(c, launch_colmax(Rr, n, n, nrhs, sm, c->stream));
-      HIPCHK(c, launch_colmax(X, n, n, nrhs, sm + nrhs, c->stream));
-      HIPCHK(c, hipMemcpyAsync(h.data(), sm, sizeof(double) * 4 * nrhs, hipMemcpyDeviceToHost, c->stream));
-      HIPCHK(c, hipStreamSynchronize(c->stream));
-      be_max = 0.0;
-      for (int64_t r = 0; r < nrhs; ++r) {
-        const double den = c->Minf * h[nrhs + r] + h[2 * nrhs + r];
-        const double be = den > 0 ? h[r] / den : 0.0;
-        be_max = std::max(be_max, be);
-      }
-      if (be_max <= tol) break;
-      if (it >= max_iter) {
-        status = GDM_E_NOCONV;
-        break;
-      }
-      if (it > 0) {
-        bool stagnated = true;
-        for (int64_t r = 0; r < nrhs; ++r)
-          if (!(h[3 * nrhs + r] > 0.5 * prev_c[r])) stagnated = false;
-        if (stagnated) {
-          status = GDM_E_NOCONV;
-          break;
-        }
-        for (int64_t r = 0; r < nrhs; ++r) prev_c[r] = h[3 * nrhs + r];
-      }
-      HIPCHK(c, launch_convert_d2f(Rr, n, C32, n, n, nrhs, c->stream));
-      HIPCHK(c, c->prof.begin(c->stream, PROF_SOLVE, solve_flops));
-      HIPCHK(c, lu_solve<float>(0, c->M.p, c->ld, c->plan, w, C32, n, nrhs, c->stream));
-      HIPCHK(c, c->prof.end(c->stream));
-      HIPCHK(c, launch_axpy_f2d(C32, n, X, n, n, nrhs, sm + 3 * nrhs, c->stream));
-      ++iters;
-    }
-    HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
-  }
+  SolveStats ss;
+  gdm_status status = solve_core(c, 0, nrhs, reinterpret_cast<const double2*>(f0), X, tol, max_iter, ss);
+  if (status != GDM_OK && status != GDM_E_NOCONV) return status;
   HIPCHK(c, launch_apply_alpha(d, X, n, reinterpret_cast<double2*>(q_out), n, nrhs, c->stream));
   if (f_out) HIPCHK(c, launch_copy_d(X, n, reinterpret_cast<double2*>(f_out), n, n, nrhs, c->stream));
   HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
   HIPCHK(c, hipEventSynchronize(c->ev[3]));
   float ms_total = 0.f;
   (void)hipEventElapsedTime(&ms_total, c->ev[0], c->ev[3]);
-  if (c->prec == GDM_PREC_FP32_IR) (void)hipEventElapsedTime(&ms_ir, c->ev[1], c->ev[2]);
   c->prof.collect();
   if (info) {
-    info->ir_iters = iters;
-    info->backward_err = be_max;
+    info->ir_iters = ss.iters;
+    info->backward_err = ss.be;
     info->bad_index = -1;
     info->ms_assemble = c->ms_assemble;
     info->ms_factor = c->ms_factor;
-    info->ms_solve = ms_total - ms_ir;
-    info->ms_ir = ms_ir;
+    info->ms_solve = ms_total - ss.ms_ir;
+    info->ms_ir = ss.ms_ir;
   }
-  if (status == GDM_E_NOCONV) FAIL(c, GDM_E_NOCONV, "refinement stopped at backward error %.3e > tol %.3e", be_max, tol);
+  if (status == GDM_E_NOCONV)
+    FAIL(c, GDM_E_NOCONV, "refinement stopped at backward error %.3e > tol %.3e", ss.be, ss.tol);
+  return GDM_OK;
+}
+
+gdm_status gdm_adjoint(gdm_ctx* c, int64_t nrhs, const double* khat, const double* e0, const double* f0,
+                       const double* q, const double* f, const double* g_sigma, int64_t P, const double* r_probe,
+                       const double* g_e, double tol, int32_t max_iter, double* grad_r, double* grad_eps,
+                       double* grad_wl, gdm_info* info) {
+  if (!c) return GDM_E_ARG;
+  if (!c->factored) FAIL(c, GDM_E_STATE, "gdm_adjoint needs the factors of gdm_factorize");
+  if (nrhs <= 0 || nrhs > 65535) FAIL(c, GDM_E_ARG, "need 0 < n_rhs <= 65535");
+  if (!khat || !e0 || !f0 || !q || !f) FAIL(c, GDM_E_ARG, "khat, e0, f0, q and f are required");
+  if (!grad_r || !grad_wl || (c->nc > 0 && !grad_eps)) FAIL(c, GDM_E_ARG, "grad_r, grad_eps and grad_wl are required");
+  if (P < 0 || (P > 0 && g_e && !r_probe)) FAIL(c, GDM_E_ARG, "bad probe arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int64_t n = c->n, N = c->N, nc = c->nc;
+  const bool probes = P > 0 && g_e;
+  const Wave w = wave_of(c, c->wavelength);
+  const DipoleView d = view_of(c, self_term(c, w));
+  const double2* F0 = reinterpret_cast<const double2*>(f0);
+  const double2* Fs = reinterpret_cast<const double2*>(f);
+  const double2* Q = reinterpret_cast<const double2*>(q);
+  const double2* E0 = reinterpret_cast<const double2*>(e0);
+  const double2* gE = reinterpret_cast<const double2*>(g_e);
+  // workspace layout (doubles): Cr | sums5 | pdk parts | pgr probe | pgr pair | then complex arrays
+  const int nz = adjoint_rhs_chunks(nrhs);
+  const int sp = probes ? adjoint_probe_splits(P, N, c->num_cu) : 0;
+  const int sq = adjoint_pair_splits(N, c->num_cu);
+  const int64_t nb_probe = probes ? (int64_t)nz * sp * adjoint_probe_blocks(N) : 0;
+  const int64_t nb_pair = (int64_t)nz * sq * adjoint_pair_blocks(N);
+  const int64_t nb_fin = adjoint_finish_blocks(N);
+  const int64_t nb_einc = probes ? adjoint_einc_blocks(P, nrhs) : 0;
+  const int64_t nparts = nb_probe + nb_pair + nb_fin + nb_einc;
+  const int64_t nd = 6 * nrhs + nparts + 3 * N * ((int64_t)nz * sp + (int64_t)nz * sq);
+  const int64_t ndp = (nd + 1) / 2;  // in double2 units
+  const int64_t nzz = (int64_t)sp * nrhs * n + (int64_t)sq * nrhs * std::max<int64_t>(nc, 1) * 3 + 2 * nrhs * n;
+  HIPCHK(c, c->adj.ensure(sizeof(double2) * (ndp + nzz)));
+  HIPCHK(c, c->Lam.ensure(sizeof(double2) * n * nrhs));
+  HIPCHK(c, c->flag.ensure(sizeof(int) * 4));
+  double* Cr = c->adj.as<double>();
+  double* sums5 = Cr + nrhs;
+  double* parts = sums5 + 5 * nrhs;
+  double* pdk_probe = parts;
+  double* pdk_pair = pdk_probe + nb_probe;
+  double* pdk_fin = pdk_pair + nb_pair;
+  double* pdk_einc = pdk_fin + nb_fin;
+  double* pgr_probe = parts + nparts;
+  double* pgr_pair = pgr_probe + 3 * N * (int64_t)nz * sp;
+  double2* zb = c->adj.as<double2>() + ndp;
+  double2* pacc = zb;
+  double2* pv = pacc + (int64_t)sp * nrhs * n;
+  double2* gqe = pv + (int64_t)sq * nrhs * std::max<int64_t>(nc, 1) * 3;
+  double2* rhs = gqe + nrhs * n;
+  double2* lam = c->Lam.as<double2>();
+
+  HIPCHK(c, launch_adjoint_cr(w, c->n_env, E0, nrhs, Cr, c->stream));
+  if (probes) {
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, c->stream, c->flag.as<int>(), 4, 0);
+    HIPCHK(c, c->prof.begin(c->stream, PROF_ADJ_PROBE, (double)P * (double)N * (double)nrhs));
+    HIPCHK(c, launch_adjoint_probe(d, w, c->n_env, Q, n, nrhs, r_probe, gE, P, sp, pacc, pgr_probe, pdk_probe,
+                                   1e-18 * c->step * c->step, c->flag.as<int>(), c->stream));
+    HIPCHK(c, c->prof.end(c->stream));
+    HIPCHK(c, launch_adjoint_einc(w, c->n_env, khat, E0, r_probe, gE, P, nrhs, pdk_einc, c->stream));
+  }
+  HIPCHK(c, launch_adjoint_seed(d, w, F0, Fs, Q, n, nrhs, Cr, g_sigma, pacc, sp, gqe, rhs, c->stream));
+  SolveStats ss;
+  gdm_status status = solve_core(c, 1, nrhs, rhs, lam, tol, max_iter, ss);
+  if (status != GDM_OK && status != GDM_E_NOCONV) return status;
+  HIPCHK(c, c->prof.begin(c->stream, PROF_ADJ_PAIR, (double)N * (double)(N - 1) * (double)nrhs));
+  HIPCHK(c, launch_adjoint_pair(d, w, c->n_env, lam, Q, n, nrhs, sq, pgr_pair, pv, pdk_pair, c->stream));
+  HIPCHK(c, c->prof.end(c->stream));
+  HIPCHK(c, launch_adjoint_finish(d, w, c->n_env, c->step, c->self_mode == GDM_SELF_RADIATIVE ? 1 : 0, F0, Fs, Q, lam,
+                                  gqe, n, nrhs, khat, Cr, g_sigma, pgr_probe, nz * sp, pgr_pair, nz * sq, pv, sq,
+                                  grad_r, grad_eps, pdk_fin, c->stream));
+  if (g_sigma) HIPCHK(c, launch_cs_sums(d, F0, Q, Fs, n, nrhs, sums5, c->stream));
+  HIPCHK(c, launch_adjoint_wl(w, c->wavelength, parts, nparts, sums5, Cr, g_sigma, nrhs, grad_wl, c->stream));
+  int flag = 0;
+  if (probes) HIPCHK(c, hipMemcpyAsync(&flag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->prof.collect();
+  if (info) {
+    info->ir_iters = ss.iters;
+    info->backward_err = ss.be;
+    info->bad_index = -1;
+    info->ms_ir = ss.ms_ir;
+  }
+  if (flag) FAIL(c, GDM_E_PROBE_AT_DIPOLE, "a probe point lies on a dipole (|R| < 1e-9 step)");
+  if (status == GDM_E_NOCONV)
+    FAIL(c, GDM_E_NOCONV, "adjoint refinement stopped at backward error %.3e > tol %.3e", ss.be, ss.tol);
   return GDM_OK;
 }
 
@@ -497,9 +623,11 @@ gdm_status gdm_fields(gdm_ctx* c, int64_t nrhs, const double* q, int64_t P, cons
   HIPCHK(c, c->flag.ensure(sizeof(int) * 4));
   hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, c->stream, c->flag.as<int>(), 4, 0);
   const double rmin = 1e-9 * c->step;
+  HIPCHK(c, c->prof.begin(c->stream, PROF_FIELDS, (double)P * (double)c->N * (double)nrhs));
   HIPCHK(c, launch_fields(d, w, reinterpret_cast<const double2*>(q), c->n, nrhs, rp, P, reinterpret_cast<double2*>(E),
                           reinterpret_cast<double2*>(H), c->scratch.as<double2>(), nsplit, rmin * rmin,
                           c->flag.as<int>(), c->stream));
+  HIPCHK(c, c->prof.end(c->stream));
   int flag = 0;
   HIPCHK(c, hipMemcpyAsync(&flag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));

@@ -50,7 +50,10 @@ enum ProfTag {
   PROF_PERM = 4,
   PROF_SOLVE = 5,
   PROF_RESID = 6,
-  PROF_NTAGS = 7
+  PROF_ADJ_PAIR = 7,
+  PROF_ADJ_PROBE = 8,
+  PROF_FIELDS = 9,
+  PROF_NTAGS = 10
 };
 struct Prof {
   bool on = false;

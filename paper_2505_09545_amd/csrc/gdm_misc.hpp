@@ -46,6 +46,8 @@ hipError_t launch_axpy_f2d(const float2* c, int64_t ldc, double2* x, int64_t ldx
 hipError_t launch_colmax(const double2* a, int64_t lda, int64_t m, int64_t n, double* out, hipStream_t st);
 // row sums of |M| (infinity norm = max row sum), out[m] (zeroed by the kernel driver)
 hipError_t launch_rowsum_abs(const double2* M, int64_t ld, int64_t n, double* rows, hipStream_t st);
+// column sums of |M| (1-norm = max column sum), out[n]
+hipError_t launch_colsum_abs(const double2* M, int64_t ld, int64_t n, double* cols, hipStream_t st);
 
 int fields_num_splits(int64_t P, int64_t N, int num_cu);
 hipError_t launch_fields(const DipoleView& d, const Wave& w, const double2* q, int64_t ldq, int64_t nrhs,

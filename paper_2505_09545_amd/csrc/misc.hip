@@ -354,6 +354,30 @@ hipError_t launch_colmax(const double2* a, int64_t lda, int64_t m, int64_t n, do
   return hipGetLastError();
 }
 
+// cols[j] = sum_i |M_ij| (one workgroup per column, fixed-order reduction)
+__global__ void __launch_bounds__(256) colsum_abs_kernel(const double2* M, int64_t ld, int64_t n, double* cols) {
+  const int64_t col = blockIdx.x;
+  double s = 0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) {
+    const double2 v = M[i + col * ld];
+    s += sqrt(v.x * v.x + v.y * v.y);
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) cols[col] = red[0];
+}
+
+hipError_t launch_colsum_abs(const double2* M, int64_t ld, int64_t n, double* cols, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(colsum_abs_kernel, dim3((unsigned)n), dim3(256), 0, st, M, ld, n, cols);
+  return hipGetLastError();
+}
+
 // rows[i] = sum_j |M_ij|: grid (row blocks of 256) x (column chunks), one FP64 atomic per (row, chunk)
 constexpr int RS_CHUNK = 512;
 __global__ void __launch_bounds__(256) rowsum_abs_kernel(const double2* M, int64_t ld, int64_t n, double* rows) {

@@ -28,7 +28,7 @@ SELF_STATIC, SELF_RADIATIVE = 0, 1
 
 EXPORTED = ["gdm_create", "gdm_destroy", "gdm_last_error", "gdm_set_environment", "gdm_set_structure",
             "gdm_num_unknowns", "gdm_assemble", "gdm_factorize", "gdm_incident_planewave", "gdm_solve",
-            "gdm_planewave", "gdm_fields", "gdm_cross_sections", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
+            "gdm_planewave", "gdm_fields", "gdm_cross_sections", "gdm_adjoint", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
             "gdm_profile", "gdm_profile_read"]
 
 
@@ -70,6 +70,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gdm_planewave": ([P, I64, P, P, I64, P, P, P], ctypes.c_int),
         "gdm_fields": ([P, I64, P, I64, P, P, P], ctypes.c_int),
         "gdm_cross_sections": ([P, I64, P, P, P, P, I32, P], ctypes.c_int),
+        "gdm_adjoint": ([P, I64, P, P, P, P, P, P, I64, P, P, D, I32, P, P, P, ctypes.POINTER(GDMInfo)],
+                        ctypes.c_int),
         "gdm_getrf": ([P, ctypes.c_int, I64, P, I64, P, ctypes.POINTER(GDMInfo)], ctypes.c_int),
         "gdm_getrs": ([P, ctypes.c_int, ctypes.c_int, I64, I64, P, I64, P, I64], ctypes.c_int),
         "gdm_gemm": ([P, ctypes.c_int, ctypes.c_int, ctypes.c_int, I64, I64, I64, P, I64, P, I64, P, I64],
@@ -113,6 +115,8 @@ class Context:
         self.h = h
         self.info = GDMInfo()
         self._keep = []
+        # bumped by every call that replaces the structure or the factors
+        self.state_id = 0
 
     def close(self):
         if getattr(self, "h", None):
@@ -142,6 +146,7 @@ class Context:
 
     # -- structure / environment ------------------------------------------------
     def set_environment(self, n_env: float):
+        self.state_id += 1
         self._check(self.lib.gdm_set_environment(self.h, float(n_env)))
 
     def set_structure(self, r_cell, step, eps_cell, r_eff=None, alpha_eff=None, selfterm=SELF_STATIC):
@@ -152,6 +157,7 @@ class Context:
         re = self._dev(r_eff, torch.float64, (ne, 3), "r_eff") if ne else None
         ae = self._dev(alpha_eff, torch.complex128, (ne, 6, 6), "alpha_eff") if ne else None
         self._keep = [rc, ec, re, ae]
+        self.state_id += 1
         self._check(self.lib.gdm_set_structure(self.h, nc, _ptr(rc), float(step), _ptr(ec), ne, _ptr(re), _ptr(ae),
                                                int(selfterm)))
         self.n_cell, self.n_eff = nc, ne
@@ -169,6 +175,7 @@ class Context:
         return out.t()  # column-major storage -> M[i, j]
 
     def factorize(self, wavelength, prec=PREC_FP64):
+        self.state_id += 1
         self._check(self.lib.gdm_factorize(self.h, float(wavelength), int(prec), ctypes.byref(self.info)))
         return self.info
 
@@ -219,6 +226,36 @@ class Context:
                                                 int(bool(want_ff)), _ptr(out)))
         return out
 
+    def adjoint(self, khat, e0, f0, q, f, g_sigma=None, r_probe=None, g_e=None, tol=0.0, max_iter=-1):
+        """Reverse pass (include/gdm.h, gdm_adjoint): returns (grad_r [N, 3],
+        grad_eps [n_cell, 2] = d/d(Re eps, Im eps), grad_wl [1]).  g_sigma [n_rhs, 3]
+        real dL/d(ext, sca, abs); g_e [n_rhs, P, 3] Wirtinger dL/dE_total."""
+        k = self._dev(khat, torch.float64, None, "khat").reshape(-1, 3)
+        e = self._dev(e0, torch.complex128, None, "e0").reshape(-1, 3)
+        f0 = self._dev(f0, torch.complex128, None, "f0")
+        q = self._dev(q, torch.complex128, None, "q")
+        f = self._dev(f, torch.complex128, None, "f")
+        nrhs = f0.shape[0]
+        for name, t in (("khat", k), ("e0", e), ("q", q), ("f", f)):
+            if t.shape[0] != nrhs:
+                raise ValueError(f"{name}: expected {nrhs} rows")
+        gs = self._dev(g_sigma, torch.float64, (nrhs, 3), "g_sigma")
+        P = 0
+        rp = ge = None
+        if g_e is not None:
+            rp = self._dev(r_probe, torch.float64, None, "r_probe").reshape(-1, 3)
+            P = len(rp)
+            ge = self._dev(g_e, torch.complex128, (nrhs, P, 3), "g_e")
+        N = self.n_cell + self.n_eff
+        grad_r = torch.empty((N, 3), dtype=torch.float64, device=self.device)
+        grad_eps = torch.empty((max(self.n_cell, 1), 2), dtype=torch.float64, device=self.device)
+        grad_wl = torch.empty(1, dtype=torch.float64, device=self.device)
+        st = self.lib.gdm_adjoint(self.h, nrhs, _ptr(k), _ptr(e), _ptr(f0), _ptr(q), _ptr(f), _ptr(gs), P, _ptr(rp),
+                                  _ptr(ge), float(tol), int(max_iter), _ptr(grad_r), _ptr(grad_eps), _ptr(grad_wl),
+                                  ctypes.byref(self.info))
+        self._check(st)
+        return grad_r, grad_eps[: self.n_cell], grad_wl
+
     # -- dense linear algebra entry points ---------------------------------------------
     def getrf(self, A_colmajor_storage: torch.Tensor):
         """LU of the matrix whose column-major storage is the row-major tensor
@@ -227,6 +264,7 @@ class Context:
         n = t.shape[0]
         dtype = 0 if t.dtype == torch.complex128 else 1
         ipiv = torch.empty(n, dtype=torch.int32, device=self.device)
+        self.state_id += 1
         self._check(self.lib.gdm_getrf(self.h, dtype, n, _ptr(t), t.shape[1], _ptr(ipiv), ctypes.byref(self.info)))
         return ipiv
 
@@ -245,14 +283,15 @@ class Context:
     def sync(self):
         self._check(self.lib.gdm_sync(self.h))
 
-    PROF_TAGS = ("update", "panel", "assemble", "trsm", "perm", "solve", "resid")
+    PROF_TAGS = ("update", "panel", "assemble", "trsm", "perm", "solve", "resid", "adj_pair", "adj_probe", "fields")
 
     def profile(self, enable: bool):
         self._check(self.lib.gdm_profile(self.h, int(bool(enable))))
 
     def profile_read(self) -> dict:
-        buf = (ctypes.c_double * 21)()
-        self._check(self.lib.gdm_profile_read(self.h, buf, 21))
+        nt = 3 * len(self.PROF_TAGS)
+        buf = (ctypes.c_double * nt)()
+        self._check(self.lib.gdm_profile_read(self.h, buf, nt))
         return {t: dict(ms=buf[3 * i], work=buf[3 * i + 1], launches=int(buf[3 * i + 2]))
                 for i, t in enumerate(self.PROF_TAGS)}
 

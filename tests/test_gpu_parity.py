@@ -237,3 +237,37 @@ def test_argument_errors(ctx):
     with pytest.raises(gdm.GDMError) as e:
         ctx.factorize(-5.0)
     assert e.value.status == gdm.GDM_E_ARG
+
+
+# ---------------------------------------------------------------------------
+# full size: the 12 000-unknown benchmark workload against stored oracle values
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("prec", [1, 0])
+def test_full_config2_vs_golden(ctx, prec):
+    """n = 12 000, 66 RHS, in the launch configuration bench.py times: every
+    cross section, the 2-norm of every column of q and F, and q, F at 97 seeded
+    sample unknowns of every RHS against tests/golden/config2_samples.npz (written
+    by tests/golden/make_golden.py from the oracle)."""
+    import os
+    say("full config2", "prec", prec)
+    ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config2_samples.npz"))
+    w = gi.config2()
+    from paper_2505_09545_amd import gdm
+    out = gdm.run_forward(ctx, w, prec=prec, tol=1e-14 if prec == 1 else 0.0, probes=False)
+    q = out["q"]
+    f = out["f"]
+    qn = torch.linalg.vector_norm(q, dim=1).cpu().numpy()
+    fn = torch.linalg.vector_norm(f, dim=1).cpu().numpy()
+    assert np.max(np.abs(qn - ref["q_norm"]) / ref["q_norm"]) < 1e-10
+    assert np.max(np.abs(fn - ref["F_norm"]) / ref["F_norm"]) < 1e-10
+    idx = torch.as_tensor(ref["idx"], device=q.device)
+    qs = q[:, idx].cpu().numpy()
+    fs = f[:, idx].cpu().numpy()
+    # per RHS column: sampled entries within 1e-10 of the column norm
+    assert np.max(np.abs(qs - ref["q"]) / ref["q_norm"][:, None]) < 1e-10
+    assert np.max(np.abs(fs - ref["F"]) / ref["F_norm"][:, None]) < 1e-10
+    cs = out["cs"].cpu().numpy()
+    for col, key in ((0, "ext"), (1, "sca"), (2, "abs"), (3, "rad")):
+        assert np.max(np.abs(cs[:, col] - ref[key]) / np.abs(ref[key])) < 1e-10, key
+    if prec == 1:
+        assert out["info"].backward_err <= 1e-14
