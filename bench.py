@@ -73,6 +73,57 @@ def cpu_baseline(sample_cells: int) -> dict:
                        f"cross sections in FP64 NumPy/SciPy")
 
 
+def adjoint_timing(ctx, gdm, steps: int, warmup: int) -> dict:
+    """Forward + backward of L = sigma_sca + mean_p |E_tot(r_p)|^2 through the
+    autograd Function on the 2000-cell, 4096-probe workload (gdm_inputs.config4):
+    assembly, LU, solve, cross sections and probe fields, then the adjoint
+    (probe back-propagation, transposed solve with the saved factors, pair
+    kernel).  Inputs resident on the device; seconds per step for each precision."""
+    import torch
+    import gdm_inputs as gi
+    from paper_2505_09545_amd.autograd import GDMSetup, gdm_forward
+    w = gi.config4()
+    dev = ctx.device
+    rc = torch.tensor(w["r_cell"], dtype=torch.float64, device=dev, requires_grad=True)
+    eps = torch.tensor(w["eps_cell"], dtype=torch.complex128, device=dev, requires_grad=True)
+    wl = torch.tensor(w["wavelength"], dtype=torch.float64, device=dev, requires_grad=True)
+    e0 = torch.as_tensor(w["e0"], dtype=torch.complex128, device=dev)
+    e2 = (e0.abs() ** 2).sum(dim=1)
+    rp = torch.as_tensor(w["r_probe"], dtype=torch.float64, device=dev)
+    out = {"adjoint_workload": f"cuboid 10x10x20 = {len(w['r_cell'])} cells, 8 nm, eps 10+0.05i, 700 nm, "
+                               f"{len(rp)} probes; loss sigma_sca + mean |E|^2; grads w.r.t. all cell "
+                               f"coordinates, eps and wavelength"}
+    for name, prec, tol in (("fp32ir", gdm.PREC_FP32_IR, 1e-14), ("fp64", gdm.PREC_FP64, 0.0)):
+        sim = GDMSetup(ctx, step=w["step"], n_env=w["n_env"], khat=torch.as_tensor(w["khat"], device=dev), e0=e0,
+                       r_probe=rp, prec=prec, tol=tol)
+
+        def one():
+            for t in (rc, eps, wl):
+                t.grad = None
+            sig, E = gdm_forward(rc, eps, wl, sim)
+            L = sig[:, 1].sum() + ((E.abs() ** 2).sum(dim=(1, 2)) / e2).sum() / E.shape[1]
+            L.backward()
+
+        for _ in range(warmup):
+            one()
+        torch.cuda.synchronize()
+        ctx.profile(True)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            one()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        pr = ctx.profile_read()
+        ctx.profile(False)
+        out[f"adjoint_s_per_step_{name}"] = dt
+        out[f"adjoint_pair_ms_per_step_{name}"] = pr["adj_pair"]["ms"] / steps
+        out[f"adjoint_probe_ms_per_step_{name}"] = pr["adj_probe"]["ms"] / steps
+        out[f"adjoint_fields_ms_per_step_{name}"] = pr["fields"]["ms"] / steps
+        out[f"adjoint_factor_ms_per_step_{name}"] = (pr["panel"]["ms"] + pr["update"]["ms"] + pr["trsm"]["ms"] +
+                                                    pr["perm"]["ms"]) / steps
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,6 +132,7 @@ def main() -> int:
     ap.add_argument("--cpu-sample-cells", type=int, default=2000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the plain FP64 path")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+backward (adjoint) timing")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after the timed region, run one device copy of this many MiB (a known-size kernel "
                          "for calibrating hardware byte counters)")
@@ -187,6 +239,8 @@ def main() -> int:
             if prof["resid"]["ms"] > 0 else None,
         },
     }
+    if not args.no_adjoint:
+        line.update(adjoint_timing(ctx, gdm, args.steps, args.warmup))
     if args.copy_calib_mb > 0:
         nbytes = args.copy_calib_mb << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)

@@ -83,6 +83,7 @@ struct gdm_ctx {
   // solve / fields scratch
   DevBuf X, Rr, C32, small, scratch, flag;
   DevBuf Lam, adj;  // adjoint field and adjoint workspace
+  DevBuf part;      // split-k partial sums of the small-RHS refinement residual
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   float ms_assemble = 0, ms_factor = 0;
   Prof prof;
@@ -224,6 +225,11 @@ static gdm_status solve_core(gdm_ctx* c, int trans, int64_t nrhs, const double2*
   double2* Rr = c->Rr.as<double2>();
   float2* C32 = c->C32.as<float2>();
   double* sm = c->small.as<double>();  // [0..nrhs): |r|, [nrhs..2nrhs): |x|, [2nrhs..): |b|, [3nrhs..): |c|
+  int64_t part_elems = 0;
+  if (nrhs <= SKINNY_MAX_RHS) {
+    part_elems = std::max(skinny_t_chunks(n, 0) * nrhs * n, skinny_n_long_parts(n, n, nrhs));
+    HIPCHK(c, c->part.ensure(sizeof(double2) * part_elems));
+  }
   // first solve from B in FP32
   HIPCHK(c, launch_convert_d2f(B, n, C32, n, n, nrhs, c->stream));
   HIPCHK(c, c->prof.begin(c->stream, PROF_SOLVE, solve_flops));
@@ -238,7 +244,17 @@ static gdm_status solve_core(gdm_ctx* c, int trans, int64_t nrhs, const double2*
     // r = b - op(M) x  (FP64, stored FP64 matrix)
     HIPCHK(c, launch_copy_d(B, n, Rr, n, n, nrhs, c->stream));
     HIPCHK(c, c->prof.begin(c->stream, PROF_RESID, solve_flops));
-    HIPCHK(c, launch_gemm<double>(0, trans, n, nrhs, n, c->M64.p, n, X, n, Rr, n, c->stream));
+    if (nrhs <= SKINNY_MAX_RHS) {
+      // few right-hand sides: a GEMV-shaped residual streams M64 once on the VALUs
+      if (trans)
+        HIPCHK(c, launch_skinny_t<double>(n, nrhs, c->M64.p, n, X, n, n, nullptr, 0, nullptr, 0, 0, 0, c->part.p,
+                                          part_elems, Rr, n, c->stream));
+      else
+        HIPCHK(c, launch_skinny_n_long<double>(n, n, c->M64.p, n, X, n, Rr, n, nrhs, c->part.p, part_elems,
+                                               c->stream));
+    } else {
+      HIPCHK(c, launch_gemm<double>(0, trans, n, nrhs, n, c->M64.p, n, X, n, Rr, n, c->stream));
+    }
     HIPCHK(c, c->prof.end(c->stream));
     HIPCHK(c, launch_colmax(Rr, n, n, nrhs, sm, c->stream));
     HIPCHK(c, launch_colmax(X, n, n, nrhs, sm + nrhs, c->stream));
@@ -318,7 +334,7 @@ void gdm_destroy(gdm_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (DevBuf* b : {&c->pos, &c->eps, &c->alpha_c, &c->alpha6, &c->M, &c->M64, &c->ipiv, &c->luws, &c->rows,
-                    &c->ext_ws, &c->X, &c->Rr, &c->C32, &c->small, &c->scratch, &c->flag, &c->Lam, &c->adj})
+                    &c->ext_ws, &c->X, &c->Rr, &c->C32, &c->small, &c->scratch, &c->flag, &c->Lam, &c->adj, &c->part})
     b->release();
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);

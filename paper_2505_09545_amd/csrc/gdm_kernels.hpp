@@ -41,6 +41,27 @@ template <typename T>
 hipError_t launch_gemm_update(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
                               int64_t ldb, void* C, int64_t ldc, hipStream_t st);
 
+// Small-RHS block steps of the triangular solves (solve_small.hip).
+// C[m x nrhs] -= A[m x k] X[k x nrhs], k <= 256, optional triangle mask on A.
+template <typename T>
+hipError_t launch_skinny_n(int64_t m, int64_t k, const void* A, int64_t lda, const void* X, int64_t ldx, void* C,
+                           int64_t ldc, int64_t nrhs, hipStream_t st, GemmMask mk = GemmMask{});
+// C[mo x nrhs] -= A0^T B0 + mask(A1)^T B1 with A0 (k0 x mo) and A1 (k1 x mo)
+// stored column-major; split over k into chunks whose partial sums go to
+// `part` (capacity part_elems complex), then added to C in a fixed order.
+template <typename T>
+hipError_t launch_skinny_t(int64_t mo, int64_t nrhs, const void* A0, int64_t lda0, const void* B0, int64_t ldb0,
+                           int64_t k0, const void* A1, int64_t lda1, const void* B1, int64_t ldb1, int64_t k1,
+                           int kind1, void* part, int64_t part_elems, void* C, int64_t ldc, hipStream_t st);
+int64_t skinny_t_chunks(int64_t k0, int64_t k1);
+// C[m x nrhs] -= A[m x k] X[k x nrhs] for any k (split over k; partial sums in
+// `part`, capacity part_elems >= skinny_n_long_parts(m, k, nrhs)).
+template <typename T>
+hipError_t launch_skinny_n_long(int64_t m, int64_t k, const void* A, int64_t lda, const void* X, int64_t ldx, void* C,
+                                int64_t ldc, int64_t nrhs, void* part, int64_t part_elems, hipStream_t st);
+int64_t skinny_n_long_parts(int64_t m, int64_t k, int64_t nrhs);
+constexpr int SKINNY_MAX_RHS = 8;
+
 // Optional per-launch timing with HIP events on the launch stream.
 enum ProfTag {
   PROF_UPDATE = 0,

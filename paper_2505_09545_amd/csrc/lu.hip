@@ -673,6 +673,10 @@ LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes) {
   return p;
 }
 
+// rows of the complex scratch `tmp` (x nb columns): operand copies need n; the
+// split-k partial sums of the transposed solve need more than n for small n
+static int64_t tmp_rows(const LUPlan& p) { return p.n > 512 ? p.n : 512; }
+
 size_t lu_workspace_bytes(const LUPlan& p, int elem_bytes, int num_cu) {
   const size_t nb = (size_t)p.nb, nblk = p.blocks.size();
   const size_t ww = nb * (2 * (size_t)elem_bytes / 4);
@@ -683,7 +687,7 @@ size_t lu_workspace_bytes(const LUPlan& p, int elem_bytes, int num_cu) {
   s += 64 + 256;
   s += nblk * 2 * 2 * nb * 4 + 256;
   s += nblk * 4 + 256;
-  s += (size_t)p.n * nb * 2 * elem_bytes + 256;
+  s += (size_t)tmp_rows(p) * nb * 2 * elem_bytes + 256;
   s += nblk * nb * nb * 2 * elem_bytes + 256;
   s += nb * nb * 2 * elem_bytes + 256;
   return s + 8 * 256;
@@ -706,8 +710,8 @@ void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu,
   w.err = reinterpret_cast<int32_t*>(take(64));
   w.pairs = reinterpret_cast<int32_t*>(take(nblk * 2 * 2 * nb * 4));
   w.npairs = reinterpret_cast<int32_t*>(take(nblk * 4));
-  w.tmp = take((size_t)p.n * nb * 2 * elem_bytes);
-  w.tmp_elems = (int64_t)p.n * nb;
+  w.tmp = take((size_t)tmp_rows(p) * nb * 2 * elem_bytes);
+  w.tmp_elems = tmp_rows(p) * (int64_t)nb;
   w.dinv = take(nblk * nb * nb * 2 * elem_bytes);
   w.tmp2 = take(nb * nb * 2 * elem_bytes);
   w.events = nullptr;
@@ -889,10 +893,18 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
   CT* X = static_cast<CT*>(ws.tmp);
   hipError_t e;
   if (nrhs <= 0) return hipSuccess;
-  const int64_t chunk = ws.tmp_elems / nb;  // RHS columns that fit the copy scratch
+  // RHS columns per pass: the block copy needs nb per column; the transposed
+  // steps need (chunks of the longest product) x nb partial sums per column.
+  int64_t chunk = ws.tmp_elems / nb;
+  if (trans) {
+    const int64_t per = skinny_t_chunks(n, nb) * nb;
+    chunk = ws.tmp_elems / per;
+    if (chunk < 1) return hipErrorInvalidValue;
+  }
   for (int64_t r0 = 0; r0 < nrhs; r0 += chunk) {
     const int64_t nr = nrhs - r0 < chunk ? nrhs - r0 : chunk;
     CT* B = Ball + r0 * ldb;
+    const bool small = nr <= SKINNY_MAX_RHS;
     if (trans == 0) {
       // forward: P_b, then rows [k0, n) -= [I - L11^-1 ; L21 L11^-1] B_b
       for (int bi = 0; bi < nblk; ++bi) {
@@ -907,9 +919,9 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
         m.akind = GEMM_MASK_STRICT_LOWER;
         m.ar0 = 0;
         m.adw = b.w;
-        if ((e = launch_gemm<T>(0, 0, n - k0, nr, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, st, m)) !=
-            hipSuccess)
-          return e;
+        e = small ? launch_skinny_n<T>(n - k0, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, nr, st, m)
+                  : launch_gemm<T>(0, 0, n - k0, nr, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, st, m);
+        if (e != hipSuccess) return e;
       }
       // backward: rows [0, k0 + w) -= [U01 U11^-1 ; I - U11^-1] B_b
       for (int bi = nblk - 1; bi >= 0; --bi) {
@@ -920,39 +932,28 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
         m.akind = GEMM_MASK_UPPER;
         m.ar0 = k0;
         m.adw = b.w;
-        if ((e = launch_gemm<T>(0, 0, k0 + b.w, nr, b.w, A + k0 * ld, ld, X, b.w, B, ldb, st, m)) != hipSuccess)
-          return e;
+        e = small ? launch_skinny_n<T>(k0 + b.w, b.w, A + k0 * ld, ld, X, b.w, B, ldb, nr, st, m)
+                  : launch_gemm<T>(0, 0, k0 + b.w, nr, b.w, A + k0 * ld, ld, X, b.w, B, ldb, st, m);
+        if (e != hipSuccess) return e;
       }
     } else {
-      // M^T = U^T L_k^T P_k ... L_1^T P_1.  U^T forward:
-      //   z_b = U11^-T g_b - (U01 U11^-1)^T z_above = g_b - (U01 U11^-1)^T z_above - (I - U11^-1)^T g_b
+      // M^T = U^T L_k^T P_k ... L_1^T P_1.  U^T forward, with V = U01 U11^-1 stored above the diagonal:
+      //   z_b = U11^-T g_b - V^T z_above = g_b - V^T z_above - (I - U11^-1)^T g_b
+      // (both products read the pre-step B; the split-k partials are added afterwards)
       for (int bi = 0; bi < nblk; ++bi) {
         const LUBlock& b = plan.blocks[bi];
         const int64_t k0 = b.k0;
-        if ((e = launch_copy_block<T>(B + k0, ldb, X, b.w, b.w, nr, st)) != hipSuccess) return e;
-        if (k0 > 0)
-          if ((e = launch_gemm<T>(0, 1, b.w, nr, k0, A + k0 * ld, ld, B, ldb, B + k0, ldb, st)) != hipSuccess) return e;
-        GemmMask m;
-        m.akind = GEMM_MASK_LOWER;
-        m.ar0 = 0;
-        m.adw = b.w;
-        if ((e = launch_gemm<T>(0, 1, b.w, nr, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, st, m)) != hipSuccess)
+        if ((e = launch_skinny_t<T>(b.w, nr, A + k0 * ld, ld, B, ldb, k0, A + k0 + k0 * ld, ld, B + k0, ldb, b.w,
+                                    GEMM_MASK_LOWER, X, ws.tmp_elems, B + k0, ldb, st)) != hipSuccess)
           return e;
       }
       // then for b = k..1: z_b = L11^-T z_b - (L21 L11^-1)^T z_below, and z = P_b^T z
       for (int bi = nblk - 1; bi >= 0; --bi) {
         const LUBlock& b = plan.blocks[bi];
         const int64_t k0 = b.k0, c1 = k0 + b.w;
-        if ((e = launch_copy_block<T>(B + k0, ldb, X, b.w, b.w, nr, st)) != hipSuccess) return e;
-        if (n - c1 > 0)
-          if ((e = launch_gemm<T>(0, 1, b.w, nr, n - c1, A + c1 + k0 * ld, ld, B + c1, ldb, B + k0, ldb, st)) !=
-              hipSuccess)
-            return e;
-        GemmMask m;
-        m.akind = GEMM_MASK_STRICT_UPPER;
-        m.ar0 = 0;
-        m.adw = b.w;
-        if ((e = launch_gemm<T>(0, 1, b.w, nr, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, st, m)) != hipSuccess)
+        if ((e = launch_skinny_t<T>(b.w, nr, A + c1 + k0 * ld, ld, B + c1, ldb, n - c1, A + k0 + k0 * ld, ld, B + k0,
+                                    ldb, b.w, GEMM_MASK_STRICT_UPPER, X, ws.tmp_elems, B + k0, ldb, st)) !=
+            hipSuccess)
           return e;
         const int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;
         const int32_t* src = dst + 2 * nb;

@@ -1,9 +1,10 @@
 """Thin ctypes binding of libgdm (include/gdm.h).
 
 Argument marshalling only: every step of the hot path runs in the HIP kernels
-of libgdm.so.  Torch tensors are used as device buffers; the library works on
-the stream that is current when the context is created.  There is no CPU
-fallback: importing this module without the built library raises.
+of libgdm.so.  Torch tensors are used as device buffers; each context runs on
+its own stream, ordered with the caller's current torch stream around every
+call.  There is no CPU fallback: importing this module without the built
+library raises.
 
 Layouts follow the C header: complex arrays are torch.complex128 tensors
 (interleaved re/im doubles); vectors in the unknown layout are [n_rhs, n];
@@ -102,13 +103,20 @@ class Structure:
 
 
 class Context:
-    """One libgdm context on a CUDA (HIP) device, bound to the current stream."""
+    """One libgdm context on a CUDA (HIP) device.
+
+    The library's work runs on `stream` (default: a new torch stream of default
+    priority owned by this context).  Every call is ordered with the caller's
+    current torch stream in both directions: the library stream first waits for
+    the current stream (inputs produced there are complete), and afterwards the
+    current stream waits for the library stream (outputs are complete before
+    torch reads them, and torch's allocator does not reuse their memory early)."""
 
     def __init__(self, device: int = 0, stream=None):
         self.lib = load_library()
         self.device = torch.device("cuda", device)
         if stream is None:
-            stream = torch.cuda.current_stream(self.device)
+            stream = torch.cuda.Stream(device=self.device)
         self.stream = stream
         h = ctypes.c_void_p()
         self._check(self.lib.gdm_create(device, ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)), None)
@@ -129,6 +137,17 @@ class Context:
         except Exception:
             pass
 
+    def _call(self, name, *args):
+        """Call library function `name` ordered with the current torch stream."""
+        cur = torch.cuda.current_stream(self.device)
+        other = cur.cuda_stream != self.stream.cuda_stream
+        if other:
+            self.stream.wait_stream(cur)
+        st = getattr(self.lib, name)(*args)
+        if other:
+            cur.wait_stream(self.stream)
+        return st
+
     def _check(self, st, h="self"):
         if st != GDM_OK:
             msg = self.lib.gdm_last_error(self.h if h == "self" else None).decode()
@@ -147,7 +166,7 @@ class Context:
     # -- structure / environment ------------------------------------------------
     def set_environment(self, n_env: float):
         self.state_id += 1
-        self._check(self.lib.gdm_set_environment(self.h, float(n_env)))
+        self._check(self._call("gdm_set_environment", self.h, float(n_env)))
 
     def set_structure(self, r_cell, step, eps_cell, r_eff=None, alpha_eff=None, selfterm=SELF_STATIC):
         nc = 0 if r_cell is None else len(r_cell)
@@ -158,7 +177,7 @@ class Context:
         ae = self._dev(alpha_eff, torch.complex128, (ne, 6, 6), "alpha_eff") if ne else None
         self._keep = [rc, ec, re, ae]
         self.state_id += 1
-        self._check(self.lib.gdm_set_structure(self.h, nc, _ptr(rc), float(step), _ptr(ec), ne, _ptr(re), _ptr(ae),
+        self._check(self._call("gdm_set_structure", self.h, nc, _ptr(rc), float(step), _ptr(ec), ne, _ptr(re), _ptr(ae),
                                                int(selfterm)))
         self.n_cell, self.n_eff = nc, ne
 
@@ -170,13 +189,13 @@ class Context:
     def assemble(self, wavelength, dtype=torch.complex128):
         n = self.n
         out = torch.empty((n, n), dtype=dtype, device=self.device)
-        self._check(self.lib.gdm_assemble(self.h, float(wavelength), 0 if dtype == torch.complex128 else 1,
+        self._check(self._call("gdm_assemble", self.h, float(wavelength), 0 if dtype == torch.complex128 else 1,
                                           _ptr(out), n))
         return out.t()  # column-major storage -> M[i, j]
 
     def factorize(self, wavelength, prec=PREC_FP64):
         self.state_id += 1
-        self._check(self.lib.gdm_factorize(self.h, float(wavelength), int(prec), ctypes.byref(self.info)))
+        self._check(self._call("gdm_factorize", self.h, float(wavelength), int(prec), ctypes.byref(self.info)))
         return self.info
 
     def incident_planewave(self, khat, e0):
@@ -185,7 +204,7 @@ class Context:
         if len(k) != len(e):
             raise ValueError("khat and e0 must have the same number of plane waves")
         f0 = torch.empty((len(k), self.n), dtype=torch.complex128, device=self.device)
-        self._check(self.lib.gdm_incident_planewave(self.h, len(k), _ptr(k), _ptr(e), _ptr(f0)))
+        self._check(self._call("gdm_incident_planewave", self.h, len(k), _ptr(k), _ptr(e), _ptr(f0)))
         return f0
 
     def solve(self, f0, tol=0.0, max_iter=-1, want_field=True):
@@ -194,7 +213,7 @@ class Context:
             raise ValueError(f"f0 must be [n_rhs, {self.n}]")
         q = torch.empty_like(f0)
         f = torch.empty_like(f0) if want_field else None
-        st = self.lib.gdm_solve(self.h, f0.shape[0], _ptr(f0), float(tol), int(max_iter), _ptr(q), _ptr(f),
+        st = self._call("gdm_solve", self.h, f0.shape[0], _ptr(f0), float(tol), int(max_iter), _ptr(q), _ptr(f),
                                 ctypes.byref(self.info))
         self._check(st)
         return q, f
@@ -205,7 +224,7 @@ class Context:
         r = self._dev(r, torch.float64, None, "r").reshape(-1, 3)
         E = torch.empty((len(k), len(r), 3), dtype=torch.complex128, device=self.device)
         H = torch.empty_like(E) if want_h else None
-        self._check(self.lib.gdm_planewave(self.h, len(k), _ptr(k), _ptr(e), len(r), _ptr(r), _ptr(E), _ptr(H)))
+        self._check(self._call("gdm_planewave", self.h, len(k), _ptr(k), _ptr(e), len(r), _ptr(r), _ptr(E), _ptr(H)))
         return E, H
 
     def fields(self, q, r_probe, want_h=True):
@@ -213,7 +232,7 @@ class Context:
         r = self._dev(r_probe, torch.float64, None, "r_probe").reshape(-1, 3)
         E = torch.empty((q.shape[0], len(r), 3), dtype=torch.complex128, device=self.device)
         H = torch.empty_like(E) if want_h else None
-        self._check(self.lib.gdm_fields(self.h, q.shape[0], _ptr(q), len(r), _ptr(r), _ptr(E), _ptr(H)))
+        self._check(self._call("gdm_fields", self.h, q.shape[0], _ptr(q), len(r), _ptr(r), _ptr(E), _ptr(H)))
         return E, H
 
     def cross_sections(self, f0, q, f, e0_norm2, want_ff=False):
@@ -222,7 +241,7 @@ class Context:
         f = self._dev(f, torch.complex128, None, "f")
         e2 = self._dev(e0_norm2, torch.float64, (f0.shape[0],), "e0_norm2")
         out = torch.empty((f0.shape[0], 5), dtype=torch.float64, device=self.device)
-        self._check(self.lib.gdm_cross_sections(self.h, f0.shape[0], _ptr(f0), _ptr(q), _ptr(f), _ptr(e2),
+        self._check(self._call("gdm_cross_sections", self.h, f0.shape[0], _ptr(f0), _ptr(q), _ptr(f), _ptr(e2),
                                                 int(bool(want_ff)), _ptr(out)))
         return out
 
@@ -250,7 +269,7 @@ class Context:
         grad_r = torch.empty((N, 3), dtype=torch.float64, device=self.device)
         grad_eps = torch.empty((max(self.n_cell, 1), 2), dtype=torch.float64, device=self.device)
         grad_wl = torch.empty(1, dtype=torch.float64, device=self.device)
-        st = self.lib.gdm_adjoint(self.h, nrhs, _ptr(k), _ptr(e), _ptr(f0), _ptr(q), _ptr(f), _ptr(gs), P, _ptr(rp),
+        st = self._call("gdm_adjoint", self.h, nrhs, _ptr(k), _ptr(e), _ptr(f0), _ptr(q), _ptr(f), _ptr(gs), P, _ptr(rp),
                                   _ptr(ge), float(tol), int(max_iter), _ptr(grad_r), _ptr(grad_eps), _ptr(grad_wl),
                                   ctypes.byref(self.info))
         self._check(st)
@@ -265,33 +284,33 @@ class Context:
         dtype = 0 if t.dtype == torch.complex128 else 1
         ipiv = torch.empty(n, dtype=torch.int32, device=self.device)
         self.state_id += 1
-        self._check(self.lib.gdm_getrf(self.h, dtype, n, _ptr(t), t.shape[1], _ptr(ipiv), ctypes.byref(self.info)))
+        self._check(self._call("gdm_getrf", self.h, dtype, n, _ptr(t), t.shape[1], _ptr(ipiv), ctypes.byref(self.info)))
         return ipiv
 
     def getrs(self, A_storage: torch.Tensor, B_storage: torch.Tensor, trans: int = 0):
         """B_storage: [nrhs, n] row-major = column-major n x nrhs; solved in place."""
         dtype = 0 if A_storage.dtype == torch.complex128 else 1
         n = A_storage.shape[0]
-        self._check(self.lib.gdm_getrs(self.h, dtype, int(trans), n, B_storage.shape[0], _ptr(A_storage),
+        self._check(self._call("gdm_getrs", self.h, dtype, int(trans), n, B_storage.shape[0], _ptr(A_storage),
                                        A_storage.shape[1], _ptr(B_storage), B_storage.shape[1]))
 
     def gemm(self, mode, transA, m, n, k, A, lda, B, ldb, C, ldc):
         dtype = 0 if C.dtype == torch.complex128 else 1
-        self._check(self.lib.gdm_gemm(self.h, dtype, int(mode), int(transA), m, n, k, _ptr(A), lda, _ptr(B), ldb,
+        self._check(self._call("gdm_gemm", self.h, dtype, int(mode), int(transA), m, n, k, _ptr(A), lda, _ptr(B), ldb,
                                       _ptr(C), ldc))
 
     def sync(self):
-        self._check(self.lib.gdm_sync(self.h))
+        self._check(self._call("gdm_sync", self.h))
 
     PROF_TAGS = ("update", "panel", "assemble", "trsm", "perm", "solve", "resid", "adj_pair", "adj_probe", "fields")
 
     def profile(self, enable: bool):
-        self._check(self.lib.gdm_profile(self.h, int(bool(enable))))
+        self._check(self._call("gdm_profile", self.h, int(bool(enable))))
 
     def profile_read(self) -> dict:
         nt = 3 * len(self.PROF_TAGS)
         buf = (ctypes.c_double * nt)()
-        self._check(self.lib.gdm_profile_read(self.h, buf, nt))
+        self._check(self._call("gdm_profile_read", self.h, buf, nt))
         return {t: dict(ms=buf[3 * i], work=buf[3 * i + 1], launches=int(buf[3 * i + 2]))
                 for i, t in enumerate(self.PROF_TAGS)}
 

@@ -271,3 +271,30 @@ def test_full_config2_vs_golden(ctx, prec):
         assert np.max(np.abs(cs[:, col] - ref[key]) / np.abs(ref[key])) < 1e-10, key
     if prec == 1:
         assert out["info"].backward_err <= 1e-14
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+def test_full_config2_assembly_sampled(ctx, dtype):
+    """The 12 000 x 12 000 matrix of the benchmark workload, read right after the
+    (asynchronous) assembly call: the blocks between 64 seeded sample dipoles
+    equal the oracle's assembly of the structure made of those dipoles alone
+    (an off-diagonal block depends only on its two dipoles, a diagonal block on
+    its own)."""
+    say("full config2 assembly", dtype)
+    w = gi.config2()
+    ctx.set_environment(w["n_env"])
+    ctx.set_structure(torch.as_tensor(w["r_cell"]), w["step"], torch.as_tensor(w["eps_cell"]))
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    M = ctx.assemble(w["wavelength"], tdt)
+    idx = np.sort(np.random.default_rng(99).choice(len(w["r_cell"]), 64, replace=False))
+    u = torch.as_tensor((3 * idx[:, None] + np.arange(3)[None, :]).ravel(), device=M.device)
+    got = M[u][:, u].cpu().numpy().astype(np.complex128)
+    del M
+    sub = dict(w, r_cell=w["r_cell"][idx], eps_cell=w["eps_cell"][idx])
+    ref = O.assemble(O.Dipoles(sub))
+    if dtype == "c128":
+        assert np.max(np.abs(got - ref)) <= 1e-13 * np.max(np.abs(ref))
+    else:
+        # FP64 arithmetic rounded once to FP32, per real component
+        assert np.all(np.abs(got.real - ref.real) <= 6.0e-8 * np.abs(ref.real) + 1e-300)
+        assert np.all(np.abs(got.imag - ref.imag) <= 6.0e-8 * np.abs(ref.imag) + 1e-300)
