@@ -32,33 +32,41 @@ struct GemmMask {
 
 // C (m x n) = C - op(A) B   (mode 0)   or   C = op(A) B   (mode 1);
 // complex interleaved, column-major; op(A) = A (transA 0) or A^T (transA 1, no conjugation).
+// nbatch > 1: independent products, item z at A + z sA, B + z sB, C + z sC.
 template <typename T>
 hipError_t launch_gemm(int mode, int transA, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
-                       const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st, GemmMask mk = GemmMask{});
+                       const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st, GemmMask mk = GemmMask{},
+                       int nbatch = 1, int64_t sA = 0, int64_t sB = 0, int64_t sC = 0);
 // The LU trailing update A22 -= L21 U12: same kernel body, separate symbol so
 // that profilers report it on its own.
 template <typename T>
 hipError_t launch_gemm_update(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
-                              int64_t ldb, void* C, int64_t ldc, hipStream_t st);
+                              int64_t ldb, void* C, int64_t ldc, hipStream_t st, int nbatch = 1, int64_t sA = 0,
+                              int64_t sB = 0, int64_t sC = 0);
 
-// Small-RHS block steps of the triangular solves (solve_small.hip).
+// Small-RHS block steps of the triangular solves (solve_small.hip).  All take
+// an optional batch of nbatch independent items (item z: A + z sA, X/B + z sX/sB,
+// C + z sC; partial-sum buffers must hold nbatch times the per-item need).
 // C[m x nrhs] -= A[m x k] X[k x nrhs], k <= 256, optional triangle mask on A.
 template <typename T>
 hipError_t launch_skinny_n(int64_t m, int64_t k, const void* A, int64_t lda, const void* X, int64_t ldx, void* C,
-                           int64_t ldc, int64_t nrhs, hipStream_t st, GemmMask mk = GemmMask{});
+                           int64_t ldc, int64_t nrhs, hipStream_t st, GemmMask mk = GemmMask{}, int nbatch = 1,
+                           int64_t sA = 0, int64_t sX = 0, int64_t sC = 0);
 // C[mo x nrhs] -= A0^T B0 + mask(A1)^T B1 with A0 (k0 x mo) and A1 (k1 x mo)
 // stored column-major; split over k into chunks whose partial sums go to
 // `part` (capacity part_elems complex), then added to C in a fixed order.
 template <typename T>
 hipError_t launch_skinny_t(int64_t mo, int64_t nrhs, const void* A0, int64_t lda0, const void* B0, int64_t ldb0,
                            int64_t k0, const void* A1, int64_t lda1, const void* B1, int64_t ldb1, int64_t k1,
-                           int kind1, void* part, int64_t part_elems, void* C, int64_t ldc, hipStream_t st);
+                           int kind1, void* part, int64_t part_elems, void* C, int64_t ldc, hipStream_t st,
+                           int nbatch = 1, int64_t sA = 0, int64_t sB = 0, int64_t sC = 0);
 int64_t skinny_t_chunks(int64_t k0, int64_t k1);
 // C[m x nrhs] -= A[m x k] X[k x nrhs] for any k (split over k; partial sums in
-// `part`, capacity part_elems >= skinny_n_long_parts(m, k, nrhs)).
+// `part`, capacity part_elems >= nbatch skinny_n_long_parts(m, k, nrhs)).
 template <typename T>
 hipError_t launch_skinny_n_long(int64_t m, int64_t k, const void* A, int64_t lda, const void* X, int64_t ldx, void* C,
-                                int64_t ldc, int64_t nrhs, void* part, int64_t part_elems, hipStream_t st);
+                                int64_t ldc, int64_t nrhs, void* part, int64_t part_elems, hipStream_t st,
+                                int nbatch = 1, int64_t sA = 0, int64_t sX = 0, int64_t sC = 0);
 int64_t skinny_n_long_parts(int64_t m, int64_t k, int64_t nrhs);
 constexpr int SKINNY_MAX_RHS = 8;
 
@@ -110,40 +118,49 @@ struct LUPlan {
   std::vector<LUBlock> blocks;
 };
 
-// Device workspace of the factorisation; sized by lu_workspace_bytes().
+// Device workspace of the factorisation; sized by lu_workspace_bytes().  With a
+// batch of nbatch items every per-item field below holds nbatch copies, item z
+// at field + z * s_field (elements of the field's type).
 struct LUWork {
-  unsigned long long* cand;  // [2][gmax][2] epoch-tagged pivot keys (value, row)
+  unsigned long long* cand;  // [2][gmax][KEY_STRIDE] epoch-tagged pivot keys (value, row)
   unsigned long long* rows;  // [2][gmax][wwmax] epoch-tagged candidate rows
-  unsigned long long* drow;  // [2][wwmax] epoch-tagged copy of the diagonal row
-  int gmax;                  // max panel workgroups
+  int gmax;                  // max panel workgroups (all items together)
   int wwmax;                 // payload words per row (nb * words per complex)
-  int32_t* err;              // [2]: exchange timeout flag, first zero pivot (INT32_MAX if none)
+  int32_t* err;              // [2] (shared): exchange timeout flag, first zero pivot (INT32_MAX if none)
   int32_t* pairs;            // [nblocks][2][2 nb]: destination rows then source rows
   int32_t* npairs;           // [nblocks]
-  void* tmp;                 // [n * nb] complex scratch (operand copies)
+  void* tmp;                 // [tmp_elems] complex scratch (operand copies, split-k partials)
   void* dinv;                // [nblocks][nb][nb] complex inverses of the diagonal triangles
   void* tmp2;                // [nb * nb] complex scratch of the main stream
   std::vector<hipEvent_t>* events;  // host-side pool of reusable events (look-ahead)
-  int64_t tmp_elems;         // capacity of tmp in complex elements
+  int64_t tmp_elems;         // capacity of tmp per item in complex elements
+  int nbatch = 1;
+  int64_t s_cand = 0, s_rows = 0, s_pairs = 0, s_npairs = 0, s_tmp = 0, s_dinv = 0, s_tmp2 = 0;
+  size_t bytes = 0;          // total size (set by lu_workspace_carve)
 };
 
-LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes);
-size_t lu_workspace_bytes(const LUPlan& p, int elem_bytes, int num_cu);
-void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu, LUWork& w);
+// nbatch: number of same-size items factored together (their panels share one
+// launch, so each panel gets at most num_cu / nbatch workgroups).
+LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch = 1);
+bool lu_plan_fits(const LUPlan& p);
+size_t lu_workspace_bytes(const LUPlan& p, int elem_bytes, int num_cu, int nbatch = 1);
+void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu, LUWork& w, int nbatch = 1);
 
 // `side` (may be null): second stream for the look-ahead; all work is joined
-// back into `st` before return.
+// back into `st` before return.  Batch (ws.nbatch items): matrix z at A + z sA,
+// its pivots at ipiv + z sipiv.
 template <typename T>
 hipError_t lu_factor(void* A, int64_t ld, const LUPlan& plan, const LUWork& ws, int32_t* ipiv, hipStream_t st,
-                     Prof* prof = nullptr, hipStream_t side = nullptr);
+                     Prof* prof = nullptr, hipStream_t side = nullptr, int64_t sA = 0, int64_t sipiv = 0);
 
 // Factors are left in a solve-ready form: for every block the diagonal block
 // holds I - L11^-1 (strict lower part) and I - U11^-1 (upper part), the block
 // column below holds L21 L11^-1 and the block column above holds U01 U11^-1, so
 // that every step of a (transposed) solve is one GEMM.
-// Solve op(M) X = B in place for B (n x nrhs, ld ldb) with the factors of lu_factor.
+// Solve op(M) X = B in place for B (n x nrhs, ld ldb) with the factors of
+// lu_factor (batch: item z's factors at A + z sA, its B at B + z sB).
 template <typename T>
 hipError_t lu_solve(int trans, const void* A, int64_t ld, const LUPlan& plan, const LUWork& ws, void* B,
-                    int64_t ldb, int64_t nrhs, hipStream_t st);
+                    int64_t ldb, int64_t nrhs, hipStream_t st, int64_t sA = 0, int64_t sB = 0);
 
 }  // namespace gdm

@@ -49,8 +49,12 @@ template <typename T, int MODE, int TRANSA, int ROLE>
 __global__ void __launch_bounds__(256) cgemm_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict__ A,
                                                      int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb,
                                                      cplx<T>* __restrict__ C, int64_t ldc, int tiles_m, int tiles,
-                                                     GemmMask mk) {
+                                                     GemmMask mk, int64_t sA, int64_t sB, int64_t sC) {
   using CT = cplx<T>;
+  // batch of independent products: blockIdx.y selects the item
+  A += (int64_t)blockIdx.y * sA;
+  B += (int64_t)blockIdx.y * sB;
+  C += (int64_t)blockIdx.y * sC;
   using ACC = typename acc_of<T>::type;
   __shared__ T As[2][GBK * GBM * 2];   // [kc][mc] complex
   __shared__ T Bs[2][2 * GBK * GBN];   // [kk][nc] real view
@@ -177,8 +181,10 @@ __global__ void __launch_bounds__(256) cgemm_kernel(int64_t m, int64_t n, int64_
 
 template <typename T>
 hipError_t launch_gemm(int mode, int transA, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
-                       const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st, GemmMask mk) {
-  if (m <= 0 || n <= 0) return hipSuccess;
+                       const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st, GemmMask mk, int nbatch,
+                       int64_t sA, int64_t sB, int64_t sC) {
+  if (m <= 0 || n <= 0 || nbatch <= 0) return hipSuccess;
+  if (nbatch > 65535) return hipErrorInvalidValue;
   const int64_t tm = (m + GBM - 1) / GBM, tn = (n + GBN - 1) / GBN;
   if (tm * tn > INT32_MAX) return hipErrorInvalidValue;
   const int tiles = (int)(tm * tn);
@@ -186,30 +192,32 @@ hipError_t launch_gemm(int mode, int transA, int64_t m, int64_t n, int64_t k, co
   const auto* b = static_cast<const cplx<T>*>(B);
   auto* c = static_cast<cplx<T>*>(C);
   if (k <= 0 && mode == 0) return hipSuccess;  // C - 0
-  const dim3 grid(tiles), blk(256);
-  if (mode == 0 && transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 0, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk);
-  else if (mode == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 1, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk);
-  else if (transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 1, 0, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk);
-  else hipLaunchKernelGGL((cgemm_kernel<T, 1, 1, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk);
+  const dim3 grid(tiles, nbatch), blk(256);
+  if (mode == 0 && transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 0, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk, sA, sB, sC);
+  else if (mode == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 1, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk, sA, sB, sC);
+  else if (transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 1, 0, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk, sA, sB, sC);
+  else hipLaunchKernelGGL((cgemm_kernel<T, 1, 1, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk, sA, sB, sC);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_gemm_update(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
-                              int64_t ldb, void* C, int64_t ldc, hipStream_t st) {
-  if (m <= 0 || n <= 0 || k <= 0) return hipSuccess;
+                              int64_t ldb, void* C, int64_t ldc, hipStream_t st, int nbatch, int64_t sA, int64_t sB,
+                              int64_t sC) {
+  if (m <= 0 || n <= 0 || k <= 0 || nbatch <= 0) return hipSuccess;
+  if (nbatch > 65535) return hipErrorInvalidValue;
   const int64_t tm = (m + GBM - 1) / GBM, tn = (n + GBN - 1) / GBN;
   if (tm * tn > INT32_MAX) return hipErrorInvalidValue;
   const int tiles = (int)(tm * tn);
-  hipLaunchKernelGGL((cgemm_kernel<T, 0, 0, 1>), dim3(tiles), dim3(256), 0, st, m, n, k,
+  hipLaunchKernelGGL((cgemm_kernel<T, 0, 0, 1>), dim3(tiles, nbatch), dim3(256), 0, st, m, n, k,
                      static_cast<const cplx<T>*>(A), lda, static_cast<const cplx<T>*>(B), ldb,
-                     static_cast<cplx<T>*>(C), ldc, (int)tm, tiles, GemmMask{});
+                     static_cast<cplx<T>*>(C), ldc, (int)tm, tiles, GemmMask{}, sA, sB, sC);
   return hipGetLastError();
 }
 template hipError_t launch_gemm_update<double>(int64_t, int64_t, int64_t, const void*, int64_t, const void*, int64_t,
-                                               void*, int64_t, hipStream_t);
+                                               void*, int64_t, hipStream_t, int, int64_t, int64_t, int64_t);
 template hipError_t launch_gemm_update<float>(int64_t, int64_t, int64_t, const void*, int64_t, const void*, int64_t,
-                                              void*, int64_t, hipStream_t);
+                                              void*, int64_t, hipStream_t, int, int64_t, int64_t, int64_t);
 
 // ---- per-launch event timing -------------------------------------------------
 hipError_t Prof::begin(hipStream_t st, int t, double w) {
@@ -254,8 +262,8 @@ Prof::~Prof() {
 }
 
 template hipError_t launch_gemm<double>(int, int, int64_t, int64_t, int64_t, const void*, int64_t, const void*,
-                                        int64_t, void*, int64_t, hipStream_t, GemmMask);
+                                        int64_t, void*, int64_t, hipStream_t, GemmMask, int, int64_t, int64_t, int64_t);
 template hipError_t launch_gemm<float>(int, int, int64_t, int64_t, int64_t, const void*, int64_t, const void*,
-                                       int64_t, void*, int64_t, hipStream_t, GemmMask);
+                                       int64_t, void*, int64_t, hipStream_t, GemmMask, int, int64_t, int64_t, int64_t);
 
 }  // namespace gdm

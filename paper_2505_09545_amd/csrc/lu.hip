@@ -194,8 +194,13 @@ __device__ inline void block_argmax(u64& key, int& idx, u64* skey, int* sidx) {
 template <typename T>
 __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int64_t ld, int64_t n, int64_t k0, int w,
                                                      int R, int G, int32_t* __restrict__ ipiv, LUWork ws,
-                                                     uint32_t epoch0) {
+                                                     uint32_t epoch0, int64_t sA, int64_t sipiv) {
   using CT = cplx<T>;
+  // batch item blockIdx.y: its own matrix, pivots and exchange buffers
+  A += (int64_t)blockIdx.y * sA;
+  ipiv += (int64_t)blockIdx.y * sipiv;
+  ws.cand += (int64_t)blockIdx.y * ws.s_cand;
+  ws.rows += (int64_t)blockIdx.y * ws.s_rows;
   constexpr int NW = sizeof(CT) / 4;  // payload words per complex
   extern __shared__ unsigned char smem_raw[];
   CT* tile = reinterpret_cast<CT*>(smem_raw);           // [w][R], column c at tile + c*R
@@ -353,7 +358,13 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
 // row src[t]; rows outside the list are unchanged.
 __global__ void __launch_bounds__(64) block_perm_kernel(const int32_t* __restrict__ ipiv, int64_t k0, int w,
                                                          int32_t* __restrict__ dst, int32_t* __restrict__ src,
-                                                         int32_t* __restrict__ npairs) {
+                                                         int32_t* __restrict__ npairs, int64_t sipiv, int64_t spairs,
+                                                         int64_t snpairs) {
+  // batch item blockIdx.x
+  ipiv += (int64_t)blockIdx.x * sipiv;
+  dst += (int64_t)blockIdx.x * spairs;
+  src += (int64_t)blockIdx.x * spairs;
+  npairs += (int64_t)blockIdx.x * snpairs;
   __shared__ int32_t key[512];
   __shared__ int32_t val[512];
   __shared__ int cnt;
@@ -408,8 +419,13 @@ __global__ void __launch_bounds__(64) block_perm_kernel(const int32_t* __restric
 template <typename T>
 __global__ void __launch_bounds__(256) row_permute_kernel(cplx<T>* __restrict__ X, int64_t ld, int64_t c0,
                                                           const int32_t* __restrict__ dst, const int32_t* __restrict__ src,
-                                                          const int32_t* __restrict__ npairs) {
+                                                          const int32_t* __restrict__ npairs, int64_t sX, int64_t spairs,
+                                                          int64_t snpairs) {
   using CT = cplx<T>;
+  X += (int64_t)blockIdx.y * sX;  // batch item blockIdx.y
+  dst += (int64_t)blockIdx.y * spairs;
+  src += (int64_t)blockIdx.y * spairs;
+  npairs += (int64_t)blockIdx.y * snpairs;
   const int np = *npairs;
   const int64_t col = c0 + blockIdx.x;
   CT* x = X + col * ld;
@@ -431,8 +447,13 @@ __global__ void __launch_bounds__(256) row_permute_kernel(cplx<T>* __restrict__ 
 template <typename T>
 __global__ void __launch_bounds__(256) row_permute_inv_kernel(cplx<T>* __restrict__ X, int64_t ld, int64_t c0,
                                                               const int32_t* __restrict__ dst, const int32_t* __restrict__ src,
-                                                              const int32_t* __restrict__ npairs) {
+                                                              const int32_t* __restrict__ npairs, int64_t sX,
+                                                              int64_t spairs, int64_t snpairs) {
   using CT = cplx<T>;
+  X += (int64_t)blockIdx.y * sX;  // batch item blockIdx.y
+  dst += (int64_t)blockIdx.y * spairs;
+  src += (int64_t)blockIdx.y * spairs;
+  npairs += (int64_t)blockIdx.y * snpairs;
   const int np = *npairs;
   const int64_t col = c0 + blockIdx.x;
   CT* x = X + col * ld;
@@ -538,8 +559,11 @@ __device__ inline void trsm_sweep(const cplx<T>* __restrict__ Tri, int64_t ldt, 
 // Dinv[b] (nb x nb column-major, zeros in the other triangle).
 template <typename T, int UPPER>
 __global__ void __launch_bounds__(256) block_inv_kernel(const cplx<T>* __restrict__ A, int64_t ld, int64_t n, int nb,
-                                                        int b0, cplx<T>* __restrict__ Dinv, int PW) {
+                                                        int b0, cplx<T>* __restrict__ Dinv, int PW, int64_t sA,
+                                                        int64_t sD) {
   using CT = cplx<T>;
+  A += (int64_t)blockIdx.z * sA;  // batch item blockIdx.z
+  Dinv += (int64_t)blockIdx.z * sD;
   constexpr int CPW = 4;
   extern __shared__ unsigned char smem_raw[];
   CT* Ls = reinterpret_cast<CT*>(smem_raw);
@@ -571,8 +595,10 @@ __global__ void __launch_bounds__(256) block_inv_kernel(const cplx<T>* __restric
 // upper incl. diagonal <- I - Uinv (UPPER 1).
 template <typename T, int UPPER>
 __global__ void __launch_bounds__(256) diag_store_kernel(cplx<T>* __restrict__ A, int64_t ld, int64_t n, int nb, int b0,
-                                                         const cplx<T>* __restrict__ Dinv) {
+                                                         const cplx<T>* __restrict__ Dinv, int64_t sA, int64_t sD) {
   using CT = cplx<T>;
+  A += (int64_t)blockIdx.z * sA;  // batch item blockIdx.z
+  Dinv += (int64_t)blockIdx.z * sD;
   const int bb = b0 + blockIdx.y;
   const int64_t k0 = (int64_t)bb * nb;
   const int w = (int)(n - k0 < nb ? n - k0 : nb);
@@ -596,7 +622,10 @@ __global__ void __launch_bounds__(256) diag_store_kernel(cplx<T>* __restrict__ A
 
 template <typename T>
 __global__ void __launch_bounds__(256) copy_block_kernel(const cplx<T>* __restrict__ S, int64_t lds,
-                                                         cplx<T>* __restrict__ D, int64_t ldd, int64_t m, int64_t n) {
+                                                         cplx<T>* __restrict__ D, int64_t ldd, int64_t m, int64_t n,
+                                                         int64_t sS, int64_t sD) {
+  S += (int64_t)blockIdx.z * sS;  // batch item blockIdx.z
+  D += (int64_t)blockIdx.z * sD;
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= m) return;
   for (int64_t j = blockIdx.y; j < n; j += gridDim.y) D[i + j * ldd] = S[i + j * lds];
@@ -604,11 +633,11 @@ __global__ void __launch_bounds__(256) copy_block_kernel(const cplx<T>* __restri
 
 template <typename T>
 static hipError_t launch_copy_block(const cplx<T>* S, int64_t lds, cplx<T>* D, int64_t ldd, int64_t m, int64_t n,
-                                    hipStream_t st) {
-  if (m <= 0 || n <= 0) return hipSuccess;
+                                    hipStream_t st, int nbatch = 1, int64_t sS = 0, int64_t sD = 0) {
+  if (m <= 0 || n <= 0 || nbatch <= 0) return hipSuccess;
   const unsigned gy = (unsigned)(n < 65535 ? n : 65535);
-  hipLaunchKernelGGL(copy_block_kernel<T>, dim3((unsigned)((m + 255) / 256), gy), dim3(256), 0, st, S, lds, D, ldd, m,
-                     n);
+  hipLaunchKernelGGL(copy_block_kernel<T>, dim3((unsigned)((m + 255) / 256), gy, (unsigned)nbatch), dim3(256), 0, st, S,
+                     lds, D, ldd, m, n, sS, sD);
   return hipGetLastError();
 }
 
@@ -621,16 +650,16 @@ static int trsm_pw(int w, int elem) {
 
 template <typename T, int UPPER>
 static hipError_t launch_block_inv(const cplx<T>* A, int64_t ld, int64_t n, int nb, int b0, int nblocks, cplx<T>* Dinv,
-                                   hipStream_t st) {
-  if (nblocks <= 0) return hipSuccess;
+                                   hipStream_t st, int nbatch, int64_t sA, int64_t sD) {
+  if (nblocks <= 0 || nbatch <= 0) return hipSuccess;
   const int PW = trsm_pw(nb, (int)sizeof(T));
   const size_t lds = (size_t)PW * nb * sizeof(cplx<T>);
-  hipLaunchKernelGGL((block_inv_kernel<T, UPPER>), dim3((unsigned)((nb + 15) / 16), (unsigned)nblocks), dim3(256), lds,
-                     st, A, ld, n, nb, b0, Dinv, PW);
+  hipLaunchKernelGGL((block_inv_kernel<T, UPPER>), dim3((unsigned)((nb + 15) / 16), (unsigned)nblocks, (unsigned)nbatch),
+                     dim3(256), lds, st, A, ld, n, nb, b0, Dinv, PW, sA, sD);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((diag_store_kernel<T, UPPER>), dim3(16, (unsigned)nblocks), dim3(256), 0, st,
-                     const_cast<cplx<T>*>(A), ld, n, nb, b0, Dinv);
+  hipLaunchKernelGGL((diag_store_kernel<T, UPPER>), dim3(16, (unsigned)nblocks, (unsigned)nbatch), dim3(256), 0, st,
+                     const_cast<cplx<T>*>(A), ld, n, nb, b0, Dinv, sA, sD);
   return hipGetLastError();
 }
 
@@ -644,15 +673,17 @@ static size_t panel_lds_bytes(int w, int R, size_t cbytes) {
   return ((size_t)w * R + w + R) * cbytes + (size_t)(R + w) * 4;
 }
 
-LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes) {
+LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch) {
   LUPlan p;
   p.n = n;
-  p.max_wg = num_cu;
+  if (nbatch < 1) nbatch = 1;
+  // the panels of all items run in one launch and must all be resident
+  p.max_wg = num_cu / nbatch > 0 ? num_cu / nbatch : 1;
   const int cbytes = 2 * elem_bytes;
   int nb = 128;
-  // the panel must fit: ceil(n / num_cu) rows x nb columns in LDS
+  // the panel must fit: ceil(n / max_wg) rows x nb columns in LDS
   while (nb > 16) {
-    const int64_t R = (n + num_cu - 1) / num_cu;
+    const int64_t R = (n + p.max_wg - 1) / p.max_wg;
     if ((int64_t)panel_lds_bytes(nb, (int)R, cbytes) + LDS_RESERVE <= lds_bytes) break;
     nb /= 2;
   }
@@ -662,7 +693,7 @@ LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes) {
     b.k0 = k0;
     b.w = (int)(n - k0 < nb ? n - k0 : nb);
     const int64_t m = n - k0;
-    int64_t R = (m + num_cu - 1) / num_cu;
+    int64_t R = (m + p.max_wg - 1) / p.max_wg;
     if (R < 32) R = 32;
     const int64_t Rmax = (lds_bytes - LDS_RESERVE - (int64_t)b.w * (cbytes + 4)) / ((int64_t)(b.w + 1) * cbytes + 4);
     if (R > Rmax) R = Rmax;
@@ -673,56 +704,63 @@ LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes) {
   return p;
 }
 
+bool lu_plan_fits(const LUPlan& p) {
+  for (const LUBlock& b : p.blocks)
+    if (b.G > p.max_wg || (int64_t)b.G * b.R < p.n - b.k0) return false;
+  return true;
+}
+
 // rows of the complex scratch `tmp` (x nb columns): operand copies need n; the
 // split-k partial sums of the transposed solve need more than n for small n
 static int64_t tmp_rows(const LUPlan& p) { return p.n > 512 ? p.n : 512; }
 
-size_t lu_workspace_bytes(const LUPlan& p, int elem_bytes, int num_cu) {
-  const size_t nb = (size_t)p.nb, nblk = p.blocks.size();
-  const size_t ww = nb * (2 * (size_t)elem_bytes / 4);
-  size_t s = 0;
-  s += 2 * (size_t)num_cu * KEY_STRIDE * 8 + 256;
-  s += 2 * (size_t)num_cu * ww * 8 + 256;
-  s += 2 * ww * 8 + 256;
-  s += 64 + 256;
-  s += nblk * 2 * 2 * nb * 4 + 256;
-  s += nblk * 4 + 256;
-  s += (size_t)tmp_rows(p) * nb * 2 * elem_bytes + 256;
-  s += nblk * nb * nb * 2 * elem_bytes + 256;
-  s += nb * nb * 2 * elem_bytes + 256;
-  return s + 8 * 256;
+static size_t al256(size_t b) { return (b + 255) / 256 * 256; }
+
+size_t lu_workspace_bytes(const LUPlan& p, int elem_bytes, int num_cu, int nbatch) {
+  LUWork w;
+  lu_workspace_carve(nullptr, p, elem_bytes, num_cu, w, nbatch);
+  return w.bytes;
 }
 
-void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu, LUWork& w) {
+// Every per-item field is nbatch consecutive copies `s_*` elements apart.
+void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu, LUWork& w, int nbatch) {
+  if (nbatch < 1) nbatch = 1;
   const size_t nb = (size_t)p.nb, nblk = p.blocks.size();
   const size_t ww = nb * (2 * (size_t)elem_bytes / 4);
+  const size_t cb = 2 * (size_t)elem_bytes;
   char* b = static_cast<char*>(base);
+  size_t off = 0;
   auto take = [&](size_t bytes) {
-    char* r = b;
-    b += (bytes + 255) / 256 * 256 + 256;
+    char* r = b ? b + off : nullptr;
+    off += al256(bytes) + 256;
     return r;
   };
+  w.nbatch = nbatch;
   w.gmax = num_cu;
   w.wwmax = (int)ww;
-  w.cand = reinterpret_cast<unsigned long long*>(take(2 * (size_t)num_cu * KEY_STRIDE * 8));
-  w.rows = reinterpret_cast<unsigned long long*>(take(2 * (size_t)num_cu * ww * 8));
-  w.drow = reinterpret_cast<unsigned long long*>(take(2 * ww * 8));
+  w.s_cand = (int64_t)(al256(2 * (size_t)num_cu * KEY_STRIDE * 8) / 8);
+  w.s_rows = (int64_t)(al256(2 * (size_t)num_cu * ww * 8) / 8);
+  w.cand = reinterpret_cast<unsigned long long*>(take((size_t)nbatch * w.s_cand * 8));
+  w.rows = reinterpret_cast<unsigned long long*>(take((size_t)nbatch * w.s_rows * 8));
   w.err = reinterpret_cast<int32_t*>(take(64));
-  w.pairs = reinterpret_cast<int32_t*>(take(nblk * 2 * 2 * nb * 4));
-  w.npairs = reinterpret_cast<int32_t*>(take(nblk * 4));
-  w.tmp = take((size_t)tmp_rows(p) * nb * 2 * elem_bytes);
+  w.s_pairs = (int64_t)(al256(nblk * 2 * 2 * nb * 4) / 4);
+  w.s_npairs = (int64_t)(al256(nblk * 4) / 4);
+  w.pairs = reinterpret_cast<int32_t*>(take((size_t)nbatch * w.s_pairs * 4));
+  w.npairs = reinterpret_cast<int32_t*>(take((size_t)nbatch * w.s_npairs * 4));
   w.tmp_elems = tmp_rows(p) * (int64_t)nb;
-  w.dinv = take(nblk * nb * nb * 2 * elem_bytes);
-  w.tmp2 = take(nb * nb * 2 * elem_bytes);
+  w.s_tmp = (int64_t)(al256((size_t)w.tmp_elems * cb) / cb);
+  w.tmp = take((size_t)nbatch * w.s_tmp * cb);
+  w.s_dinv = (int64_t)(al256(nblk * nb * nb * cb) / cb);
+  w.dinv = take((size_t)nbatch * w.s_dinv * cb);
+  w.s_tmp2 = (int64_t)(al256(nb * nb * cb) / cb);
+  w.tmp2 = take((size_t)nbatch * w.s_tmp2 * cb);
   w.events = nullptr;
+  w.bytes = off + 256;
 }
 
-// ---------------------------------------------------------------------------
-// drivers
-// ---------------------------------------------------------------------------
 template <typename T>
 hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws, int32_t* ipiv, hipStream_t st,
-                     Prof* prof, hipStream_t side) {
+                     Prof* prof, hipStream_t side, int64_t sA, int64_t sipiv) {
   Prof noprof;
   Prof& P = prof ? *prof : noprof;
   using CT = cplx<T>;
@@ -730,15 +768,18 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
   const int64_t n = plan.n;
   const int nb = plan.nb;
   const int nblk = (int)plan.blocks.size();
+  const int NB = ws.nbatch;
+  const double fb = (double)NB;
   hipError_t e;
+  if (NB < 1 || NB > 65535 || !lu_plan_fits(plan) || plan.max_wg * NB > ws.gmax) return hipErrorInvalidValue;
   hipLaunchKernelGGL(init_err_kernel, dim3(1), dim3(64), 0, st, ws.err);
   // exchange buffers start from zero (epoch 0 is never used), so epochs 1, 2, ...
   // of this factorisation are unique
   {
-    const size_t nc = (size_t)ws.gmax * 2 * KEY_STRIDE, nr = (size_t)2 * ws.gmax * ws.wwmax, nd = (size_t)2 * ws.wwmax;
-    const size_t nmax = std::max(nc, std::max(nr, nd));
+    const size_t nc = (size_t)NB * ws.s_cand, nr = (size_t)NB * ws.s_rows;
+    const size_t nmax = std::max(nc, nr);
     hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)((nmax + 255) / 256)), dim3(256), 0, st, ws.cand, nc, ws.rows, nr,
-                       ws.drow, nd);
+                       ws.rows, (size_t)0);
   }
   uint32_t epoch = 1;
   // panels may need more than the default 64 KB of dynamic LDS
@@ -771,42 +812,38 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
     ev = (*ws.events)[ev_used++];
     return hipSuccess;
   };
-  auto cleanup = [&]() {};
-#define LUCHK(x)            \
-  do {                      \
+#define LUCHK(x)                   \
+  do {                             \
     if ((e = (x)) != hipSuccess) { \
-      cleanup();            \
-      return e;             \
-    }                       \
+      return e;                    \
+    }                              \
   } while (0)
-  CT* tmpB = static_cast<CT*>(ws.tmp);   // side-stream operand copies (n x nb)
-  CT* tmpA = static_cast<CT*>(ws.tmp2);  // main-stream operand copies (nb x nb)
+  CT* tmpB = static_cast<CT*>(ws.tmp);   // side-stream operand copies (n x nb per item)
+  CT* tmpA = static_cast<CT*>(ws.tmp2);  // main-stream operand copies (nb x nb per item)
   CT* dinv = static_cast<CT*>(ws.dinv);
   hipEvent_t bulk_done = nullptr;  // side stream finished the previous block's bulk update
   for (int bi = 0; bi < nblk; ++bi) {
     const LUBlock& b = plan.blocks[bi];
     const int64_t k0 = b.k0;
     const int w = b.w;
-    // the panel's workgroups must all be resident at once (one per CU at most)
-    if (b.G > plan.max_wg || b.G > ws.gmax || b.w > nb || (int64_t)b.G * b.R < n - k0) {
-      cleanup();
-      return hipErrorInvalidValue;
-    }
     const size_t lds = panel_lds_bytes(w, b.R, sizeof(CT));
-    LUCHK(P.begin(st, PROF_PANEL, (double)w));
-    hipLaunchKernelGGL(panel_kernel<T>, dim3(b.G), dim3(256), lds, st, A, ld, n, k0, w, b.R, b.G, ipiv, ws, epoch);
+    LUCHK(P.begin(st, PROF_PANEL, (double)w * fb));
+    hipLaunchKernelGGL(panel_kernel<T>, dim3(b.G, NB), dim3(256), lds, st, A, ld, n, k0, w, b.R, b.G, ipiv, ws, epoch,
+                       sA, sipiv);
     epoch += (uint32_t)w;
     LUCHK(hipGetLastError());
     LUCHK(P.end(st));
     int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;
     int32_t* src = dst + 2 * nb;
-    hipLaunchKernelGGL(block_perm_kernel, dim3(1), dim3(64), 0, st, ipiv, k0, w, dst, src, ws.npairs + bi);
+    int32_t* npr = ws.npairs + bi;
+    hipLaunchKernelGGL(block_perm_kernel, dim3(NB), dim3(64), 0, st, ipiv, k0, w, dst, src, npr, sipiv, ws.s_pairs,
+                       ws.s_npairs);
     const int64_t c1 = k0 + w;
     const int64_t nr = n - c1;
     CT* diag = A + k0 + k0 * ld;
     // L11^-1 -> strict lower part of the diagonal block holds I - L11^-1
     LUCHK(P.begin(st, PROF_TRSM, 0.0));
-    LUCHK((launch_block_inv<T, 0>(A, ld, n, nb, bi, 1, dinv, st)));
+    LUCHK((launch_block_inv<T, 0>(A, ld, n, nb, bi, 1, dinv, st, NB, sA, ws.s_dinv)));
     LUCHK(P.end(st));
     if (bulk_done) LUCHK(hipStreamWaitEvent(st, bulk_done, 0));  // columns of this step were in the bulk
     if (nr <= 0) break;
@@ -821,27 +858,29 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
     ml.adw = w;
     // columns [c1, c1 + wa) on the main stream, [c1 + wa, n) on the side stream
     const int64_t wa = la ? std::min<int64_t>(nr, nb) : nr;
-    auto update_cols = [&](hipStream_t s, int64_t cb, int64_t ncols, CT* tmp) -> hipError_t {
+    auto update_cols = [&](hipStream_t s, int64_t cb, int64_t ncols, CT* tmp, int64_t stmp) -> hipError_t {
       hipError_t r;
       if (ncols <= 0) return hipSuccess;
       if ((r = P.begin(s, PROF_PERM, 0.0)) != hipSuccess) return r;
-      hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)ncols), dim3(256), 0, s, A, ld, cb, dst, src,
-                         ws.npairs + bi);
+      hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)ncols, NB), dim3(256), 0, s, A, ld, cb, dst, src, npr,
+                         sA, ws.s_pairs, ws.s_npairs);
       if ((r = P.end(s)) != hipSuccess) return r;
       // U12 = L11^-1 A12 = A12 - (I - L11^-1) A12
-      if ((r = P.begin(s, PROF_TRSM, 8.0 * w * w * (double)ncols)) != hipSuccess) return r;
-      if ((r = launch_copy_block<T>(A + k0 + cb * ld, ld, tmp, w, w, ncols, s)) != hipSuccess) return r;
-      if ((r = launch_gemm<T>(0, 0, w, ncols, w, diag, ld, tmp, w, A + k0 + cb * ld, ld, s, ml)) != hipSuccess)
+      if ((r = P.begin(s, PROF_TRSM, 8.0 * w * w * (double)ncols * fb)) != hipSuccess) return r;
+      if ((r = launch_copy_block<T>(A + k0 + cb * ld, ld, tmp, w, w, ncols, s, NB, sA, stmp)) != hipSuccess) return r;
+      if ((r = launch_gemm<T>(0, 0, w, ncols, w, diag, ld, tmp, w, A + k0 + cb * ld, ld, s, ml, NB, sA, stmp, sA)) !=
+          hipSuccess)
         return r;
       if ((r = P.end(s)) != hipSuccess) return r;
       // A22[:, cols] -= L21 U12[:, cols]
-      if ((r = P.begin(s, PROF_UPDATE, 8.0 * (double)nr * (double)ncols * w)) != hipSuccess) return r;
+      if ((r = P.begin(s, PROF_UPDATE, 8.0 * (double)nr * (double)ncols * w * fb)) != hipSuccess) return r;
       if ((r = launch_gemm_update<T>(nr, ncols, w, A + c1 + k0 * ld, ld, A + k0 + cb * ld, ld, A + c1 + cb * ld, ld,
-                                     s)) != hipSuccess)
+                                     s, NB, sA, sA, sA)) != hipSuccess)
         return r;
       return P.end(s);
     };
-    LUCHK(update_cols(st, c1, wa, la ? tmpA : tmpB));
+    if (la) LUCHK(update_cols(st, c1, wa, tmpA, ws.s_tmp2));
+    else LUCHK(update_cols(st, c1, wa, tmpB, ws.s_tmp));
     hipEvent_t main_updated = nullptr;
     if (la) {
       LUCHK(new_event(main_updated));
@@ -849,15 +888,15 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
     }
     hipStream_t sb = la ? side : st;
     if (la) LUCHK(hipStreamWaitEvent(sb, factored, 0));
-    LUCHK(update_cols(sb, c1 + wa, nr - wa, tmpB));
+    LUCHK(update_cols(sb, c1 + wa, nr - wa, tmpB, ws.s_tmp));
     // L21 is read by both parts of this step's update: transform it after both
     if (la) LUCHK(hipStreamWaitEvent(sb, main_updated, 0));
     // solve-ready form: L21 <- L21 L11^-1 = L21 - L21 (I - L11^-1)
-    LUCHK(P.begin(sb, PROF_TRSM, 8.0 * w * w * (double)nr));
-    LUCHK(launch_copy_block<T>(A + c1 + k0 * ld, ld, tmpB, nr, nr, w, sb));
+    LUCHK(P.begin(sb, PROF_TRSM, 8.0 * w * w * (double)nr * fb));
+    LUCHK(launch_copy_block<T>(A + c1 + k0 * ld, ld, tmpB, nr, nr, w, sb, NB, sA, ws.s_tmp));
     GemmMask mb;
     mb.bkind = GEMM_MASK_STRICT_LOWER;
-    LUCHK(launch_gemm<T>(0, 0, nr, w, w, tmpB, nr, diag, ld, A + c1 + k0 * ld, ld, sb, mb));
+    LUCHK(launch_gemm<T>(0, 0, nr, w, w, tmpB, nr, diag, ld, A + c1 + k0 * ld, ld, sb, mb, NB, ws.s_tmp, sA, sA));
     LUCHK(P.end(sb));
     if (la) {
       LUCHK(new_event(bulk_done));
@@ -867,14 +906,15 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
   if (bulk_done) LUCHK(hipStreamWaitEvent(st, bulk_done, 0));
   // upper parts: diagonal blocks hold I - U11^-1, block columns above hold U01 U11^-1
   LUCHK(P.begin(st, PROF_TRSM, 0.0));
-  LUCHK((launch_block_inv<T, 1>(A, ld, n, nb, 0, nblk, dinv, st)));
+  LUCHK((launch_block_inv<T, 1>(A, ld, n, nb, 0, nblk, dinv, st, NB, sA, ws.s_dinv)));
   for (int bi = 1; bi < nblk; ++bi) {
     const LUBlock& b = plan.blocks[bi];
     const int64_t k0 = b.k0;
-    LUCHK(launch_copy_block<T>(A + k0 * ld, ld, tmpB, k0, k0, b.w, st));
+    LUCHK(launch_copy_block<T>(A + k0 * ld, ld, tmpB, k0, k0, b.w, st, NB, sA, ws.s_tmp));
     GemmMask mu;
     mu.bkind = GEMM_MASK_UPPER;
-    LUCHK(launch_gemm<T>(0, 0, k0, b.w, b.w, tmpB, k0, A + k0 + k0 * ld, ld, A + k0 * ld, ld, st, mu));
+    LUCHK(launch_gemm<T>(0, 0, k0, b.w, b.w, tmpB, k0, A + k0 + k0 * ld, ld, A + k0 * ld, ld, st, mu, NB, ws.s_tmp, sA,
+                         sA));
   }
   LUCHK(P.end(st));
   return hipGetLastError();
@@ -883,14 +923,16 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
 
 template <typename T>
 hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws, void* Bv,
-                    int64_t ldb, int64_t nrhs, hipStream_t st) {
+                    int64_t ldb, int64_t nrhs, hipStream_t st, int64_t sA, int64_t sB) {
   using CT = cplx<T>;
   const CT* A = static_cast<const CT*>(Av);
   CT* Ball = static_cast<CT*>(Bv);
   const int64_t n = plan.n;
   const int nb = plan.nb;
   const int nblk = (int)plan.blocks.size();
+  const int NB = ws.nbatch;
   CT* X = static_cast<CT*>(ws.tmp);
+  const int64_t sX = ws.s_tmp;
   hipError_t e;
   if (nrhs <= 0) return hipSuccess;
   // RHS columns per pass: the block copy needs nb per column; the transposed
@@ -901,6 +943,7 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
     chunk = ws.tmp_elems / per;
     if (chunk < 1) return hipErrorInvalidValue;
   }
+  const int64_t part_elems = (int64_t)NB * sX;  // the transposed partial sums of all items
   for (int64_t r0 = 0; r0 < nrhs; r0 += chunk) {
     const int64_t nr = nrhs - r0 < chunk ? nrhs - r0 : chunk;
     CT* B = Ball + r0 * ldb;
@@ -912,28 +955,29 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
         const int64_t k0 = b.k0;
         const int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;
         const int32_t* src = dst + 2 * nb;
-        hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)nr), dim3(256), 0, st, B, ldb, (int64_t)0, dst, src,
-                           ws.npairs + bi);
-        if ((e = launch_copy_block<T>(B + k0, ldb, X, b.w, b.w, nr, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)nr, NB), dim3(256), 0, st, B, ldb, (int64_t)0, dst, src,
+                           ws.npairs + bi, sB, ws.s_pairs, ws.s_npairs);
+        if ((e = launch_copy_block<T>(B + k0, ldb, X, b.w, b.w, nr, st, NB, sB, sX)) != hipSuccess) return e;
         GemmMask m;
         m.akind = GEMM_MASK_STRICT_LOWER;
         m.ar0 = 0;
         m.adw = b.w;
-        e = small ? launch_skinny_n<T>(n - k0, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, nr, st, m)
-                  : launch_gemm<T>(0, 0, n - k0, nr, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, st, m);
+        e = small ? launch_skinny_n<T>(n - k0, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, nr, st, m, NB, sA, sX, sB)
+                  : launch_gemm<T>(0, 0, n - k0, nr, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, st, m, NB, sA, sX,
+                                   sB);
         if (e != hipSuccess) return e;
       }
       // backward: rows [0, k0 + w) -= [U01 U11^-1 ; I - U11^-1] B_b
       for (int bi = nblk - 1; bi >= 0; --bi) {
         const LUBlock& b = plan.blocks[bi];
         const int64_t k0 = b.k0;
-        if ((e = launch_copy_block<T>(B + k0, ldb, X, b.w, b.w, nr, st)) != hipSuccess) return e;
+        if ((e = launch_copy_block<T>(B + k0, ldb, X, b.w, b.w, nr, st, NB, sB, sX)) != hipSuccess) return e;
         GemmMask m;
         m.akind = GEMM_MASK_UPPER;
         m.ar0 = k0;
         m.adw = b.w;
-        e = small ? launch_skinny_n<T>(k0 + b.w, b.w, A + k0 * ld, ld, X, b.w, B, ldb, nr, st, m)
-                  : launch_gemm<T>(0, 0, k0 + b.w, nr, b.w, A + k0 * ld, ld, X, b.w, B, ldb, st, m);
+        e = small ? launch_skinny_n<T>(k0 + b.w, b.w, A + k0 * ld, ld, X, b.w, B, ldb, nr, st, m, NB, sA, sX, sB)
+                  : launch_gemm<T>(0, 0, k0 + b.w, nr, b.w, A + k0 * ld, ld, X, b.w, B, ldb, st, m, NB, sA, sX, sB);
         if (e != hipSuccess) return e;
       }
     } else {
@@ -944,7 +988,7 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
         const LUBlock& b = plan.blocks[bi];
         const int64_t k0 = b.k0;
         if ((e = launch_skinny_t<T>(b.w, nr, A + k0 * ld, ld, B, ldb, k0, A + k0 + k0 * ld, ld, B + k0, ldb, b.w,
-                                    GEMM_MASK_LOWER, X, ws.tmp_elems, B + k0, ldb, st)) != hipSuccess)
+                                    GEMM_MASK_LOWER, X, part_elems, B + k0, ldb, st, NB, sA, sB, sB)) != hipSuccess)
           return e;
       }
       // then for b = k..1: z_b = L11^-T z_b - (L21 L11^-1)^T z_below, and z = P_b^T z
@@ -952,13 +996,13 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
         const LUBlock& b = plan.blocks[bi];
         const int64_t k0 = b.k0, c1 = k0 + b.w;
         if ((e = launch_skinny_t<T>(b.w, nr, A + c1 + k0 * ld, ld, B + c1, ldb, n - c1, A + k0 + k0 * ld, ld, B + k0,
-                                    ldb, b.w, GEMM_MASK_STRICT_UPPER, X, ws.tmp_elems, B + k0, ldb, st)) !=
+                                    ldb, b.w, GEMM_MASK_STRICT_UPPER, X, part_elems, B + k0, ldb, st, NB, sA, sB, sB)) !=
             hipSuccess)
           return e;
         const int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;
         const int32_t* src = dst + 2 * nb;
-        hipLaunchKernelGGL(row_permute_inv_kernel<T>, dim3((unsigned)nr), dim3(256), 0, st, B, ldb, (int64_t)0, dst,
-                           src, ws.npairs + bi);
+        hipLaunchKernelGGL(row_permute_inv_kernel<T>, dim3((unsigned)nr, NB), dim3(256), 0, st, B, ldb, (int64_t)0, dst,
+                           src, ws.npairs + bi, sB, ws.s_pairs, ws.s_npairs);
       }
     }
   }
@@ -966,12 +1010,12 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
 }
 
 template hipError_t lu_factor<double>(void*, int64_t, const LUPlan&, const LUWork&, int32_t*, hipStream_t, Prof*,
-                                      hipStream_t);
+                                      hipStream_t, int64_t, int64_t);
 template hipError_t lu_factor<float>(void*, int64_t, const LUPlan&, const LUWork&, int32_t*, hipStream_t, Prof*,
-                                     hipStream_t);
+                                     hipStream_t, int64_t, int64_t);
 template hipError_t lu_solve<double>(int, const void*, int64_t, const LUPlan&, const LUWork&, void*, int64_t, int64_t,
-                                     hipStream_t);
+                                     hipStream_t, int64_t, int64_t);
 template hipError_t lu_solve<float>(int, const void*, int64_t, const LUPlan&, const LUWork&, void*, int64_t, int64_t,
-                                    hipStream_t);
+                                    hipStream_t, int64_t, int64_t);
 
 }  // namespace gdm

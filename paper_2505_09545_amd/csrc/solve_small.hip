@@ -46,16 +46,23 @@ __device__ inline void cfma_t(cplx<T>& acc, const cplx<T>& a, const cplx<T>& b) 
 // k range split over its four waves.
 // With PART, blockIdx.z selects the k chunk [z SK_KMAX, (z + 1) SK_KMAX) of a
 // longer product and the sums go to part[(z * nrhs + r) * m + row] instead.
+// Batch: blockIdx.z = item (x nchunk + chunk with PART); item z reads A + z sA,
+// X + z sX and writes C + z sC (PART: its own nchunk x nrhs x m partials).
 template <typename T, int NR, bool PART>
 __global__ void __launch_bounds__(256) skinny_n_kernel(int64_t m, int64_t k, const cplx<T>* __restrict__ A,
                                                         int64_t lda, const cplx<T>* __restrict__ X, int64_t ldx,
                                                         cplx<T>* __restrict__ C, int64_t ldc, int64_t nrhs,
-                                                        GemmMask mk) {
+                                                        GemmMask mk, int nchunk, int64_t sA, int64_t sX, int64_t sC) {
   using CT = cplx<T>;
   __shared__ CT xs[SK_KMAX][NR];
   __shared__ CT red[3][64][NR];
+  const int64_t item = PART ? blockIdx.z / nchunk : blockIdx.z;
+  const int64_t chunk = PART ? blockIdx.z - item * nchunk : 0;
+  A += item * sA;
+  X += item * sX;
+  C += PART ? item * nchunk * nrhs * m : item * sC;
   if (PART) {
-    const int64_t kc0 = (int64_t)blockIdx.z * SK_KMAX;
+    const int64_t kc0 = chunk * SK_KMAX;
     A += kc0 * lda;
     X += kc0;
     k = k - kc0 < SK_KMAX ? k - kc0 : SK_KMAX;
@@ -101,7 +108,7 @@ __global__ void __launch_bounds__(256) skinny_n_kernel(int64_t m, int64_t k, con
         s.y += red[w][lane][r].y;
       }
       if (PART) {
-        C[((int64_t)blockIdx.z * nrhs + r0 + r) * m + row] = s;
+        C[(chunk * nrhs + r0 + r) * m + row] = s;
       } else {
         CT* p = C + row + (r0 + r) * ldc;
         CT c = *p;
@@ -138,9 +145,11 @@ __device__ inline float wave_sum(float v) {
 // blockIdx.x = chunk * ngroups + column group (16 columns, 4 per wave).
 template <typename T, int NR>
 __global__ void __launch_bounds__(256) skinny_t_kernel(SkSeg s0, SkSeg s1, int64_t mo, int64_t nrhs, int ngroups,
-                                                        cplx<T>* __restrict__ part) {
+                                                        cplx<T>* __restrict__ part, int64_t sA, int64_t sB) {
   using CT = cplx<T>;
   __shared__ CT bs[SK_KC][NR];
+  const int64_t item = blockIdx.z;  // batch item: A + item sA, B + item sB, own partials
+  part += item * (int64_t)(s0.nchunk + s1.nchunk) * nrhs * mo;
   const int chunk = blockIdx.x / ngroups, grp = blockIdx.x - chunk * ngroups;
   const bool second = chunk >= s0.nchunk;
   const SkSeg& s = second ? s1 : s0;
@@ -148,8 +157,8 @@ __global__ void __launch_bounds__(256) skinny_t_kernel(SkSeg s0, SkSeg s1, int64
   const int64_t kc1 = kc0 + SK_KC < s.k ? kc0 + SK_KC : s.k;
   const int64_t r0 = (int64_t)blockIdx.y * NR;
   const int nr = (int)(nrhs - r0 < NR ? nrhs - r0 : NR);
-  const CT* A = static_cast<const CT*>(s.A);
-  const CT* B = static_cast<const CT*>(s.B);
+  const CT* A = static_cast<const CT*>(s.A) + item * sA;
+  const CT* B = static_cast<const CT*>(s.B) + item * sB;
   for (int t = threadIdx.x; t < (kc1 - kc0) * NR; t += 256) {
     const int kk = t % (int)(kc1 - kc0), r = t / (int)(kc1 - kc0);
     CT v;
@@ -191,10 +200,13 @@ __global__ void __launch_bounds__(256) skinny_t_kernel(SkSeg s0, SkSeg s1, int64
 // C[i + r ldc] -= sum_chunk part[(chunk * nrhs + r) * mo + i], chunks in order
 template <typename T>
 __global__ void skinny_reduce_kernel(const cplx<T>* __restrict__ part, int nchunk, int64_t mo, int64_t nrhs,
-                                     cplx<T>* __restrict__ C, int64_t ldc) {
+                                     cplx<T>* __restrict__ C, int64_t ldc, int64_t sC) {
   using CT = cplx<T>;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= mo * nrhs) return;
+  // batch item blockIdx.y: its partials follow those of the previous items
+  part += (int64_t)blockIdx.y * nchunk * nrhs * mo;
+  C += (int64_t)blockIdx.y * sC;
   const int64_t r = t / mo, i = t - r * mo;
   CT s;
   s.x = 0;
@@ -215,19 +227,20 @@ static int pick_nr(int64_t nrhs) { return nrhs <= 1 ? 1 : nrhs <= 2 ? 2 : nrhs <
 
 template <typename T>
 hipError_t launch_skinny_n(int64_t m, int64_t k, const void* A, int64_t lda, const void* X, int64_t ldx, void* C,
-                           int64_t ldc, int64_t nrhs, hipStream_t st, GemmMask mk) {
-  if (m <= 0 || nrhs <= 0 || k <= 0) return hipSuccess;
-  if (k > SK_KMAX) return hipErrorInvalidValue;
+                           int64_t ldc, int64_t nrhs, hipStream_t st, GemmMask mk, int nbatch, int64_t sA, int64_t sX,
+                           int64_t sC) {
+  if (m <= 0 || nrhs <= 0 || k <= 0 || nbatch <= 0) return hipSuccess;
+  if (k > SK_KMAX || nbatch > 65535) return hipErrorInvalidValue;
   const int NRp = pick_nr(nrhs);
-  const dim3 grid((unsigned)((m + 63) / 64), (unsigned)((nrhs + NRp - 1) / NRp));
+  const dim3 grid((unsigned)((m + 63) / 64), (unsigned)((nrhs + NRp - 1) / NRp), (unsigned)nbatch);
   const auto* a = static_cast<const cplx<T>*>(A);
   const auto* x = static_cast<const cplx<T>*>(X);
   auto* c = static_cast<cplx<T>*>(C);
   switch (NRp) {
-    case 1: hipLaunchKernelGGL((skinny_n_kernel<T, 1, false>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, c, ldc, nrhs, mk); break;
-    case 2: hipLaunchKernelGGL((skinny_n_kernel<T, 2, false>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, c, ldc, nrhs, mk); break;
-    case 4: hipLaunchKernelGGL((skinny_n_kernel<T, 4, false>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, c, ldc, nrhs, mk); break;
-    default: hipLaunchKernelGGL((skinny_n_kernel<T, 8, false>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, c, ldc, nrhs, mk); break;
+    case 1: hipLaunchKernelGGL((skinny_n_kernel<T, 1, false>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, c, ldc, nrhs, mk, 1, sA, sX, sC); break;
+    case 2: hipLaunchKernelGGL((skinny_n_kernel<T, 2, false>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, c, ldc, nrhs, mk, 1, sA, sX, sC); break;
+    case 4: hipLaunchKernelGGL((skinny_n_kernel<T, 4, false>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, c, ldc, nrhs, mk, 1, sA, sX, sC); break;
+    default: hipLaunchKernelGGL((skinny_n_kernel<T, 8, false>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, c, ldc, nrhs, mk, 1, sA, sX, sC); break;
   }
   return hipGetLastError();
 }
@@ -238,25 +251,28 @@ int64_t skinny_n_long_parts(int64_t m, int64_t k, int64_t nrhs) {
 
 template <typename T>
 hipError_t launch_skinny_n_long(int64_t m, int64_t k, const void* A, int64_t lda, const void* X, int64_t ldx, void* C,
-                                int64_t ldc, int64_t nrhs, void* part, int64_t part_elems, hipStream_t st) {
-  if (m <= 0 || nrhs <= 0 || k <= 0) return hipSuccess;
+                                int64_t ldc, int64_t nrhs, void* part, int64_t part_elems, hipStream_t st, int nbatch,
+                                int64_t sA, int64_t sX, int64_t sC) {
+  if (m <= 0 || nrhs <= 0 || k <= 0 || nbatch <= 0) return hipSuccess;
   const int64_t nchunk = (k + SK_KMAX - 1) / SK_KMAX;
-  if (skinny_n_long_parts(m, k, nrhs) > part_elems || nchunk > 65535) return hipErrorInvalidValue;
+  if (nbatch * skinny_n_long_parts(m, k, nrhs) > part_elems || nchunk * nbatch > 65535 || nbatch > 65535)
+    return hipErrorInvalidValue;
   const int NRp = pick_nr(nrhs);
-  const dim3 grid((unsigned)((m + 63) / 64), (unsigned)((nrhs + NRp - 1) / NRp), (unsigned)nchunk);
+  const dim3 grid((unsigned)((m + 63) / 64), (unsigned)((nrhs + NRp - 1) / NRp), (unsigned)(nchunk * nbatch));
   const auto* a = static_cast<const cplx<T>*>(A);
   const auto* x = static_cast<const cplx<T>*>(X);
   auto* p = static_cast<cplx<T>*>(part);
   const GemmMask mk{};
+  const int nc = (int)nchunk;
   switch (NRp) {
-    case 1: hipLaunchKernelGGL((skinny_n_kernel<T, 1, true>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, p, m, nrhs, mk); break;
-    case 2: hipLaunchKernelGGL((skinny_n_kernel<T, 2, true>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, p, m, nrhs, mk); break;
-    case 4: hipLaunchKernelGGL((skinny_n_kernel<T, 4, true>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, p, m, nrhs, mk); break;
-    default: hipLaunchKernelGGL((skinny_n_kernel<T, 8, true>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, p, m, nrhs, mk); break;
+    case 1: hipLaunchKernelGGL((skinny_n_kernel<T, 1, true>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, p, m, nrhs, mk, nc, sA, sX, (int64_t)0); break;
+    case 2: hipLaunchKernelGGL((skinny_n_kernel<T, 2, true>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, p, m, nrhs, mk, nc, sA, sX, (int64_t)0); break;
+    case 4: hipLaunchKernelGGL((skinny_n_kernel<T, 4, true>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, p, m, nrhs, mk, nc, sA, sX, (int64_t)0); break;
+    default: hipLaunchKernelGGL((skinny_n_kernel<T, 8, true>), grid, dim3(256), 0, st, m, k, a, lda, x, ldx, p, m, nrhs, mk, nc, sA, sX, (int64_t)0); break;
   }
   const int64_t tot = m * nrhs;
-  hipLaunchKernelGGL(skinny_reduce_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, p, (int)nchunk, m,
-                     nrhs, static_cast<cplx<T>*>(C), ldc);
+  hipLaunchKernelGGL(skinny_reduce_kernel<T>, dim3((unsigned)((tot + 255) / 256), (unsigned)nbatch), dim3(256), 0, st, p,
+                     nc, m, nrhs, static_cast<cplx<T>*>(C), ldc, sC);
   return hipGetLastError();
 }
 
@@ -267,44 +283,47 @@ int64_t skinny_t_chunks(int64_t k0, int64_t k1) {
 template <typename T>
 hipError_t launch_skinny_t(int64_t mo, int64_t nrhs, const void* A0, int64_t lda0, const void* B0, int64_t ldb0,
                            int64_t k0, const void* A1, int64_t lda1, const void* B1, int64_t ldb1, int64_t k1,
-                           int kind1, void* part, int64_t part_elems, void* C, int64_t ldc, hipStream_t st) {
-  if (mo <= 0 || nrhs <= 0) return hipSuccess;
+                           int kind1, void* part, int64_t part_elems, void* C, int64_t ldc, hipStream_t st, int nbatch,
+                           int64_t sA, int64_t sB, int64_t sC) {
+  if (mo <= 0 || nrhs <= 0 || nbatch <= 0) return hipSuccess;
   SkSeg s0{A0, lda0, B0, ldb0, k0, 0, (int)((k0 + SK_KC - 1) / SK_KC)};
   SkSeg s1{A1, lda1, B1, ldb1, k1, kind1, (int)((k1 + SK_KC - 1) / SK_KC)};
   const int nchunk = s0.nchunk + s1.nchunk;
   if (nchunk == 0) return hipSuccess;
-  if ((int64_t)nchunk * nrhs * mo > part_elems) return hipErrorInvalidValue;
+  if ((int64_t)nbatch * nchunk * nrhs * mo > part_elems || nbatch > 65535) return hipErrorInvalidValue;
   const int64_t ngroups = (mo + SK_TCOLS - 1) / SK_TCOLS;
   if ((int64_t)nchunk * ngroups > INT32_MAX) return hipErrorInvalidValue;
   const int NRp = pick_nr(nrhs);
-  const dim3 grid((unsigned)(nchunk * ngroups), (unsigned)((nrhs + NRp - 1) / NRp));
+  const dim3 grid((unsigned)(nchunk * ngroups), (unsigned)((nrhs + NRp - 1) / NRp), (unsigned)nbatch);
   auto* p = static_cast<cplx<T>*>(part);
   const int ng = (int)ngroups;
   switch (NRp) {
-    case 1: hipLaunchKernelGGL((skinny_t_kernel<T, 1>), grid, dim3(256), 0, st, s0, s1, mo, nrhs, ng, p); break;
-    case 2: hipLaunchKernelGGL((skinny_t_kernel<T, 2>), grid, dim3(256), 0, st, s0, s1, mo, nrhs, ng, p); break;
-    case 4: hipLaunchKernelGGL((skinny_t_kernel<T, 4>), grid, dim3(256), 0, st, s0, s1, mo, nrhs, ng, p); break;
-    default: hipLaunchKernelGGL((skinny_t_kernel<T, 8>), grid, dim3(256), 0, st, s0, s1, mo, nrhs, ng, p); break;
+    case 1: hipLaunchKernelGGL((skinny_t_kernel<T, 1>), grid, dim3(256), 0, st, s0, s1, mo, nrhs, ng, p, sA, sB); break;
+    case 2: hipLaunchKernelGGL((skinny_t_kernel<T, 2>), grid, dim3(256), 0, st, s0, s1, mo, nrhs, ng, p, sA, sB); break;
+    case 4: hipLaunchKernelGGL((skinny_t_kernel<T, 4>), grid, dim3(256), 0, st, s0, s1, mo, nrhs, ng, p, sA, sB); break;
+    default: hipLaunchKernelGGL((skinny_t_kernel<T, 8>), grid, dim3(256), 0, st, s0, s1, mo, nrhs, ng, p, sA, sB); break;
   }
   const int64_t tot = mo * nrhs;
-  hipLaunchKernelGGL(skinny_reduce_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, p, nchunk, mo,
-                     nrhs, static_cast<cplx<T>*>(C), ldc);
+  hipLaunchKernelGGL(skinny_reduce_kernel<T>, dim3((unsigned)((tot + 255) / 256), (unsigned)nbatch), dim3(256), 0, st, p,
+                     nchunk, mo, nrhs, static_cast<cplx<T>*>(C), ldc, sC);
   return hipGetLastError();
 }
 
 template hipError_t launch_skinny_n<double>(int64_t, int64_t, const void*, int64_t, const void*, int64_t, void*,
-                                            int64_t, int64_t, hipStream_t, GemmMask);
+                                            int64_t, int64_t, hipStream_t, GemmMask, int, int64_t, int64_t, int64_t);
 template hipError_t launch_skinny_n<float>(int64_t, int64_t, const void*, int64_t, const void*, int64_t, void*,
-                                           int64_t, int64_t, hipStream_t, GemmMask);
+                                           int64_t, int64_t, hipStream_t, GemmMask, int, int64_t, int64_t, int64_t);
 template hipError_t launch_skinny_n_long<double>(int64_t, int64_t, const void*, int64_t, const void*, int64_t, void*,
-                                                 int64_t, int64_t, void*, int64_t, hipStream_t);
+                                                 int64_t, int64_t, void*, int64_t, hipStream_t, int, int64_t, int64_t,
+                                                 int64_t);
 template hipError_t launch_skinny_n_long<float>(int64_t, int64_t, const void*, int64_t, const void*, int64_t, void*,
-                                                int64_t, int64_t, void*, int64_t, hipStream_t);
+                                                int64_t, int64_t, void*, int64_t, hipStream_t, int, int64_t, int64_t,
+                                                int64_t);
 template hipError_t launch_skinny_t<double>(int64_t, int64_t, const void*, int64_t, const void*, int64_t, int64_t,
                                             const void*, int64_t, const void*, int64_t, int64_t, int, void*, int64_t,
-                                            void*, int64_t, hipStream_t);
+                                            void*, int64_t, hipStream_t, int, int64_t, int64_t, int64_t);
 template hipError_t launch_skinny_t<float>(int64_t, int64_t, const void*, int64_t, const void*, int64_t, int64_t,
                                            const void*, int64_t, const void*, int64_t, int64_t, int, void*, int64_t,
-                                           void*, int64_t, hipStream_t);
+                                           void*, int64_t, hipStream_t, int, int64_t, int64_t, int64_t);
 
 }  // namespace gdm
