@@ -167,6 +167,34 @@ gdm_status gdm_adjoint(gdm_ctx* ctx, int64_t n_rhs, const double* khat, const do
                        const double* r_probe, const double* g_e, double tol, int32_t max_iter, double* grad_r,
                        double* grad_eps, double* grad_wl, gdm_info* info);
 
+/* Batched spectra (the paper's spectra over wavelengths and structures, Sec.
+ * "Implementation technical details"): for every structure s and wavelength l
+ * solve the system of the structure's cubic cells with one permittivity
+ * eps[s][l] for all its cells, and write the extinction, scattering and
+ * absorption cross sections of n_pw plane waves.  The systems of one structure
+ * are solved in groups that share every launch (assembly, LU, solve,
+ * refinement, cross sections); each group shape is captured once into a HIP
+ * graph and replayed; the group size and LU panel width are measured on the
+ * first groups of each size class (kept in the context for later calls).
+ *   cell_offset [n_struct + 1] HOST: structure s owns cells cell_offset[s] ..
+ *       cell_offset[s+1] - 1 of r_cell [total][3] (device, nm); step_nm
+ *       [n_struct] HOST; wavelengths [n_wl] HOST (nm);
+ *   eps [n_struct][n_wl] complex (device); khat [n_pw][3], e0 [n_pw][3] complex
+ *       (device) as in gdm_incident_planewave; the environment index is the
+ *       context's (gdm_set_environment), `selfterm` as in gdm_set_structure;
+ *   prec GDM_PREC_FP32_IR: FP32 LU and exactly ir_iters FP64 refinement
+ *       corrections (ir_iters < 0 selects 2), be_out [n_struct][n_wl] (device,
+ *       may be NULL) receives each system's normwise backward error after them;
+ *       GDM_PREC_FP64: FP64 LU, be_out not written;
+ *   cs_out [n_struct][n_wl][n_pw][3] (device) = (ext, sca = ext - abs, abs) nm^2.
+ * info->backward_err = max of be_out, info->ms_factor = GPU time of the whole
+ * batch.  GDM_E_OOM if a structure does not fit; GDM_E_SINGULAR on an exactly
+ * zero pivot.  Cells only (no effective dipoles); at most 65535 plane waves. */
+gdm_status gdm_batch_spectra(gdm_ctx* ctx, int64_t n_struct, const int64_t* cell_offset, const double* r_cell,
+                             const double* step_nm, int64_t n_wl, const double* wavelengths, const double* eps,
+                             int64_t n_pw, const double* khat, const double* e0, gdm_precision prec, int32_t ir_iters,
+                             gdm_selfterm selfterm, double* cs_out, double* be_out, gdm_info* info);
+
 /* Dense LU of a caller matrix (dtype 0: complex double, 1: complex float),
  * column-major n x n, leading dimension lda, factored in place; ipiv [n]
  * receives 0-based pivot rows.  The factors are in the library's factored form

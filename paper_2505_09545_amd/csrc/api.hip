@@ -1,6 +1,7 @@
 // C-ABI of libgdm (declared in include/gdm.h): context, device buffers, argument
 // validation and the host drivers that chain the kernels of the hot path.
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -12,6 +13,7 @@
 #include "gdm_kernels.hpp"
 #include "gdm_misc.hpp"
 #include "gdm_adjoint.hpp"
+#include "gdm_batch.hpp"
 
 using namespace gdm;
 
@@ -84,6 +86,9 @@ struct gdm_ctx {
   DevBuf X, Rr, C32, small, scratch, flag;
   DevBuf Lam, adj;  // adjoint field and adjoint workspace
   DevBuf part;      // split-k partial sums of the small-RHS refinement residual
+  // batched spectra: workspaces and the measured batch configuration per size class
+  DevBuf bM64, bM32, bipiv, bws, bvec, bpart, bsmall, bpos, bwl;
+  std::map<int64_t, std::pair<int, int>> batch_tune;  // n / 256 -> (items per group, nb)
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   float ms_assemble = 0, ms_factor = 0;
   Prof prof;
@@ -296,6 +301,362 @@ static gdm_status solve_core(gdm_ctx* c, int trans, int64_t nrhs, const double2*
 }
 
 
+// ---------------------------------------------------------------------------
+// batched spectra
+// ---------------------------------------------------------------------------
+namespace {
+
+struct BatchShape {
+  int64_t n = 0;
+  int B = 0;
+  int nb = 0;
+  LUPlan plan;
+};
+
+// Device views of the batched workspaces (pointers fixed for the whole call, so
+// that a captured group graph can be replayed for every group of the same shape).
+struct BatchBufs {
+  double2* M64;
+  float2* M32;
+  int32_t* ipiv;
+  void* ws;
+  double2 *F0, *X, *R, *Q;
+  float2* C32;
+  void* part;
+  int64_t part_elems;
+  double *rmax, *xmax, *bmax, *cmax, *minf, *rows, *sums5, *k0, *cs, *be, *be_max;
+  double2* alpha;
+  int32_t* sticky;
+  double* pos;
+  double* wl;
+};
+
+int64_t batch_part_elems(int64_t n, int B, int64_t npw) {
+  return npw <= SKINNY_MAX_RHS ? (int64_t)B * skinny_n_long_parts(n, n, npw) : 0;
+}
+
+}  // namespace
+
+static bool batch_shape_for(gdm_ctx* c, int64_t n, int B, int nb_max, bool ir, BatchShape& sh) {
+  const int eb = ir ? 4 : 8;
+  sh.n = n;
+  sh.B = B;
+  sh.plan = lu_plan(n, eb, c->num_cu, c->lds_bytes, B, nb_max);
+  sh.nb = sh.plan.nb;
+  return sh.plan.nb >= 32 && lu_plan_fits(sh.plan) && sh.plan.max_wg * B <= c->num_cu;
+}
+
+static size_t batch_item_bytes(int64_t n, bool ir) { return (size_t)n * n * (ir ? 24 : 16); }
+
+// Enqueue the whole pipeline of one group on c->stream (captured into a graph by
+// the caller): assembly, LU, incident field, solve with a fixed number of FP64
+// refinement corrections and the backward error, q = alpha F, cross sections.
+static gdm_status batch_enqueue_group(gdm_ctx* c, const BatchShape& sh, const BatchBufs& b, int64_t npw,
+                                      const double* khat, const double2* e0, bool ir, int ir_iters, int radiative,
+                                      double step) {
+  const int64_t n = sh.n, N = n / 3, nn = n * n, sv = npw * n;
+  const int B = sh.B;
+  const int64_t cols = (int64_t)B * npw;
+  hipStream_t st = c->stream;
+  LUWork w;
+  lu_workspace_carve(b.ws, sh.plan, ir ? 4 : 8, c->num_cu, w, B);
+  w.events = &c->lu_events;
+  HIPCHK(c, launch_batch_assemble(b.pos, N, b.alpha, b.k0, c->n_env, step, radiative, b.M64, ir ? b.M32 : nullptr, B,
+                                  st));
+  if (ir) HIPCHK(c, launch_batch_minf(b.M64, n, B, b.rows, b.minf, st));
+  if (ir)
+    HIPCHK(c, lu_factor<float>(b.M32, n, sh.plan, w, b.ipiv, st, nullptr, c->lookahead ? c->side : nullptr, nn, n));
+  else
+    HIPCHK(c, lu_factor<double>(b.M64, n, sh.plan, w, b.ipiv, st, nullptr, c->lookahead ? c->side : nullptr, nn, n));
+  HIPCHK(c, launch_batch_err(w.err, b.sticky, st));
+  HIPCHK(c, launch_batch_incident(b.pos, n, b.k0, c->n_env, npw, khat, e0, b.F0, B, st));
+  auto residual = [&]() -> hipError_t {
+    // R = F0 - M X per item (FP64, stored FP64 matrix)
+    hipError_t e = launch_copy_d(b.F0, n, b.R, n, n, cols, st);
+    if (e != hipSuccess) return e;
+    if (npw <= SKINNY_MAX_RHS)
+      return launch_skinny_n_long<double>(n, n, b.M64, n, b.X, n, b.R, n, npw, b.part, b.part_elems, st, B, nn, sv, sv);
+    return launch_gemm<double>(0, 0, n, npw, n, b.M64, n, b.X, n, b.R, n, st, GemmMask{}, B, nn, sv, sv);
+  };
+  if (!ir) {
+    HIPCHK(c, launch_copy_d(b.F0, n, b.X, n, n, cols, st));
+    HIPCHK(c, lu_solve<double>(0, b.M64, n, sh.plan, w, b.X, n, npw, st, nn, sv));
+  } else {
+    HIPCHK(c, launch_convert_d2f(b.F0, n, b.C32, n, n, cols, st));
+    HIPCHK(c, lu_solve<float>(0, b.M32, n, sh.plan, w, b.C32, n, npw, st, nn, sv));
+    HIPCHK(c, launch_convert_f2d(b.C32, n, b.X, n, n, cols, st));
+    for (int it = 0; it < ir_iters; ++it) {
+      HIPCHK(c, residual());
+      HIPCHK(c, launch_convert_d2f(b.R, n, b.C32, n, n, cols, st));
+      HIPCHK(c, lu_solve<float>(0, b.M32, n, sh.plan, w, b.C32, n, npw, st, nn, sv));
+      HIPCHK(c, launch_axpy_f2d(b.C32, n, b.X, n, n, cols, b.cmax, st));
+    }
+    HIPCHK(c, residual());
+    HIPCHK(c, launch_colmax(b.R, n, n, cols, b.rmax, st));
+    HIPCHK(c, launch_colmax(b.X, n, n, cols, b.xmax, st));
+    HIPCHK(c, launch_colmax(b.F0, n, n, cols, b.bmax, st));
+    HIPCHK(c, launch_batch_be(b.rmax, b.xmax, b.bmax, b.minf, npw, B, b.be, st));
+  }
+  HIPCHK(c, launch_batch_apply_alpha(b.alpha, b.X, b.Q, n, npw, B, st));
+  DipoleView d{};
+  d.pos = b.pos;
+  d.N = N;
+  d.nc = N;
+  d.ne = 0;
+  HIPCHK(c, launch_cs_sums(d, b.F0, b.Q, b.X, n, cols, b.sums5, st));
+  HIPCHK(c, launch_batch_cs(b.sums5, b.k0, c->n_env, e0, npw, B, b.cs, st));
+  return GDM_OK;
+}
+
+static gdm_status batch_capture(gdm_ctx* c, const BatchShape& sh, const BatchBufs& b, int64_t npw, const double* khat,
+                                const double2* e0, bool ir, int ir_iters, int radiative, double step,
+                                hipGraphExec_t* exec) {
+  // one-time settings and event pool before the capture
+  if (ir) HIPCHK(c, lu_prepare<float>(sh.plan));
+  else HIPCHK(c, lu_prepare<double>(sh.plan));
+  while (c->lu_events.size() < 4 * sh.plan.blocks.size() + 8) {
+    hipEvent_t x;
+    HIPCHK(c, hipEventCreateWithFlags(&x, hipEventDisableTiming));
+    c->lu_events.push_back(x);
+  }
+  const bool prof_on = c->prof.on;
+  c->prof.on = false;
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  gdm_status s = batch_enqueue_group(c, sh, b, npw, khat, e0, ir, ir_iters, radiative, step);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(c->stream, &g);
+  c->prof.on = prof_on;
+  if (s != GDM_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return s;
+  }
+  HIPCHK(c, e);
+  e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHK(c, e);
+  return GDM_OK;
+}
+
+extern "C" gdm_status gdm_batch_spectra(gdm_ctx* c, int64_t n_struct, const int64_t* cell_offset,
+                                        const double* r_cell, const double* step_nm, int64_t n_wl,
+                                        const double* wavelengths, const double* eps, int64_t n_pw, const double* khat,
+                                        const double* e0, gdm_precision prec, int32_t ir_iters, gdm_selfterm selfterm,
+                                        double* cs_out, double* be_out, gdm_info* info) {
+  if (!c) return GDM_E_ARG;
+  if (n_struct <= 0 || !cell_offset || !r_cell || !step_nm || n_wl <= 0 || !wavelengths || !eps || n_pw <= 0 ||
+      !khat || !e0 || !cs_out)
+    FAIL(c, GDM_E_ARG, "bad batch arguments");
+  if (prec != GDM_PREC_FP64 && prec != GDM_PREC_FP32_IR) FAIL(c, GDM_E_ARG, "unknown precision");
+  if (selfterm != GDM_SELF_STATIC && selfterm != GDM_SELF_RADIATIVE) FAIL(c, GDM_E_ARG, "unknown self-term mode");
+  if (n_pw > 65535 || n_wl > (int64_t)INT32_MAX) FAIL(c, GDM_E_ARG, "too many plane waves or wavelengths");
+  if (cell_offset[0] != 0) FAIL(c, GDM_E_ARG, "cell_offset[0] must be 0");
+  int64_t nmax = 0;
+  for (int64_t s = 0; s < n_struct; ++s) {
+    const int64_t N = cell_offset[s + 1] - cell_offset[s];
+    if (N <= 0) FAIL(c, GDM_E_ARG, "structure %lld has no cells", (long long)s);
+    if (3 * N > 200000) FAIL(c, GDM_E_ARG, "structure %lld too large for the batched driver", (long long)s);
+    if (!(step_nm[s] > 0.0) || !std::isfinite(step_nm[s])) FAIL(c, GDM_E_ARG, "step_nm[%lld] must be > 0", (long long)s);
+    nmax = std::max(nmax, 3 * N);
+  }
+  for (int64_t l = 0; l < n_wl; ++l)
+    if (!(wavelengths[l] > 0.0) || !std::isfinite(wavelengths[l])) FAIL(c, GDM_E_ARG, "wavelengths must be > 0");
+  if (ir_iters < 0) ir_iters = 2;
+  if (ir_iters > 20) FAIL(c, GDM_E_ARG, "at most 20 refinement corrections");
+  const bool ir = prec == GDM_PREC_FP32_IR;
+  const int radiative = selfterm == GDM_SELF_RADIATIVE ? 1 : 0;
+  HIPCHK(c, hipSetDevice(c->device));
+  size_t free_b = 0, total_b = 0;
+  HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
+  const size_t budget = std::min<size_t>(free_b / 2, (size_t)64 << 30);
+
+  // largest feasible group per structure size: panels of all items co-resident,
+  // matrices within the memory budget, at most 32 items and n_wl
+  auto bmax_for = [&](int64_t n) {
+    int best = 0;
+    for (int B = 1; B <= 32 && B <= n_wl; B *= 2) {
+      BatchShape sh;
+      if (batch_shape_for(c, n, B, 128, ir, sh) && (size_t)B * batch_item_bytes(n, ir) <= budget) best = B;
+    }
+    return best;
+  };
+  // size the workspaces for the largest group any structure may use
+  size_t m_elems = 0, ws_bytes = 0, vec_elems = 0, part_elems = 0, pos_elems = 0;
+  int Bcap = 0;
+  std::vector<int> bmax(n_struct);
+  for (int64_t s = 0; s < n_struct; ++s) {
+    const int64_t n = 3 * (cell_offset[s + 1] - cell_offset[s]);
+    bmax[s] = bmax_for(n);
+    if (bmax[s] == 0) FAIL(c, GDM_E_OOM, "structure %lld (n = %lld) does not fit the batched driver", (long long)s, (long long)n);
+    for (int B = 1; B <= bmax[s]; B *= 2)
+      for (int nbm : {128, 64}) {
+        BatchShape sh;
+        if (!batch_shape_for(c, n, B, nbm, ir, sh)) continue;
+        ws_bytes = std::max(ws_bytes, lu_workspace_bytes(sh.plan, ir ? 4 : 8, c->num_cu, B));
+      }
+    m_elems = std::max(m_elems, (size_t)bmax[s] * n * n);
+    vec_elems = std::max(vec_elems, (size_t)bmax[s] * n_pw * n);
+    part_elems = std::max(part_elems, (size_t)batch_part_elems(n, bmax[s], n_pw));
+    pos_elems = std::max(pos_elems, (size_t)n);
+    Bcap = std::max(Bcap, bmax[s]);
+  }
+  HIPCHK(c, c->bM64.ensure(sizeof(double2) * m_elems));
+  if (ir) HIPCHK(c, c->bM32.ensure(sizeof(float2) * m_elems));
+  HIPCHK(c, c->bipiv.ensure(sizeof(int32_t) * (size_t)Bcap * nmax));
+  HIPCHK(c, c->bws.ensure(ws_bytes));
+  HIPCHK(c, c->bvec.ensure(sizeof(double2) * 4 * vec_elems + sizeof(float2) * vec_elems + 256));
+  HIPCHK(c, c->bpart.ensure(sizeof(double2) * std::max<size_t>(part_elems, 1)));
+  const size_t ncol = (size_t)Bcap * n_pw;
+  const size_t nsmall = 4 * ncol + 2 * (size_t)Bcap + (size_t)Bcap * nmax + 5 * ncol + (size_t)Bcap + 3 * ncol +
+                        (size_t)Bcap + 1 + 2 * (size_t)Bcap + 64;
+  HIPCHK(c, c->bsmall.ensure(sizeof(double) * nsmall));
+  HIPCHK(c, c->bpos.ensure(sizeof(double) * pos_elems));
+  HIPCHK(c, c->bwl.ensure(sizeof(double) * n_wl));
+  HIPCHK(c, hipMemcpyAsync(c->bwl.p, wavelengths, sizeof(double) * n_wl, hipMemcpyHostToDevice, c->stream));
+  BatchBufs b{};
+  b.M64 = c->bM64.as<double2>();
+  b.M32 = ir ? c->bM32.as<float2>() : nullptr;
+  b.ipiv = c->bipiv.as<int32_t>();
+  b.ws = c->bws.p;
+  b.F0 = c->bvec.as<double2>();
+  b.X = b.F0 + vec_elems;
+  b.R = b.X + vec_elems;
+  b.Q = b.R + vec_elems;
+  b.C32 = reinterpret_cast<float2*>(b.Q + vec_elems);
+  b.part = c->bpart.p;
+  b.part_elems = (int64_t)std::max<size_t>(part_elems, 1);
+  double* sp = c->bsmall.as<double>();
+  b.rmax = sp; sp += ncol;
+  b.xmax = sp; sp += ncol;
+  b.bmax = sp; sp += ncol;
+  b.cmax = sp; sp += ncol;
+  b.minf = sp; sp += Bcap;
+  b.k0 = sp; sp += Bcap;
+  b.rows = sp; sp += (size_t)Bcap * nmax;
+  b.sums5 = sp; sp += 5 * ncol;
+  b.be = sp; sp += Bcap;
+  b.cs = sp; sp += 3 * ncol;
+  b.be_max = sp; sp += 1;
+  b.alpha = reinterpret_cast<double2*>(sp); sp += 2 * (size_t)Bcap;
+  b.sticky = reinterpret_cast<int32_t*>(sp);
+  b.pos = c->bpos.as<double>();
+  b.wl = c->bwl.as<double>();
+  HIPCHK(c, launch_batch_err_init(b.sticky, c->stream));
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int*>(b.be_max), 2, 0);
+  const double2* E0 = reinterpret_cast<const double2*>(e0);
+  const double2* EPS = reinterpret_cast<const double2*>(eps);
+
+  struct Cached {
+    int64_t n;
+    int B, nb;
+    double step;
+    hipGraphExec_t exec;
+  };
+  std::vector<Cached> graphs;
+  auto release = [&]() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.exec);
+    graphs.clear();
+  };
+  hipEvent_t t0, t1, tstart, tend;
+  HIPCHK(c, hipEventCreate(&t0));
+  HIPCHK(c, hipEventCreate(&t1));
+  HIPCHK(c, hipEventCreate(&tstart));
+  HIPCHK(c, hipEventCreate(&tend));
+  HIPCHK(c, hipEventRecord(tstart, c->stream));
+  gdm_status status = GDM_OK;
+  int64_t items_done = 0;
+  for (int64_t s = 0; s < n_struct && status == GDM_OK; ++s) {
+    const int64_t N = cell_offset[s + 1] - cell_offset[s], n = 3 * N;
+    const double step = step_nm[s];
+    HIPCHK(c, hipMemcpyAsync(b.pos, r_cell + 3 * cell_offset[s], sizeof(double) * 3 * N, hipMemcpyDeviceToDevice,
+                             c->stream));
+    // batch configuration: measured for this size class, or measured now on the
+    // first groups of this structure (they are real work, not discarded)
+    // candidates: (items per group, panel width), distinct actual shapes only
+    std::vector<std::pair<int, int>> cand;
+    const int64_t key = n / 256;
+    auto it = c->batch_tune.find(key);
+    auto add_cand = [&](int B, int nbm) {
+      BatchShape sh;
+      if (!batch_shape_for(c, n, B, nbm, ir, sh)) return;
+      for (auto& x : cand)
+        if (x.first == B && x.second == sh.nb) return;
+      cand.push_back({B, sh.nb});
+    };
+    if (it != c->batch_tune.end() && it->second.first <= bmax[s]) add_cand(it->second.first, it->second.second);
+    if (cand.empty()) {
+      for (int B = bmax[s]; B >= 1 && (int)cand.size() < 3; B /= 2) add_cand(B, 128);
+      add_cand(bmax[s], 64);
+    }
+    double best_rate = -1.0;
+    std::pair<int, int> best = cand[0];
+    size_t ci = 0;
+    for (int64_t l0 = 0; l0 < n_wl && status == GDM_OK;) {
+      const bool tuning = cand.size() > 1 && ci < cand.size();
+      const std::pair<int, int> cfg = tuning ? cand[ci] : best;
+      BatchShape sh;
+      if (!batch_shape_for(c, n, cfg.first, cfg.second, ir, sh)) {
+        status = GDM_E_STATE;
+        break;
+      }
+      hipGraphExec_t ex = nullptr;
+      for (auto& g : graphs)
+        if (g.n == sh.n && g.B == sh.B && g.nb == sh.nb && g.step == step) ex = g.exec;
+      if (!ex) {
+        status = batch_capture(c, sh, b, n_pw, khat, E0, ir, ir_iters, radiative, step, &ex);
+        if (status != GDM_OK) break;
+        graphs.push_back({sh.n, sh.B, sh.nb, step, ex});
+      }
+      const int64_t nvalid = std::min<int64_t>(sh.B, n_wl - l0);
+      HIPCHK(c, launch_batch_stage(EPS, n_wl, s, l0, nvalid, sh.B, b.wl, c->n_env * c->n_env, step, b.alpha, b.k0,
+                                   c->stream));
+      HIPCHK(c, hipEventRecord(t0, c->stream));
+      HIPCHK(c, hipGraphLaunch(ex, c->stream));
+      HIPCHK(c, hipEventRecord(t1, c->stream));
+      HIPCHK(c, launch_batch_unstage(b.cs, ir ? b.be : nullptr, nvalid, n_pw, s * n_wl + l0, cs_out,
+                                     ir ? be_out : nullptr, c->stream));
+      if (ir) HIPCHK(c, launch_batch_bemax(b.be, nvalid, b.be_max, c->stream));
+      if (tuning) {
+        // the candidates run on real groups (results kept); rate = items per ms
+        HIPCHK(c, hipEventSynchronize(t1));
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, t0, t1);
+        const double rate = (double)sh.B / std::max(ms, 1e-3f);
+        if (rate > best_rate) {
+          best_rate = rate;
+          best = cfg;
+        }
+        if (++ci == cand.size()) c->batch_tune[key] = best;
+      }
+      items_done += nvalid;
+      l0 += nvalid;
+    }
+  }
+  (void)items_done;
+  HIPCHK(c, hipEventRecord(tend, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float ms_total = 0.f;
+  (void)hipEventElapsedTime(&ms_total, tstart, tend);
+  int32_t sticky[2] = {0, 0};
+  double be_max = 0.0;
+  HIPCHK(c, hipMemcpy(sticky, b.sticky, sizeof(sticky), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(&be_max, b.be_max, sizeof(double), hipMemcpyDeviceToHost));
+  release();
+  for (hipEvent_t ev : {t0, t1, tstart, tend}) (void)hipEventDestroy(ev);
+  if (status != GDM_OK) return status;
+  if (info) {
+    info->ir_iters = ir ? ir_iters : 0;
+    info->backward_err = ir ? be_max : 0.0;
+    info->bad_index = -1;
+    info->ms_factor = ms_total;
+  }
+  if (sticky[0]) FAIL(c, GDM_E_DEVICE, "LU panel exchange timed out in the batched driver");
+  if (sticky[1] != INT32_MAX) {
+    if (info) info->bad_index = sticky[1];
+    FAIL(c, GDM_E_SINGULAR, "exactly zero pivot in column %d of a batched system", sticky[1]);
+  }
+  return GDM_OK;
+}
+
 extern "C" {
 
 gdm_status gdm_create(int device, void* hip_stream, gdm_ctx** out) {
@@ -334,7 +695,8 @@ void gdm_destroy(gdm_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   for (DevBuf* b : {&c->pos, &c->eps, &c->alpha_c, &c->alpha6, &c->M, &c->M64, &c->ipiv, &c->luws, &c->rows,
-                    &c->ext_ws, &c->X, &c->Rr, &c->C32, &c->small, &c->scratch, &c->flag, &c->Lam, &c->adj, &c->part})
+                    &c->ext_ws, &c->X, &c->Rr, &c->C32, &c->small, &c->scratch, &c->flag, &c->Lam, &c->adj, &c->part, &c->bM64, &c->bM32, &c->bipiv,
+                    &c->bws, &c->bvec, &c->bpart, &c->bsmall, &c->bpos, &c->bwl})
     b->release();
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);

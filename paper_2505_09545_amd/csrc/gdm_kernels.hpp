@@ -141,7 +141,10 @@ struct LUWork {
 
 // nbatch: number of same-size items factored together (their panels share one
 // launch, so each panel gets at most num_cu / nbatch workgroups).
-LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch = 1);
+LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch = 1, int nb_max = 128);
+// one-time host-side kernel settings for a plan (call before graph capture)
+template <typename T>
+hipError_t lu_prepare(const LUPlan& plan);
 bool lu_plan_fits(const LUPlan& p);
 size_t lu_workspace_bytes(const LUPlan& p, int elem_bytes, int num_cu, int nbatch = 1);
 void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu, LUWork& w, int nbatch = 1);

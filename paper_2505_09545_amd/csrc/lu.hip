@@ -673,14 +673,14 @@ static size_t panel_lds_bytes(int w, int R, size_t cbytes) {
   return ((size_t)w * R + w + R) * cbytes + (size_t)(R + w) * 4;
 }
 
-LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch) {
+LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch, int nb_max) {
   LUPlan p;
   p.n = n;
   if (nbatch < 1) nbatch = 1;
   // the panels of all items run in one launch and must all be resident
   p.max_wg = num_cu / nbatch > 0 ? num_cu / nbatch : 1;
   const int cbytes = 2 * elem_bytes;
-  int nb = 128;
+  int nb = nb_max >= 16 && nb_max <= 128 ? nb_max : 128;
   // the panel must fit: ceil(n / max_wg) rows x nb columns in LDS
   while (nb > 16) {
     const int64_t R = (n + p.max_wg - 1) / p.max_wg;
@@ -758,6 +758,26 @@ void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu,
   w.bytes = off + 256;
 }
 
+// Panels may need more than the default 64 KB of dynamic LDS: raise the
+// kernel's limit once (a host-side setting; done before any graph capture).
+template <typename T>
+hipError_t lu_prepare(const LUPlan& plan) {
+  size_t lds_need = 0;
+  for (const LUBlock& b : plan.blocks)
+    lds_need = std::max(lds_need, panel_lds_bytes(b.w, b.R, sizeof(cplx<T>)));
+  static size_t lds_set[2] = {0, 0};
+  size_t& cur = lds_set[sizeof(T) == 8 ? 0 : 1];
+  if (lds_need > 64 * 1024 && lds_need > cur) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&panel_kernel<T>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_need);
+    if (e != hipSuccess) return e;
+    cur = lds_need;
+  }
+  return hipSuccess;
+}
+template hipError_t lu_prepare<double>(const LUPlan&);
+template hipError_t lu_prepare<float>(const LUPlan&);
+
 template <typename T>
 hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws, int32_t* ipiv, hipStream_t st,
                      Prof* prof, hipStream_t side, int64_t sA, int64_t sipiv) {
@@ -782,18 +802,7 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
                        ws.rows, (size_t)0);
   }
   uint32_t epoch = 1;
-  // panels may need more than the default 64 KB of dynamic LDS
-  size_t lds_need = 0;
-  for (const LUBlock& b : plan.blocks)
-    lds_need = std::max(lds_need, panel_lds_bytes(b.w, b.R, sizeof(CT)));
-  static size_t lds_set[2] = {0, 0};
-  size_t& cur = lds_set[sizeof(T) == 8 ? 0 : 1];
-  if (lds_need > 64 * 1024 && lds_need > cur) {
-    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(&panel_kernel<T>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_need)) != hipSuccess)
-      return e;
-    cur = lds_need;
-  }
+  if ((e = lu_prepare<T>(plan)) != hipSuccess) return e;
   // Look-ahead: the main stream runs the panels and the update of the next
   // panel's columns; the side stream runs the bulk of each trailing update (and
   // the solve-ready transform of L21), overlapping the next panel.

@@ -29,7 +29,7 @@ SELF_STATIC, SELF_RADIATIVE = 0, 1
 
 EXPORTED = ["gdm_create", "gdm_destroy", "gdm_last_error", "gdm_set_environment", "gdm_set_structure",
             "gdm_num_unknowns", "gdm_assemble", "gdm_factorize", "gdm_incident_planewave", "gdm_solve",
-            "gdm_planewave", "gdm_fields", "gdm_cross_sections", "gdm_adjoint", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
+            "gdm_planewave", "gdm_fields", "gdm_cross_sections", "gdm_adjoint", "gdm_batch_spectra", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
             "gdm_profile", "gdm_profile_read"]
 
 
@@ -73,6 +73,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gdm_cross_sections": ([P, I64, P, P, P, P, I32, P], ctypes.c_int),
         "gdm_adjoint": ([P, I64, P, P, P, P, P, P, I64, P, P, D, I32, P, P, P, ctypes.POINTER(GDMInfo)],
                         ctypes.c_int),
+        "gdm_batch_spectra": ([P, I64, P, P, P, I64, P, P, I64, P, P, ctypes.c_int, I32, ctypes.c_int, P, P,
+                               ctypes.POINTER(GDMInfo)], ctypes.c_int),
         "gdm_getrf": ([P, ctypes.c_int, I64, P, I64, P, ctypes.POINTER(GDMInfo)], ctypes.c_int),
         "gdm_getrs": ([P, ctypes.c_int, ctypes.c_int, I64, I64, P, I64, P, I64], ctypes.c_int),
         "gdm_gemm": ([P, ctypes.c_int, ctypes.c_int, ctypes.c_int, I64, I64, I64, P, I64, P, I64, P, I64],
@@ -274,6 +276,36 @@ class Context:
                                   ctypes.byref(self.info))
         self._check(st)
         return grad_r, grad_eps[: self.n_cell], grad_wl
+
+    def batch_spectra(self, r_cells, step, wavelengths, eps, khat, e0, prec=PREC_FP32_IR, ir_iters=-1,
+                      selfterm=SELF_STATIC, want_be=True):
+        """Cross sections of many structures x wavelengths (include/gdm.h,
+        gdm_batch_spectra).  r_cells: list of [N_s, 3] cell positions; step: one
+        value or one per structure; eps [n_struct, n_wl] complex (one permittivity
+        per structure and wavelength).  Returns (cs [n_struct, n_wl, n_pw, 3] =
+        (ext, sca, abs), be [n_struct, n_wl] or None)."""
+        import numpy as np
+        counts = [len(r) for r in r_cells]
+        ns = len(counts)
+        off = np.zeros(ns + 1, dtype=np.int64)
+        off[1:] = np.cumsum(counts)
+        rc = self._dev(torch.cat([torch.as_tensor(r, dtype=torch.float64) for r in r_cells]), torch.float64,
+                       (int(off[-1]), 3), "r_cells")
+        steps = np.broadcast_to(np.asarray(step, dtype=np.float64), (ns,)).copy()
+        wl = np.ascontiguousarray(np.asarray(wavelengths, dtype=np.float64).ravel())
+        ep = self._dev(eps, torch.complex128, (ns, len(wl)), "eps")
+        k = self._dev(khat, torch.float64, None, "khat").reshape(-1, 3)
+        e = self._dev(e0, torch.complex128, None, "e0").reshape(-1, 3)
+        if len(k) != len(e):
+            raise ValueError("khat and e0 must have the same number of plane waves")
+        cs = torch.empty((ns, len(wl), len(k), 3), dtype=torch.float64, device=self.device)
+        be = torch.empty((ns, len(wl)), dtype=torch.float64, device=self.device) if want_be else None
+        host = ctypes.c_void_p  # host arrays: cell offsets, steps, wavelengths
+        st = self._call("gdm_batch_spectra", self.h, ns, host(off.ctypes.data), _ptr(rc), host(steps.ctypes.data),
+                        len(wl), host(wl.ctypes.data), _ptr(ep), len(k), _ptr(k), _ptr(e), int(prec), int(ir_iters),
+                        int(selfterm), _ptr(cs), _ptr(be), ctypes.byref(self.info))
+        self._check(st)
+        return cs, (be if prec == PREC_FP32_IR else None)
 
     # -- dense linear algebra entry points ---------------------------------------------
     def getrf(self, A_colmajor_storage: torch.Tensor):

@@ -1,0 +1,132 @@
+"""GPU parity of the batched spectra driver (gdm_batch_spectra through the
+C-ABI) against the FP64 oracle, item by item.
+
+Tolerance: cross sections within 1e-10 relative of the oracle (the bar of the
+method's FP64 mode), in FP64 and after FP32 LU + 2 FP64 refinement corrections
+(the backward error after them must be <= 1e-14, which at the conditioning of
+these systems bounds the forward error far below 1e-10).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import gdm_inputs as gi
+from oracle import gdm_oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_09545_amd import gdm
+    c = gdm.Context(0)
+    yield c
+    c.close()
+
+
+def small_batch(seed=41, n_wl=11):
+    """The batch recipe at sizes the oracle finishes in seconds: an ellipsoid, a
+    box and a z-cylinder of 10 nm cells (uneven counts), Drude-Lorentz
+    permittivities drawn like the full batch, n_wl wavelengths in 400-900 nm
+    (so groups end ragged), x and y polarised normal incidence."""
+    rng = np.random.default_rng(seed)
+    structs = [gi.ellipsoid_cells(np.array([52.0, 35.0, 25.0]), 10.0),
+               gi.box_cells(np.array([35.0, 24.0, 14.0]), 10.0),
+               gi.zcylinder_cells(np.array([28.0, 33.0, 23.0]), 23.0, 10.0)]
+    wl = np.linspace(400.0, 900.0, n_wl)
+    eps = np.stack([gi.drude_lorentz(wl, dict(eps_inf=rng.uniform(1.5, 3.0), de=rng.uniform(1.0, 6.0),
+                                              wL=rng.uniform(4.0, 5.5), gL=rng.uniform(0.05, 0.3),
+                                              wp=rng.uniform(0.0, 1.5), gD=rng.uniform(0.05, 0.2)))
+                    for _ in structs])
+    khat, e0 = gi.normal_incidence_xy()
+    return structs, wl, eps, khat, e0
+
+
+_CACHE = {}
+
+
+def oracle_cs(r, step, eps, wl, khat, e0, mode="static"):
+    key = (len(r), float(r.sum()), step, complex(eps), float(wl), mode)
+    if key in _CACHE:
+        return _CACHE[key]
+    w = dict(r_cell=r, step=step, eps_cell=np.full(len(r), eps), n_env=1.0, wavelength=float(wl), khat=khat, e0=e0,
+             r_eff=np.zeros((0, 3)), alpha_eff=np.zeros((0, 6, 6), dtype=np.complex128))
+    s = O.simulate(w, mode=mode)
+    _CACHE[key] = np.stack([s["ext"], s["sca"], s["abs"]], axis=1)  # [n_pw, 3]
+    return _CACHE[key]
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_batch_matches_oracle(ctx, prec):
+    say("batch vs oracle prec", prec)
+    structs, wl, eps, khat, e0 = small_batch()
+    ctx.set_environment(1.0)
+    cs, be = ctx.batch_spectra(structs, 10.0, wl, eps, khat, e0, prec=prec)
+    cs = cs.cpu().numpy()
+    print("  cells", [len(r) for r in structs], "info ms", ctx.info.ms_factor, flush=True)
+    for s, r in enumerate(structs):
+        for l in range(len(wl)):
+            ref = oracle_cs(r, 10.0, eps[s, l], wl[l], khat, e0)
+            err = np.max(np.abs(cs[s, l] - ref) / np.abs(ref))
+            assert err < 1e-10, (s, l, err)
+    if prec == 1:
+        b = be.cpu().numpy()
+        assert np.all(b <= 1e-14) and np.all(b > 0), b
+        assert ctx.info.backward_err == pytest.approx(float(b.max()))
+
+
+def test_batch_radiative_and_repeat(ctx):
+    """Radiative self-term option; a second call (with the measured group
+    configuration cached in the context) gives the same numbers bit for bit."""
+    say("batch radiative + repeat")
+    structs, wl, eps, khat, e0 = small_batch(seed=43, n_wl=9)
+    ctx.set_environment(1.0)
+    a, _ = ctx.batch_spectra(structs, 10.0, wl, eps, khat, e0, selfterm=1)
+    b, _ = ctx.batch_spectra(structs, 10.0, wl, eps, khat, e0, selfterm=1)
+    assert torch.equal(a, b)
+    a = a.cpu().numpy()
+    for s in (0, 2):
+        for l in (0, 4, 8):
+            ref = oracle_cs(structs[s], 10.0, eps[s, l], wl[l], khat, e0, mode="radiative")
+            assert np.max(np.abs(a[s, l] - ref) / np.abs(ref)) < 1e-10
+
+
+def test_batch_argument_errors(ctx):
+    say("batch errors")
+    from paper_2505_09545_amd import gdm
+    structs, wl, eps, khat, e0 = small_batch(n_wl=3)
+    with pytest.raises(gdm.GDMError) as e:
+        ctx.batch_spectra(structs, 10.0, -wl, eps, khat, e0)
+    assert e.value.status == gdm.GDM_E_ARG
+    with pytest.raises(ValueError):
+        ctx.batch_spectra(structs, 10.0, wl, eps[:, :2], khat, e0)
+
+
+def test_batch_full_config3_vs_golden(ctx):
+    """The full 32-structure x 128-wavelength batch (300..3000 cells per
+    structure, 4096 systems, FP32 LU + 2 FP64 corrections) in one call; 64
+    seeded items against the oracle (tests/golden/make_golden.py), every system's
+    backward error <= 1e-14."""
+    say("batch full config3")
+    ref = np.load(os.path.join(GOLDEN, "config3_samples.npz"))
+    w = gi.config3()
+    ctx.set_environment(w["n_env"])
+    cs, be = ctx.batch_spectra([s["r_cell"] for s in w["structs"]], w["step"], w["wavelengths"], w["eps"], w["khat"],
+                               w["e0"])
+    print("  batch ms", ctx.info.ms_factor, flush=True)
+    cs = cs.cpu().numpy()
+    got = np.stack([cs[s, l] for s, l in ref["items"]])
+    err = np.max(np.abs(got - ref["cs"]) / np.abs(ref["cs"]))
+    assert err < 1e-10, err
+    assert float(be.max()) <= 1e-14
