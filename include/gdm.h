@@ -195,6 +195,12 @@ gdm_status gdm_batch_spectra(gdm_ctx* ctx, int64_t n_struct, const int64_t* cell
                              int64_t n_pw, const double* khat, const double* e0, gdm_precision prec, int32_t ir_iters,
                              gdm_selfterm selfterm, double* cs_out, double* be_out, gdm_info* info);
 
+/* The batch configurations measured so far by gdm_batch_spectra on this context:
+ * returns their number; if out is not NULL, writes up to max_entries triples
+ * (smallest n of the size class, systems per group, LU panel width) to the HOST
+ * array out [max_entries][3]. */
+int32_t gdm_batch_tuning(const gdm_ctx* ctx, int32_t* out, int32_t max_entries);
+
 /* Dense LU of a caller matrix (dtype 0: complex double, 1: complex float),
  * column-major n x n, leading dimension lda, factored in place; ipiv [n]
  * receives 0-based pivot rows.  The factors are in the library's factored form

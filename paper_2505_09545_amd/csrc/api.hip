@@ -437,6 +437,20 @@ static gdm_status batch_capture(gdm_ctx* c, const BatchShape& sh, const BatchBuf
   return GDM_OK;
 }
 
+extern "C" int32_t gdm_batch_tuning(const gdm_ctx* c, int32_t* out, int32_t max_entries) {
+  if (!c) return 0;
+  int32_t k = 0;
+  for (const auto& e : c->batch_tune) {
+    if (out && k < max_entries) {
+      out[3 * k + 0] = (int32_t)(e.first * 256);
+      out[3 * k + 1] = e.second.first;
+      out[3 * k + 2] = e.second.second;
+    }
+    ++k;
+  }
+  return k;
+}
+
 extern "C" gdm_status gdm_batch_spectra(gdm_ctx* c, int64_t n_struct, const int64_t* cell_offset,
                                         const double* r_cell, const double* step_nm, int64_t n_wl,
                                         const double* wavelengths, const double* eps, int64_t n_pw, const double* khat,

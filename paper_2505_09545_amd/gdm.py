@@ -29,7 +29,7 @@ SELF_STATIC, SELF_RADIATIVE = 0, 1
 
 EXPORTED = ["gdm_create", "gdm_destroy", "gdm_last_error", "gdm_set_environment", "gdm_set_structure",
             "gdm_num_unknowns", "gdm_assemble", "gdm_factorize", "gdm_incident_planewave", "gdm_solve",
-            "gdm_planewave", "gdm_fields", "gdm_cross_sections", "gdm_adjoint", "gdm_batch_spectra", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
+            "gdm_planewave", "gdm_fields", "gdm_cross_sections", "gdm_adjoint", "gdm_batch_spectra", "gdm_batch_tuning", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
             "gdm_profile", "gdm_profile_read"]
 
 
@@ -75,6 +75,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                         ctypes.c_int),
         "gdm_batch_spectra": ([P, I64, P, P, P, I64, P, P, I64, P, P, ctypes.c_int, I32, ctypes.c_int, P, P,
                                ctypes.POINTER(GDMInfo)], ctypes.c_int),
+        "gdm_batch_tuning": ([P, P, I32], I32),
         "gdm_getrf": ([P, ctypes.c_int, I64, P, I64, P, ctypes.POINTER(GDMInfo)], ctypes.c_int),
         "gdm_getrs": ([P, ctypes.c_int, ctypes.c_int, I64, I64, P, I64, P, I64], ctypes.c_int),
         "gdm_gemm": ([P, ctypes.c_int, ctypes.c_int, ctypes.c_int, I64, I64, I64, P, I64, P, I64, P, I64],
@@ -306,6 +307,14 @@ class Context:
                         int(selfterm), _ptr(cs), _ptr(be), ctypes.byref(self.info))
         self._check(st)
         return cs, (be if prec == PREC_FP32_IR else None)
+
+    def batch_config(self) -> dict:
+        """Measured batch configurations: {smallest n of the size class: (systems
+        per group, LU panel width)}."""
+        k = int(self.lib.gdm_batch_tuning(self.h, None, 0))
+        buf = (ctypes.c_int32 * (3 * max(k, 1)))()
+        self.lib.gdm_batch_tuning(self.h, buf, k)
+        return {int(buf[3 * i]): (int(buf[3 * i + 1]), int(buf[3 * i + 2])) for i in range(k)}
 
     # -- dense linear algebra entry points ---------------------------------------------
     def getrf(self, A_colmajor_storage: torch.Tensor):
