@@ -816,11 +816,8 @@ gdm_status gdm_factorize(gdm_ctx* c, double wl, gdm_precision prec, gdm_info* in
   } else {
     HIPCHK(c, c->M64.ensure(sizeof(double2) * n * n));
     HIPCHK(c, c->M.ensure(sizeof(float2) * n * n));
-    HIPCHK(c, c->prof.begin(c->stream, PROF_ASSEMBLE, 16.0 * nn));
-    HIPCHK(c, launch_assemble<double>(d, w, c->M64.p, n, c->stream));
-    HIPCHK(c, c->prof.end(c->stream));
-    HIPCHK(c, c->prof.begin(c->stream, PROF_ASSEMBLE, 8.0 * nn));
-    HIPCHK(c, launch_assemble<float>(d, w, c->M.p, n, c->stream));
+    HIPCHK(c, c->prof.begin(c->stream, PROF_ASSEMBLE, 24.0 * nn));
+    HIPCHK(c, launch_assemble_dual(d, w, c->M64.as<double2>(), c->M.as<float2>(), n, c->stream));
     HIPCHK(c, c->prof.end(c->stream));
     HIPCHK(c, c->rows.ensure(sizeof(double) * n));
     HIPCHK(c, launch_rowsum_abs(c->M64.as<double2>(), n, n, c->rows.as<double>(), c->stream));

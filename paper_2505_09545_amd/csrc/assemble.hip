@@ -16,96 +16,154 @@
 // for effective point dipoles.  All arithmetic in FP64 (one sincos per pair);
 // the value is rounded to the storage type only at the store.
 //
-// Memory layout: column-major, interleaved complex, leading dimension ld.  Each
-// thread owns one row slot of one column dipole, so the 3 complex rows it
-// writes per column sit next to those of its neighbours (coalesced stream).
+// Memory layout: column-major, interleaved complex, leading dimension ld.  A
+// workgroup owns 256 consecutive row slots (768 consecutive rows) of one column
+// dipole; each thread evaluates its 3 x 3 (or 3 x 6) block in FP64 in
+// registers, then every column of the workgroup's strip (768 values) is staged
+// in LDS and written with consecutive lanes on consecutive elements, so each
+// store instruction covers one contiguous span (full cache lines).  With both
+// outputs the FP64 evaluation is shared by the complex-double and the
+// complex-float matrix.
 #include "gdm_common.hpp"
 #include "gdm_kernels.hpp"
 
 namespace gdm {
 
-template <typename T>
-__global__ void __launch_bounds__(256) assemble_kernel(DipoleView d, Wave w, cplx<T>* __restrict__ M,
-                                                        int64_t ld, int64_t row_blocks) {
-  const int64_t j = blockIdx.x / row_blocks;  // column dipole (uniform in the block)
-  const int64_t s = (blockIdx.x % row_blocks) * blockDim.x + threadIdx.x;
-  const int64_t N = d.N, nc = d.nc;
-  if (s >= N + d.ne) return;
-  const int f = s < N ? 0 : 1;                 // field type of the row slot: E or H
-  const int64_t dr = f == 0 ? s : nc + (s - N);  // row dipole
-  const bool col_eff = j >= nc;
-  const int64_t row0 = 3 * s;
-  cplx<T>* colE = M + row0 + (3 * j) * ld;
-  if (dr == j) {
-    // diagonal block I - S alpha (cells: scalar S^Ep and alpha; effective: S = 0)
-    if (!col_eff) {
-      const double2 v = csub(make_double2(1.0, 0.0), cmul(d.self_c, d.alpha_c[j]));
+// One strip: column dipole j (an effective dipole iff EFF: 6 columns, else 3)
+// and row slots [s0, s0 + 256).  All block indices are compile-time so the
+// block stays in registers.
+template <bool EFF, bool W64, bool W32>
+__device__ inline void assemble_strip(const DipoleView& d, const Wave& w, double2* __restrict__ M64,
+                                      float2* __restrict__ M32, int64_t ld, int64_t j, int64_t s0, double2* stage) {
+  constexpr int NC = EFF ? 6 : 3;
+  const int tid = threadIdx.x;
+  const int64_t s = s0 + tid;
+  const int64_t N = d.N, nc = d.nc, slots = N + d.ne;
+  const bool live = s < slots;
+  const int f = s < N ? 0 : 1;                    // field type of the row slot: E or H
+  const int64_t dr = f == 0 ? s : nc + (s - N);   // row dipole
+  double2 v[NC][3];  // v[column][row a] of this thread's block
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+  for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) colE[a + c * ld] = to_c<T>(a == c ? v : make_double2(0.0, 0.0));
-    } else {
-      cplx<T>* colH = M + row0 + (3 * (N + j - nc)) * ld;
+    for (int a = 0; a < 3; ++a) v[c][a] = make_double2(0.0, 0.0);
+  if (live) {
+    if (dr == j) {
+      // diagonal block I - S alpha (cells: scalar S^Ep and alpha; effective: S = 0)
+      if (!EFF) {
+        const double2 dg = csub(make_double2(1.0, 0.0), cmul(d.self_c, d.alpha_c[j]));
 #pragma unroll
-      for (int c = 0; c < 3; ++c)
+        for (int a = 0; a < 3; ++a) v[a][a] = dg;
+      } else {
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          colE[a + c * ld] = to_c<T>(make_double2((f == 0 && a == c) ? 1.0 : 0.0, 0.0));
-          colH[a + c * ld] = to_c<T>(make_double2((f == 1 && a == c) ? 1.0 : 0.0, 0.0));
+          v[a][a] = make_double2(f == 0 ? 1.0 : 0.0, 0.0);
+          v[(3 + a) % NC][a] = make_double2(f == 1 ? 1.0 : 0.0, 0.0);
         }
+      }
+    } else {
+      const double Rx = d.pos[3 * dr + 0] - d.pos[3 * j + 0];
+      const double Ry = d.pos[3 * dr + 1] - d.pos[3 * j + 1];
+      const double Rz = d.pos[3 * dr + 2] - d.pos[3 * j + 2];
+      Green g;
+      green_eh(Rx, Ry, Rz, w, f == 1 || EFF, g);
+      if (!EFF) {
+        // -G^{f p} alpha_j : 3 x 3
+        const double2 al = d.alpha_c[j];
+        const double2 ma = make_double2(-al.x, -al.y);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+          for (int a = 0; a < 3; ++a) v[c][a] = cmul(f == 0 ? gep(g, a, c) : ghp(g, a, c), ma);
+      } else {
+        // -[G^{f p} G^{f m}] alpha6_j : 3 x 6
+        const double2* al = d.alpha6 + (j - nc) * 36;
+        double2 gr[3][6];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+#pragma unroll
+          for (int b = 0; b < 6; ++b) gr[a][b] = f == 0 ? g6(g, w.eps_env, a, b) : g6(g, w.eps_env, 3 + a, b);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+#pragma unroll
+          for (int b = 0; b < 6; ++b) {
+            const double2 ab = al[b * 6 + c];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) cfma(v[c][a], gr[a][b], ab);
+          }
+#pragma unroll
+          for (int a = 0; a < 3; ++a) v[c][a] = make_double2(-v[c][a].x, -v[c][a].y);
+        }
+      }
     }
-    return;
   }
-  const double Rx = d.pos[3 * dr + 0] - d.pos[3 * j + 0];
-  const double Ry = d.pos[3 * dr + 1] - d.pos[3 * j + 1];
-  const double Rz = d.pos[3 * dr + 2] - d.pos[3 * j + 2];
-  Green g;
-  green_eh(Rx, Ry, Rz, w, f == 1 || col_eff, g);
-  if (!col_eff) {
-    // -G^{f p} alpha_j : 3 x 3
-    const double2 al = d.alpha_c[j];
-    const double2 ma = make_double2(-al.x, -al.y);
+  // write the strip column by column through LDS (coalesced stores)
+  const int64_t row0 = 3 * s0;
+  const int nrows = (int)(3 * ((slots - s0) < 256 ? (slots - s0) : 256));
 #pragma unroll
-    for (int c = 0; c < 3; ++c)
+  for (int c = 0; c < NC; ++c) {
+    const int64_t col = c < 3 ? 3 * j + c : 3 * (N + j - nc) + (c - 3);
+    __syncthreads();
 #pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const double2 gv = f == 0 ? gep(g, a, c) : ghp(g, a, c);
-        colE[a + c * ld] = to_c<T>(cmul(gv, ma));
+    for (int a = 0; a < 3; ++a) stage[3 * tid + a] = v[c][a];
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+      const int t = tid + 256 * i;
+      if (t < nrows) {
+        const double2 x = stage[t];
+        if (W64) M64[row0 + t + col * ld] = x;
+        if (W32) M32[row0 + t + col * ld] = make_float2((float)x.x, (float)x.y);
       }
-  } else {
-    // -[G^{f p} G^{f m}] alpha6_j : 3 x 6
-    const double2* al = d.alpha6 + (j - nc) * 36;
-    cplx<T>* colH = M + row0 + (3 * (N + j - nc)) * ld;
-    double2 gr[3][6];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 6; ++b) gr[a][b] = g6(g, w.eps_env, 3 * f + a, b);
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      double2 acc[3] = {make_double2(0.0, 0.0), make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
-#pragma unroll
-      for (int b = 0; b < 6; ++b) {
-        const double2 ab = al[b * 6 + c];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) cfma(acc[a], gr[a][b], ab);
-      }
-      cplx<T>* col = c < 3 ? colE + c * ld : colH + (c - 3) * ld;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) col[a] = to_c<T>(make_double2(-acc[a].x, -acc[a].y));
     }
   }
 }
 
-template <typename T>
-hipError_t launch_assemble(const DipoleView& d, const Wave& w, void* M, int64_t ld, hipStream_t st) {
+// Column dipoles j0 + blockIdx.x / row_blocks, all cells (EFF false) or all
+// effective dipoles (EFF true): one launch per column type.
+template <bool EFF, bool W64, bool W32>
+__global__ void __launch_bounds__(256) assemble_kernel(DipoleView d, Wave w, double2* __restrict__ M64,
+                                                        float2* __restrict__ M32, int64_t ld, int64_t row_blocks,
+                                                        int64_t j0) {
+  __shared__ double2 stage[768];
+  const int64_t j = j0 + blockIdx.x / row_blocks;  // column dipole (uniform in the block)
+  const int64_t s0 = (blockIdx.x % row_blocks) * 256;
+  assemble_strip<EFF, W64, W32>(d, w, M64, M32, ld, j, s0, stage);
+}
+
+template <bool W64, bool W32>
+static void launch_assemble_cols(const DipoleView& d, const Wave& w, double2* M64, float2* M32, int64_t ld,
+                                 int64_t row_blocks, hipStream_t st) {
+  if (d.nc > 0)
+    hipLaunchKernelGGL((assemble_kernel<false, W64, W32>), dim3((unsigned)(row_blocks * d.nc)), dim3(256), 0, st, d, w,
+                       M64, M32, ld, row_blocks, (int64_t)0);
+  if (d.ne > 0)
+    hipLaunchKernelGGL((assemble_kernel<true, W64, W32>), dim3((unsigned)(row_blocks * d.ne)), dim3(256), 0, st, d, w,
+                       M64, M32, ld, row_blocks, d.nc);
+}
+
+static hipError_t launch_assemble_impl(const DipoleView& d, const Wave& w, double2* M64, float2* M32, int64_t ld,
+                                       hipStream_t st) {
   const int64_t slots = d.N + d.ne;
   if (slots == 0) return hipSuccess;
   const int64_t row_blocks = (slots + 255) / 256;
   const int64_t blocks = row_blocks * d.N;
-  hipLaunchKernelGGL(assemble_kernel<T>, dim3((unsigned)blocks), dim3(256), 0, st, d, w,
-                     static_cast<cplx<T>*>(M), ld, row_blocks);
+  if (blocks > (int64_t)UINT32_MAX) return hipErrorInvalidValue;
+  if (M64 && M32) launch_assemble_cols<true, true>(d, w, M64, M32, ld, row_blocks, st);
+  else if (M64) launch_assemble_cols<true, false>(d, w, M64, M32, ld, row_blocks, st);
+  else launch_assemble_cols<false, true>(d, w, M64, M32, ld, row_blocks, st);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_assemble(const DipoleView& d, const Wave& w, void* M, int64_t ld, hipStream_t st) {
+  if (sizeof(T) == 8) return launch_assemble_impl(d, w, static_cast<double2*>(M), nullptr, ld, st);
+  return launch_assemble_impl(d, w, nullptr, static_cast<float2*>(M), ld, st);
+}
+
+hipError_t launch_assemble_dual(const DipoleView& d, const Wave& w, double2* M64, float2* M32, int64_t ld,
+                                hipStream_t st) {
+  return launch_assemble_impl(d, w, M64, M32, ld, st);
 }
 
 template hipError_t launch_assemble<double>(const DipoleView&, const Wave&, void*, int64_t, hipStream_t);

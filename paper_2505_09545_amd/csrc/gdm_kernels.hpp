@@ -17,6 +17,9 @@ struct DipoleView {
 
 template <typename T>
 hipError_t launch_assemble(const DipoleView& d, const struct Wave& w, void* M, int64_t ld, hipStream_t st);
+// both precisions from one FP64 evaluation of every entry
+hipError_t launch_assemble_dual(const DipoleView& d, const struct Wave& w, double2* M64, float2* M32, int64_t ld,
+                                hipStream_t st);
 
 // Optional operand masks: rows [ar0, ar0 + adw) of op(A) are a square block
 // (row r - ar0, column k) of which only one triangle is read (kind below); a
