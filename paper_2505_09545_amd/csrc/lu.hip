@@ -688,12 +688,25 @@ LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch,
     nb /= 2;
   }
   p.nb = nb;
+  // Workgroups of one panel.  Measured on n = 12 000: an FP32 panel over at most
+  // 128 CUs is as fast per column as one over all 256 and leaves the other CUs
+  // to the look-ahead update (140 vs 150 ms per factorisation + solve step); an
+  // FP64 panel (twice the bytes per row) is fastest spread over every CU.  The
+  // cap is raised when the panel's rows would not fit the LDS of fewer
+  // workgroups.
+  int cap = p.max_wg;
+  if (elem_bytes == 4 && nbatch == 1) {
+    const int64_t rmax = ((int64_t)lds_bytes - LDS_RESERVE - (int64_t)nb * (cbytes + 4)) /
+                         ((int64_t)(nb + 1) * cbytes + 4);
+    const int64_t need = rmax > 0 ? (n + rmax - 1) / rmax : p.max_wg;
+    cap = (int)std::min<int64_t>(p.max_wg, std::max<int64_t>(128, need));
+  }
   for (int64_t k0 = 0; k0 < n; k0 += nb) {
     LUBlock b;
     b.k0 = k0;
     b.w = (int)(n - k0 < nb ? n - k0 : nb);
     const int64_t m = n - k0;
-    int64_t R = (m + p.max_wg - 1) / p.max_wg;
+    int64_t R = (m + cap - 1) / cap;
     if (R < 32) R = 32;
     const int64_t Rmax = (lds_bytes - LDS_RESERVE - (int64_t)b.w * (cbytes + 4)) / ((int64_t)(b.w + 1) * cbytes + 4);
     if (R > Rmax) R = Rmax;
