@@ -299,6 +299,30 @@ def assemble(D: Dipoles) -> np.ndarray:
     return M
 
 
+def matvec_rows(D: Dipoles, rows: np.ndarray, x: np.ndarray):
+    """(M x)[rows] for selected unknowns without forming M: with q = A x,
+    (M x)_u = x_u - [sum_{j != i} G6(r_i - r_j) q_j + S6_i q_i]_c for u = idx(i, c)
+    (Eq. GDM_system_of_equations read as M = I - G~ A).  Also returns
+    sum of the moduli of the terms, |x_u| + sum |G6_ij q_j|_c + |S6_i q_i|_c,
+    a scale for round-off bounds.  x: [n] (one vector)."""
+    rows = np.asarray(rows, dtype=np.int64)
+    q6 = np.einsum("dab,db->da", D.alpha6, D.to6(x))  # [N, 6]
+    # (dipole, component) of every requested unknown
+    where = {int(D.idx[d, c]): (d, c) for d in range(D.N) for c in range(6) if D.idx[d, c] >= 0}
+    out = np.zeros(len(rows), dtype=np.complex128)
+    scale = np.zeros(len(rows))
+    for t, u in enumerate(rows):
+        i, c = where[int(u)]
+        R = D.pos[i][None, :] - D.pos
+        R[i] = 1.0  # placeholder, replaced by the self-term below
+        g = green6(R, D.k0, D.n_env)[:, c, :]  # [N, 6]
+        terms = np.einsum("jb,jb->j", g, q6)
+        terms[i] = D.S6[i][c] @ q6[i]
+        out[t] = x[u] - np.sum(terms)
+        scale[t] = abs(x[u]) + np.sum(np.abs(terms))
+    return out, scale
+
+
 # ----------------------------------------------------------------------------
 # illumination  (Appendix, 3D illuminations: plane wave)
 # ----------------------------------------------------------------------------

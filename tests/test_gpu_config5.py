@@ -1,0 +1,119 @@
+"""The multi-scale workload (3000 cells inside a 100 x 100 lattice of 6x6
+effective dipoles, n = 69 000, 10^6 probes) on the GPU, FP32 LU + FP64
+refinement.
+
+The dense oracle cannot factor n = 69 000, so the full-size run is checked on
+what the oracle computes item by item from the GPU's solution:
+  * residual rows: for 60 seeded unknowns (cell E, dipole E, dipole H) the
+    oracle's direct per-pair evaluation of (M F)_u against F0_u; the residual
+    must be <= 1e-12 of the sum of the moduli of the terms (the refinement
+    reaches a normwise backward error <= 1e-14 w.r.t. the GPU's FP64 matrix);
+  * the incident field at the dipoles, q = A F on sampled dipoles, the cross
+    sections from (F0, F, q), and the scattered field at 256 seeded probes out
+    of the 10^6, all within 1e-10 relative of the oracle.
+A reduced replica (the same cells, a 4 x 4 sub-lattice with the same per-site
+draws, n = 9 096) is compared with the oracle's full solution (moments, fields,
+cross sections within 1e-10).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import gdm_inputs as gi
+from oracle import gdm_oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_09545_amd import gdm
+    c = gdm.Context(0)
+    yield c
+    c.close()
+
+
+def relcol(a, b):
+    a = np.asarray(a).reshape(len(a), -1)
+    b = np.asarray(b).reshape(len(b), -1)
+    return float(np.max(np.linalg.norm(a - b, axis=1) / np.linalg.norm(b, axis=1)))
+
+
+def test_config5_reduced_replica(ctx):
+    say("config5 replica 4x4")
+    from paper_2505_09545_amd import gdm
+    w = gi.config5(sub=(48, 52), probes=40)
+    out = gdm.run_forward(ctx, w, prec=gdm.PREC_FP32_IR, tol=1e-14, want_ff=True)
+    sim = O.simulate(w)
+    assert ctx.n == 9096
+    assert relcol(out["q"].cpu().numpy(), sim["q"].T) < 1e-10
+    assert relcol(out["f"].cpu().numpy(), sim["F"].T) < 1e-10
+    cs = out["cs"].cpu().numpy()
+    for col, key in ((0, "ext"), (1, "sca"), (2, "abs"), (3, "rad")):
+        assert np.max(np.abs(cs[:, col] - sim[key]) / np.abs(sim[key])) < 1e-10, key
+    e2 = np.sum(np.abs(w["e0"]) ** 2, axis=1)
+    ff = O.sca_farfield_doublesum(sim["D"], sim["q"], e2)
+    assert np.max(np.abs(cs[:, 4] - ff) / np.abs(ff)) < 1e-10
+    Es, Hs = O.scattered_fields(sim["D"], sim["q"], w["r_probe"])
+    assert relcol(out["E_sca"].cpu().numpy(), Es) < 1e-10
+    assert relcol(out["H_sca"].cpu().numpy(), Hs) < 1e-10
+
+
+def test_config5_full_size_sampled(ctx):
+    say("config5 full n = 69000")
+    from paper_2505_09545_amd import gdm
+    w = gi.config5()
+    ne = len(w["r_eff"])
+    ctx.set_environment(w["n_env"])
+    ctx.set_structure(torch.as_tensor(w["r_cell"]), w["step"], torch.as_tensor(w["eps_cell"]),
+                      torch.as_tensor(w["r_eff"]), torch.as_tensor(w["alpha_eff"]))
+    assert ctx.n == 69000
+    ctx.factorize(w["wavelength"], gdm.PREC_FP32_IR)
+    khat, e0, e2 = gdm.plane_wave_inputs(w, ctx.device)
+    f0 = ctx.incident_planewave(khat, e0)
+    q, f = ctx.solve(f0, tol=1e-14)
+    print("  backward error", ctx.info.backward_err, "corrections", ctx.info.ir_iters, flush=True)
+    assert ctx.info.backward_err <= 1e-14
+    cs = ctx.cross_sections(f0, q, f, e2).cpu().numpy()
+    rp = torch.as_tensor(w["r_probe"], device=ctx.device)
+    E, _ = ctx.fields(q, rp, want_h=False)
+    rng = np.random.default_rng(55)
+    pidx = np.sort(rng.choice(len(w["r_probe"]), 256, replace=False))
+    E_s = E[0, torch.as_tensor(pidx, device=ctx.device)].cpu().numpy()
+    del E
+    F0 = f0[0].cpu().numpy()
+    F = f[0].cpu().numpy()
+    Q = q[0].cpu().numpy()
+    D = O.Dipoles(w)
+    # incident field at the dipoles
+    F0o = O.incident_at_dipoles(D, w["khat"], w["e0"])[:, 0]
+    assert np.max(np.abs(F0 - F0o)) <= 1e-13 * np.max(np.abs(F0o))
+    # q = A F on sampled dipoles (cells and effective)
+    dsel = np.concatenate([rng.choice(D.nc, 20, replace=False), D.nc + rng.choice(D.ne, 20, replace=False)])
+    F6, Q6 = D.to6(F), D.to6(Q)
+    Qo = np.einsum("dab,db->da", D.alpha6[dsel], F6[dsel])
+    assert np.max(np.abs(Q6[dsel] - Qo)) <= 1e-13 * np.max(np.abs(Qo))
+    # residual rows by direct per-pair sums
+    rows = np.sort(np.concatenate([rng.choice(3 * D.nc, 20, replace=False),
+                                   3 * D.nc + rng.choice(3 * D.ne, 20, replace=False),
+                                   3 * D.N + rng.choice(3 * D.ne, 20, replace=False)]))
+    MF, scale = O.matvec_rows(D, rows, F)
+    res = np.abs(F0[rows] - MF)
+    print("  max residual / scale", float(np.max(res / (scale + np.abs(F0[rows])))), flush=True)
+    assert np.all(res <= 1e-12 * (scale + np.abs(F0[rows])))
+    # cross sections from the GPU's (F0, F, q) by the oracle's formulas
+    cso = O.cross_sections(D, F0[:, None], F[:, None], Q[:, None], e2.cpu().numpy())
+    for col, key in ((0, "ext"), (1, "sca"), (2, "abs"), (3, "rad")):
+        assert abs(cs[0, col] - cso[key][0]) <= 1e-10 * abs(cso[key][0]), key
+    # scattered field at sampled probes
+    Eo, _ = O.scattered_fields(D, Q[:, None], w["r_probe"][pidx])
+    assert relcol(E_s[None], Eo) < 1e-10
