@@ -231,10 +231,24 @@ static gdm_status solve_core(gdm_ctx* c, int trans, int64_t nrhs, const double2*
   float2* C32 = c->C32.as<float2>();
   double* sm = c->small.as<double>();  // [0..nrhs): |r|, [nrhs..2nrhs): |x|, [2nrhs..): |b|, [3nrhs..): |c|
   int64_t part_elems = 0;
+  struct {
+    int64_t kc = 0, gemm_part = 0;
+  } rs;
   if (nrhs <= SKINNY_MAX_RHS) {
     part_elems = std::max(skinny_t_chunks(n, 0) * nrhs * n, skinny_n_long_parts(n, n, nrhs));
-    HIPCHK(c, c->part.ensure(sizeof(double2) * part_elems));
+  } else if (!trans) {
+    // k split of the residual product: about 4 workgroups per CU in total
+    const int64_t rem = nrhs % 64 <= SKINNY_MAX_RHS ? nrhs % 64 : 0;
+    const int64_t nfull = nrhs - rem;
+    const int64_t tiles = ((n + 63) / 64) * ((nfull + 63) / 64);
+    int64_t splits = tiles > 0 ? (4 * (int64_t)c->num_cu + tiles - 1) / tiles : 1;
+    splits = std::max<int64_t>(1, std::min<int64_t>(splits, 32));
+    rs.kc = std::max<int64_t>(64, ((n + splits - 1) / splits + 7) / 8 * 8);
+    const int64_t nchunk = n / rs.kc + (n % rs.kc > 0);
+    rs.gemm_part = nchunk * n * nfull;
+    part_elems = rs.gemm_part + (rem > 0 ? skinny_n_long_parts(n, n, rem) : 0);
   }
+  if (part_elems > 0) HIPCHK(c, c->part.ensure(sizeof(double2) * part_elems));
   // first solve from B in FP32
   HIPCHK(c, launch_convert_d2f(B, n, C32, n, n, nrhs, c->stream));
   HIPCHK(c, c->prof.begin(c->stream, PROF_SOLVE, solve_flops));
@@ -257,8 +271,29 @@ static gdm_status solve_core(gdm_ctx* c, int trans, int64_t nrhs, const double2*
       else
         HIPCHK(c, launch_skinny_n_long<double>(n, n, c->M64.p, n, X, n, Rr, n, nrhs, c->part.p, part_elems,
                                                c->stream));
-    } else {
+    } else if (trans) {
       HIPCHK(c, launch_gemm<double>(0, trans, n, nrhs, n, c->M64.p, n, X, n, Rr, n, c->stream));
+    } else {
+      // Whole 64-column tiles on the matrix cores, split over k into independent
+      // products (enough workgroups to fill the chip) whose partial sums are
+      // added in order; a remainder of <= 8 columns streams M64 once more on
+      // the VALUs instead of occupying a nearly empty tile.
+      const int64_t rem = nrhs % 64 <= SKINNY_MAX_RHS ? nrhs % 64 : 0;
+      const int64_t nfull = nrhs - rem;
+      if (nfull > 0) {
+        const int64_t kc = rs.kc, nk = n / kc, tail = n - nk * kc;
+        double2* part = c->part.as<double2>();
+        HIPCHK(c, launch_gemm<double>(1, 0, n, nfull, kc, c->M64.p, n, X, n, part, n, c->stream, GemmMask{}, (int)nk,
+                                      kc * n, kc, n * nfull));
+        if (tail > 0)
+          HIPCHK(c, launch_gemm<double>(1, 0, n, nfull, tail, c->M64.as<double2>() + nk * kc * n, n, X + nk * kc, n,
+                                        part + nk * n * nfull, n, c->stream));
+        HIPCHK(c, launch_partial_reduce<double>(part, (int)(nk + (tail > 0)), n, nfull, Rr, n, c->stream));
+      }
+      if (rem > 0)
+        HIPCHK(c, launch_skinny_n_long<double>(n, n, c->M64.p, n, X + nfull * n, n, Rr + nfull * n, n, rem,
+                                               c->part.as<double2>() + rs.gemm_part, part_elems - rs.gemm_part,
+                                               c->stream));
     }
     HIPCHK(c, c->prof.end(c->stream));
     HIPCHK(c, launch_colmax(Rr, n, n, nrhs, sm, c->stream));

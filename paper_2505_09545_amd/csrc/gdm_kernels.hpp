@@ -71,6 +71,10 @@ hipError_t launch_skinny_n_long(int64_t m, int64_t k, const void* A, int64_t lda
                                 int64_t ldc, int64_t nrhs, void* part, int64_t part_elems, hipStream_t st,
                                 int nbatch = 1, int64_t sA = 0, int64_t sX = 0, int64_t sC = 0);
 int64_t skinny_n_long_parts(int64_t m, int64_t k, int64_t nrhs);
+// C[mo x nrhs] -= sum over nchunk partial blocks part[(chunk nrhs + r) mo + i], in order
+template <typename T>
+hipError_t launch_partial_reduce(const void* part, int nchunk, int64_t mo, int64_t nrhs, void* C, int64_t ldc,
+                                 hipStream_t st);
 constexpr int SKINNY_MAX_RHS = 8;
 
 // Optional per-launch timing with HIP events on the launch stream.

@@ -276,6 +276,18 @@ hipError_t launch_skinny_n_long(int64_t m, int64_t k, const void* A, int64_t lda
   return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_partial_reduce(const void* part, int nchunk, int64_t mo, int64_t nrhs, void* C, int64_t ldc,
+                                 hipStream_t st) {
+  if (mo <= 0 || nrhs <= 0 || nchunk <= 0) return hipSuccess;
+  const int64_t tot = mo * nrhs;
+  hipLaunchKernelGGL(skinny_reduce_kernel<T>, dim3((unsigned)((tot + 255) / 256), 1), dim3(256), 0, st,
+                     static_cast<const cplx<T>*>(part), nchunk, mo, nrhs, static_cast<cplx<T>*>(C), ldc, (int64_t)0);
+  return hipGetLastError();
+}
+template hipError_t launch_partial_reduce<double>(const void*, int, int64_t, int64_t, void*, int64_t, hipStream_t);
+template hipError_t launch_partial_reduce<float>(const void*, int, int64_t, int64_t, void*, int64_t, hipStream_t);
+
 int64_t skinny_t_chunks(int64_t k0, int64_t k1) {
   return (k0 + SK_KC - 1) / SK_KC + (k1 + SK_KC - 1) / SK_KC;
 }
