@@ -124,7 +124,7 @@ def adjoint_timing(ctx, gdm, steps: int, warmup: int) -> dict:
     return out
 
 
-def batch_timing(ctx, gdm, runs: int) -> dict:
+def batch_timing(ctx, gdm, runs: int, n_struct: int = 0, n_wl: int = 0) -> dict:
     """The batched spectra workload (gdm_inputs.config3): 32 structures of
     300..3000 cells x 128 wavelengths x 2 polarisations, FP32 LU + 2 FP64
     refinement corrections, in one gdm_batch_spectra call (inputs resident on the
@@ -134,6 +134,9 @@ def batch_timing(ctx, gdm, runs: int) -> dict:
     import torch
     import gdm_inputs as gi
     w = gi.config3()
+    if n_struct > 0 or n_wl > 0:  # a leading subset (for profiler runs)
+        ns_, nw_ = n_struct or len(w["structs"]), n_wl or len(w["wavelengths"])
+        w = dict(w, structs=w["structs"][:ns_], eps=w["eps"][:ns_, :nw_], wavelengths=w["wavelengths"][:nw_])
     dev = ctx.device
     r_cells = [torch.as_tensor(st["r_cell"], device=dev) for st in w["structs"]]
     eps = torch.as_tensor(w["eps"], device=dev)
@@ -171,6 +174,8 @@ def main() -> int:
     ap.add_argument("--no-fp64", action="store_true", help="skip timing the plain FP64 path")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the forward+backward (adjoint) timing")
     ap.add_argument("--batch-runs", type=int, default=1, help="timed runs of the batched spectra (0: skip)")
+    ap.add_argument("--batch-structs", type=int, default=0, help="only the first K structures of the batch (0: all)")
+    ap.add_argument("--batch-wavelengths", type=int, default=0, help="only the first L wavelengths (0: all)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after the timed region, run one device copy of this many MiB (a known-size kernel "
                          "for calibrating hardware byte counters)")
@@ -280,7 +285,7 @@ def main() -> int:
     if not args.no_adjoint:
         line.update(adjoint_timing(ctx, gdm, args.steps, args.warmup))
     if args.batch_runs > 0:
-        line.update(batch_timing(ctx, gdm, args.batch_runs))
+        line.update(batch_timing(ctx, gdm, args.batch_runs, args.batch_structs, args.batch_wavelengths))
     if args.copy_calib_mb > 0:
         nbytes = args.copy_calib_mb << 20
         src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
