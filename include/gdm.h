@@ -224,7 +224,12 @@ gdm_status gdm_sync(gdm_ctx* ctx);
  * launch (for benchmarks; adds a few microseconds per launch).  enable != 0
  * clears the counters and starts recording; 0 stops. */
 gdm_status gdm_profile(gdm_ctx* ctx, int enable);
-/* Counters accumulated since gdm_profile(ctx, 1), written to the HOST array
+/* The same for a subset of the tags listed under gdm_profile_read: launches of
+ * tag t are timed iff bit t of mask is set (mask 0 stops; 1023 = all).  Timing
+ * only the kernels one needs keeps the events off the critical path of the
+ * rest.  GDM_E_ARG for a mask outside [0, 1024). */
+gdm_status gdm_profile_mask(gdm_ctx* ctx, int32_t mask);
+/* Counters accumulated since gdm_profile / gdm_profile_mask, written to the HOST array
  * out (n_out >= 30): out[3 t + 0..2] = (milliseconds, work, launches) for
  * t = 0 LU trailing-update GEMM (work = real flops 8 m n k), 1 LU panel (work =
  * columns), 2 assembly (work = bytes written), 3 block triangular solve of the

@@ -454,13 +454,13 @@ static gdm_status batch_capture(gdm_ctx* c, const BatchShape& sh, const BatchBuf
     HIPCHK(c, hipEventCreateWithFlags(&x, hipEventDisableTiming));
     c->lu_events.push_back(x);
   }
-  const bool prof_on = c->prof.on;
-  c->prof.on = false;
+  const uint32_t prof_mask = c->prof.mask;
+  c->prof.mask = 0;
   HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   gdm_status s = batch_enqueue_group(c, sh, b, npw, khat, e0, ir, ir_iters, radiative, step);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(c->stream, &g);
-  c->prof.on = prof_on;
+  c->prof.mask = prof_mask;
   if (s != GDM_OK) {
     if (g) (void)hipGraphDestroy(g);
     return s;
@@ -1146,14 +1146,17 @@ gdm_status gdm_gemm(gdm_ctx* c, int dtype, int mode, int transA, int64_t m, int6
   return GDM_OK;
 }
 
-gdm_status gdm_profile(gdm_ctx* c, int enable) {
+gdm_status gdm_profile_mask(gdm_ctx* c, int32_t mask) {
   if (!c) return GDM_E_ARG;
+  if (mask < 0 || mask >= (1 << PROF_NTAGS)) FAIL(c, GDM_E_ARG, "tag mask %d outside [0, 2^%d)", mask, PROF_NTAGS);
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->prof.collect();
   c->prof.reset();
-  c->prof.on = enable != 0;
+  c->prof.mask = (uint32_t)mask;
   return GDM_OK;
 }
+
+gdm_status gdm_profile(gdm_ctx* c, int enable) { return gdm_profile_mask(c, enable ? (1 << PROF_NTAGS) - 1 : 0); }
 
 gdm_status gdm_profile_read(gdm_ctx* c, double* out, int32_t n_out) {
   if (!c) return GDM_E_ARG;

@@ -92,7 +92,8 @@ enum ProfTag {
   PROF_NTAGS = 10
 };
 struct Prof {
-  bool on = false;
+  uint32_t mask = 0;  // bit t: record launches of tag t
+  bool open = false;  // the last begin() recorded (its end() must too)
   std::vector<hipEvent_t> ev;
   std::vector<int> tag;
   std::vector<double> work;

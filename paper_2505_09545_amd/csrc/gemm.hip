@@ -219,48 +219,6 @@ template hipError_t launch_gemm_update<double>(int64_t, int64_t, int64_t, const 
 template hipError_t launch_gemm_update<float>(int64_t, int64_t, int64_t, const void*, int64_t, const void*, int64_t,
                                               void*, int64_t, hipStream_t, int, int64_t, int64_t, int64_t);
 
-// ---- per-launch event timing -------------------------------------------------
-hipError_t Prof::begin(hipStream_t st, int t, double w) {
-  if (!on) return hipSuccess;
-  if (2 * used + 2 > ev.size()) {
-    for (int i = 0; i < 2; ++i) {
-      hipEvent_t e;
-      hipError_t r = hipEventCreate(&e);
-      if (r != hipSuccess) return r;
-      ev.push_back(e);
-    }
-    tag.push_back(0);
-    work.push_back(0);
-  }
-  tag[used] = t;
-  work[used] = w;
-  return hipEventRecord(ev[2 * used], st);
-}
-hipError_t Prof::end(hipStream_t st) {
-  if (!on) return hipSuccess;
-  hipError_t r = hipEventRecord(ev[2 * used + 1], st);
-  ++used;
-  return r;
-}
-void Prof::collect() {
-  for (size_t i = 0; i < used; ++i) {
-    float t = 0.f;
-    if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) == hipSuccess) {
-      ms[tag[i]] += t;
-      wsum[tag[i]] += work[i];
-      cnt[tag[i]] += 1;
-    }
-  }
-  used = 0;
-}
-void Prof::reset() {
-  used = 0;
-  for (int i = 0; i < PROF_NTAGS; ++i) ms[i] = wsum[i] = cnt[i] = 0;
-}
-Prof::~Prof() {
-  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-}
-
 template hipError_t launch_gemm<double>(int, int, int64_t, int64_t, int64_t, const void*, int64_t, const void*,
                                         int64_t, void*, int64_t, hipStream_t, GemmMask, int, int64_t, int64_t, int64_t);
 template hipError_t launch_gemm<float>(int, int, int64_t, int64_t, int64_t, const void*, int64_t, const void*,

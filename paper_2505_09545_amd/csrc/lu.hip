@@ -215,8 +215,22 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
   const int64_t rbase = k0 + (int64_t)g * R;
   const int myR = (int)(n - rbase < (int64_t)R ? (n - rbase > 0 ? n - rbase : 0) : R);
   if (tid == 0) bad = 0;
-  for (int c = 0; c < w; ++c)
-    for (int lr = tid; lr < myR; lr += 256) tile[c * R + lr] = A[(rbase + lr) + (k0 + c) * ld];
+  // columns in batches of LB loads in flight per thread (a load followed by its
+  // LDS store in one loop body would put one memory latency per column on the
+  // panel's critical path)
+  constexpr int LB = 128 / (int)sizeof(CT);
+  const int wfull = w - w % LB;
+  for (int lr = tid; lr < myR; lr += 256) {
+    const CT* src = A + (rbase + lr) + k0 * ld;
+    for (int c0 = 0; c0 < wfull; c0 += LB) {
+      CT v[LB];
+#pragma unroll
+      for (int u = 0; u < LB; ++u) v[u] = src[(c0 + u) * ld];
+#pragma unroll
+      for (int u = 0; u < LB; ++u) tile[(c0 + u) * R + lr] = v[u];
+    }
+    for (int c = wfull; c < w; ++c) tile[c * R + lr] = src[c * ld];
+  }
   for (int lr = tid; lr < myR; lr += 256) lab[lr] = (int32_t)(rbase + lr);
   // 2D mapping for the rank-1 update: RP rows x CG column groups
   int RP = 1;
@@ -347,8 +361,17 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
     for (int j = tid; j < w; j += 256) ipiv[k0 + j] = pl[j];
     if (tid == 0 && zero_col >= 0) atomicMin(&ws.err[1], (int)(k0 + zero_col));
   }
-  for (int c = 0; c < w; ++c)
-    for (int lr = tid; lr < myR; lr += 256) A[lab[lr] + (k0 + c) * ld] = tile[c * R + lr];
+  for (int lr = tid; lr < myR; lr += 256) {
+    CT* dst = A + lab[lr] + k0 * ld;
+    for (int c0 = 0; c0 < wfull; c0 += LB) {
+      CT v[LB];
+#pragma unroll
+      for (int u = 0; u < LB; ++u) v[u] = tile[(c0 + u) * R + lr];
+#pragma unroll
+      for (int u = 0; u < LB; ++u) dst[(c0 + u) * ld] = v[u];
+    }
+    for (int c = wfull; c < w; ++c) dst[c * ld] = tile[c * R + lr];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -511,10 +534,32 @@ __device__ inline void trsm_sweep(const cplx<T>* __restrict__ Tri, int64_t ldt, 
     const int hi = forward ? w : jb + pw;
     const int len = hi - lo;
     __syncthreads();
-    for (int idx = tid; idx < pw * len; idx += 256) {
-      int i, cc;
+    // staged in batches of SB loads in flight per thread (then a remainder)
+    constexpr int SB = 128 / (int)sizeof(CT);
+    const int tot = pw * len, full = tot - tot % (256 * SB);
+    auto at = [&](int idx, int& i, int& cc) {
       if (!transposed) { i = lo + idx % len; cc = idx / len; }
       else { cc = idx % pw; i = lo + idx / pw; }
+    };
+    for (int base = tid; base < full; base += 256 * SB) {
+      CT v[SB];
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        int i, cc;
+        at(base + 256 * u, i, cc);
+        const int j = jb + cc;
+        v[u] = transposed ? Tri[j + (int64_t)i * ldt] : Tri[i + (int64_t)j * ldt];
+      }
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        int i, cc;
+        at(base + 256 * u, i, cc);
+        Ls[cc * w + i] = v[u];
+      }
+    }
+    for (int idx = full + tid; idx < tot; idx += 256) {
+      int i, cc;
+      at(idx, i, cc);
       const int j = jb + cc;
       Ls[cc * w + i] = transposed ? Tri[j + (int64_t)i * ldt] : Tri[i + (int64_t)j * ldt];
     }

@@ -405,4 +405,49 @@ hipError_t launch_rowsum_abs(const double2* M, int64_t ld, int64_t n, double* ro
   return hipGetLastError();
 }
 
+// ---- per-launch event timing -------------------------------------------------
+hipError_t Prof::begin(hipStream_t st, int t, double w) {
+  open = ((mask >> t) & 1u) != 0;
+  if (!open) return hipSuccess;
+  if (2 * used + 2 > ev.size()) {
+    for (int i = 0; i < 2; ++i) {
+      hipEvent_t e;
+      hipError_t r = hipEventCreate(&e);
+      if (r != hipSuccess) return r;
+      ev.push_back(e);
+    }
+    tag.push_back(0);
+    work.push_back(0);
+  }
+  tag[used] = t;
+  work[used] = w;
+  return hipEventRecord(ev[2 * used], st);
+}
+hipError_t Prof::end(hipStream_t st) {
+  if (!open) return hipSuccess;
+  open = false;
+  hipError_t r = hipEventRecord(ev[2 * used + 1], st);
+  ++used;
+  return r;
+}
+void Prof::collect() {
+  for (size_t i = 0; i < used; ++i) {
+    float t = 0.f;
+    if (hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]) == hipSuccess) {
+      ms[tag[i]] += t;
+      wsum[tag[i]] += work[i];
+      cnt[tag[i]] += 1;
+    }
+  }
+  used = 0;
+}
+void Prof::reset() {
+  used = 0;
+  for (int i = 0; i < PROF_NTAGS; ++i) ms[i] = wsum[i] = cnt[i] = 0;
+}
+Prof::~Prof() {
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+}
+
+
 }  // namespace gdm

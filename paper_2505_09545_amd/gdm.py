@@ -30,7 +30,7 @@ SELF_STATIC, SELF_RADIATIVE = 0, 1
 EXPORTED = ["gdm_create", "gdm_destroy", "gdm_last_error", "gdm_set_environment", "gdm_set_structure",
             "gdm_num_unknowns", "gdm_assemble", "gdm_factorize", "gdm_incident_planewave", "gdm_solve",
             "gdm_planewave", "gdm_fields", "gdm_cross_sections", "gdm_adjoint", "gdm_batch_spectra", "gdm_batch_tuning", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
-            "gdm_profile", "gdm_profile_read"]
+            "gdm_profile", "gdm_profile_mask", "gdm_profile_read"]
 
 
 class GDMInfo(ctypes.Structure):
@@ -82,6 +82,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
                      ctypes.c_int),
         "gdm_sync": ([P], ctypes.c_int),
         "gdm_profile": ([P, ctypes.c_int], ctypes.c_int),
+        "gdm_profile_mask": ([P, I32], ctypes.c_int),
         "gdm_profile_read": ([P, ctypes.POINTER(ctypes.c_double), I32], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
@@ -345,8 +346,16 @@ class Context:
 
     PROF_TAGS = ("update", "panel", "assemble", "trsm", "perm", "solve", "resid", "adj_pair", "adj_probe", "fields")
 
-    def profile(self, enable: bool):
-        self._check(self._call("gdm_profile", self.h, int(bool(enable))))
+    def profile(self, enable: bool, tags=None):
+        """Start (clearing the counters) or stop per-launch event timing; `tags`
+        (names from PROF_TAGS) restricts it to those launches."""
+        if tags is None or not enable:
+            self._check(self._call("gdm_profile", self.h, int(bool(enable))))
+        else:
+            mask = 0
+            for t in tags:
+                mask |= 1 << self.PROF_TAGS.index(t)
+            self._check(self._call("gdm_profile_mask", self.h, mask))
 
     def profile_read(self) -> dict:
         nt = 3 * len(self.PROF_TAGS)
