@@ -292,7 +292,10 @@ __global__ void adj_seed_kernel(DipoleView d, Wave w, const double2* __restrict_
   const double k3 = (2.0 / 3.0) * w.k * w.k * w.k;
   const int64_t o = r * n;
   double2 g[6], gF[6];
-  for (int a = 0; a < nu; ++a) {
+#pragma unroll
+  for (int a = 0; a < 6; ++a) {
+    g[a] = gF[a] = make_double2(0.0, 0.0);
+    if (a >= nu) continue;  // compile-time indices (no private-memory arrays)
     const double2 F0 = f0[o + u[a]], F = f[o + u[a]], Q = q[o + u[a]];
     // conj(z)/(2i) = (-Im z, -Re z)/2
     double2 gq = make_double2(-0.5 * (be * F0.y + bb * F.y), -0.5 * (be * F0.x + bb * F.x));
@@ -309,11 +312,14 @@ __global__ void adj_seed_kernel(DipoleView d, Wave w, const double2* __restrict_
   }
   if (!mag) {
     const double2 al = d.alpha_c[j];
+#pragma unroll
     for (int a = 0; a < 3; ++a) rhs[o + u[a]] = cadd(gF[a], cmul(al, g[a]));
   } else {
     const double2* A = d.alpha6 + 36 * (j - nc);  // row-major [6][6]; (A^T g)_a = sum_b A[b][a] g_b
+#pragma unroll
     for (int a = 0; a < 6; ++a) {
       double2 s = gF[a];
+#pragma unroll
       for (int b = 0; b < 6; ++b) cfma(s, A[6 * b + a], g[b]);
       rhs[o + u[a]] = s;
     }

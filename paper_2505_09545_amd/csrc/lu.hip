@@ -21,6 +21,7 @@
 // 0-based global row indices (LAPACK semantics otherwise).
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 #include <vector>
 
 #include "gdm_common.hpp"
@@ -504,6 +505,9 @@ __global__ void __launch_bounds__(256) row_permute_inv_kernel(cplx<T>* __restric
 // lane with readlane, so the w sequential steps need no workgroup barrier.  The
 // columns of op(Tri) are staged in LDS, PW at a time, shared by the 4 waves.
 constexpr int TRSM_LS_BYTES = 64 * 1024;
+// columns of the inverse per wave: one keeps the per-step work of the
+// substitution chain minimal (the chain, not the arithmetic, sets the time)
+constexpr int BINV_CPW = 1;
 
 __device__ inline float2 readlane_c(float2 v, int l) {
   return make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), l)),
@@ -526,6 +530,8 @@ __device__ inline void trsm_sweep(const cplx<T>* __restrict__ Tri, int64_t ldt, 
   constexpr bool forward = (KIND == 0 || KIND == 2);
   constexpr bool unit = (KIND == 0 || KIND == 3);
   constexpr bool transposed = (KIND >= 2);
+  // this lane's two rows, clamped into the staged column (masked below)
+  const int i0 = lane < w ? lane : w - 1, i1 = lane + 64 < w ? lane + 64 : w - 1;
   for (int ph = 0; ph < w; ph += PW) {
     const int pw = w - ph < PW ? w - ph : PW;
     // columns of op(Tri) handled in this phase: [jb, jb + pw); rows needed: [lo, hi)
@@ -564,37 +570,60 @@ __device__ inline void trsm_sweep(const cplx<T>* __restrict__ Tri, int64_t ldt, 
       Ls[cc * w + i] = transposed ? Tri[j + (int64_t)i * ldt] : Tri[i + (int64_t)j * ldt];
     }
     __syncthreads();
-    for (int s = 0; s < pw; ++s) {
-      const int j = forward ? jb + s : jb + pw - 1 - s;
-      const CT* lcol = Ls + (j - jb) * w;
-      const int jl = j & 63;
-      CT x[CPW];
-#pragma unroll
-      for (int c = 0; c < CPW; ++c) x[c] = readlane_c(j < 64 ? b[0][c] : b[1][c], jl);
-      if (!unit) {
-        const CT inv = cinv_t(lcol[j]);
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-          x[c] = cmul_t(x[c], inv);
-          if (lane == jl) {
-            if (j < 64) b[0][c] = x[c];
-            else b[1][c] = x[c];
-          }
+    // Columns [jb, jb + pw) in order; x_j sits in lane j & 63 of half j >> 6, so
+    // the sweep is split at column 64 to make that half a compile-time choice.
+    // The L entries of the next steps do not depend on x: with no branches in
+    // the loop their LDS reads can run ahead of the substitution chain.
+    auto sweep = [&](auto half, int ja, int jz) __attribute__((always_inline)) {
+      constexpr int H = decltype(half)::value;
+      const int cnt = jz - ja;
+      if (cnt <= 0) return;
+      // this lane's entries of the next column, read one step ahead
+      const CT* lnext = Ls + ((forward ? ja : jz - 1) - jb) * w;
+      CT n0 = lnext[i0], n1 = lnext[i1];
+      for (int s = 0; s < cnt; ++s) {
+        const int j = forward ? ja + s : jz - 1 - s;
+        const CT* lcol = Ls + (j - jb) * w;
+        const CT l0 = n0, l1 = n1;
+        if (s + 1 < cnt) {
+          lnext = lcol + (forward ? w : -w);
+          n0 = lnext[i0];
+          n1 = lnext[i1];
         }
-      }
+        const bool a0 = forward ? (lane > j && lane < w) : (lane < j);
+        const bool a1 = forward ? (lane + 64 > j && lane + 64 < w) : (lane + 64 < j);
+        CT x[CPW];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int i = lane + 64 * h;
-        const bool act = forward ? (i > j && i < w) : (i < j);
-        if (act) {
-          const CT t = lcol[i];
+        for (int c = 0; c < CPW; ++c) x[c] = readlane_c(b[H][c], j & 63);
+        if (!unit) {
+          const CT inv = cinv_t(lcol[j]);
 #pragma unroll
           for (int c = 0; c < CPW; ++c) {
-            b[h][c].x -= t.x * x[c].x - t.y * x[c].y;
-            b[h][c].y -= t.x * x[c].y + t.y * x[c].x;
+            x[c] = cmul_t(x[c], inv);
+            if (lane == (j & 63)) b[H][c] = x[c];
           }
         }
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          CT u0 = b[0][c], u1 = b[1][c];
+          u0.x -= l0.x * x[c].x - l0.y * x[c].y;
+          u0.y -= l0.x * x[c].y + l0.y * x[c].x;
+          u1.x -= l1.x * x[c].x - l1.y * x[c].y;
+          u1.y -= l1.x * x[c].y + l1.y * x[c].x;
+          b[0][c].x = a0 ? u0.x : b[0][c].x;
+          b[0][c].y = a0 ? u0.y : b[0][c].y;
+          b[1][c].x = a1 ? u1.x : b[1][c].x;
+          b[1][c].y = a1 ? u1.y : b[1][c].y;
+        }
       }
+    };
+    const int je = jb + pw;
+    if (forward) {
+      if (jb < 64) sweep(std::integral_constant<int, 0>{}, jb, je < 64 ? je : 64);
+      if (je > 64) sweep(std::integral_constant<int, 1>{}, jb > 64 ? jb : 64, je);
+    } else {
+      if (je > 64) sweep(std::integral_constant<int, 1>{}, jb > 64 ? jb : 64, je);
+      if (jb < 64) sweep(std::integral_constant<int, 0>{}, jb, je < 64 ? je : 64);
     }
   }
 }
@@ -609,7 +638,7 @@ __global__ void __launch_bounds__(256) block_inv_kernel(const cplx<T>* __restric
   using CT = cplx<T>;
   A += (int64_t)blockIdx.z * sA;  // batch item blockIdx.z
   Dinv += (int64_t)blockIdx.z * sD;
-  constexpr int CPW = 4;
+  constexpr int CPW = BINV_CPW;
   extern __shared__ unsigned char smem_raw[];
   CT* Ls = reinterpret_cast<CT*>(smem_raw);
   const int bb = b0 + blockIdx.y;
@@ -699,7 +728,8 @@ static hipError_t launch_block_inv(const cplx<T>* A, int64_t ld, int64_t n, int 
   if (nblocks <= 0 || nbatch <= 0) return hipSuccess;
   const int PW = trsm_pw(nb, (int)sizeof(T));
   const size_t lds = (size_t)PW * nb * sizeof(cplx<T>);
-  hipLaunchKernelGGL((block_inv_kernel<T, UPPER>), dim3((unsigned)((nb + 15) / 16), (unsigned)nblocks, (unsigned)nbatch),
+  hipLaunchKernelGGL((block_inv_kernel<T, UPPER>),
+                     dim3((unsigned)((nb + 4 * BINV_CPW - 1) / (4 * BINV_CPW)), (unsigned)nblocks, (unsigned)nbatch),
                      dim3(256), lds, st, A, ld, n, nb, b0, Dinv, PW, sA, sD);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;

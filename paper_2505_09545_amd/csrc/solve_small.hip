@@ -100,7 +100,9 @@ __global__ void __launch_bounds__(256) skinny_n_kernel(int64_t m, int64_t k, con
     for (int r = 0; r < NR; ++r) red[wave - 1][lane][r] = acc[r];
   __syncthreads();
   if (wave == 0 && row < m) {
-    for (int r = 0; r < nr; ++r) {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r >= nr) break;  // compile-time indices into acc (no private-memory copy)
       CT s = acc[r];
 #pragma unroll
       for (int w = 0; w < 3; ++w) {
