@@ -13,10 +13,17 @@
 // expansion of A costs one LDS load per lane (the lane picks re or im and the
 // sign from its (row, k) parity); no extra storage and no 3M/4M bookkeeping.
 //
-// Tile: 64 complex rows x 64 columns per 256-thread workgroup (2 x 2 waves, each
-// 64 real rows x 32 columns = 4 x 2 MFMA blocks), 8 complex k per stage,
-// double-buffered LDS.  Workgroups are remapped so that each of the 8 XCDs works
-// on a contiguous range of tiles (their operands then share that XCD's L2).
+// Tiles: 2 x 2 waves per 256-thread workgroup, each wave WM x WN MFMA blocks of
+// 16 real rows x 16 columns, BK complex k per stage, double-buffered LDS:
+//   64 complex rows x 64 columns x 8 k (WM 4, WN 2) for launches that fill the
+//     chip (the bulk of the trailing update);
+//   32 x 32 x 16 (WM 2, WN 1) for launches of fewer than two 64 x 64 tiles per
+//     CU (look-ahead update, U12 blocks, solve steps): four times the
+//     workgroups and half the stages, for products whose time is set by the
+//     latency of the k loop rather than by the matrix cores.
+// Both load two complex elements of A and two of B per thread and stage.
+// Workgroups are remapped so that each of the 8 XCDs works on a contiguous
+// range of tiles (their operands then share that XCD's L2).
 #include "gdm_common.hpp"
 #include "gdm_kernels.hpp"
 
@@ -28,10 +35,6 @@ template <> struct acc_of<float> { using type = v4f; };
 
 __device__ inline v4d mfma16(double a, double b, v4d c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
 __device__ inline v4f mfma16(float a, float b, v4f c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
-
-constexpr int GBM = 64;  // complex rows per tile
-constexpr int GBN = 64;  // columns per tile
-constexpr int GBK = 8;   // complex k per stage
 
 // Operand masks (used by the triangular-block solves): an element (r, c) of a
 // masked square block is kept iff the relation holds, else read as zero.
@@ -45,43 +48,47 @@ __device__ inline bool mask_keep(int kind, int64_t r, int64_t c) {
   }
 }
 
-template <typename T, int MODE, int TRANSA, int ROLE>
+template <typename T, int MODE, int TRANSA, int ROLE, int WM, int WN, int BK>
 __global__ void __launch_bounds__(256) cgemm_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict__ A,
                                                      int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb,
                                                      cplx<T>* __restrict__ C, int64_t ldc, int tiles_m, int tiles,
                                                      GemmMask mk, int64_t sA, int64_t sB, int64_t sC) {
   using CT = cplx<T>;
+  constexpr int BM = 16 * WM;  // complex rows per tile
+  constexpr int BN = 32 * WN;  // columns per tile
+  constexpr int AL = BM * BK / 256, BL = BK * BN / 256;  // elements per thread and stage
+  static_assert(AL * 256 == BM * BK && BL * 256 == BK * BN && BK % 2 == 0, "tile shape");
   // batch of independent products: blockIdx.y selects the item
   A += (int64_t)blockIdx.y * sA;
   B += (int64_t)blockIdx.y * sB;
   C += (int64_t)blockIdx.y * sC;
   using ACC = typename acc_of<T>::type;
-  __shared__ T As[2][GBK * GBM * 2];   // [kc][mc] complex
-  __shared__ T Bs[2][2 * GBK * GBN];   // [kk][nc] real view
+  __shared__ T As[2][BK * BM * 2];   // [kc][mc] complex
+  __shared__ T Bs[2][2 * BK * BN];   // [kk][nc] real view
   // XCD-aware remap: hardware places workgroup b on XCD b % 8.
   const int bid = blockIdx.x;
   const int xcd = bid & 7, loc = bid >> 3;
   const int per = tiles >> 3, rem = tiles & 7;
   const int tile = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + loc;
   const int tm = tile % tiles_m, tn = tile / tiles_m;
-  const int64_t m0 = (int64_t)tm * GBM, n0 = (int64_t)tn * GBN;
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wrow = (wave & 1) * 64;  // real-row offset of the wave inside the tile
-  const int wcol = (wave >> 1) * 32;
+  const int wrow = (wave & 1) * 16 * WM;  // real-row offset of the wave inside the tile
+  const int wcol = (wave >> 1) * 16 * WN;
 
-  ACC acc[4][2];
+  ACC acc[WM][WN];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < WM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = ACC{0, 0, 0, 0};
+    for (int j = 0; j < WN; ++j) acc[i][j] = ACC{0, 0, 0, 0};
 
-  CT ra[2], rb[2];
+  CT ra[AL], rb[BL];
   auto gload = [&](int64_t kb) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < AL; ++i) {
       const int idx = tid + 256 * i;
       int mc, kc;
-      if (TRANSA == 0) { mc = idx % GBM; kc = idx / GBM; } else { kc = idx % GBK; mc = idx / GBK; }
+      if (TRANSA == 0) { mc = idx % BM; kc = idx / BM; } else { kc = idx % BK; mc = idx / BK; }
       const int64_t gm = m0 + mc, gk = kb + kc;
       CT v;
       v.x = 0; v.y = 0;
@@ -89,7 +96,11 @@ __global__ void __launch_bounds__(256) cgemm_kernel(int64_t m, int64_t n, int64_
       if (mk.akind && gm >= mk.ar0 && gm < mk.ar0 + mk.adw) keep = keep && mask_keep(mk.akind, gm - mk.ar0, gk);
       if (keep) v = TRANSA == 0 ? A[gm + gk * lda] : A[gk + gm * lda];
       ra[i] = v;
-      const int kc2 = idx % GBK, nc = idx / GBK;
+    }
+#pragma unroll
+    for (int i = 0; i < BL; ++i) {
+      const int idx = tid + 256 * i;
+      const int kc2 = idx % BK, nc = idx / BK;
       const int64_t gn = n0 + nc, gk2 = kb + kc2;
       CT u;
       u.x = 0; u.y = 0;
@@ -101,19 +112,23 @@ __global__ void __launch_bounds__(256) cgemm_kernel(int64_t m, int64_t n, int64_
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < AL; ++i) {
       const int idx = tid + 256 * i;
       int mc, kc;
-      if (TRANSA == 0) { mc = idx % GBM; kc = idx / GBM; } else { kc = idx % GBK; mc = idx / GBK; }
-      As[buf][(kc * GBM + mc) * 2 + 0] = ra[i].x;
-      As[buf][(kc * GBM + mc) * 2 + 1] = ra[i].y;
-      const int kc2 = idx % GBK, nc = idx / GBK;
-      Bs[buf][(2 * kc2 + 0) * GBN + nc] = rb[i].x;
-      Bs[buf][(2 * kc2 + 1) * GBN + nc] = rb[i].y;
+      if (TRANSA == 0) { mc = idx % BM; kc = idx / BM; } else { kc = idx % BK; mc = idx / BK; }
+      As[buf][(kc * BM + mc) * 2 + 0] = ra[i].x;
+      As[buf][(kc * BM + mc) * 2 + 1] = ra[i].y;
+    }
+#pragma unroll
+    for (int i = 0; i < BL; ++i) {
+      const int idx = tid + 256 * i;
+      const int kc2 = idx % BK, nc = idx / BK;
+      Bs[buf][(2 * kc2 + 0) * BN + nc] = rb[i].x;
+      Bs[buf][(2 * kc2 + 1) * BN + nc] = rb[i].y;
     }
   };
 
-  const int64_t ktiles = (k + GBK - 1) / GBK;
+  const int64_t ktiles = (k + BK - 1) / BK;
   gload(0);
   sstore(0);
   __syncthreads();
@@ -127,34 +142,34 @@ __global__ void __launch_bounds__(256) cgemm_kernel(int64_t m, int64_t n, int64_
   const int arow = sizeof(T) == 8 ? (4 * (lr & 3) + (lr >> 2)) : lr;
   for (int64_t kt = 0; kt < ktiles; ++kt) {
     const int buf = (int)(kt & 1);
-    if (kt + 1 < ktiles) gload((kt + 1) * GBK);
+    if (kt + 1 < ktiles) gload((kt + 1) * BK);
 #pragma unroll
-    for (int s = 0; s < 4; ++s) {
+    for (int s = 0; s < BK / 2; ++s) {
       const int kk = 4 * s + lk;       // real k inside the stage
       const int kc = kk >> 1, sb = kk & 1;
-      T a[4], b[2];
+      T a[WM], b[WN];
 #pragma unroll
-      for (int bm = 0; bm < 4; ++bm) {
+      for (int bm = 0; bm < WM; ++bm) {
         const int r = wrow + bm * 16 + arow;  // real row inside the tile
         const int t = r & 1;
-        T v = As[buf][(kc * GBM + (r >> 1)) * 2 + (sb ^ t)];
+        T v = As[buf][(kc * BM + (r >> 1)) * 2 + (sb ^ t)];
         a[bm] = (sb == 1 && t == 0) ? -v : v;
       }
 #pragma unroll
-      for (int bn = 0; bn < 2; ++bn) b[bn] = Bs[buf][kk * GBN + wcol + bn * 16 + lr];
+      for (int bn = 0; bn < WN; ++bn) b[bn] = Bs[buf][kk * BN + wcol + bn * 16 + lr];
 #pragma unroll
-      for (int bm = 0; bm < 4; ++bm)
+      for (int bm = 0; bm < WM; ++bm)
 #pragma unroll
-        for (int bn = 0; bn < 2; ++bn) acc[bm][bn] = mfma16(a[bm], b[bn], acc[bm][bn]);
+        for (int bn = 0; bn < WN; ++bn) acc[bm][bn] = mfma16(a[bm], b[bn], acc[bm][bn]);
     }
     if (kt + 1 < ktiles) sstore(buf ^ 1);
     __syncthreads();
   }
   // epilogue: lane holds real rows 4*lk + {0..3} = two complex rows of column lane%16
 #pragma unroll
-  for (int bm = 0; bm < 4; ++bm)
+  for (int bm = 0; bm < WM; ++bm)
 #pragma unroll
-    for (int bn = 0; bn < 2; ++bn) {
+    for (int bn = 0; bn < WN; ++bn) {
       const int64_t col = n0 + wcol + bn * 16 + lr;
       const int64_t crow = m0 + ((wrow + bm * 16) >> 1) + 2 * lk;
       if (col >= n) continue;
@@ -179,25 +194,61 @@ __global__ void __launch_bounds__(256) cgemm_kernel(int64_t m, int64_t n, int64_
     }
 }
 
+// Compute units of the current device (queried once per device).
+static int gemm_num_cu() {
+  static int cu[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cu[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    cu[dev] = v;
+  }
+  return cu[dev];
+}
+
+// Launch with the tile shape (WM, WN, BK); tile counts checked by the caller's shape.
+template <typename T, int MODE, int TRANSA, int ROLE, int WM, int WN, int BK>
+static hipError_t launch_tiles(int64_t m, int64_t n, int64_t k, const cplx<T>* a, int64_t lda, const cplx<T>* b,
+                               int64_t ldb, cplx<T>* c, int64_t ldc, hipStream_t st, GemmMask mk, int nbatch,
+                               int64_t sA, int64_t sB, int64_t sC) {
+  const int64_t tm = (m + 16 * WM - 1) / (16 * WM), tn = (n + 32 * WN - 1) / (32 * WN);
+  if (tm * tn > INT32_MAX) return hipErrorInvalidValue;
+  const int tiles = (int)(tm * tn);
+  hipLaunchKernelGGL((cgemm_kernel<T, MODE, TRANSA, ROLE, WM, WN, BK>), dim3(tiles, nbatch), dim3(256), 0, st, m, n, k,
+                     a, lda, b, ldb, c, ldc, (int)tm, tiles, mk, sA, sB, sC);
+  return hipGetLastError();
+}
+
+// Small tiles when the 64 x 64 tiling gives fewer than two workgroups per CU.
+static bool use_small_tiles(int64_t m, int64_t n, int nbatch) {
+  const int64_t big = ((m + 63) / 64) * ((n + 63) / 64) * (int64_t)nbatch;
+  return big < 2 * (int64_t)gemm_num_cu();
+}
+
+template <typename T, int MODE, int TRANSA, int ROLE>
+static hipError_t launch_cfg(int64_t m, int64_t n, int64_t k, const cplx<T>* a, int64_t lda, const cplx<T>* b,
+                             int64_t ldb, cplx<T>* c, int64_t ldc, hipStream_t st, GemmMask mk, int nbatch, int64_t sA,
+                             int64_t sB, int64_t sC) {
+  if (use_small_tiles(m, n, nbatch))
+    return launch_tiles<T, MODE, TRANSA, ROLE, 2, 1, 16>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
+  return launch_tiles<T, MODE, TRANSA, ROLE, 4, 2, 8>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
+}
+
 template <typename T>
 hipError_t launch_gemm(int mode, int transA, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
                        const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st, GemmMask mk, int nbatch,
                        int64_t sA, int64_t sB, int64_t sC) {
   if (m <= 0 || n <= 0 || nbatch <= 0) return hipSuccess;
   if (nbatch > 65535) return hipErrorInvalidValue;
-  const int64_t tm = (m + GBM - 1) / GBM, tn = (n + GBN - 1) / GBN;
-  if (tm * tn > INT32_MAX) return hipErrorInvalidValue;
-  const int tiles = (int)(tm * tn);
   const auto* a = static_cast<const cplx<T>*>(A);
   const auto* b = static_cast<const cplx<T>*>(B);
   auto* c = static_cast<cplx<T>*>(C);
   if (k <= 0 && mode == 0) return hipSuccess;  // C - 0
-  const dim3 grid(tiles, nbatch), blk(256);
-  if (mode == 0 && transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 0, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk, sA, sB, sC);
-  else if (mode == 0) hipLaunchKernelGGL((cgemm_kernel<T, 0, 1, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk, sA, sB, sC);
-  else if (transA == 0) hipLaunchKernelGGL((cgemm_kernel<T, 1, 0, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk, sA, sB, sC);
-  else hipLaunchKernelGGL((cgemm_kernel<T, 1, 1, 0>), grid, blk, 0, st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk, sA, sB, sC);
-  return hipGetLastError();
+  if (mode == 0 && transA == 0) return launch_cfg<T, 0, 0, 0>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
+  if (mode == 0) return launch_cfg<T, 0, 1, 0>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
+  if (transA == 0) return launch_cfg<T, 1, 0, 0>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
+  return launch_cfg<T, 1, 1, 0>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
 }
 
 template <typename T>
@@ -206,13 +257,8 @@ hipError_t launch_gemm_update(int64_t m, int64_t n, int64_t k, const void* A, in
                               int64_t sC) {
   if (m <= 0 || n <= 0 || k <= 0 || nbatch <= 0) return hipSuccess;
   if (nbatch > 65535) return hipErrorInvalidValue;
-  const int64_t tm = (m + GBM - 1) / GBM, tn = (n + GBN - 1) / GBN;
-  if (tm * tn > INT32_MAX) return hipErrorInvalidValue;
-  const int tiles = (int)(tm * tn);
-  hipLaunchKernelGGL((cgemm_kernel<T, 0, 0, 1>), dim3(tiles, nbatch), dim3(256), 0, st, m, n, k,
-                     static_cast<const cplx<T>*>(A), lda, static_cast<const cplx<T>*>(B), ldb,
-                     static_cast<cplx<T>*>(C), ldc, (int)tm, tiles, GemmMask{}, sA, sB, sC);
-  return hipGetLastError();
+  return launch_cfg<T, 0, 0, 1>(m, n, k, static_cast<const cplx<T>*>(A), lda, static_cast<const cplx<T>*>(B), ldb,
+                                static_cast<cplx<T>*>(C), ldc, st, GemmMask{}, nbatch, sA, sB, sC);
 }
 template hipError_t launch_gemm_update<double>(int64_t, int64_t, int64_t, const void*, int64_t, const void*, int64_t,
                                                void*, int64_t, hipStream_t, int, int64_t, int64_t, int64_t);
