@@ -55,7 +55,7 @@ __device__ inline unsigned long long shfl_xor_u64(unsigned long long v, int m) {
 }
 
 __global__ void zero_u64_kernel(unsigned long long* a, size_t na, unsigned long long* b, size_t nb,
-                                unsigned long long* c, size_t nc) {
+                                int32_t* c, size_t nc) {
   const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < na) a[i] = 0;
   if (i < nb) b[i] = 0;
@@ -192,16 +192,26 @@ __device__ inline void block_argmax(u64& key, int& idx, u64* skey, int* sidx) {
   idx = key ? sidx[wbest] : -1;
 }
 
+// The panel also lists the rows it moved, as (final position, original
+// position) pairs: a row's label is its final position, so a workgroup knows
+// its moved rows without replaying the interchanges.  Slots are claimed with an
+// atomic counter (zeroed before the factorisation); the order of the list is
+// irrelevant, since the permutation gathers every source before it scatters.
 template <typename T>
 __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int64_t ld, int64_t n, int64_t k0, int w,
                                                      int R, int G, int32_t* __restrict__ ipiv, LUWork ws,
-                                                     uint32_t epoch0, int64_t sA, int64_t sipiv) {
+                                                     uint32_t epoch0, int64_t sA, int64_t sipiv,
+                                                     int32_t* __restrict__ mdst, int32_t* __restrict__ msrc,
+                                                     int32_t* __restrict__ mcount, int mcap) {
   using CT = cplx<T>;
   // batch item blockIdx.y: its own matrix, pivots and exchange buffers
   A += (int64_t)blockIdx.y * sA;
   ipiv += (int64_t)blockIdx.y * sipiv;
   ws.cand += (int64_t)blockIdx.y * ws.s_cand;
   ws.rows += (int64_t)blockIdx.y * ws.s_rows;
+  mdst += (int64_t)blockIdx.y * ws.s_pairs;
+  msrc += (int64_t)blockIdx.y * ws.s_pairs;
+  mcount += (int64_t)blockIdx.y * ws.s_npairs;
   constexpr int NW = sizeof(CT) / 4;  // payload words per complex
   extern __shared__ unsigned char smem_raw[];
   CT* tile = reinterpret_cast<CT*>(smem_raw);           // [w][R], column c at tile + c*R
@@ -363,6 +373,16 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
     if (tid == 0 && zero_col >= 0) atomicMin(&ws.err[1], (int)(k0 + zero_col));
   }
   for (int lr = tid; lr < myR; lr += 256) {
+    const int32_t orig = (int32_t)(rbase + lr);
+    if (lab[lr] != orig) {
+      const int slot = __hip_atomic_fetch_add(mcount, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (slot < mcap) {
+        mdst[slot] = lab[lr];
+        msrc[slot] = orig;
+      }
+    }
+  }
+  for (int lr = tid; lr < myR; lr += 256) {
     CT* dst = A + lab[lr] + k0 * ld;
     for (int c0 = 0; c0 < wfull; c0 += LB) {
       CT v[LB];
@@ -376,69 +396,8 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
 }
 
 // ---------------------------------------------------------------------------
-// 2. net permutation of a block's interchanges (one wave)
+// 2. row permutations (a block's moved rows, listed by its panel)
 // ---------------------------------------------------------------------------
-// After the w interchanges (k0+i <-> ipiv[k0+i]), row dst[t] holds the former
-// row src[t]; rows outside the list are unchanged.
-__global__ void __launch_bounds__(64) block_perm_kernel(const int32_t* __restrict__ ipiv, int64_t k0, int w,
-                                                         int32_t* __restrict__ dst, int32_t* __restrict__ src,
-                                                         int32_t* __restrict__ npairs, int64_t sipiv, int64_t spairs,
-                                                         int64_t snpairs) {
-  // batch item blockIdx.x
-  ipiv += (int64_t)blockIdx.x * sipiv;
-  dst += (int64_t)blockIdx.x * spairs;
-  src += (int64_t)blockIdx.x * spairs;
-  npairs += (int64_t)blockIdx.x * snpairs;
-  __shared__ int32_t key[512];
-  __shared__ int32_t val[512];
-  __shared__ int cnt;
-  const int lane = threadIdx.x;
-  for (int i = lane; i < w; i += 64) {
-    key[i] = (int32_t)(k0 + i);
-    val[i] = (int32_t)(k0 + i);
-  }
-  if (lane == 0) cnt = w;
-  __syncthreads();
-  for (int i = 0; i < w; ++i) {
-    const int32_t b = ipiv[k0 + i];
-    if (b == (int32_t)(k0 + i)) continue;
-    int bi;
-    if (b < (int32_t)(k0 + w)) {
-      bi = (int)(b - k0);
-    } else {
-      const int c = cnt;
-      int found = -1;
-      for (int t = w + lane; t < c; t += 64)
-        if (key[t] == b) found = t;
-      unsigned long long mask = __ballot(found >= 0);
-      if (mask) {
-        const int src_lane = __ffsll((long long)mask) - 1;
-        bi = __shfl(found, src_lane);
-      } else {
-        bi = c;
-        if (lane == 0) {
-          key[c] = b;
-          val[c] = b;
-          cnt = c + 1;
-        }
-      }
-    }
-    __syncthreads();
-    if (lane == 0) {
-      const int32_t t = val[i];
-      val[i] = val[bi];
-      val[bi] = t;
-    }
-    __syncthreads();
-  }
-  const int c = cnt;
-  for (int t = lane; t < c; t += 64) {
-    dst[t] = key[t];
-    src[t] = val[t];
-  }
-  if (lane == 0) *npairs = c;
-}
-
 // X[dst[t], col] = Xold[src[t], col] for the columns [c0, c0 + ncols).
 template <typename T>
 __global__ void __launch_bounds__(256) row_permute_kernel(cplx<T>* __restrict__ X, int64_t ld, int64_t c0,
@@ -505,9 +464,6 @@ __global__ void __launch_bounds__(256) row_permute_inv_kernel(cplx<T>* __restric
 // lane with readlane, so the w sequential steps need no workgroup barrier.  The
 // columns of op(Tri) are staged in LDS, PW at a time, shared by the 4 waves.
 constexpr int TRSM_LS_BYTES = 64 * 1024;
-// columns of the inverse per wave: one keeps the per-step work of the
-// substitution chain minimal (the chain, not the arithmetic, sets the time)
-constexpr int BINV_CPW = 1;
 
 __device__ inline float2 readlane_c(float2 v, int l) {
   return make_float2(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), l)),
@@ -631,14 +587,13 @@ __device__ inline void trsm_sweep(const cplx<T>* __restrict__ Tri, int64_t ldt, 
 // Inverse of the diagonal triangle of blocks b0 + blockIdx.y (UPPER 0: unit lower
 // L11, 1: non-unit upper U11) by substitution on identity columns; written to
 // Dinv[b] (nb x nb column-major, zeros in the other triangle).
-template <typename T, int UPPER>
+template <typename T, int UPPER, int CPW>
 __global__ void __launch_bounds__(256) block_inv_kernel(const cplx<T>* __restrict__ A, int64_t ld, int64_t n, int nb,
                                                         int b0, cplx<T>* __restrict__ Dinv, int PW, int64_t sA,
                                                         int64_t sD) {
   using CT = cplx<T>;
   A += (int64_t)blockIdx.z * sA;  // batch item blockIdx.z
   Dinv += (int64_t)blockIdx.z * sD;
-  constexpr int CPW = BINV_CPW;
   extern __shared__ unsigned char smem_raw[];
   CT* Ls = reinterpret_cast<CT*>(smem_raw);
   const int bb = b0 + blockIdx.y;
@@ -722,15 +677,23 @@ static int trsm_pw(int w, int elem) {
   return PW;
 }
 
+// One column of the inverse per wave keeps the per-step work of the substitution
+// chain minimal (the chain, not the arithmetic, sets the time of one triangle);
+// with many triangles at once (more workgroups than CUs) four columns per wave
+// stage each triangle into LDS four times less often.
 template <typename T, int UPPER>
 static hipError_t launch_block_inv(const cplx<T>* A, int64_t ld, int64_t n, int nb, int b0, int nblocks, cplx<T>* Dinv,
-                                   hipStream_t st, int nbatch, int64_t sA, int64_t sD) {
+                                   hipStream_t st, int nbatch, int64_t sA, int64_t sD, int ncu) {
   if (nblocks <= 0 || nbatch <= 0) return hipSuccess;
   const int PW = trsm_pw(nb, (int)sizeof(T));
   const size_t lds = (size_t)PW * nb * sizeof(cplx<T>);
-  hipLaunchKernelGGL((block_inv_kernel<T, UPPER>),
-                     dim3((unsigned)((nb + 4 * BINV_CPW - 1) / (4 * BINV_CPW)), (unsigned)nblocks, (unsigned)nbatch),
-                     dim3(256), lds, st, A, ld, n, nb, b0, Dinv, PW, sA, sD);
+  const dim3 g1((unsigned)((nb + 3) / 4), (unsigned)nblocks, (unsigned)nbatch);
+  if ((int64_t)g1.x * nblocks * nbatch <= ncu) {
+    hipLaunchKernelGGL((block_inv_kernel<T, UPPER, 1>), g1, dim3(256), lds, st, A, ld, n, nb, b0, Dinv, PW, sA, sD);
+  } else {
+    const dim3 g4((unsigned)((nb + 15) / 16), (unsigned)nblocks, (unsigned)nbatch);
+    hipLaunchKernelGGL((block_inv_kernel<T, UPPER, 4>), g4, dim3(256), lds, st, A, ld, n, nb, b0, Dinv, PW, sA, sD);
+  }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((diag_store_kernel<T, UPPER>), dim3(16, (unsigned)nblocks, (unsigned)nbatch), dim3(256), 0, st,
@@ -883,11 +846,12 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
   hipLaunchKernelGGL(init_err_kernel, dim3(1), dim3(64), 0, st, ws.err);
   // exchange buffers start from zero (epoch 0 is never used), so epochs 1, 2, ...
   // of this factorisation are unique
+  // (and the moved-row counters of every block, which the panels fill)
   {
-    const size_t nc = (size_t)NB * ws.s_cand, nr = (size_t)NB * ws.s_rows;
-    const size_t nmax = std::max(nc, nr);
+    const size_t nc = (size_t)NB * ws.s_cand, nr = (size_t)NB * ws.s_rows, np = (size_t)NB * ws.s_npairs;
+    const size_t nmax = std::max(std::max(nc, nr), np);
     hipLaunchKernelGGL(zero_u64_kernel, dim3((unsigned)((nmax + 255) / 256)), dim3(256), 0, st, ws.cand, nc, ws.rows, nr,
-                       ws.rows, (size_t)0);
+                       ws.npairs, np);
   }
   uint32_t epoch = 1;
   if ((e = lu_prepare<T>(plan)) != hipSuccess) return e;
@@ -925,22 +889,20 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
     const int w = b.w;
     const size_t lds = panel_lds_bytes(w, b.R, sizeof(CT));
     LUCHK(P.begin(st, PROF_PANEL, (double)w * fb));
+    int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;  // moved rows: destinations, then sources 2 nb later
+    int32_t* src = dst + 2 * nb;
+    int32_t* npr = ws.npairs + bi;
     hipLaunchKernelGGL(panel_kernel<T>, dim3(b.G, NB), dim3(256), lds, st, A, ld, n, k0, w, b.R, b.G, ipiv, ws, epoch,
-                       sA, sipiv);
+                       sA, sipiv, dst, src, npr, 2 * nb);
     epoch += (uint32_t)w;
     LUCHK(hipGetLastError());
     LUCHK(P.end(st));
-    int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;
-    int32_t* src = dst + 2 * nb;
-    int32_t* npr = ws.npairs + bi;
-    hipLaunchKernelGGL(block_perm_kernel, dim3(NB), dim3(64), 0, st, ipiv, k0, w, dst, src, npr, sipiv, ws.s_pairs,
-                       ws.s_npairs);
     const int64_t c1 = k0 + w;
     const int64_t nr = n - c1;
     CT* diag = A + k0 + k0 * ld;
     // L11^-1 -> strict lower part of the diagonal block holds I - L11^-1
     LUCHK(P.begin(st, PROF_TRSM, 0.0));
-    LUCHK((launch_block_inv<T, 0>(A, ld, n, nb, bi, 1, dinv, st, NB, sA, ws.s_dinv)));
+    LUCHK((launch_block_inv<T, 0>(A, ld, n, nb, bi, 1, dinv, st, NB, sA, ws.s_dinv, ws.gmax)));
     LUCHK(P.end(st));
     if (bulk_done) LUCHK(hipStreamWaitEvent(st, bulk_done, 0));  // columns of this step were in the bulk
     if (nr <= 0) break;
@@ -1003,7 +965,7 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
   if (bulk_done) LUCHK(hipStreamWaitEvent(st, bulk_done, 0));
   // upper parts: diagonal blocks hold I - U11^-1, block columns above hold U01 U11^-1
   LUCHK(P.begin(st, PROF_TRSM, 0.0));
-  LUCHK((launch_block_inv<T, 1>(A, ld, n, nb, 0, nblk, dinv, st, NB, sA, ws.s_dinv)));
+  LUCHK((launch_block_inv<T, 1>(A, ld, n, nb, 0, nblk, dinv, st, NB, sA, ws.s_dinv, ws.gmax)));
   for (int bi = 1; bi < nblk; ++bi) {
     const LUBlock& b = plan.blocks[bi];
     const int64_t k0 = b.k0;
