@@ -353,13 +353,45 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
         }
         c += CG;
       }
+      // FP32: batches of UB columns, all reads first, then the updates, then all
+      // writes (written one column at a time, each read would wait for the
+      // previous column's write, since the compiler cannot tell them apart).
+      // Measured: FP32 panel 6.5 -> 6.3 us per column; the same batching makes
+      // the FP64 panel slower, so FP64 keeps the column-at-a-time loop.
+      constexpr int UB = 8;
+      if constexpr (sizeof(T) == 4)
+      for (; c + (UB - 1) * CG < w; c += UB * CG) {
+        CT t[UB], u[UB];
+#pragma unroll
+        for (int e = 0; e < UB; ++e) {
+          u[e] = prow[c + e * CG];
+          t[e] = tile[(c + e * CG) * R + lr];
+        }
+#pragma unroll
+        for (int e = 0; e < UB; ++e) {
+          t[e].x -= l.x * u[e].x - l.y * u[e].y;
+          t[e].y -= l.x * u[e].y + l.y * u[e].x;
+        }
+#pragma unroll
+        for (int e = 0; e < UB; ++e) tile[(c + e * CG) * R + lr] = t[e];
+      }
+      if constexpr (sizeof(T) == 4) {
+        for (; c < w; c += CG) {
+          const CT u = prow[c];
+          CT t = tile[c * R + lr];
+          t.x -= l.x * u.x - l.y * u.y;
+          t.y -= l.x * u.y + l.y * u.x;
+          tile[c * R + lr] = t;
+        }
+      } else {
 #pragma unroll 8
-      for (; c < w; c += CG) {
-        const CT u = prow[c];
-        CT t = tile[c * R + lr];
-        t.x -= l.x * u.x - l.y * u.y;
-        t.y -= l.x * u.y + l.y * u.x;
-        tile[c * R + lr] = t;
+        for (; c < w; c += CG) {
+          const CT u = prow[c];
+          CT t = tile[c * R + lr];
+          t.x -= l.x * u.x - l.y * u.y;
+          t.y -= l.x * u.y + l.y * u.x;
+          tile[c * R + lr] = t;
+        }
       }
     }
     // (the barrier inside the next block_argmax orders the update before any read)
