@@ -184,8 +184,8 @@ def main() -> int:
                          "for calibrating hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on exactly one GPU (got --gpus {args.gpus}); "
-              "the multi-GPU layout is described in DESIGN.md and not benchmarked", file=sys.stderr)
+        print(f"bench.py: the GDM path runs on exactly one GPU (got --gpus {args.gpus}); "
+              "a multi-GPU run is not implemented", file=sys.stderr)
         return 2
 
     import torch
