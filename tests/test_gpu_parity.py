@@ -239,6 +239,31 @@ def test_argument_errors(ctx):
     assert e.value.status == gdm.GDM_E_ARG
 
 
+def test_profile_tag_mask(ctx):
+    """gdm_profile_mask times only the launches of the tags it is given (the
+    benchmark's timed region keeps events on the update GEMM only);
+    gdm_profile(ctx, 1) times every tag; a mask outside [0, 1024) is an
+    argument error."""
+    say("profile tag mask")
+    from paper_2505_09545_amd import gdm
+    w = gi.config1()
+    ctx.profile(True, tags=["update", "panel"])
+    gdm.run_forward(ctx, w, prec=gdm.PREC_FP32_IR, tol=1e-14, probes=False)
+    p = ctx.profile_read()
+    ctx.profile(False)
+    assert p["update"]["launches"] > 0 and p["panel"]["launches"] > 0
+    assert all(p[t]["launches"] == 0 for t in gdm.Context.PROF_TAGS if t not in ("update", "panel")), p
+    ctx.profile(True)
+    gdm.run_forward(ctx, w, prec=gdm.PREC_FP32_IR, tol=1e-14, probes=False)
+    p = ctx.profile_read()
+    ctx.profile(False)
+    for t in ("update", "panel", "assemble", "trsm", "solve", "resid"):
+        assert p[t]["launches"] > 0 and p[t]["ms"] > 0, (t, p[t])
+    with pytest.raises(gdm.GDMError) as e:
+        ctx._check(ctx._call("gdm_profile_mask", ctx.h, 1 << 10))
+    assert e.value.status == gdm.GDM_E_ARG
+
+
 # ---------------------------------------------------------------------------
 # full size: the 12 000-unknown benchmark workload against stored oracle values
 # ---------------------------------------------------------------------------
