@@ -49,7 +49,7 @@ __device__ inline bool mask_keep(int kind, int64_t r, int64_t c) {
 }
 
 template <typename T, int MODE, int TRANSA, int ROLE, int WM, int WN, int BK>
-__global__ void __launch_bounds__(256) cgemm_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict__ A,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) cgemm_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict__ A,
                                                      int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb,
                                                      cplx<T>* __restrict__ C, int64_t ldc, int tiles_m, int tiles,
                                                      GemmMask mk, int64_t sA, int64_t sB, int64_t sC) {
