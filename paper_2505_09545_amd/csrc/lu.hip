@@ -458,6 +458,40 @@ __global__ void __launch_bounds__(256) row_permute_kernel(cplx<T>* __restrict__ 
   }
 }
 
+// Row interchanges of one block on the columns [0, ncols) of X (as
+// row_permute_kernel), then the permuted rows [k0, k0 + w) copied to D (w x ncols,
+// leading dimension w): one launch per block of a forward solve.
+template <typename T>
+__global__ void __launch_bounds__(256) permute_copy_kernel(cplx<T>* __restrict__ X, int64_t ld, int64_t k0, int w,
+                                                           cplx<T>* __restrict__ D, const int32_t* __restrict__ dst,
+                                                           const int32_t* __restrict__ src,
+                                                           const int32_t* __restrict__ npairs, int64_t sX, int64_t sD,
+                                                           int64_t spairs, int64_t snpairs) {
+  using CT = cplx<T>;
+  X += (int64_t)blockIdx.y * sX;  // batch item blockIdx.y
+  D += (int64_t)blockIdx.y * sD;
+  dst += (int64_t)blockIdx.y * spairs;
+  src += (int64_t)blockIdx.y * spairs;
+  npairs += (int64_t)blockIdx.y * snpairs;
+  const int np = *npairs;
+  const int64_t col = blockIdx.x;
+  CT* x = X + col * ld;
+  CT v[2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int t = threadIdx.x + 256 * i;
+    if (t < np) v[i] = x[src[t]];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int t = threadIdx.x + 256 * i;
+    if (t < np) x[dst[t]] = v[i];
+  }
+  __syncthreads();  // (makes the interchanged rows visible to the whole workgroup)
+  for (int r = threadIdx.x; r < w; r += 256) D[r + col * w] = x[k0 + r];
+}
+
 // inverse: Xnew[src[t]] = Xold[dst[t]] (for the transposed solve)
 template <typename T>
 __global__ void __launch_bounds__(256) row_permute_inv_kernel(cplx<T>* __restrict__ X, int64_t ld, int64_t c0,
@@ -1083,9 +1117,10 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
         const int64_t k0 = b.k0;
         const int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;
         const int32_t* src = dst + 2 * nb;
-        hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)nr, NB), dim3(256), 0, st, B, ldb, (int64_t)0, dst, src,
-                           ws.npairs + bi, sB, ws.s_pairs, ws.s_npairs);
-        if ((e = launch_copy_block<T>(B + k0, ldb, X, b.w, b.w, nr, st, NB, sB, sX)) != hipSuccess) return e;
+        // P_b, and B_b copied out (the product below reads it while it rewrites those rows)
+        hipLaunchKernelGGL(permute_copy_kernel<T>, dim3((unsigned)nr, NB), dim3(256), 0, st, B, ldb, k0, b.w, X, dst,
+                           src, ws.npairs + bi, sB, sX, ws.s_pairs, ws.s_npairs);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
         GemmMask m;
         m.akind = GEMM_MASK_STRICT_LOWER;
         m.ar0 = 0;
