@@ -59,8 +59,6 @@ struct gdm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   hipStream_t side = nullptr;  // look-ahead stream of the factorisation (default priority)
-  hipStream_t pstream = nullptr;    // panel path of the factorisation: half of the CUs
-  hipStream_t side_half = nullptr;  // look-ahead update on the other half
   bool own_stream = false;
   int num_cu = 256;
   int lds_bytes = 160 * 1024;
@@ -169,8 +167,7 @@ static gdm_status run_lu(gdm_ctx* c, void* A, int64_t n, int64_t ld, LUPlan& pla
     HIPCHK(c, ipiv.ensure(sizeof(int32_t) * n));
     piv = ipiv.as<int32_t>();
   }
-  HIPCHK(c, lu_factor<T>(A, ld, plan, w, piv, c->stream, &c->prof, c->lookahead ? c->side : nullptr, 0, 0,
-                         c->lookahead ? c->pstream : nullptr, c->lookahead ? c->side_half : nullptr));
+  HIPCHK(c, lu_factor<T>(A, ld, plan, w, piv, c->stream, &c->prof, c->lookahead ? c->side : nullptr));
   int32_t err[2] = {0, 0};
   HIPCHK(c, hipMemcpyAsync(err, w.err, sizeof(err), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -737,16 +734,6 @@ gdm_status gdm_create(int device, void* hip_stream, gdm_ctx** out) {
     c->own_stream = true;
   }
   for (auto& e : c->ev) (void)hipEventCreate(&e);
-  {
-    // the factorisation's panel path and its look-ahead update on disjoint
-    // halves of the CUs: the panel's workgroups never share a CU with the bulk
-    // of the update
-    std::vector<uint32_t> ma((c->num_cu + 31) / 32, 0u), mb((c->num_cu + 31) / 32, 0u);
-    for (int i = 0; i < c->num_cu; ++i) (i < c->num_cu / 2 ? ma : mb)[i / 32] |= 1u << (i % 32);
-    if (hipExtStreamCreateWithCUMask(&c->pstream, (uint32_t)ma.size(), ma.data()) != hipSuccess) c->pstream = nullptr;
-    if (hipExtStreamCreateWithCUMask(&c->side_half, (uint32_t)mb.size(), mb.data()) != hipSuccess)
-      c->side_half = nullptr;
-  }
   if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) c->side = nullptr;
   *out = c;
   return GDM_OK;
@@ -767,11 +754,6 @@ void gdm_destroy(gdm_ctx* c) {
     (void)hipStreamSynchronize(c->side);
     (void)hipStreamDestroy(c->side);
   }
-  for (hipStream_t x : {c->pstream, c->side_half})
-    if (x) {
-      (void)hipStreamSynchronize(x);
-      (void)hipStreamDestroy(x);
-    }
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }

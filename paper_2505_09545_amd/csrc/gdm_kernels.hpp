@@ -162,8 +162,7 @@ void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu,
 // its pivots at ipiv + z sipiv.
 template <typename T>
 hipError_t lu_factor(void* A, int64_t ld, const LUPlan& plan, const LUWork& ws, int32_t* ipiv, hipStream_t st,
-                     Prof* prof = nullptr, hipStream_t side = nullptr, int64_t sA = 0, int64_t sipiv = 0,
-                     hipStream_t pst = nullptr, hipStream_t side_half = nullptr);
+                     Prof* prof = nullptr, hipStream_t side = nullptr, int64_t sA = 0, int64_t sipiv = 0);
 
 // Factors are left in a solve-ready form: for every block the diagonal block
 // holds I - L11^-1 (strict lower part) and I - U11^-1 (upper part), the block

@@ -771,9 +771,7 @@ static hipError_t launch_block_inv(const cplx<T>* A, int64_t ld, int64_t n, int 
 // planning and workspace
 // ---------------------------------------------------------------------------
 static const int LDS_RESERVE = 2048;
-// order up to which a factorisation with a separate panel stream runs the bulk
-// of each update on the CUs the panel path does not use
-static const int64_t LU_ISOLATE_ROWS = 6144;
+
 
 // dynamic LDS of a panel workgroup: tile, pivot row, multipliers, labels, pivots
 static size_t panel_lds_bytes(int w, int R, size_t cbytes) {
@@ -899,9 +897,8 @@ template hipError_t lu_prepare<double>(const LUPlan&);
 template hipError_t lu_prepare<float>(const LUPlan&);
 
 template <typename T>
-hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws, int32_t* ipiv, hipStream_t st0,
-                     Prof* prof, hipStream_t side, int64_t sA, int64_t sipiv, hipStream_t pst,
-                     hipStream_t side_half) {
+hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws, int32_t* ipiv, hipStream_t st,
+                     Prof* prof, hipStream_t side, int64_t sA, int64_t sipiv) {
   Prof noprof;
   Prof& P = prof ? *prof : noprof;
   using CT = cplx<T>;
@@ -913,30 +910,7 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
   const double fb = (double)NB;
   hipError_t e;
   if (NB < 1 || NB > 65535 || !lu_plan_fits(plan) || plan.max_wg * NB > ws.gmax) return hipErrorInvalidValue;
-  // the panel path runs on pst when given (joined to st0 at both ends)
-  hipStream_t st = st0;
-  bool half_fits = true;  // every panel's workgroups co-resident on half the CUs
-  for (const LUBlock& b : plan.blocks) half_fits = half_fits && (int64_t)b.G * NB <= ws.gmax / 2;
-  // Small systems: the panels, not the update, set the pace; the panel path and
-  // the bulk of each update then run on disjoint halves of the CUs (a panel
-  // sharing CUs with the update is slower per column).  Measured: n = 6000
-  // FP32, 47 -> 44 ms per adjoint step; at n = 12 000 the same split for the
-  // late steps (trailing rows < 6144) changed nothing and the early steps need
-  // every CU for the update, so larger systems keep the shared layout.
-  if (pst && side && side_half && ws.events && half_fits && n <= LU_ISOLATE_ROWS) st = pst;
-  if (st != st0) {
-    if (ws.events->empty()) {
-      hipEvent_t x;
-      if ((e = hipEventCreateWithFlags(&x, hipEventDisableTiming)) != hipSuccess) return e;
-      ws.events->push_back(x);
-    }
-  }
-  hipLaunchKernelGGL(init_err_kernel, dim3(1), dim3(64), 0, st0, ws.err);
-  if (st != st0) {
-    // (an event re-recorded later does not affect a wait already enqueued)
-    if ((e = hipEventRecord((*ws.events)[0], st0)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(st, (*ws.events)[0], 0)) != hipSuccess) return e;
-  }
+  hipLaunchKernelGGL(init_err_kernel, dim3(1), dim3(64), 0, st, ws.err);
   // exchange buffers start from zero (epoch 0 is never used), so epochs 1, 2, ...
   // of this factorisation are unique
   // (and the moved-row counters of every block, which the panels fill)
@@ -1038,9 +1012,7 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
       LUCHK(new_event(main_updated));
       LUCHK(hipEventRecord(main_updated, st));
     }
-    // (one side stream for the whole factorisation: its bulk updates are in
-    // stream order)
-    hipStream_t sb = la ? (st != st0 ? side_half : side) : st;
+    hipStream_t sb = la ? side : st;
     if (la) LUCHK(hipStreamWaitEvent(sb, factored, 0));
     LUCHK(update_cols(sb, c1 + wa, nr - wa, tmpB, ws.s_tmp));
     // L21 is read by both parts of this step's update: transform it after both
@@ -1058,14 +1030,6 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
     }
   }
   if (bulk_done) LUCHK(hipStreamWaitEvent(st, bulk_done, 0));
-  if (st != st0) {
-    // back on the caller's stream (every CU) for the rest
-    hipEvent_t done = nullptr;
-    LUCHK(new_event(done));
-    LUCHK(hipEventRecord(done, st));
-    LUCHK(hipStreamWaitEvent(st0, done, 0));
-    st = st0;
-  }
   // upper parts: diagonal blocks hold I - U11^-1, block columns above hold U01 U11^-1
   LUCHK(P.begin(st, PROF_TRSM, 0.0));
   LUCHK((launch_block_inv<T, 1>(A, ld, n, nb, 0, nblk, dinv, st, NB, sA, ws.s_dinv, ws.gmax)));
@@ -1173,9 +1137,9 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
 }
 
 template hipError_t lu_factor<double>(void*, int64_t, const LUPlan&, const LUWork&, int32_t*, hipStream_t, Prof*,
-                                      hipStream_t, int64_t, int64_t, hipStream_t, hipStream_t);
+                                      hipStream_t, int64_t, int64_t);
 template hipError_t lu_factor<float>(void*, int64_t, const LUPlan&, const LUWork&, int32_t*, hipStream_t, Prof*,
-                                     hipStream_t, int64_t, int64_t, hipStream_t, hipStream_t);
+                                     hipStream_t, int64_t, int64_t);
 template hipError_t lu_solve<double>(int, const void*, int64_t, const LUPlan&, const LUWork&, void*, int64_t, int64_t,
                                      hipStream_t, int64_t, int64_t);
 template hipError_t lu_solve<float>(int, const void*, int64_t, const LUPlan&, const LUWork&, void*, int64_t, int64_t,
