@@ -686,6 +686,43 @@ __global__ void __launch_bounds__(256) block_inv_kernel(const cplx<T>* __restric
     }
 }
 
+// X <- L11^-1 X in place for ncols columns of X (the rows of block b0, leading
+// dimension ldx): the forward substitution of block_inv_kernel applied to the
+// columns of X instead of identity columns (the look-ahead U12 block, without
+// waiting for the triangle's inverse).
+template <typename T, int CPW>
+__global__ void __launch_bounds__(256) block_trsm_kernel(const cplx<T>* __restrict__ A, int64_t ld, int64_t n, int nb,
+                                                         int b0, cplx<T>* __restrict__ X, int64_t ldx, int ncols,
+                                                         int PW, int64_t sA, int64_t sX) {
+  using CT = cplx<T>;
+  A += (int64_t)blockIdx.z * sA;  // batch item blockIdx.z
+  X += (int64_t)blockIdx.z * sX;
+  extern __shared__ unsigned char smem_raw[];
+  CT* Ls = reinterpret_cast<CT*>(smem_raw);
+  const int64_t k0 = (int64_t)b0 * nb;
+  const int w = (int)(n - k0 < nb ? n - k0 : nb);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col0 = blockIdx.x * (4 * CPW) + wave * CPW;
+  CT b[2][CPW];
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int i = lane + 64 * h;
+      b[h][c].x = 0;
+      b[h][c].y = 0;
+      if (i < w && col0 + c < ncols) b[h][c] = X[i + (int64_t)(col0 + c) * ldx];
+    }
+  trsm_sweep<T, 0, CPW>(A + k0 + k0 * ld, ld, w, b, Ls, PW);  // every wave takes part (barriers)
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int c = 0; c < CPW; ++c) {
+      const int i = lane + 64 * h;
+      if (i < w && col0 + c < ncols) X[i + (int64_t)(col0 + c) * ldx] = b[h][c];
+    }
+}
+
 // Diagonal block of block b0 + blockIdx.y: strict lower <- -Linv (UPPER 0), or
 // upper incl. diagonal <- I - Uinv (UPPER 1).
 template <typename T, int UPPER>
@@ -764,6 +801,17 @@ static hipError_t launch_block_inv(const cplx<T>* A, int64_t ld, int64_t n, int 
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((diag_store_kernel<T, UPPER>), dim3(16, (unsigned)nblocks, (unsigned)nbatch), dim3(256), 0, st,
                      const_cast<cplx<T>*>(A), ld, n, nb, b0, Dinv, sA, sD);
+  return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t launch_block_trsm(const cplx<T>* A, int64_t ld, int64_t n, int nb, int b0, cplx<T>* X, int64_t ldx,
+                                   int64_t ncols, hipStream_t st, int nbatch, int64_t sA, int64_t sX) {
+  if (ncols <= 0 || nbatch <= 0) return hipSuccess;
+  const int PW = trsm_pw(nb, (int)sizeof(T));
+  const size_t lds = (size_t)PW * nb * sizeof(cplx<T>);
+  hipLaunchKernelGGL((block_trsm_kernel<T, 1>), dim3((unsigned)((ncols + 3) / 4), 1, (unsigned)nbatch), dim3(256), lds,
+                     st, A, ld, n, nb, b0, X, ldx, (int)ncols, PW, sA, sX);
   return hipGetLastError();
 }
 
@@ -967,17 +1015,19 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
     const int64_t c1 = k0 + w;
     const int64_t nr = n - c1;
     CT* diag = A + k0 + k0 * ld;
-    // L11^-1 -> strict lower part of the diagonal block holds I - L11^-1
-    LUCHK(P.begin(st, PROF_TRSM, 0.0));
-    LUCHK((launch_block_inv<T, 0>(A, ld, n, nb, bi, 1, dinv, st, NB, sA, ws.s_dinv, ws.gmax)));
-    LUCHK(P.end(st));
+    // L11^-1 -> strict lower part of the diagonal block holds I - L11^-1.  With
+    // look-ahead it is formed on the side stream, once the main stream has
+    // solved the next panel's U12 block directly (that solve reads L11).
+    auto form_inverse = [&](hipStream_t s) -> hipError_t {
+      hipError_t r;
+      if ((r = P.begin(s, PROF_TRSM, 0.0)) != hipSuccess) return r;
+      if ((r = launch_block_inv<T, 0>(A, ld, n, nb, bi, 1, dinv, s, NB, sA, ws.s_dinv, ws.gmax)) != hipSuccess)
+        return r;
+      return P.end(s);
+    };
+    if (!la || nr <= 0) LUCHK(form_inverse(st));
     if (bulk_done) LUCHK(hipStreamWaitEvent(st, bulk_done, 0));  // columns of this step were in the bulk
     if (nr <= 0) break;
-    hipEvent_t factored = nullptr;
-    if (la) {
-      LUCHK(new_event(factored));
-      LUCHK(hipEventRecord(factored, st));
-    }
     GemmMask ml;
     ml.akind = GEMM_MASK_STRICT_LOWER;
     ml.ar0 = 0;
@@ -1005,15 +1055,33 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
         return r;
       return P.end(s);
     };
-    if (la) LUCHK(update_cols(st, c1, wa, tmpA, ws.s_tmp2));
-    else LUCHK(update_cols(st, c1, wa, tmpB, ws.s_tmp));
-    hipEvent_t main_updated = nullptr;
+    hipEvent_t l11_read = nullptr, main_updated = nullptr;
     if (la) {
+      // next panel's columns: interchanges, U12 by substitution, update
+      LUCHK(P.begin(st, PROF_PERM, 0.0));
+      hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)wa, NB), dim3(256), 0, st, A, ld, c1, dst, src, npr, sA,
+                         ws.s_pairs, ws.s_npairs);
+      LUCHK(hipGetLastError());
+      LUCHK(P.end(st));
+      LUCHK(P.begin(st, PROF_TRSM, 8.0 * w * w * (double)wa * fb));
+      LUCHK(launch_block_trsm<T>(A, ld, n, nb, bi, A + k0 + c1 * ld, ld, wa, st, NB, sA, sA));
+      LUCHK(P.end(st));
+      LUCHK(new_event(l11_read));
+      LUCHK(hipEventRecord(l11_read, st));
+      LUCHK(P.begin(st, PROF_UPDATE, 8.0 * (double)nr * (double)wa * w * fb));
+      LUCHK(launch_gemm_update<T>(nr, wa, w, A + c1 + k0 * ld, ld, A + k0 + c1 * ld, ld, A + c1 + c1 * ld, ld, st, NB,
+                                  sA, sA, sA));
+      LUCHK(P.end(st));
       LUCHK(new_event(main_updated));
       LUCHK(hipEventRecord(main_updated, st));
+    } else {
+      LUCHK(update_cols(st, c1, wa, tmpB, ws.s_tmp));
     }
     hipStream_t sb = la ? side : st;
-    if (la) LUCHK(hipStreamWaitEvent(sb, factored, 0));
+    if (la) {
+      LUCHK(hipStreamWaitEvent(sb, l11_read, 0));
+      LUCHK(form_inverse(sb));
+    }
     LUCHK(update_cols(sb, c1 + wa, nr - wa, tmpB, ws.s_tmp));
     // L21 is read by both parts of this step's update: transform it after both
     if (la) LUCHK(hipStreamWaitEvent(sb, main_updated, 0));
