@@ -8,14 +8,18 @@
 //      |re|+|im| in the column, lowest row on ties).  One cooperative launch of
 //      G workgroups; each holds R rows of the panel in LDS and the workgroups
 //      agree on every pivot through one device-wide barrier per column.
-//   2. the net row permutation of the block's w interchanges is computed once
-//      (<= 2w rows move) and applied to the trailing columns and, in the solve,
-//      to the right-hand sides.  Interchanges are never applied to the columns
-//      left of the block: the factors are kept in the factored form
+//   2. the panel also lists the block's net row permutation (<= 2w rows move,
+//      read off the row labels), which is applied to the trailing columns and,
+//      in the solve, to the right-hand sides.  Interchanges are never applied
+//      to the columns left of the block: the factors are kept in the factored
+//      form
 //          M = P1^T L1 P2^T L2 ... Pk^T Lk U
 //      and the solve applies P_b before using L_b, which is equivalent.
-//   3. U12 = L11^-1 A12 (triangular solve), 4. A22 -= L21 U12 (complex GEMM on
-//      MFMA, gemm.hip).
+//   3. U12 = L11^-1 A12 (by substitution for the next panel's columns, by a
+//      product with the inverse of L11 for the rest), 4. A22 -= L21 U12
+//      (complex GEMM on MFMA, gemm.hip).  With look-ahead, steps 3-4 for the
+//      next panel's columns run on the main stream and the rest of the trailing
+//      matrix on a side stream, overlapping the next panel.
 //
 // Layout: column-major interleaved complex, leading dimension ld.  ipiv holds
 // 0-based global row indices (LAPACK semantics otherwise).
