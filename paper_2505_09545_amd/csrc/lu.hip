@@ -41,6 +41,12 @@ template <typename CT> __device__ inline CT cmul_t(CT a, CT b) {
   r.y = a.x * b.y + a.y * b.x;
   return r;
 }
+// t - l u: one entry of a rank-1 update
+template <typename CT> __device__ inline CT r1_upd(CT t, const CT& l, const CT& u) {
+  t.x -= l.x * u.x - l.y * u.y;
+  t.y -= l.x * u.y + l.y * u.x;
+  return t;
+}
 template <typename CT> __device__ inline CT cinv_t(CT a) {
   // 1/a with scaling against overflow of |a|^2
   const auto s = fabs(a.x) > fabs(a.y) ? fabs(a.x) : fabs(a.y);
@@ -220,8 +226,7 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
   extern __shared__ unsigned char smem_raw[];
   CT* tile = reinterpret_cast<CT*>(smem_raw);           // [w][R], column c at tile + c*R
   CT* prow = tile + (size_t)w * R;                      // [w] pivot row
-  CT* lst = prow + w;                                   // [R] multipliers of the current column
-  int32_t* lab = reinterpret_cast<int32_t*>(lst + R);   // [R] row labels (final positions)
+  int32_t* lab = reinterpret_cast<int32_t*>(prow + w);  // [R] row labels (final positions)
   int32_t* pl = lab + R;                                // [w] pivot positions of this panel
   __shared__ u64 skey1[4], skey2[4];
   __shared__ int sidx1[4], sidx2[4];
@@ -264,31 +269,75 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
     }
   }
   int zero_col = -1;
+  // Column j's rank-1 update is split: column j + 1 right after the pivot is
+  // known (it holds the next pivot candidates), the rest of the trailing
+  // columns after the next candidate has been published, so that it runs while
+  // the other workgroups' keys for column j + 1 are on their way.  Every row
+  // receives every update exactly once: the candidate row gets its deferred part
+  // when it is published, the other rows in the bulk step.
   for (int j = 0; j < w; ++j) {
     const int64_t gj = k0 + j;
     const uint32_t E = epoch0 + (uint32_t)j;
     const int par = j & 1;
     u64* cand = ws.cand + (size_t)par * ws.gmax * KEY_STRIDE;
     u64* rows = ws.rows + (size_t)par * ws.gmax * ws.wwmax;
-    // workgroup candidate over its active rows (labels >= gj); the tile is final
+    // workgroup candidate over its active rows (labels >= gj); column j is final
     block_argmax(best, brow, skey1, sidx1);
     const u64 mybest = best;
     const int lrow = best ? brow : -1;
-    // the multipliers of the previous column enter the tile now (nobody reads
-    // column j - 1 of the tile again inside the panel)
-    if (j > 0)
-      for (int lr = tid; lr < myR; lr += 256)
-        if (lab[lr] > (int32_t)(gj - 1)) tile[(j - 1) * R + lr] = lst[lr];
-    // publish key (value, label) and columns j.. of the candidate row
+    // publish key (value, label) and columns j.. of the candidate row; its
+    // columns j + 1.. first receive the deferred update by pivot j - 1 (the
+    // multipliers of pivot j - 1 sit in tile column j - 1)
     if (tid == 0) {
       ll_put(&cand[KEY_STRIDE * g + 0], E, mybest ? (uint32_t)(mybest >> 32) : 0u);
       ll_put(&cand[KEY_STRIDE * g + 1], E, mybest ? (0xffffffffu - (uint32_t)(mybest & 0xffffffffu)) : 0xffffffffu);
     }
-    const int WW = (w - j) * NW;  // payload words still needed by the others
+    const int WC = w - j;  // columns still needed by the others
     if (lrow >= 0)
-      for (int t = tid; t < WW; t += 256)
-        ll_put(&rows[(size_t)g * ws.wwmax + t], E, cword(tile[(j + t / NW) * R + lrow], t % NW));
-    // gather all keys; winner = largest |re|+|im|, lowest label on ties
+      for (int tc = tid; tc < WC; tc += 256) {
+        const int c = j + tc;
+        CT v = tile[c * R + lrow];
+        if (j > 0 && tc > 0) {
+          v = r1_upd(v, tile[(j - 1) * R + lrow], prow[c]);
+          tile[c * R + lrow] = v;
+        }
+#pragma unroll
+        for (int q = 0; q < NW; ++q) ll_put(&rows[(size_t)g * ws.wwmax + (size_t)tc * NW + q], E, cword(v, q));
+      }
+    // deferred part of pivot j - 1's update: columns j + 1.. of the other active rows
+    if (j > 0) {
+      for (int lr = ulr0; lr < myR; lr += RP) {
+        if (lab[lr] <= (int32_t)(gj - 1) || lr == lrow) continue;
+        const CT l = tile[(j - 1) * R + lr];
+        int c = j + 1 + ucg;
+        // FP32: batches of UB columns, all reads first, then the updates, then
+        // all writes (written one column at a time, each read would wait for
+        // the previous column's write, since the compiler cannot tell them
+        // apart).  The same batching makes the FP64 panel slower, so FP64 keeps
+        // the column-at-a-time loop.
+        constexpr int UB = 8;
+        if constexpr (sizeof(T) == 4) {
+          for (; c + (UB - 1) * CG < w; c += UB * CG) {
+            CT t[UB], u[UB];
+#pragma unroll
+            for (int e = 0; e < UB; ++e) {
+              u[e] = prow[c + e * CG];
+              t[e] = tile[(c + e * CG) * R + lr];
+            }
+#pragma unroll
+            for (int e = 0; e < UB; ++e) t[e] = r1_upd(t[e], l, u[e]);
+#pragma unroll
+            for (int e = 0; e < UB; ++e) tile[(c + e * CG) * R + lr] = t[e];
+          }
+          for (; c < w; c += CG) tile[c * R + lr] = r1_upd(tile[c * R + lr], l, prow[c]);
+        } else {
+#pragma unroll 8
+          for (; c < w; c += CG) tile[c * R + lr] = r1_upd(tile[c * R + lr], l, prow[c]);
+        }
+      }
+    }
+    // gather all keys; winner = largest |re|+|im|, lowest label on ties (the
+    // barrier inside block_argmax also ends every read of prow above)
     u64 k = 0;
     int owner = -1;
     if (tid < G) {
@@ -303,6 +352,7 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
     const uint32_t plabel = 0xffffffffu - (uint32_t)(k & 0xffffffffu);
     // pivot row, columns j..
     if (gp >= 0) {
+      const int WW = WC * NW;
       const u64* src = rows + (size_t)gp * ws.wwmax;
       uint32_t* dstw = reinterpret_cast<uint32_t*>(prow + j);
       int t = tid;
@@ -334,75 +384,29 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
     if (zero && zero_col < 0) zero_col = j;
     CT inv;
     if (zero) { inv.x = 0; inv.y = 0; } else inv = cinv_t(piv);
-    // rank-1 update of the rows below (labels > gj) with multipliers computed on
-    // the fly; column group 0 owns column j + 1 and its pivot candidate
+    // multipliers of the rows below (labels > gj) into tile column j, and the
+    // update of column j + 1 with the next pivot candidates
     best = 0;
     brow = -1;
-    for (int lr = ulr0; lr < myR; lr += RP) {
+    const bool nxt = j + 1 < w;
+    const CT u1 = nxt ? prow[j + 1] : piv;
+    for (int lr = tid; lr < myR; lr += 256) {
       const int32_t lb = lab[lr];
       if (lb <= (int32_t)gj) continue;
       const CT l = cmul_t(tile[j * R + lr], inv);
-      if (ucg == 0) lst[lr] = l;
-      int c = j + 1 + ucg;
-      if (ucg == 0 && c < w) {
-        const CT u = prow[c];
-        CT t = tile[c * R + lr];
-        t.x -= l.x * u.x - l.y * u.y;
-        t.y -= l.x * u.y + l.y * u.x;
-        tile[c * R + lr] = t;
+      tile[j * R + lr] = l;
+      if (nxt) {
+        const CT t = r1_upd(tile[(j + 1) * R + lr], l, u1);
+        tile[(j + 1) * R + lr] = t;
         const u64 kk = pivot_key(t, (uint32_t)lb);
         if (kk > best) {
           best = kk;
           brow = lr;
         }
-        c += CG;
-      }
-      // FP32: batches of UB columns, all reads first, then the updates, then all
-      // writes (written one column at a time, each read would wait for the
-      // previous column's write, since the compiler cannot tell them apart).
-      // Measured: FP32 panel 6.5 -> 6.3 us per column; the same batching makes
-      // the FP64 panel slower, so FP64 keeps the column-at-a-time loop.
-      constexpr int UB = 8;
-      if constexpr (sizeof(T) == 4)
-      for (; c + (UB - 1) * CG < w; c += UB * CG) {
-        CT t[UB], u[UB];
-#pragma unroll
-        for (int e = 0; e < UB; ++e) {
-          u[e] = prow[c + e * CG];
-          t[e] = tile[(c + e * CG) * R + lr];
-        }
-#pragma unroll
-        for (int e = 0; e < UB; ++e) {
-          t[e].x -= l.x * u[e].x - l.y * u[e].y;
-          t[e].y -= l.x * u[e].y + l.y * u[e].x;
-        }
-#pragma unroll
-        for (int e = 0; e < UB; ++e) tile[(c + e * CG) * R + lr] = t[e];
-      }
-      if constexpr (sizeof(T) == 4) {
-        for (; c < w; c += CG) {
-          const CT u = prow[c];
-          CT t = tile[c * R + lr];
-          t.x -= l.x * u.x - l.y * u.y;
-          t.y -= l.x * u.y + l.y * u.x;
-          tile[c * R + lr] = t;
-        }
-      } else {
-#pragma unroll 8
-        for (; c < w; c += CG) {
-          const CT u = prow[c];
-          CT t = tile[c * R + lr];
-          t.x -= l.x * u.x - l.y * u.y;
-          t.y -= l.x * u.y + l.y * u.x;
-          tile[c * R + lr] = t;
-        }
       }
     }
-    // (the barrier inside the next block_argmax orders the update before any read)
+    // (the barrier inside the next block_argmax orders these writes before any read)
   }
-  __syncthreads();
-  for (int lr = tid; lr < myR; lr += 256)
-    if (lab[lr] > (int32_t)(k0 + w - 1)) tile[(w - 1) * R + lr] = lst[lr];
   __syncthreads();
   if (g == 0) {
     for (int j = tid; j < w; j += 256) ipiv[k0 + j] = pl[j];
@@ -827,7 +831,7 @@ static const int LDS_RESERVE = 2048;
 
 // dynamic LDS of a panel workgroup: tile, pivot row, multipliers, labels, pivots
 static size_t panel_lds_bytes(int w, int R, size_t cbytes) {
-  return ((size_t)w * R + w + R) * cbytes + (size_t)(R + w) * 4;
+  return ((size_t)w * R + w) * cbytes + (size_t)(R + w) * 4;
 }
 
 LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch, int nb_max) {
