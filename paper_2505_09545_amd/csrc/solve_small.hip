@@ -87,12 +87,28 @@ __global__ void __launch_bounds__(256) skinny_n_kernel(int64_t m, int64_t k, con
   for (int r = 0; r < NR; ++r) acc[r].x = acc[r].y = 0;
   if (row < m) {
     const bool masked = mk.akind && row >= mk.ar0 && row < mk.ar0 + mk.adw;
-#pragma unroll 8
-    for (int64_t kk = ka; kk < kb; ++kk) {
-      if (masked && !sk_keep(mk.akind, row - mk.ar0, kk)) continue;
-      const CT a = A[row + kk * lda];
+    // KB loads in flight per lane, then their products (a load and its use in
+    // one loop body put one memory latency per k on the path); the masked
+    // triangle is stored, so it is read and replaced by zero
+    constexpr int KB = 16;
+    for (int64_t k0 = ka; k0 < kb; k0 += KB) {
+      CT a[KB];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) cfma_t<T>(acc[r], a, xs[kk][r]);
+      for (int u = 0; u < KB; ++u) {
+        a[u].x = 0;
+        a[u].y = 0;
+        if (k0 + u < kb) a[u] = A[row + (k0 + u) * lda];
+      }
+#pragma unroll
+      for (int u = 0; u < KB; ++u) {
+        const int64_t kk = k0 + u;
+        if (kk < kb) {
+          CT v = a[u];
+          if (masked && !sk_keep(mk.akind, row - mk.ar0, kk)) v.x = v.y = 0;
+#pragma unroll
+          for (int r = 0; r < NR; ++r) cfma_t<T>(acc[r], v, xs[kk][r]);
+        }
+      }
     }
   }
   if (wave > 0)
@@ -171,20 +187,37 @@ __global__ void __launch_bounds__(256) skinny_t_kernel(SkSeg s0, SkSeg s1, int64
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll 1
-  for (int c = 0; c < SK_TCOLS / 4; ++c) {
-    const int64_t i = (int64_t)grp * SK_TCOLS + wave * (SK_TCOLS / 4) + c;
+  // all of this wave's loads (CPW columns x KS steps of 64 rows) in flight at
+  // once, then the products column by column; masked entries are stored, so
+  // they are read and replaced by zero
+  constexpr int CPW = SK_TCOLS / 4, KS = SK_KC / 64;
+  const int64_t i0 = (int64_t)grp * SK_TCOLS + wave * CPW;
+  CT a[CPW][KS];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c)
+#pragma unroll
+    for (int q = 0; q < KS; ++q) {
+      const int64_t kk = kc0 + lane + 64 * q;
+      a[c][q].x = 0;
+      a[c][q].y = 0;
+      if (i0 + c < mo && kk < kc1) a[c][q] = A[kk + (i0 + c) * s.lda];
+    }
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int64_t i = i0 + c;
     if (i >= mo) break;
-    const CT* col = A + i * s.lda;
     CT acc[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) acc[r].x = acc[r].y = 0;
-#pragma unroll 4
-    for (int64_t kk = kc0 + lane; kk < kc1; kk += 64) {
-      if (s.kind && !sk_keep(s.kind, i, kk)) continue;
-      const CT a = col[kk];
 #pragma unroll
-      for (int r = 0; r < NR; ++r) cfma_t<T>(acc[r], a, bs[kk - kc0][r]);
+    for (int q = 0; q < KS; ++q) {
+      const int64_t kk = kc0 + lane + 64 * q;
+      if (kk < kc1) {
+        CT v = a[c][q];
+        if (s.kind && !sk_keep(s.kind, i, kk)) v.x = v.y = 0;
+#pragma unroll
+        for (int r = 0; r < NR; ++r) cfma_t<T>(acc[r], v, bs[kk - kc0][r]);
+      }
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
