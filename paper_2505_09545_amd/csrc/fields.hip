@@ -52,21 +52,34 @@ __global__ void __launch_bounds__(256) fields_kernel(DipoleView d, Wave w, const
   for (int64_t t0 = j0; t0 < j1; t0 += FT) {
     const int nt = (int)(j1 - t0 < FT ? j1 - t0 : FT);
     __syncthreads();
+    // a thread's loads all issued before its LDS stores (the position array is
+    // reached through a generic pointer, which the compiler must assume may
+    // point into LDS: interleaved, each load would wait before the next store)
     for (int t = threadIdx.x; t < nt; t += 256) {
       const int64_t j = t0 + t;
-      spos[t][0] = d.pos[3 * j];
-      spos[t][1] = d.pos[3 * j + 1];
-      spos[t][2] = d.pos[3 * j + 2];
+      double pv[3];
+      double2 qv[NR][3], mv[NR][3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) pv[a] = d.pos[3 * j + a];
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const bool rv = r0 + r < nrhs;
         const double2* qc = q + (int64_t)(r0 + r) * ldq;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-          sp[t][r][a] = rv ? qc[3 * j + a] : make_double2(0, 0);
-          sm[t][r][a] = (rv && j >= nc) ? qc[3 * N + 3 * (j - nc) + a] : make_double2(0, 0);
+          qv[r][a] = rv ? qc[3 * j + a] : make_double2(0, 0);
+          mv[r][a] = (rv && j >= nc) ? qc[3 * N + 3 * (j - nc) + a] : make_double2(0, 0);
         }
       }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) spos[t][a] = pv[a];
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          sp[t][r][a] = qv[r][a];
+          sm[t][r][a] = mv[r][a];
+        }
     }
     __syncthreads();
     if (!live) continue;
