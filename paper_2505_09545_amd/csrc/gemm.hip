@@ -17,11 +17,14 @@
 // 16 real rows x 16 columns, BK complex k per stage, double-buffered LDS:
 //   64 complex rows x 64 columns x 8 k (WM 4, WN 2) for launches that fill the
 //     chip (the bulk of the trailing update);
-//   32 x 32 x 16 (WM 2, WN 1) for launches of fewer than two 64 x 64 tiles per
+//   32 x 32 x 8 (WM 2, WN 1) for launches of fewer than two 64 x 64 tiles per
 //     CU (look-ahead update, U12 blocks, solve steps): four times the
-//     workgroups and half the stages, for products whose time is set by the
-//     latency of the k loop rather than by the matrix cores.
-// Both load two complex elements of A and two of B per thread and stage.
+//     workgroups, for products whose time is set by latency rather than by the
+//     matrix cores.  Measured on the 66-RHS solves: 8 complex k per stage
+//     11.6 ms, 16: 12.4, 32: 14.7, 64: 17.6 (the smaller stage leaves more
+//     workgroups resident per CU); wider tiles over all 66 columns: 16.5.
+// The big tile loads two complex elements of A and two of B per thread and
+// stage, the small one one of each.
 // Workgroups are remapped so that each of the 8 XCDs works on a contiguous
 // range of tiles (their operands then share that XCD's L2).
 #include "gdm_common.hpp"
@@ -272,7 +275,7 @@ static hipError_t launch_cfg(int64_t m, int64_t n, int64_t k, const cplx<T>* a, 
                              int64_t ldb, cplx<T>* c, int64_t ldc, hipStream_t st, GemmMask mk, int nbatch, int64_t sA,
                              int64_t sB, int64_t sC) {
   if (use_small_tiles(m, n, nbatch))
-    return launch_tiles<T, MODE, TRANSA, ROLE, 2, 1, 16>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
+    return launch_tiles<T, MODE, TRANSA, ROLE, 2, 1, 8>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
   return launch_tiles<T, MODE, TRANSA, ROLE, 4, 2, 8>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
 }
 
