@@ -15,16 +15,17 @@
 //
 // Tiles: 2 x 2 waves per 256-thread workgroup, each wave WM x WN MFMA blocks of
 // 16 real rows x 16 columns, BK complex k per stage, double-buffered LDS:
-//   64 complex rows x 64 columns x 8 k (WM 4, WN 2) for launches that fill the
-//     chip (the bulk of the trailing update);
+//   64 complex rows x 64 columns (WM 4, WN 2) for launches that fill the chip
+//     (the bulk of the trailing update, the FP64 residual), 4 complex k per
+//     stage for one system's products, 8 for batched launches;
 //   32 x 32 x 8 (WM 2, WN 1) for launches of fewer than two 64 x 64 tiles per
 //     CU (look-ahead update, U12 blocks, solve steps): four times the
 //     workgroups, for products whose time is set by latency rather than by the
 //     matrix cores.  Measured on the 66-RHS solves: 8 complex k per stage
 //     11.6 ms, 16: 12.4, 32: 14.7, 64: 17.6 (the smaller stage leaves more
 //     workgroups resident per CU); wider tiles over all 66 columns: 16.5.
-// The big tile loads two complex elements of A and two of B per thread and
-// stage, the small one one of each.
+// Per thread and stage the big tile loads one (4 k) or two (8 k) complex
+// elements of A and as many of B, the small one one of each.
 // Workgroups are remapped so that each of the 8 XCDs works on a contiguous
 // range of tiles (their operands then share that XCD's L2).
 #include "gdm_common.hpp"
@@ -276,6 +277,11 @@ static hipError_t launch_cfg(int64_t m, int64_t n, int64_t k, const cplx<T>* a, 
                              int64_t sB, int64_t sC) {
   if (use_small_tiles(m, n, nbatch))
     return launch_tiles<T, MODE, TRANSA, ROLE, 2, 1, 8>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
+  // 4 complex k per stage for the products of one system (update GEMM: FP32
+  // 87.5 -> 90, FP64 40 -> 45 TFLOP/s; FP64 step 158.6 -> 148.8 ms), 8 for
+  // batched launches (83 vs 78 systems/s on the batched spectra)
+  if (nbatch == 1)
+    return launch_tiles<T, MODE, TRANSA, ROLE, 4, 2, 4>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
   return launch_tiles<T, MODE, TRANSA, ROLE, 4, 2, 8>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
 }
 
