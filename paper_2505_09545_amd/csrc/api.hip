@@ -90,6 +90,7 @@ struct gdm_ctx {
   DevBuf bM64, bM32, bipiv, bws, bvec, bpart, bsmall, bpos, bwl;
   std::map<int64_t, std::pair<int, int>> batch_tune;  // n / 256 -> (items per group, nb)
   hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t sev[2] = {nullptr, nullptr};  // ordering only: the residual's side-stream part
   float ms_assemble = 0, ms_factor = 0;
   Prof prof;
   bool lookahead = true;
@@ -280,6 +281,18 @@ static gdm_status solve_core(gdm_ctx* c, int trans, int64_t nrhs, const double2*
       // the VALUs instead of occupying a nearly empty tile.
       const int64_t rem = nrhs % 64 <= SKINNY_MAX_RHS ? nrhs % 64 : 0;
       const int64_t nfull = nrhs - rem;
+      // The remainder (HBM-bound) runs on the side stream while the matrix
+      // cores run the 64-column tiles: the two write disjoint columns of Rr and
+      // disjoint parts of the partial-sum buffer.
+      const bool rem_side = rem > 0 && nfull > 0 && c->side && c->sev[0] && c->sev[1];
+      if (rem_side) {
+        HIPCHK(c, hipEventRecord(c->sev[0], c->stream));  // x and the copy of b in Rr are ready
+        HIPCHK(c, hipStreamWaitEvent(c->side, c->sev[0], 0));
+        HIPCHK(c, launch_skinny_n_long<double>(n, n, c->M64.p, n, X + nfull * n, n, Rr + nfull * n, n, rem,
+                                               c->part.as<double2>() + rs.gemm_part, part_elems - rs.gemm_part,
+                                               c->side));
+        HIPCHK(c, hipEventRecord(c->sev[1], c->side));
+      }
       if (nfull > 0) {
         const int64_t kc = rs.kc, nk = n / kc, tail = n - nk * kc;
         double2* part = c->part.as<double2>();
@@ -290,10 +303,11 @@ static gdm_status solve_core(gdm_ctx* c, int trans, int64_t nrhs, const double2*
                                         part + nk * n * nfull, n, c->stream));
         HIPCHK(c, launch_partial_reduce<double>(part, (int)(nk + (tail > 0)), n, nfull, Rr, n, c->stream));
       }
-      if (rem > 0)
+      if (rem > 0 && !rem_side)
         HIPCHK(c, launch_skinny_n_long<double>(n, n, c->M64.p, n, X + nfull * n, n, Rr + nfull * n, n, rem,
                                                c->part.as<double2>() + rs.gemm_part, part_elems - rs.gemm_part,
                                                c->stream));
+      if (rem_side) HIPCHK(c, hipStreamWaitEvent(c->stream, c->sev[1], 0));
     }
     HIPCHK(c, c->prof.end(c->stream));
     HIPCHK(c, launch_colmax(Rr, n, n, nrhs, sm, c->stream));
@@ -734,6 +748,8 @@ gdm_status gdm_create(int device, void* hip_stream, gdm_ctx** out) {
     c->own_stream = true;
   }
   for (auto& e : c->ev) (void)hipEventCreate(&e);
+  for (auto& e : c->sev)
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
   if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) c->side = nullptr;
   *out = c;
   return GDM_OK;
@@ -748,6 +764,8 @@ void gdm_destroy(gdm_ctx* c) {
                     &c->bws, &c->bvec, &c->bpart, &c->bsmall, &c->bpos, &c->bwl})
     b->release();
   for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& e : c->sev)
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->lu_events) (void)hipEventDestroy(e);
   if (c->side) {
