@@ -48,13 +48,17 @@ template <typename CT> __device__ inline CT r1_upd(CT t, const CT& l, const CT& 
   return t;
 }
 template <typename CT> __device__ inline CT cinv_t(CT a) {
-  // 1/a with scaling against overflow of |a|^2
+  // 1/a = conj(a) / |a|^2, with a scaled by the power of two 2^-e of its larger
+  // component (exact) so that |a|^2 can neither overflow nor underflow; one
+  // division (a = 0 gives NaN, as the quotient form did)
   const auto s = fabs(a.x) > fabs(a.y) ? fabs(a.x) : fabs(a.y);
+  int e;
+  (void)frexp(s, &e);
+  const auto ar = ldexp(a.x, -e), ai = ldexp(a.y, -e);
+  const auto id = 1 / (ar * ar + ai * ai);
   CT r;
-  const auto ar = a.x / s, ai = a.y / s;
-  const auto d = s * (ar * ar + ai * ai);
-  r.x = ar / d;
-  r.y = -ai / d;
+  r.x = ldexp(ar * id, -e);
+  r.y = ldexp(-ai * id, -e);
   return r;
 }
 
