@@ -51,7 +51,11 @@ def oracle_q_rhs_major(sim):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
 @pytest.mark.parametrize("m,n,k,mode,trans", [(64, 64, 8, 0, 0), (200, 131, 77, 0, 0), (333, 70, 129, 1, 0),
-                                              (129, 66, 300, 0, 1), (70, 5, 260, 1, 1), (1, 1, 1, 0, 0)])
+                                              (129, 66, 300, 0, 1), (70, 5, 260, 1, 1), (1, 1, 1, 0, 0),
+                                              # >= 2 tiles of 64 x 64 per CU: the large tile, k not a
+                                              # multiple of its 4 complex k per stage
+                                              (1500, 1430, 130, 0, 0), (1430, 1500, 131, 1, 0),
+                                              (1500, 1400, 66, 0, 1)])
 def test_gemm_matches_numpy(ctx, dtype, m, n, k, mode, trans):
     say("gemm", dtype, m, n, k, mode, trans)
     rng = np.random.default_rng(m * 7 + n * 3 + k)
