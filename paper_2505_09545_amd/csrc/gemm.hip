@@ -67,12 +67,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
   B += (int64_t)blockIdx.y * sB;
   C += (int64_t)blockIdx.y * sC;
   using ACC = typename acc_of<T>::type;
-  // rows padded by 16 elements: the MFMA operand reads of one instruction span
-  // 2 (A) or 4 (B) rows, which would otherwise fall on the same LDS banks
-  // (measured: FP32+IR step 95.8 -> 95.2 ms, the 66-RHS solves 12.1 -> 11.8 ms)
-  constexpr int AST = BM * 2 + 16, BST = BN + 16;
-  __shared__ T As[2][BK * AST];      // [kc][mc] complex
-  __shared__ T Bs[2][2 * BK * BST];  // [kk][nc] real view
+  // A: rows padded by 16 elements (the MFMA operand reads of one instruction
+  // span 2 rows, which would otherwise fall on the same LDS banks).  B: stored
+  // column by column ([nc][kk], real view) with a stride of 2 BK + 4 elements:
+  // a thread's (re, im) pair is one 64-bit store, and the 16 columns x 4 k of
+  // one MFMA operand read fall on 64 distinct banks ((2 BK + 4) / 4 is odd).
+  constexpr int AST = BM * 2 + 16, BSK = 2 * BK + 4;
+  __shared__ T As[2][BK * AST];  // [kc][mc] complex
+  __shared__ T Bs[2][BN * BSK];  // [nc][kk] real view
   // XCD-aware remap: hardware places workgroup b on XCD b % 8.
   const int bid = blockIdx.x;
   const int xcd = bid & 7, loc = bid >> 3;
@@ -131,8 +133,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
     for (int i = 0; i < BL; ++i) {
       const int idx = tid + 256 * i;
       const int kc2 = idx % BK, nc = idx / BK;
-      Bs[buf][(2 * kc2 + 0) * BST + nc] = rb[i].x;
-      Bs[buf][(2 * kc2 + 1) * BST + nc] = rb[i].y;
+      Bs[buf][nc * BSK + 2 * kc2 + 0] = rb[i].x;
+      Bs[buf][nc * BSK + 2 * kc2 + 1] = rb[i].y;
     }
   };
 
@@ -164,7 +166,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
         a[bm] = (sb == 1 && t == 0) ? -v : v;
       }
 #pragma unroll
-      for (int bn = 0; bn < WN; ++bn) b[bn] = Bs[buf][kk * BST + wcol + bn * 16 + lr];
+      for (int bn = 0; bn < WN; ++bn) b[bn] = Bs[buf][(wcol + bn * 16 + lr) * BSK + kk];
 #pragma unroll
       for (int bm = 0; bm < WM; ++bm)
 #pragma unroll
