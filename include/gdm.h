@@ -225,20 +225,22 @@ gdm_status gdm_sync(gdm_ctx* ctx);
  * clears the counters and starts recording; 0 stops. */
 gdm_status gdm_profile(gdm_ctx* ctx, int enable);
 /* The same for a subset of the tags listed under gdm_profile_read: launches of
- * tag t are timed iff bit t of mask is set (mask 0 stops; 1023 = all).  Timing
+ * tag t are timed iff bit t of mask is set (mask 0 stops; 2047 = all).  Timing
  * only the kernels one needs keeps the events off the critical path of the
- * rest.  GDM_E_ARG for a mask outside [0, 1024). */
+ * rest.  GDM_E_ARG for a mask outside [0, 2048). */
 gdm_status gdm_profile_mask(gdm_ctx* ctx, int32_t mask);
 /* Counters accumulated since gdm_profile / gdm_profile_mask, written to the HOST array
- * out (n_out >= 30): out[3 t + 0..2] = (milliseconds, work, launches) for
- * t = 0 LU trailing-update GEMM (work = real flops 8 m n k), 1 LU panel (work =
+ * out (n_out >= 33): out[3 t + 0..2] = (milliseconds, work, launches) for
+ * t = 0 LU trailing-update GEMM, bulk part (the columns after the next panel's;
+ * work = real flops 8 m n k), 1 LU panel (work =
  * columns), 2 assembly (work = bytes written), 3 block triangular solve of the
  * factorisation (work = real flops), 4 row permutation of the trailing columns,
  * 5 forward + backward substitution of gdm_solve / gdm_adjoint (work =
  * 8 n^2 n_rhs), 6 FP64 refinement residual (work = 8 n^2 n_rhs), 7 adjoint
  * dipole-pair kernel (work = ordered pairs x n_rhs), 8 adjoint probe kernel
  * (work = probe-dipole pairs x n_rhs), 9 probe fields (work = probe-dipole
- * pairs x n_rhs). */
+ * pairs x n_rhs), 10 LU trailing-update GEMM of the next panel's columns (the
+ * look-ahead product; work = real flops). */
 gdm_status gdm_profile_read(gdm_ctx* ctx, double* out, int32_t n_out);
 
 #ifdef __cplusplus

@@ -89,7 +89,8 @@ enum ProfTag {
   PROF_ADJ_PAIR = 7,
   PROF_ADJ_PROBE = 8,
   PROF_FIELDS = 9,
-  PROF_NTAGS = 10
+  PROF_LOOKAHEAD = 10,
+  PROF_NTAGS = 11
 };
 struct Prof {
   uint32_t mask = 0;  // bit t: record launches of tag t

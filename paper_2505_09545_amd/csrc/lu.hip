@@ -1085,7 +1085,7 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
       LUCHK(P.begin(st, PROF_TRSM, 8.0 * w * w * (double)wa * fb));
       LUCHK(launch_block_trsm<T>(A, ld, n, nb, bi, A + k0 + c1 * ld, ld, wa, st, NB, sA, sA));
       LUCHK(P.end(st));
-      LUCHK(P.begin(st, PROF_UPDATE, 8.0 * (double)nr * (double)wa * w * fb));
+      LUCHK(P.begin(st, PROF_LOOKAHEAD, 8.0 * (double)nr * (double)wa * w * fb));
       LUCHK(launch_gemm_update<T>(nr, wa, w, A + c1 + k0 * ld, ld, A + k0 + c1 * ld, ld, A + c1 + c1 * ld, ld, st, NB,
                                   sA, sA, sA));
       LUCHK(P.end(st));

@@ -344,7 +344,8 @@ class Context:
     def sync(self):
         self._check(self._call("gdm_sync", self.h))
 
-    PROF_TAGS = ("update", "panel", "assemble", "trsm", "perm", "solve", "resid", "adj_pair", "adj_probe", "fields")
+    PROF_TAGS = ("update", "panel", "assemble", "trsm", "perm", "solve", "resid", "adj_pair", "adj_probe", "fields",
+                 "lookahead")
 
     def profile(self, enable: bool, tags=None):
         """Start (clearing the counters) or stop per-launch event timing; `tags`
