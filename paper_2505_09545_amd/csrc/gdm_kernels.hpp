@@ -140,11 +140,10 @@ struct LUWork {
   int32_t* npairs;           // [nblocks]
   void* tmp;                 // [tmp_elems] complex scratch (operand copies, split-k partials)
   void* dinv;                // [nblocks][nb][nb] complex inverses of the diagonal triangles
-  void* tmp2;                // [nb * nb] complex scratch of the main stream
   std::vector<hipEvent_t>* events;  // host-side pool of reusable events (look-ahead)
   int64_t tmp_elems;         // capacity of tmp per item in complex elements
   int nbatch = 1;
-  int64_t s_cand = 0, s_rows = 0, s_pairs = 0, s_npairs = 0, s_tmp = 0, s_dinv = 0, s_tmp2 = 0;
+  int64_t s_cand = 0, s_rows = 0, s_pairs = 0, s_npairs = 0, s_tmp = 0, s_dinv = 0;
   size_t bytes = 0;          // total size (set by lu_workspace_carve)
 };
 

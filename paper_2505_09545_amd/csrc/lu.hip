@@ -930,8 +930,6 @@ void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu,
   w.tmp = take((size_t)nbatch * w.s_tmp * cb);
   w.s_dinv = (int64_t)(al256(nblk * nb * nb * cb) / cb);
   w.dinv = take((size_t)nbatch * w.s_dinv * cb);
-  w.s_tmp2 = (int64_t)(al256(nb * nb * cb) / cb);
-  w.tmp2 = take((size_t)nbatch * w.s_tmp2 * cb);
   w.events = nullptr;
   w.bytes = off + 256;
 }
@@ -1007,7 +1005,6 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
     }                              \
   } while (0)
   CT* tmpB = static_cast<CT*>(ws.tmp);   // side-stream operand copies (n x nb per item)
-  CT* tmpA = static_cast<CT*>(ws.tmp2);  // main-stream operand copies (nb x nb per item)
   CT* dinv = static_cast<CT*>(ws.dinv);
   hipEvent_t bulk_done = nullptr;  // side stream finished the previous block's bulk update
   for (int bi = 0; bi < nblk; ++bi) {
