@@ -159,12 +159,17 @@ def _forward(ctx, w, prec, tol=0.0, want_ff=True):
     return gdm.run_forward(ctx, w, prec=prec, tol=tol, want_ff=want_ff)
 
 
-@pytest.mark.parametrize("which", ["config1", "mixed", "config4_small"])
+@pytest.mark.parametrize("which", ["config1", "mixed", "config4_small", "config2_66rhs"])
 @pytest.mark.parametrize("prec", [0, 1])
 def test_forward_matches_oracle(ctx, which, prec):
     say("forward", which, "prec", prec)
     if which == "config1":
         w = gi.config1()
+    elif which == "config2_66rhs":
+        # the config-2 recipe at 600 cells (n = 1800) with all 66 plane waves:
+        # solves over 66 RHS (three column tiles) and, in FP32+IR, residuals as
+        # one 64-column tile plus a 2-column remainder on the side stream
+        w = gi.config2(ncell=600)
     elif which == "mixed":
         w = gi.small_mixed(seed=22, n_cell_side=5, n_eff=12)
     else:
