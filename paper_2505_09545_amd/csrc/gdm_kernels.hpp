@@ -31,6 +31,12 @@ struct GemmMask {
   int akind = 0;
   int64_t ar0 = 0, adw = 0;
   int bkind = 0;
+  // Optional second destination (launch_gemm only): rows [ar0, ar0 + adw) of
+  // the result go to c2 (row r - ar0, leading dimension ldc2, item stride sc2)
+  // instead of C; mode 0 still reads their old values from C.  With it a
+  // product may read its B operand from those rows of C in place.
+  void* c2 = nullptr;
+  int64_t ldc2 = 0, sc2 = 0;
 };
 
 // C (m x n) = C - op(A) B   (mode 0)   or   C = op(A) B   (mode 1);

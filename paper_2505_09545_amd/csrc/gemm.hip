@@ -176,6 +176,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
     __syncthreads();
   }
   // epilogue: lane holds real rows 4*lk + {0..3} = two complex rows of column lane%16
+  // (general products only: rows [ar0, ar0 + adw) optionally written to mk.c2)
+  CT* const c2 = ROLE == 0 && mk.c2 ? static_cast<CT*>(mk.c2) + (int64_t)blockIdx.y * mk.sc2 : nullptr;
+  auto dest = [&](int64_t row, int64_t col) -> CT* {
+    if (ROLE == 0 && c2 && row >= mk.ar0 && row < mk.ar0 + mk.adw) return c2 + (row - mk.ar0) + col * mk.ldc2;
+    return C + row + col * ldc;
+  };
   if constexpr (MODE == 0 && CB) {
     // Every C load issued before the first store (a load after a store to the
     // same array waits for it, since the compiler cannot tell the addresses
@@ -207,7 +213,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
           CT c = cold[bm][bn][h];
           c.x -= acc[bm][bn][2 * h];
           c.y -= acc[bm][bn][2 * h + 1];
-          C[row + col * ldc] = c;
+          *dest(row, col) = c;
         }
     return;
   }
@@ -222,18 +228,17 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
       for (int h = 0; h < 2; ++h) {
         const int64_t row = crow + h;
         if (row >= m) continue;
-        CT* p = C + row + col * ldc;
         const T vr = acc[bm][bn][2 * h], vi = acc[bm][bn][2 * h + 1];
         if (MODE == 0) {
-          CT c = *p;
+          CT c = C[row + col * ldc];
           c.x -= vr;
           c.y -= vi;
-          *p = c;
+          *dest(row, col) = c;
         } else {
           CT c;
           c.x = vr;
           c.y = vi;
-          *p = c;
+          *dest(row, col) = c;
         }
       }
     }

@@ -1151,12 +1151,55 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
     chunk = ws.tmp_elems / per;
     if (chunk < 1) return hipErrorInvalidValue;
   }
+  // With more than SKINNY_MAX_RHS columns the plain solve keeps the forward
+  // result in tmp (n x nr, leading dimension n), so that every block step reads
+  // its operand rows in place: the step's product writes those rows to the
+  // other buffer (the forward into tmp, the backward back into B), no copy.
+  if (!trans && ws.tmp_elems / n < chunk) chunk = ws.tmp_elems / n;
+  if (chunk < 1) return hipErrorInvalidValue;
   const int64_t part_elems = (int64_t)NB * sX;  // the transposed partial sums of all items
   for (int64_t r0 = 0; r0 < nrhs; r0 += chunk) {
     const int64_t nr = nrhs - r0 < chunk ? nrhs - r0 : chunk;
     CT* B = Ball + r0 * ldb;
     const bool small = nr <= SKINNY_MAX_RHS;
-    if (trans == 0) {
+    if (trans == 0 && !small) {
+      CT* Y = X;  // n x nr
+      // forward: P_b, then rows [k0, n) -= [I - L11^-1 ; L21 L11^-1] B_b, rows [k0, k0 + w) into Y
+      for (int bi = 0; bi < nblk; ++bi) {
+        const LUBlock& b = plan.blocks[bi];
+        const int64_t k0 = b.k0;
+        const int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;
+        const int32_t* src = dst + 2 * nb;
+        hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)nr, NB), dim3(256), 0, st, B, ldb, (int64_t)0, dst,
+                           src, ws.npairs + bi, sB, ws.s_pairs, ws.s_npairs);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        GemmMask m;
+        m.akind = GEMM_MASK_STRICT_LOWER;
+        m.ar0 = 0;
+        m.adw = b.w;
+        m.c2 = Y + k0;
+        m.ldc2 = n;
+        m.sc2 = sX;
+        if ((e = launch_gemm<T>(0, 0, n - k0, nr, b.w, A + k0 + k0 * ld, ld, B + k0, ldb, B + k0, ldb, st, m, NB, sA,
+                                sB, sB)) != hipSuccess)
+          return e;
+      }
+      // backward on Y: rows [0, k0 + w) -= [U01 U11^-1 ; I - U11^-1] Y_b, rows [k0, k0 + w) into B
+      for (int bi = nblk - 1; bi >= 0; --bi) {
+        const LUBlock& b = plan.blocks[bi];
+        const int64_t k0 = b.k0;
+        GemmMask m;
+        m.akind = GEMM_MASK_UPPER;
+        m.ar0 = k0;
+        m.adw = b.w;
+        m.c2 = B + k0;
+        m.ldc2 = ldb;
+        m.sc2 = sB;
+        if ((e = launch_gemm<T>(0, 0, k0 + b.w, nr, b.w, A + k0 * ld, ld, Y + k0, n, Y, n, st, m, NB, sA, sX, sX)) !=
+            hipSuccess)
+          return e;
+      }
+    } else if (trans == 0) {
       // forward: P_b, then rows [k0, n) -= [I - L11^-1 ; L21 L11^-1] B_b
       for (int bi = 0; bi < nblk; ++bi) {
         const LUBlock& b = plan.blocks[bi];
@@ -1171,9 +1214,7 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
         m.akind = GEMM_MASK_STRICT_LOWER;
         m.ar0 = 0;
         m.adw = b.w;
-        e = small ? launch_skinny_n<T>(n - k0, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, nr, st, m, NB, sA, sX, sB)
-                  : launch_gemm<T>(0, 0, n - k0, nr, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, st, m, NB, sA, sX,
-                                   sB);
+        e = launch_skinny_n<T>(n - k0, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, nr, st, m, NB, sA, sX, sB);
         if (e != hipSuccess) return e;
       }
       // backward: rows [0, k0 + w) -= [U01 U11^-1 ; I - U11^-1] B_b
@@ -1185,8 +1226,7 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
         m.akind = GEMM_MASK_UPPER;
         m.ar0 = k0;
         m.adw = b.w;
-        e = small ? launch_skinny_n<T>(k0 + b.w, b.w, A + k0 * ld, ld, X, b.w, B, ldb, nr, st, m, NB, sA, sX, sB)
-                  : launch_gemm<T>(0, 0, k0 + b.w, nr, b.w, A + k0 * ld, ld, X, b.w, B, ldb, st, m, NB, sA, sX, sB);
+        e = launch_skinny_n<T>(k0 + b.w, b.w, A + k0 * ld, ld, X, b.w, B, ldb, nr, st, m, NB, sA, sX, sB);
         if (e != hipSuccess) return e;
       }
     } else {

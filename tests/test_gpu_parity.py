@@ -87,7 +87,7 @@ def test_gemm_matches_numpy(ctx, dtype, m, n, k, mode, trans):
 # LU + solve on random matrices (several blocks, ragged tail)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("dtype", ["c128", "c64"])
-@pytest.mark.parametrize("n,nrhs", [(1, 1), (37, 3), (300, 5), (777, 66)])
+@pytest.mark.parametrize("n,nrhs", [(1, 1), (37, 3), (300, 5), (777, 66), (777, 133)])
 def test_getrf_getrs_random(ctx, dtype, n, nrhs):
     say("getrf/getrs", dtype, n, nrhs)
     rng = np.random.default_rng(n)
