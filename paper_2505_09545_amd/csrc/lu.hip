@@ -470,40 +470,6 @@ __global__ void __launch_bounds__(256) row_permute_kernel(cplx<T>* __restrict__ 
   }
 }
 
-// Row interchanges of one block on the columns [0, ncols) of X (as
-// row_permute_kernel), then the permuted rows [k0, k0 + w) copied to D (w x ncols,
-// leading dimension w): one launch per block of a forward solve.
-template <typename T>
-__global__ void __launch_bounds__(256) permute_copy_kernel(cplx<T>* __restrict__ X, int64_t ld, int64_t k0, int w,
-                                                           cplx<T>* __restrict__ D, const int32_t* __restrict__ dst,
-                                                           const int32_t* __restrict__ src,
-                                                           const int32_t* __restrict__ npairs, int64_t sX, int64_t sD,
-                                                           int64_t spairs, int64_t snpairs) {
-  using CT = cplx<T>;
-  X += (int64_t)blockIdx.y * sX;  // batch item blockIdx.y
-  D += (int64_t)blockIdx.y * sD;
-  dst += (int64_t)blockIdx.y * spairs;
-  src += (int64_t)blockIdx.y * spairs;
-  npairs += (int64_t)blockIdx.y * snpairs;
-  const int np = *npairs;
-  const int64_t col = blockIdx.x;
-  CT* x = X + col * ld;
-  CT v[2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int t = threadIdx.x + 256 * i;
-    if (t < np) v[i] = x[src[t]];
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < 2; ++i) {
-    const int t = threadIdx.x + 256 * i;
-    if (t < np) x[dst[t]] = v[i];
-  }
-  __syncthreads();  // (makes the interchanged rows visible to the whole workgroup)
-  for (int r = threadIdx.x; r < w; r += 256) D[r + col * w] = x[k0 + r];
-}
-
 // inverse: Xnew[src[t]] = Xold[dst[t]] (for the transposed solve)
 template <typename T>
 __global__ void __launch_bounds__(256) row_permute_inv_kernel(cplx<T>* __restrict__ X, int64_t ld, int64_t c0,
@@ -1143,27 +1109,21 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
   const int64_t sX = ws.s_tmp;
   hipError_t e;
   if (nrhs <= 0) return hipSuccess;
-  // RHS columns per pass: the block copy needs nb per column; the transposed
-  // steps need (chunks of the longest product) x nb partial sums per column.
-  int64_t chunk = ws.tmp_elems / nb;
-  if (trans) {
-    const int64_t per = skinny_t_chunks(n, nb) * nb;
-    chunk = ws.tmp_elems / per;
-    if (chunk < 1) return hipErrorInvalidValue;
-  }
-  // With more than SKINNY_MAX_RHS columns the plain solve keeps the forward
-  // result in tmp (n x nr, leading dimension n), so that every block step reads
-  // its operand rows in place: the step's product writes those rows to the
-  // other buffer (the forward into tmp, the backward back into B), no copy.
-  if (!trans && ws.tmp_elems / n < chunk) chunk = ws.tmp_elems / n;
+  // RHS columns per pass: the plain solve keeps n per column in tmp; the
+  // transposed steps need (chunks of the longest product) x nb partial sums per column.
+  const int64_t chunk = ws.tmp_elems / (trans ? skinny_t_chunks(n, nb) * nb : n);
   if (chunk < 1) return hipErrorInvalidValue;
   const int64_t part_elems = (int64_t)NB * sX;  // the transposed partial sums of all items
   for (int64_t r0 = 0; r0 < nrhs; r0 += chunk) {
     const int64_t nr = nrhs - r0 < chunk ? nrhs - r0 : chunk;
     CT* B = Ball + r0 * ldb;
     const bool small = nr <= SKINNY_MAX_RHS;
-    if (trans == 0 && !small) {
-      CT* Y = X;  // n x nr
+    if (trans == 0) {
+      // The forward result goes to tmp (Y, n x nr, leading dimension n), so that
+      // every block step reads its operand rows in place: the step's product
+      // writes those rows to the other buffer (the forward into Y, the backward
+      // back into B), and no step needs a copy of them.
+      CT* Y = X;
       // forward: P_b, then rows [k0, n) -= [I - L11^-1 ; L21 L11^-1] B_b, rows [k0, k0 + w) into Y
       for (int bi = 0; bi < nblk; ++bi) {
         const LUBlock& b = plan.blocks[bi];
@@ -1180,9 +1140,11 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
         m.c2 = Y + k0;
         m.ldc2 = n;
         m.sc2 = sX;
-        if ((e = launch_gemm<T>(0, 0, n - k0, nr, b.w, A + k0 + k0 * ld, ld, B + k0, ldb, B + k0, ldb, st, m, NB, sA,
-                                sB, sB)) != hipSuccess)
-          return e;
+        e = small ? launch_skinny_n<T>(n - k0, b.w, A + k0 + k0 * ld, ld, B + k0, ldb, B + k0, ldb, nr, st, m, NB, sA,
+                                       sB, sB)
+                  : launch_gemm<T>(0, 0, n - k0, nr, b.w, A + k0 + k0 * ld, ld, B + k0, ldb, B + k0, ldb, st, m, NB,
+                                   sA, sB, sB);
+        if (e != hipSuccess) return e;
       }
       // backward on Y: rows [0, k0 + w) -= [U01 U11^-1 ; I - U11^-1] Y_b, rows [k0, k0 + w) into B
       for (int bi = nblk - 1; bi >= 0; --bi) {
@@ -1195,38 +1157,8 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
         m.c2 = B + k0;
         m.ldc2 = ldb;
         m.sc2 = sB;
-        if ((e = launch_gemm<T>(0, 0, k0 + b.w, nr, b.w, A + k0 * ld, ld, Y + k0, n, Y, n, st, m, NB, sA, sX, sX)) !=
-            hipSuccess)
-          return e;
-      }
-    } else if (trans == 0) {
-      // forward: P_b, then rows [k0, n) -= [I - L11^-1 ; L21 L11^-1] B_b
-      for (int bi = 0; bi < nblk; ++bi) {
-        const LUBlock& b = plan.blocks[bi];
-        const int64_t k0 = b.k0;
-        const int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;
-        const int32_t* src = dst + 2 * nb;
-        // P_b, and B_b copied out (the product below reads it while it rewrites those rows)
-        hipLaunchKernelGGL(permute_copy_kernel<T>, dim3((unsigned)nr, NB), dim3(256), 0, st, B, ldb, k0, b.w, X, dst,
-                           src, ws.npairs + bi, sB, sX, ws.s_pairs, ws.s_npairs);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
-        GemmMask m;
-        m.akind = GEMM_MASK_STRICT_LOWER;
-        m.ar0 = 0;
-        m.adw = b.w;
-        e = launch_skinny_n<T>(n - k0, b.w, A + k0 + k0 * ld, ld, X, b.w, B + k0, ldb, nr, st, m, NB, sA, sX, sB);
-        if (e != hipSuccess) return e;
-      }
-      // backward: rows [0, k0 + w) -= [U01 U11^-1 ; I - U11^-1] B_b
-      for (int bi = nblk - 1; bi >= 0; --bi) {
-        const LUBlock& b = plan.blocks[bi];
-        const int64_t k0 = b.k0;
-        if ((e = launch_copy_block<T>(B + k0, ldb, X, b.w, b.w, nr, st, NB, sB, sX)) != hipSuccess) return e;
-        GemmMask m;
-        m.akind = GEMM_MASK_UPPER;
-        m.ar0 = k0;
-        m.adw = b.w;
-        e = launch_skinny_n<T>(k0 + b.w, b.w, A + k0 * ld, ld, X, b.w, B, ldb, nr, st, m, NB, sA, sX, sB);
+        e = small ? launch_skinny_n<T>(k0 + b.w, b.w, A + k0 * ld, ld, Y + k0, n, Y, n, nr, st, m, NB, sA, sX, sX)
+                  : launch_gemm<T>(0, 0, k0 + b.w, nr, b.w, A + k0 * ld, ld, Y + k0, n, Y, n, st, m, NB, sA, sX, sX);
         if (e != hipSuccess) return e;
       }
     } else {

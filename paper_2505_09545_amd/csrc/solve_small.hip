@@ -128,11 +128,14 @@ __global__ void __launch_bounds__(256) skinny_n_kernel(int64_t m, int64_t k, con
       if (PART) {
         C[(chunk * nrhs + r0 + r) * m + row] = s;
       } else {
-        CT* p = C + row + (r0 + r) * ldc;
-        CT c = *p;
+        // rows [ar0, ar0 + adw) optionally to the second destination mk.c2
+        CT c = C[row + (r0 + r) * ldc];
         c.x -= s.x;
         c.y -= s.y;
-        *p = c;
+        if (mk.c2 && row >= mk.ar0 && row < mk.ar0 + mk.adw)
+          static_cast<CT*>(mk.c2)[item * mk.sc2 + (row - mk.ar0) + (r0 + r) * mk.ldc2] = c;
+        else
+          C[row + (r0 + r) * ldc] = c;
       }
     }
   }
