@@ -1088,6 +1088,17 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
       LUCHK(form_inverse(sb));
     }
     LUCHK(update_cols(sb, c1 + wa, nr - wa, tmpB, ws.s_tmp));
+    // The next step's main stream needs only the update above; the work below
+    // touches block column bi alone, which no later step of the factorisation
+    // reads, so for one system it runs while the main stream goes on (measured
+    // at n = 12 000: FP32+IR 92.4 -> 91.8 ms, FP64 144.9 -> 144.0 ms; batched
+    // groups, whose side stream sets the pace, were 1 % slower and keep the
+    // record after it).
+    auto record_bulk_done = [&]() -> hipError_t {
+      hipError_t r = new_event(bulk_done);
+      return r != hipSuccess ? r : hipEventRecord(bulk_done, sb);
+    };
+    if (la && NB == 1) LUCHK(record_bulk_done());
     // L21 is read by both parts of this step's update: transform it after both
     // (the side stream already waited for the main stream's part above)
     // solve-ready form: L21 <- L21 L11^-1 = L21 - L21 (I - L11^-1)
@@ -1097,10 +1108,8 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
     mb.bkind = GEMM_MASK_STRICT_LOWER;
     LUCHK(launch_gemm<T>(0, 0, nr, w, w, tmpB, nr, diag, ld, A + c1 + k0 * ld, ld, sb, mb, NB, ws.s_tmp, sA, sA));
     LUCHK(P.end(sb));
+    if (la && NB > 1) LUCHK(record_bulk_done());
     if (la) {
-      LUCHK(new_event(bulk_done));
-      LUCHK(hipEventRecord(bulk_done, sb));
-      // (after bulk_done, which is all the main stream waits for)
       if (NB == 1 && (2 * nr <= n || n <= 4096))
         for (int q = 0; q < 3 && u_next <= bi; ++q) LUCHK(upper_parts(sb, u_next++));
     }
