@@ -668,10 +668,16 @@ __global__ void __launch_bounds__(256) block_inv_kernel(const cplx<T>* __restric
 // dimension ldx): the forward substitution of block_inv_kernel applied to the
 // columns of X instead of identity columns (the look-ahead U12 block, without
 // waiting for the triangle's inverse).
-template <typename T, int CPW>
+// PERM: first the block's row interchanges on each owned column (rows [k0, n),
+// X pointing at row k0; moved rows as listed by the panel), as
+// row_permute_kernel does, so that one launch replaces two.
+template <typename T, int CPW, bool PERM>
 __global__ void __launch_bounds__(256) block_trsm_kernel(const cplx<T>* __restrict__ A, int64_t ld, int64_t n, int nb,
                                                          int b0, cplx<T>* __restrict__ X, int64_t ldx, int ncols,
-                                                         int PW, int64_t sA, int64_t sX) {
+                                                         int PW, int64_t sA, int64_t sX, const int32_t* __restrict__ dst,
+                                                         const int32_t* __restrict__ src,
+                                                         const int32_t* __restrict__ npairs, int64_t spairs,
+                                                         int64_t snpairs) {
   using CT = cplx<T>;
   A += (int64_t)blockIdx.z * sA;  // batch item blockIdx.z
   X += (int64_t)blockIdx.z * sX;
@@ -681,6 +687,28 @@ __global__ void __launch_bounds__(256) block_trsm_kernel(const cplx<T>* __restri
   const int w = (int)(n - k0 < nb ? n - k0 : nb);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int col0 = blockIdx.x * (4 * CPW) + wave * CPW;
+  if constexpr (PERM) {
+    dst += (int64_t)blockIdx.z * spairs;
+    src += (int64_t)blockIdx.z * spairs;
+    const int np = npairs[(int64_t)blockIdx.z * snpairs];  // <= 2 nb <= 256
+    CT v[CPW][4];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int t = lane + 64 * q;
+        if (t < np && col0 + c < ncols) v[c][q] = X[(src[t] - k0) + (int64_t)(col0 + c) * ldx];
+      }
+    __syncthreads();  // every source read before any destination is written
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int t = lane + 64 * q;
+        if (t < np && col0 + c < ncols) X[(dst[t] - k0) + (int64_t)(col0 + c) * ldx] = v[c][q];
+      }
+    __syncthreads();  // the interchanged rows visible to the whole workgroup
+  }
   CT b[2][CPW];
 #pragma unroll
   for (int h = 0; h < 2; ++h)
@@ -784,12 +812,19 @@ static hipError_t launch_block_inv(const cplx<T>* A, int64_t ld, int64_t n, int 
 
 template <typename T>
 static hipError_t launch_block_trsm(const cplx<T>* A, int64_t ld, int64_t n, int nb, int b0, cplx<T>* X, int64_t ldx,
-                                   int64_t ncols, hipStream_t st, int nbatch, int64_t sA, int64_t sX) {
+                                   int64_t ncols, hipStream_t st, int nbatch, int64_t sA, int64_t sX,
+                                   const int32_t* dst = nullptr, const int32_t* src = nullptr,
+                                   const int32_t* npairs = nullptr, int64_t spairs = 0, int64_t snpairs = 0) {
   if (ncols <= 0 || nbatch <= 0) return hipSuccess;
   const int PW = trsm_pw(nb, (int)sizeof(T));
   const size_t lds = (size_t)PW * nb * sizeof(cplx<T>);
-  hipLaunchKernelGGL((block_trsm_kernel<T, 1>), dim3((unsigned)((ncols + 3) / 4), 1, (unsigned)nbatch), dim3(256), lds,
-                     st, A, ld, n, nb, b0, X, ldx, (int)ncols, PW, sA, sX);
+  const dim3 g((unsigned)((ncols + 3) / 4), 1, (unsigned)nbatch);
+  if (npairs)
+    hipLaunchKernelGGL((block_trsm_kernel<T, 1, true>), g, dim3(256), lds, st, A, ld, n, nb, b0, X, ldx, (int)ncols,
+                       PW, sA, sX, dst, src, npairs, spairs, snpairs);
+  else
+    hipLaunchKernelGGL((block_trsm_kernel<T, 1, false>), g, dim3(256), lds, st, A, ld, n, nb, b0, X, ldx, (int)ncols,
+                       PW, sA, sX, dst, src, npairs, spairs, snpairs);
   return hipGetLastError();
 }
 
@@ -1064,14 +1099,12 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
     // spectra 83 -> 98 systems/s with one event, FP32+IR step 95.6 -> 95.2 ms).
     hipEvent_t main_updated = nullptr;
     if (la) {
-      // next panel's columns: interchanges, U12 by substitution, update
-      LUCHK(P.begin(st, PROF_PERM, 0.0));
-      hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)wa, NB), dim3(256), 0, st, A, ld, c1, dst, src, npr, sA,
-                         ws.s_pairs, ws.s_npairs);
-      LUCHK(hipGetLastError());
-      LUCHK(P.end(st));
+      // next panel's columns: interchanges and U12 by substitution in one
+      // launch (one launch and its gap fewer per block on the panels' path),
+      // then the update
       LUCHK(P.begin(st, PROF_TRSM, 8.0 * w * w * (double)wa * fb));
-      LUCHK(launch_block_trsm<T>(A, ld, n, nb, bi, A + k0 + c1 * ld, ld, wa, st, NB, sA, sA));
+      LUCHK(launch_block_trsm<T>(A, ld, n, nb, bi, A + k0 + c1 * ld, ld, wa, st, NB, sA, sA, dst, src, npr,
+                                 ws.s_pairs, ws.s_npairs));
       LUCHK(P.end(st));
       LUCHK(P.begin(st, PROF_LOOKAHEAD, 8.0 * (double)nr * (double)wa * w * fb));
       LUCHK(launch_gemm_update<T>(nr, wa, w, A + c1 + k0 * ld, ld, A + k0 + c1 * ld, ld, A + c1 + c1 * ld, ld, st, NB,
