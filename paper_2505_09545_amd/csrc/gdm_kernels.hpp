@@ -144,7 +144,7 @@ struct LUWork {
   int32_t* err;              // [2] (shared): exchange timeout flag, first zero pivot (INT32_MAX if none)
   int32_t* pairs;            // [nblocks][2][2 nb]: destination rows then source rows
   int32_t* npairs;           // [nblocks]
-  void* tmp;                 // [tmp_elems] complex scratch (operand copies, split-k partials)
+  void* tmp;                 // [tmp_elems] complex scratch (operand copies, split-k partials, solve sweeps)
   void* dinv;                // [nblocks][nb][nb] complex inverses of the diagonal triangles
   std::vector<hipEvent_t>* events;  // host-side pool of reusable events (look-ahead)
   int64_t tmp_elems;         // capacity of tmp per item in complex elements
