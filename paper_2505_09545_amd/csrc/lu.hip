@@ -730,31 +730,37 @@ __global__ void __launch_bounds__(256) block_trsm_kernel(const cplx<T>* __restri
 }
 
 // Diagonal block of block b0 + blockIdx.y: strict lower <- -Linv (UPPER 0), or
-// upper incl. diagonal <- I - Uinv (UPPER 1).
+// upper incl. diagonal <- I - Uinv (UPPER 1).  MODE 2: the strict lower part
+// of Dinv itself <- -Linv (A untouched); MODE 3: strict lower <- that part of
+// Dinv as it stands (after MODE 2).
 template <typename T, int UPPER>
 __global__ void __launch_bounds__(256) diag_store_kernel(cplx<T>* __restrict__ A, int64_t ld, int64_t n, int nb, int b0,
-                                                         const cplx<T>* __restrict__ Dinv, int64_t sA, int64_t sD) {
+                                                         cplx<T>* __restrict__ Dinv, int64_t sA, int64_t sD) {
   using CT = cplx<T>;
   A += (int64_t)blockIdx.z * sA;  // batch item blockIdx.z
   Dinv += (int64_t)blockIdx.z * sD;
   const int bb = b0 + blockIdx.y;
   const int64_t k0 = (int64_t)bb * nb;
   const int w = (int)(n - k0 < nb ? n - k0 : nb);
-  const CT* D = Dinv + (size_t)bb * nb * nb;
+  CT* D = Dinv + (size_t)bb * nb * nb;
   for (int idx = blockIdx.x * 256 + threadIdx.x; idx < w * w; idx += gridDim.x * 256) {
     const int i = idx % w, j = idx / w;
     const CT d = D[i + (int64_t)j * nb];
     CT v;
-    if (!UPPER) {
+    if (UPPER != 1) {
       if (i <= j) continue;
-      v.x = -d.x;
-      v.y = -d.y;
+      v = d;
+      if (UPPER != 3) {
+        v.x = -d.x;
+        v.y = -d.y;
+      }
     } else {
       if (i > j) continue;
       v.x = (i == j ? 1 : 0) - d.x;
       v.y = -d.y;
     }
-    A[(k0 + i) + (k0 + j) * ld] = v;
+    if (UPPER == 2) D[i + (int64_t)j * nb] = v;
+    else A[(k0 + i) + (k0 + j) * ld] = v;
   }
 }
 
@@ -790,7 +796,8 @@ static int trsm_pw(int w, int elem) {
 // chain minimal (the chain, not the arithmetic, sets the time of one triangle);
 // with many triangles at once (more workgroups than CUs) four columns per wave
 // stage each triangle into LDS four times less often.
-template <typename T, int UPPER>
+// STORE: diag_store_kernel mode applied after the inverse (UPPER by default).
+template <typename T, int UPPER, int STORE = UPPER>
 static hipError_t launch_block_inv(const cplx<T>* A, int64_t ld, int64_t n, int nb, int b0, int nblocks, cplx<T>* Dinv,
                                    hipStream_t st, int nbatch, int64_t sA, int64_t sD, int ncu) {
   if (nblocks <= 0 || nbatch <= 0) return hipSuccess;
@@ -805,7 +812,7 @@ static hipError_t launch_block_inv(const cplx<T>* A, int64_t ld, int64_t n, int 
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((diag_store_kernel<T, UPPER>), dim3(16, (unsigned)nblocks, (unsigned)nbatch), dim3(256), 0, st,
+  hipLaunchKernelGGL((diag_store_kernel<T, STORE>), dim3(16, (unsigned)nblocks, (unsigned)nbatch), dim3(256), 0, st,
                      const_cast<cplx<T>*>(A), ld, n, nb, b0, Dinv, sA, sD);
   return hipGetLastError();
 }
@@ -1061,15 +1068,29 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
       return P.end(s);
     };
     if (!la || nr <= 0) LUCHK(form_inverse(st));
+    // columns [c1, c1 + wa) on the main stream, [c1 + wa, n) on the side stream
+    const int64_t wa = la ? std::min<int64_t>(nr, nb) : nr;
+    // While the trailing matrix is large (one system), the bulk update sets the
+    // pace: the side stream then starts its part as soon as the panel is done,
+    // beside the main stream's part.  L11^-1 goes to the block's inverse slot in
+    // its masked-operand form (-L11^-1 below the diagonal, = I - L11^-1 there),
+    // and reaches the diagonal block of A only after the main stream's
+    // substitution has read L11.
+    const bool early = la && NB == 1 && nr - wa > 0 && 4 * nr > 3 * n;
+    hipEvent_t panel_done = nullptr;
+    if (early) {
+      LUCHK(new_event(panel_done));
+      LUCHK(hipEventRecord(panel_done, st));
+    }
     if (bulk_done) LUCHK(hipStreamWaitEvent(st, bulk_done, 0));  // columns of this step were in the bulk
     if (nr <= 0) break;
     GemmMask ml;
     ml.akind = GEMM_MASK_STRICT_LOWER;
     ml.ar0 = 0;
     ml.adw = w;
-    // columns [c1, c1 + wa) on the main stream, [c1 + wa, n) on the side stream
-    const int64_t wa = la ? std::min<int64_t>(nr, nb) : nr;
-    auto update_cols = [&](hipStream_t s, int64_t cb, int64_t ncols, CT* tmp, int64_t stmp) -> hipError_t {
+    // lop: I - L11^-1 below its diagonal (leading dimension lld, item stride slop)
+    auto update_cols = [&](hipStream_t s, int64_t cb, int64_t ncols, CT* tmp, int64_t stmp, const CT* lop,
+                           int64_t lld, int64_t slop) -> hipError_t {
       hipError_t r;
       if (ncols <= 0) return hipSuccess;
       if ((r = P.begin(s, PROF_PERM, 0.0)) != hipSuccess) return r;
@@ -1079,7 +1100,7 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
       // U12 = L11^-1 A12 = A12 - (I - L11^-1) A12
       if ((r = P.begin(s, PROF_TRSM, 8.0 * w * w * (double)ncols * fb)) != hipSuccess) return r;
       if ((r = launch_copy_block<T>(A + k0 + cb * ld, ld, tmp, w, w, ncols, s, NB, sA, stmp)) != hipSuccess) return r;
-      if ((r = launch_gemm<T>(0, 0, w, ncols, w, diag, ld, tmp, w, A + k0 + cb * ld, ld, s, ml, NB, sA, stmp, sA)) !=
+      if ((r = launch_gemm<T>(0, 0, w, ncols, w, lop, lld, tmp, w, A + k0 + cb * ld, ld, s, ml, NB, slop, stmp, sA)) !=
           hipSuccess)
         return r;
       if ((r = P.end(s)) != hipSuccess) return r;
@@ -1113,14 +1134,23 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
       LUCHK(new_event(main_updated));
       LUCHK(hipEventRecord(main_updated, st));
     } else {
-      LUCHK(update_cols(st, c1, wa, tmpB, ws.s_tmp));
+      LUCHK(update_cols(st, c1, wa, tmpB, ws.s_tmp, diag, ld, sA));
     }
     hipStream_t sb = la ? side : st;
-    if (la) {
-      LUCHK(hipStreamWaitEvent(sb, main_updated, 0));
-      LUCHK(form_inverse(sb));
+    CT* dslot = dinv + (size_t)bi * nb * nb;  // this block's inverse slot
+    if (early) {
+      LUCHK(hipStreamWaitEvent(sb, panel_done, 0));
+      LUCHK(P.begin(sb, PROF_TRSM, 0.0));
+      LUCHK((launch_block_inv<T, 0, 2>(A, ld, n, nb, bi, 1, dinv, sb, NB, sA, ws.s_dinv, ws.gmax)));
+      LUCHK(P.end(sb));
+      LUCHK(update_cols(sb, c1 + wa, nr - wa, tmpB, ws.s_tmp, dslot, nb, ws.s_dinv));
+    } else {
+      if (la) {
+        LUCHK(hipStreamWaitEvent(sb, main_updated, 0));
+        LUCHK(form_inverse(sb));
+      }
+      LUCHK(update_cols(sb, c1 + wa, nr - wa, tmpB, ws.s_tmp, diag, ld, sA));
     }
-    LUCHK(update_cols(sb, c1 + wa, nr - wa, tmpB, ws.s_tmp));
     // The next step's main stream needs only the update above; the work below
     // touches block column bi alone, which no later step of the factorisation
     // reads, so for one system it runs while the main stream goes on (measured
@@ -1132,6 +1162,14 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
       return r != hipSuccess ? r : hipEventRecord(bulk_done, sb);
     };
     if (la && NB == 1) LUCHK(record_bulk_done());
+    if (early) {
+      LUCHK(hipStreamWaitEvent(sb, main_updated, 0));
+      LUCHK(P.begin(sb, PROF_TRSM, 0.0));
+      hipLaunchKernelGGL((diag_store_kernel<T, 3>), dim3(16, 1, (unsigned)NB), dim3(256), 0, sb, A, ld, n, nb, bi, dinv,
+                         sA, ws.s_dinv);
+      LUCHK(hipGetLastError());
+      LUCHK(P.end(sb));
+    }
     // L21 is read by both parts of this step's update: transform it after both
     // (the side stream already waited for the main stream's part above)
     // solve-ready form: L21 <- L21 L11^-1 = L21 - L21 (I - L11^-1)
