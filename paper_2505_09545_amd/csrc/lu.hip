@@ -1111,13 +1111,12 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
         return r;
       return P.end(s);
     };
-    // One event per block orders the side stream after the main stream's part:
-    // the side overwrites L11 with its inverse form (the substitution below read
-    // L11) and transforms L21 (the look-ahead product read it).  Each event
-    // record or wait costs 6-11 us on the GPU timeline; with a second event
-    // right after the substitution the side would start 25 us earlier but the
-    // main stream would pay one more record per block (measured: batched
-    // spectra 83 -> 98 systems/s with one event, FP32+IR step 95.6 -> 95.2 ms).
+    // This event orders the side stream's writes of L11 (its inverse form; the
+    // substitution below reads L11) and of L21 (its transform; the look-ahead
+    // product reads it) after the main stream's part.  Each event record or
+    // wait costs 6-11 us on the GPU timeline, so outside the early blocks above
+    // it is the only one per block (measured: batched spectra 83 -> 98
+    // systems/s with one event instead of two, FP32+IR step 95.6 -> 95.2 ms).
     hipEvent_t main_updated = nullptr;
     if (la) {
       // next panel's columns: interchanges and U12 by substitution in one
