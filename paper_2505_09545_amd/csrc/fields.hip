@@ -7,8 +7,9 @@
 // Work decomposition: one thread per probe and RHS chunk; the dipoles are
 // swept in tiles of 256 staged in LDS (position + moments), so each dipole is
 // read from HBM once per workgroup.  When there are few probes the dipole sum is
-// split over several workgroups that write FP64 partial sums, reduced in a fixed
-// order by a second kernel (deterministic result).
+// split over several workgroups (down to 32 dipoles each) that write FP64
+// partial sums, reduced in a fixed order by a second kernel (deterministic
+// result).
 //
 // Moment layout q[r][u] (u = unknown index): p of dipole d at u = 3d..3d+2 for
 // all N dipoles, m of effective dipole e at u = 3N + 3e.  Output E, H [nrhs][P][3].
@@ -149,14 +150,31 @@ __global__ void reduce_splits_kernel(const double2* __restrict__ part, int nspli
   out[i] = s;
 }
 
+// Dipoles per split: a multiple of SPLIT_GRAIN (a split may be smaller than one
+// LDS tile, so that a launch with few probes still spreads over every CU).
+constexpr int SPLIT_GRAIN = 32;
+
+static int64_t fields_split_len(int64_t N, int nsplit) {
+  return ((N + nsplit - 1) / nsplit + SPLIT_GRAIN - 1) / SPLIT_GRAIN * SPLIT_GRAIN;
+}
+
+// Number of dipole splits of a launch: enough workgroups for four per CU, at
+// most 64 partial sums per output, and no empty split.
 int fields_num_splits(int64_t P, int64_t N, int num_cu) {
   const int64_t pblocks = (P + 255) / 256;
   int64_t want = (4 * (int64_t)num_cu + pblocks - 1) / pblocks;
-  int64_t maxs = (N + FT - 1) / FT;
+  const int64_t maxs = (N + SPLIT_GRAIN - 1) / SPLIT_GRAIN;
   if (want > maxs) want = maxs;
   if (want < 1) want = 1;
   if (want > 64) want = 64;
-  return (int)want;
+  const int64_t len = fields_split_len(N, (int)want);
+  return (int)((N + len - 1) / len);
+}
+
+// Scratch bytes launch_fields needs for nsplit > 1 (partial sums of E, and of H if wanted).
+size_t fields_scratch_bytes(int64_t nrhs, int64_t P, int nsplit, bool want_h) {
+  if (nsplit <= 1) return 0;
+  return sizeof(double2) * (want_h ? 2 : 1) * (size_t)nsplit * (size_t)nrhs * (size_t)P * 3;
 }
 
 hipError_t launch_fields(const DipoleView& d, const Wave& w, const double2* q, int64_t ldq, int64_t nrhs,
@@ -164,7 +182,7 @@ hipError_t launch_fields(const DipoleView& d, const Wave& w, const double2* q, i
                          double min_r2, int* flag, hipStream_t st) {
   if (P <= 0 || nrhs <= 0) return hipSuccess;
   const int64_t count = nrhs * P * 3;
-  const int64_t jps = ((d.N + nsplit - 1) / nsplit + FT - 1) / FT * FT;
+  const int64_t jps = fields_split_len(d.N, nsplit);
   double2* oE = nsplit > 1 ? scratch : E;
   double2* oH = nsplit > 1 ? (H ? scratch + nsplit * count : nullptr) : H;
   const dim3 grid((unsigned)((P + 255) / 256), (unsigned)nsplit);

@@ -50,6 +50,7 @@ hipError_t launch_rowsum_abs(const double2* M, int64_t ld, int64_t n, double* ro
 hipError_t launch_colsum_abs(const double2* M, int64_t ld, int64_t n, double* cols, hipStream_t st);
 
 int fields_num_splits(int64_t P, int64_t N, int num_cu);
+size_t fields_scratch_bytes(int64_t nrhs, int64_t P, int nsplit, bool want_h);
 hipError_t launch_fields(const DipoleView& d, const Wave& w, const double2* q, int64_t ldq, int64_t nrhs,
                          const double* rp, int64_t P, double2* E, double2* H, double2* scratch, int nsplit,
                          double min_r2, int* flag, hipStream_t st);
