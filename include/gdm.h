@@ -132,6 +132,25 @@ gdm_status gdm_planewave(gdm_ctx* ctx, int64_t n_pw, const double* khat, const d
 gdm_status gdm_fields(gdm_ctx* ctx, int64_t n_rhs, const double* q, int64_t n_probe, const double* r_probe,
                       double* E_sca, double* H_sca);
 
+/* Step (c) for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation, arguments, layouts and errors as gdm_fields, and the same result
+ * bit for bit, but the partial sums of its dipole splits and its probe-on-dipole
+ * flag live in a static device array of GDM_NOALLOC_SCRATCH_BYTES instead of
+ * context buffers; the call allocates nothing (no hipMalloc, no hipFree, no
+ * allocating library routine).  Each device holds its own copy of the array
+ * from the first gdm_create on it until the process ends.  The launch needs
+ * 48 * nsplit * n_rhs * n_probe bytes (twice that with H_sca), where nsplit <= 64
+ * is the number of dipole splits (1 from about 262 000 probes on, and at most
+ * ceil(N / 32)); GDM_E_ARG, with nothing written, if that exceeds
+ * GDM_NOALLOC_SCRATCH_BYTES - 256.  Every call on a device shares that device's
+ * array and leaves its contents behind: calls that overlap on one device (from
+ * several contexts or streams) race.  GDM_E_DEVICE if the array's address could
+ * not be obtained at gdm_create. */
+#define GDM_NOALLOC_SCRATCH_BYTES (32u << 20)
+gdm_status gdm_fields_noalloc(gdm_ctx* ctx, int64_t n_rhs, const double* q, int64_t n_probe, const double* r_probe,
+                              double* E_sca, double* H_sca);
+
 /* Cross sections per RHS (Sec. "Observables"), FP64: out [n_rhs][5] =
  * (extinction, scattering = ext - abs, absorption, radiated-by-dipoles,
  * far-field scattering by the exact double sum or NaN unless want_ff).

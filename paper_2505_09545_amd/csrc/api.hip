@@ -2,6 +2,7 @@
 // validation and the host drivers that chain the kernels of the hot path.
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -720,6 +721,38 @@ extern "C" gdm_status gdm_batch_spectra(gdm_ctx* c, int64_t n_struct, const int6
   return GDM_OK;
 }
 
+// Static device scratch of gdm_fields_noalloc: each device that loads the
+// library holds its own copy until the process ends.  Host code never uses the
+// array's name as a device address: gdm_create looks up the address on its
+// device once (hipGetSymbolAddress with that device current) and every use goes
+// through that pointer.
+constexpr size_t NOALLOC_FLAG_BYTES = 256;  // probe-on-dipole flag, then the partial sums
+static __device__ __align__(256) unsigned char scratch[GDM_NOALLOC_SCRATCH_BYTES];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex noalloc_mu;
+static void* noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// device must be current; returns the status of the lookup
+static hipError_t noalloc_register(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  if (noalloc_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr) {
+    (void)hipGetLastError();
+    return e != hipSuccess ? e : hipErrorInvalidSymbol;
+  }
+  noalloc_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+static void* noalloc_scratch(int device) {
+  if (device < 0 || device >= NOALLOC_MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lk(noalloc_mu);
+  return noalloc_ptr[device];
+}
+
 extern "C" {
 
 gdm_status gdm_create(int device, void* hip_stream, gdm_ctx** out) {
@@ -751,6 +784,9 @@ gdm_status gdm_create(int device, void* hip_stream, gdm_ctx** out) {
   for (auto& e : c->sev)
     if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
   if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess) c->side = nullptr;
+  // the no-alloc entry points' static scratch on this device (a failed lookup
+  // only disables them: they report it)
+  (void)noalloc_register(device);
   *out = c;
   return GDM_OK;
 }
@@ -1051,30 +1087,71 @@ gdm_status gdm_adjoint(gdm_ctx* c, int64_t nrhs, const double* khat, const doubl
   return GDM_OK;
 }
 
-gdm_status gdm_fields(gdm_ctx* c, int64_t nrhs, const double* q, int64_t P, const double* rp, double* E, double* H) {
-  if (!c) return GDM_E_ARG;
-  if (c->wavelength <= 0) FAIL(c, GDM_E_STATE, "no wavelength set (call gdm_factorize first)");
-  if (nrhs <= 0 || P < 0 || !q || (P > 0 && (!rp || !E))) FAIL(c, GDM_E_ARG, "bad field arguments");
-  if (P == 0) return GDM_OK;
-  if ((P + 255) / 256 > (int64_t)INT32_MAX) FAIL(c, GDM_E_ARG, "too many probes");
-  HIPCHK(c, hipSetDevice(c->device));
+}  // extern "C"
+
+// Probe fields of gdm_fields and gdm_fields_noalloc: partial sums of the dipole
+// splits in `part` (capacity part_cap bytes), the probe-on-dipole flag at `flag`.
+static gdm_status fields_core(gdm_ctx* c, int64_t nrhs, const double* q, int64_t P, const double* rp, double* E,
+                              double* H, void* part, size_t part_cap, int* flag_dev, int nsplit, bool prof) {
   const Wave w = wave_of(c, c->wavelength);
   const DipoleView d = view_of(c, make_double2(0, 0));
-  const int nsplit = fields_num_splits(P, c->N, c->num_cu);
-  if (nsplit > 1) HIPCHK(c, c->scratch.ensure(sizeof(double2) * 2 * (size_t)nsplit * nrhs * P * 3));
-  HIPCHK(c, c->flag.ensure(sizeof(int) * 4));
-  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, c->stream, c->flag.as<int>(), 4, 0);
+  if (fields_scratch_bytes(nrhs, P, nsplit, H != nullptr) > part_cap)
+    FAIL(c, GDM_E_ARG, "fields scratch too small");
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, c->stream, flag_dev, 1, 0);
+  HIPCHK(c, hipGetLastError());
   const double rmin = 1e-9 * c->step;
-  HIPCHK(c, c->prof.begin(c->stream, PROF_FIELDS, (double)P * (double)c->N * (double)nrhs));
+  if (prof) HIPCHK(c, c->prof.begin(c->stream, PROF_FIELDS, (double)P * (double)c->N * (double)nrhs));
   HIPCHK(c, launch_fields(d, w, reinterpret_cast<const double2*>(q), c->n, nrhs, rp, P, reinterpret_cast<double2*>(E),
-                          reinterpret_cast<double2*>(H), c->scratch.as<double2>(), nsplit, rmin * rmin,
-                          c->flag.as<int>(), c->stream));
-  HIPCHK(c, c->prof.end(c->stream));
+                          reinterpret_cast<double2*>(H), static_cast<double2*>(part), nsplit, rmin * rmin, flag_dev,
+                          c->stream));
+  if (prof) HIPCHK(c, c->prof.end(c->stream));
   int flag = 0;
-  HIPCHK(c, hipMemcpyAsync(&flag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(&flag, flag_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (flag) FAIL(c, GDM_E_PROBE_AT_DIPOLE, "a probe point lies on a dipole (|R| < 1e-9 step)");
   return GDM_OK;
+}
+
+static gdm_status fields_check(gdm_ctx* c, int64_t nrhs, const double* q, int64_t P, const double* rp,
+                               const double* E) {
+  if (c->wavelength <= 0) FAIL(c, GDM_E_STATE, "no wavelength set (call gdm_factorize first)");
+  if (nrhs <= 0 || P < 0 || !q || (P > 0 && (!rp || !E))) FAIL(c, GDM_E_ARG, "bad field arguments");
+  if ((P + 255) / 256 > (int64_t)INT32_MAX) FAIL(c, GDM_E_ARG, "too many probes");
+  return GDM_OK;
+}
+
+extern "C" {
+
+gdm_status gdm_fields(gdm_ctx* c, int64_t nrhs, const double* q, int64_t P, const double* rp, double* E, double* H) {
+  if (!c) return GDM_E_ARG;
+  gdm_status s = fields_check(c, nrhs, q, P, rp, E);
+  if (s != GDM_OK || P == 0) return s;
+  HIPCHK(c, hipSetDevice(c->device));
+  const int nsplit = fields_num_splits(P, c->N, c->num_cu);
+  const size_t need = fields_scratch_bytes(nrhs, P, nsplit, H != nullptr);
+  if (need > 0) HIPCHK(c, c->scratch.ensure(need));
+  HIPCHK(c, c->flag.ensure(sizeof(int) * 4));
+  return fields_core(c, nrhs, q, P, rp, E, H, c->scratch.p, c->scratch.cap, c->flag.as<int>(), nsplit, true);
+}
+
+gdm_status gdm_fields_noalloc(gdm_ctx* c, int64_t nrhs, const double* q, int64_t P, const double* rp, double* E,
+                              double* H) {
+  if (!c) return GDM_E_ARG;
+  gdm_status s = fields_check(c, nrhs, q, P, rp, E);
+  if (s != GDM_OK || P == 0) return s;
+  void* base = noalloc_scratch(c->device);
+  if (!base) FAIL(c, GDM_E_DEVICE, "no address of the static scratch array on device %d", c->device);
+  HIPCHK(c, hipSetDevice(c->device));
+  const int nsplit = fields_num_splits(P, c->N, c->num_cu);
+  const size_t need = fields_scratch_bytes(nrhs, P, nsplit, H != nullptr);
+  if (need > GDM_NOALLOC_SCRATCH_BYTES - NOALLOC_FLAG_BYTES)
+    FAIL(c, GDM_E_ARG,
+         "gdm_fields_noalloc needs %zu bytes of scratch for %lld RHS x %lld probes (%d dipole splits); the static "
+         "array holds %zu",
+         need, (long long)nrhs, (long long)P, nsplit, (size_t)(GDM_NOALLOC_SCRATCH_BYTES - NOALLOC_FLAG_BYTES));
+  char* b = static_cast<char*>(base);
+  return fields_core(c, nrhs, q, P, rp, E, H, b + NOALLOC_FLAG_BYTES, GDM_NOALLOC_SCRATCH_BYTES - NOALLOC_FLAG_BYTES,
+                     reinterpret_cast<int*>(b), nsplit, false);
 }
 
 gdm_status gdm_cross_sections(gdm_ctx* c, int64_t nrhs, const double* f0, const double* q, const double* f,

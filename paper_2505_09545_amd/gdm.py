@@ -29,7 +29,7 @@ SELF_STATIC, SELF_RADIATIVE = 0, 1
 
 EXPORTED = ["gdm_create", "gdm_destroy", "gdm_last_error", "gdm_set_environment", "gdm_set_structure",
             "gdm_num_unknowns", "gdm_assemble", "gdm_factorize", "gdm_incident_planewave", "gdm_solve",
-            "gdm_planewave", "gdm_fields", "gdm_cross_sections", "gdm_adjoint", "gdm_batch_spectra", "gdm_batch_tuning", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
+            "gdm_planewave", "gdm_fields", "gdm_fields_noalloc", "gdm_cross_sections", "gdm_adjoint", "gdm_batch_spectra", "gdm_batch_tuning", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
             "gdm_profile", "gdm_profile_mask", "gdm_profile_read"]
 
 
@@ -70,6 +70,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gdm_solve": ([P, I64, P, D, I32, P, P, ctypes.POINTER(GDMInfo)], ctypes.c_int),
         "gdm_planewave": ([P, I64, P, P, I64, P, P, P], ctypes.c_int),
         "gdm_fields": ([P, I64, P, I64, P, P, P], ctypes.c_int),
+        "gdm_fields_noalloc": ([P, I64, P, I64, P, P, P], ctypes.c_int),
         "gdm_cross_sections": ([P, I64, P, P, P, P, I32, P], ctypes.c_int),
         "gdm_adjoint": ([P, I64, P, P, P, P, P, P, I64, P, P, D, I32, P, P, P, ctypes.POINTER(GDMInfo)],
                         ctypes.c_int),
@@ -238,6 +239,21 @@ class Context:
         H = torch.empty_like(E) if want_h else None
         self._check(self._call("gdm_fields", self.h, q.shape[0], _ptr(q), len(r), _ptr(r), _ptr(E), _ptr(H)))
         return E, H
+
+    def fields_noalloc(self, q, r_probe, E, H=None):
+        """gdm_fields_noalloc into caller-allocated outputs E (and H), each
+        [n_rhs, P, 3] complex128 on the context's device; allocates nothing on
+        the library side (include/gdm.h)."""
+        for name, t in (("q", q), ("r_probe", r_probe), ("E", E), ("H", H)):
+            if t is not None and (t.device != self.device or not t.is_contiguous()):
+                raise ValueError(f"{name} must be a contiguous tensor on {self.device}")
+        P = r_probe.shape[0]
+        for name, t in (("E", E), ("H", H)):
+            if t is not None and (t.dtype != torch.complex128 or tuple(t.shape) != (q.shape[0], P, 3)):
+                raise ValueError(f"{name} must be complex128 of shape {(q.shape[0], P, 3)}")
+        if q.dtype != torch.complex128 or r_probe.dtype != torch.float64:
+            raise ValueError("q must be complex128 and r_probe float64")
+        self._check(self._call("gdm_fields_noalloc", self.h, q.shape[0], _ptr(q), P, _ptr(r_probe), _ptr(E), _ptr(H)))
 
     def cross_sections(self, f0, q, f, e0_norm2, want_ff=False):
         f0 = self._dev(f0, torch.complex128, None, "f0")
