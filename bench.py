@@ -50,28 +50,140 @@ def lu_solve_flops(n: int, nrhs: int) -> float:
     return 8.0 / 3.0 * n ** 3 + 8.0 * n * n * nrhs
 
 
-def cpu_baseline(sample_cells: int) -> dict:
+PEAK_FP64_VALU = 78.6    # TFLOP/s, MI355X FP64 vector (FMA = 2 flops)
+# Algorithmic FP64 flops of the probe-field sum per (probe, dipole) pair: the
+# 6x6 dyad (distance, one sincos, the radial factors and the 9 complex entries,
+# about 100), then per right-hand side the complex products G^Ep p (9 complex
+# multiply-adds, 72 flops) and h x p (6, 48); an effective dipole adds its
+# magnetic moment's G^Em m (6, 48) and eps G^Ep m (9 plus the scaling, 84).
+FIELD_PAIR_FLOPS = 100.0
+FIELD_RHS_FLOPS_P = 72.0 + 48.0
+FIELD_RHS_FLOPS_M = 48.0 + 84.0
+
+
+def field_flops(n_probe: int, n_cell: int, n_eff: int, nrhs: int) -> float:
+    n_dip = n_cell + n_eff
+    return float(n_probe) * (n_dip * (FIELD_PAIR_FLOPS + nrhs * FIELD_RHS_FLOPS_P) + n_eff * nrhs * FIELD_RHS_FLOPS_M)
+
+
+def cpu_baseline(sample_cells: int, threads: int = 0) -> dict:
     """The FP64 oracle (never tuned) on a bounded sample: the cfg2 recipe (by
     default all 4000 cells, i.e. the timed workload itself), all 66 right-hand
-    sides, assembly + LU + solve + cross sections."""
+    sides, assembly + LU + solve + cross sections.  threads > 0 limits the BLAS
+    threads (threadpoolctl) for the run."""
+    import contextlib
     import gdm_inputs as gi
     from oracle import gdm_oracle as O
+    limit = contextlib.nullcontext()
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("internal_api") in
-                     ("openblas", "mkl", "blis")] or [os.cpu_count() or 1])
+        from threadpoolctl import threadpool_info, threadpool_limits
+        if threads > 0:
+            limit = threadpool_limits(limits=threads, user_api="blas")
     except Exception:
-        cores = os.cpu_count() or 1
+        threadpool_info = None
     w = gi.config2(ncell=sample_cells)
-    t0 = time.perf_counter()
-    s = O.simulate(w)
-    dt = time.perf_counter() - t0
+    with limit:
+        try:
+            cores = max([i.get("num_threads", 1) for i in threadpool_info() if i.get("internal_api") in
+                         ("openblas", "mkl", "blis")] or [os.cpu_count() or 1])
+        except Exception:
+            cores = threads or os.cpu_count() or 1
+        t0 = time.perf_counter()
+        s = O.simulate(w)
+        dt = time.perf_counter() - t0
     n = s["D"].n
     nrhs = len(w["khat"])
     return dict(value=lu_solve_flops(n, nrhs) / dt / 1e12, unit="TFLOP/s", cores=int(cores), kind="oracle",
                 seconds=dt,
                 sample=f"cfg2 recipe with {sample_cells} cells (n={n}, {nrhs} RHS): assembly + LU + solve + "
                        f"cross sections in FP64 NumPy/SciPy")
+
+
+def config1_timing(ctx, gdm, steps: int, warmup: int) -> dict:
+    """The 257-cell sphere (gdm_inputs.config1) in plain FP64: assembly + LU,
+    incident field, solve (2 plane waves), cross sections and the fields at 1000
+    probes, seconds per step (inputs resident on the device)."""
+    import torch
+    import gdm_inputs as gi
+    w = gi.config1()
+    dev = ctx.device
+    rp = torch.as_tensor(w["r_probe"], dtype=torch.float64, device=dev)
+    khat, e0, e2 = gdm.plane_wave_inputs(w, dev)
+    ctx.set_environment(w["n_env"])
+    ctx.set_structure(torch.as_tensor(w["r_cell"]), w["step"], torch.as_tensor(w["eps_cell"]))
+
+    def one():
+        ctx.factorize(w["wavelength"], gdm.PREC_FP64)
+        f0 = ctx.incident_planewave(khat, e0)
+        q, f = ctx.solve(f0)
+        ctx.cross_sections(f0, q, f, e2)
+        ctx.fields(q, rp)
+
+    for _ in range(warmup):
+        one()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one()
+    torch.cuda.synchronize()
+    return {"cfg1_workload": "sphere r 40 nm, 257 cells of 10 nm, eps 12+0.1i, 600 nm, 2 plane waves, 1000 probes; "
+                             "FP64", "cfg1_s_per_step_fp64": (time.perf_counter() - t0) / steps}
+
+
+def config5_timing(gdm) -> dict:
+    """The hybrid workload (gdm_inputs.config5): 3000 cells inside a 100 x 100
+    lattice of effective ED+MD dipoles, n = 69 000, FP32 LU + FP64 refinement,
+    one plane wave, then the scattered E and H at 10^6 probes.  One timed run on
+    a context of its own (its 114 GB of matrices are freed afterwards); stage
+    times with a synchronisation after each, the probe kernel also timed with
+    HIP events on its stream."""
+    import torch
+    import gdm_inputs as gi
+    w = gi.config5()
+    ctx = gdm.Context(0)
+    try:
+        dev = ctx.device
+        ctx.set_environment(w["n_env"])
+        ctx.set_structure(torch.as_tensor(w["r_cell"]), w["step"], torch.as_tensor(w["eps_cell"]),
+                          torch.as_tensor(w["r_eff"]), torch.as_tensor(w["alpha_eff"]))
+        n = ctx.n
+        khat, e0, e2 = gdm.plane_wave_inputs(w, dev)
+        rp = torch.as_tensor(w["r_probe"], dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.factorize(w["wavelength"], gdm.PREC_FP32_IR)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        f0 = ctx.incident_planewave(khat, e0)
+        q, f = ctx.solve(f0, tol=1e-14)
+        cs = ctx.cross_sections(f0, q, f, e2)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        iters, be = int(ctx.info.ir_iters), float(ctx.info.backward_err)
+        ctx.profile(True, tags=["fields"])
+        E, H = ctx.fields(q, rp)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        pf = ctx.profile_read()["fields"]
+        ctx.profile(False)
+        ncell, neff = len(w["r_cell"]), len(w["r_eff"])
+        fl = field_flops(len(rp), ncell, neff, 1)
+        fields_ms = pf["ms"]
+        out_bytes = 2 * len(rp) * 3 * 16  # E and H written once
+        return {"cfg5_workload": f"{ncell} cells (6 nm, eps 6+0.2i) in a 100x100 lattice of {neff} ED+MD dipoles, "
+                                 f"n={n}, 650 nm, 1 plane wave; FP32 LU + FP64 refinement; E and H at "
+                                 f"{len(rp)} probes",
+                "cfg5_n": n, "cfg5_factor_s": t1 - t0, "cfg5_solve_cs_s": t2 - t1, "cfg5_fields_s": t3 - t2,
+                "cfg5_s_total": t3 - t0, "cfg5_ir_iters": iters, "cfg5_backward_err": be,
+                "cfg5_lu_tflops": 8.0 / 3.0 * n ** 3 / (t1 - t0) / 1e12,
+                "cfg5_fields_kernel_ms": fields_ms,
+                "cfg5_fields_tflops": fl / (fields_ms * 1e-3) / 1e12 if fields_ms > 0 else None,
+                "cfg5_fields_frac_fp64_valu": fl / (fields_ms * 1e-3) / 1e12 / PEAK_FP64_VALU if fields_ms > 0 else None,
+                "cfg5_fields_write_GBps": out_bytes / (fields_ms * 1e-3) / 1e9 if fields_ms > 0 else None,
+                "cfg5_ext_nm2": float(cs[0, 0])}
+    finally:
+        ctx.close()
+        torch.cuda.empty_cache()
 
 
 def adjoint_timing(ctx, gdm, steps: int, warmup: int) -> dict:
@@ -123,6 +235,9 @@ def adjoint_timing(ctx, gdm, steps: int, warmup: int) -> dict:
         out[f"adjoint_pair_ms_per_step_{name}"] = pr["adj_pair"]["ms"]
         out[f"adjoint_probe_ms_per_step_{name}"] = pr["adj_probe"]["ms"]
         out[f"adjoint_fields_ms_per_step_{name}"] = pr["fields"]["ms"]
+        if pr["fields"]["ms"] > 0:
+            fl = field_flops(len(rp), len(w["r_cell"]), 0, 1)
+            out[f"adjoint_fields_frac_fp64_valu_{name}"] = fl / (pr["fields"]["ms"] * 1e-3) / 1e12 / PEAK_FP64_VALU
         out[f"adjoint_factor_ms_per_step_{name}"] = (pr["panel"]["ms"] + pr["update"]["ms"] + pr["lookahead"]["ms"] +
                                                     pr["trsm"]["ms"] + pr["perm"]["ms"])
     return out
@@ -132,9 +247,8 @@ def batch_timing(ctx, gdm, runs: int, n_struct: int = 0, n_wl: int = 0) -> dict:
     """The batched spectra workload (gdm_inputs.config3): 32 structures of
     300..3000 cells x 128 wavelengths x 2 polarisations, FP32 LU + 2 FP64
     refinement corrections, in one gdm_batch_spectra call (inputs resident on the
-    device).  Each call is timed whole; on the first call of a context the
-    group configurations are measured on the first real groups of each size
-    class (their results are kept), so that cost is inside the timed run."""
+    device), timed whole after a first call that measures the group
+    configurations (timed separately)."""
     import torch
     import gdm_inputs as gi
     w = gi.config3()
@@ -151,6 +265,15 @@ def batch_timing(ctx, gdm, runs: int, n_struct: int = 0, n_wl: int = 0) -> dict:
     sizes = np.array([3 * len(st["r_cell"]) for st in w["structs"]], dtype=np.float64)
     flops = nw * float(np.sum(8.0 / 3.0 * sizes ** 3 + 8.0 * sizes ** 2 * len(w["khat"])))
     torch.cuda.synchronize()
+    # the group configurations are measured on the first groups of each size
+    # class of a call and kept in the context: a first call over every
+    # structure and the first 32 wavelengths (groups of up to 32 systems, as in
+    # the full call) does that measurement, timed on its own
+    t0 = time.perf_counter()
+    n_tune = min(32, nw)
+    ctx.batch_spectra(r_cells, w["step"], w["wavelengths"][:n_tune], eps[:, :n_tune].contiguous(), khat, e0)
+    torch.cuda.synchronize()
+    tune_s = time.perf_counter() - t0
     best = None
     be = 0.0
     for _ in range(max(runs, 1)):
@@ -164,7 +287,8 @@ def batch_timing(ctx, gdm, runs: int, n_struct: int = 0, n_wl: int = 0) -> dict:
                               f"{int(sizes.max()) // 3} cells, 10 nm) x {nw} wavelengths x 2 polarisations, "
                               f"Drude-Lorentz eps (seed 3); FP32 LU + 2 FP64 corrections",
             "batch_systems": ns * nw, "batch_s": best, "batch_systems_per_s": ns * nw / best,
-            "batch_tflops": flops / best / 1e12, "batch_max_backward_err": be,
+            "batch_tflops": flops / best / 1e12, "batch_frac_fp32_mfma": flops / best / 1e12 / PEAK_FP32_MFMA,
+            "batch_tuning_s": tune_s, "batch_tuning_systems": ns * n_tune, "batch_max_backward_err": be,
             "batch_group_config": {str(k): v for k, v in sorted(ctx.batch_config().items())}}
 
 
@@ -180,6 +304,10 @@ def main() -> int:
     ap.add_argument("--batch-runs", type=int, default=1, help="timed runs of the batched spectra (0: skip)")
     ap.add_argument("--batch-structs", type=int, default=0, help="only the first K structures of the batch (0: all)")
     ap.add_argument("--batch-wavelengths", type=int, default=0, help="only the first L wavelengths (0: all)")
+    ap.add_argument("--no-cfg1", action="store_true", help="skip the 257-cell sphere (config 1) timing")
+    ap.add_argument("--no-cfg5", action="store_true", help="skip the n = 69 000 hybrid workload with 10^6 probes")
+    ap.add_argument("--cpu-1thread-cells", type=int, default=1500,
+                    help="cells of the single-thread oracle sample (0: skip)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after the timed region, run one device copy of this many MiB (a known-size kernel "
                          "for calibrating hardware byte counters)")
@@ -298,6 +426,8 @@ def main() -> int:
     }
     if not args.no_adjoint:
         line.update(adjoint_timing(ctx, gdm, args.steps, args.warmup))
+    if not args.no_cfg1:
+        line.update(config1_timing(ctx, gdm, args.steps, args.warmup))
     if args.batch_runs > 0:
         line.update(batch_timing(ctx, gdm, args.batch_runs, args.batch_structs, args.batch_wavelengths))
     if args.copy_calib_mb > 0:
@@ -311,10 +441,14 @@ def main() -> int:
         torch.mul(src, 1.0, out=dst)  # elementwise copy kernel (16-byte vector loads and stores)
         torch.cuda.synchronize()
         line["copy_calib_bytes"] = nbytes
+    ctx.close()
+    if not args.no_cfg5:
+        line.update(config5_timing(gdm))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample_cells)
+        if args.cpu_1thread_cells > 0:
+            line["cpu_baseline_1thread"] = cpu_baseline(args.cpu_1thread_cells, threads=1)
     print(json.dumps(line), flush=True)
-    ctx.close()
     return 0
 
 

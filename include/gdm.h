@@ -76,6 +76,28 @@ void gdm_destroy(gdm_ctx* ctx);
 /* Message of the last failing call (never NULL; owned by the context). */
 const char* gdm_last_error(const gdm_ctx* ctx);
 
+/* Limit on the device memory this context's buffers may hold (bytes; 0: no
+ * limit, the default).  A call that would need more fails with GDM_E_OOM before
+ * it allocates, as it would when the device itself is full; the batched
+ * spectra size their groups within the limit.  GDM_E_ARG for bytes < 0. */
+gdm_status gdm_set_memory_limit(gdm_ctx* ctx, int64_t bytes);
+/* Device bytes the context's buffers hold now. */
+int64_t gdm_memory_used(const gdm_ctx* ctx);
+
+/* Pivoting of the next LU factorisations of this context (gdm_factorize,
+ * gdm_getrf, gdm_batch_spectra); the paper factors by LU with partial
+ * pivoting (Sec. "Numerical solution").  columns_per_exchange = 1: partial
+ * pivoting, the largest |re| + |im| in each column (compared in FP32), lowest
+ * row on ties -- LAPACK's pivot sequence up to such near-ties; 2, 4 or 8:
+ * tournament pivoting, where the LU panel's workgroups each pick that many
+ * candidate rows for that many columns by partial pivoting on their own rows,
+ * and the pivots are chosen by partial pivoting among all candidates (one
+ * device-wide exchange per that many columns instead of one per column; FP64
+ * factorisations use at most 4); 0: the library default (1).  The factors
+ * satisfy P M = L U either way; the row interchanges may differ.  GDM_E_ARG for
+ * other values. */
+gdm_status gdm_set_pivoting(gdm_ctx* ctx, int32_t columns_per_exchange);
+
 /* Real refractive index of the lossless homogeneous host (Appendix, tg.env
  * EnvHomogeneous3D).  Must be > 0.  Invalidates the factors. */
 gdm_status gdm_set_environment(gdm_ctx* ctx, double n_env);
@@ -105,6 +127,28 @@ gdm_status gdm_assemble(gdm_ctx* ctx, double wavelength_nm, int dtype, void* M_o
  * refinement residual).  Sets the context wavelength.  GDM_E_SINGULAR on an
  * exactly zero pivot (info->bad_index, info may be NULL). */
 gdm_status gdm_factorize(gdm_ctx* ctx, double wavelength_nm, gdm_precision prec, gdm_info* info);
+
+/* Set the context wavelength without factorising (for gdm_incident_planewave,
+ * gdm_fields and gdm_cross_sections ahead of gdm_solve_iterative); factors of
+ * another wavelength are dropped.  GDM_E_STATE without a structure. */
+gdm_status gdm_set_wavelength(gdm_ctx* ctx, double wavelength_nm);
+
+/* Step (b) without the matrix: solve M F = F0 at `wavelength_nm` by restarted
+ * GMRES (restart >= 1; <= 0 selects 30) whose products with M re-evaluate the
+ * dipole couplings from the dyad every time (nothing of size n^2 is stored:
+ * the discrete dipole approximation's iterative route, Sec. "Discrete Dipole
+ * Approximation - iterative solver", for systems past the dense solver's
+ * memory, Sec. "Benchmarks"), right-preconditioned by the inverses of the
+ * diagonal blocks of M over groups of 8 consecutive dipoles.  FP64 throughout.
+ * f0 [n_rhs][n] as in gdm_solve; writes q = A F [n_rhs][n] and, if f_out is not
+ * NULL, F.  Stops when ||F0 - M F||_2 / ||F0||_2 <= tol for every RHS (tol <= 0
+ * selects 1e-13; the residual is recomputed at each restart) or after max_iter
+ * products (max_iter <= 0 selects 1000): GDM_E_NOCONV, the last iterate
+ * written.  info->ir_iters = products with M, info->backward_err = the largest
+ * relative residual.  Sets the context wavelength (for gdm_fields and
+ * gdm_cross_sections); factors of another wavelength are dropped. */
+gdm_status gdm_solve_iterative(gdm_ctx* ctx, double wavelength_nm, int64_t n_rhs, const double* f0, double tol,
+                               int32_t max_iter, int32_t restart, double* q_out, double* f_out, gdm_info* info);
 
 /* Incident plane waves at the dipoles in the unknown layout: f0 [n_pw][n] with
  * E0 = e0 exp(i k khat.r), H0 = n_env khat x E0 (Appendix, 3D illuminations);
@@ -204,7 +248,9 @@ gdm_status gdm_adjoint(gdm_ctx* ctx, int64_t n_rhs, const double* khat, const do
  *   prec GDM_PREC_FP32_IR: FP32 LU and exactly ir_iters FP64 refinement
  *       corrections (ir_iters < 0 selects 2), be_out [n_struct][n_wl] (device,
  *       may be NULL) receives each system's normwise backward error after them;
- *       GDM_PREC_FP64: FP64 LU, be_out not written;
+ *       with tol > 0, GDM_E_NOCONV if any of them exceeds tol (every output is
+ *       still written; tol = 0: no check); GDM_PREC_FP64: FP64 LU, be_out not
+ *       written, tol ignored;
  *   cs_out [n_struct][n_wl][n_pw][3] (device) = (ext, sca = ext - abs, abs) nm^2.
  * info->backward_err = max of be_out, info->ms_factor = GPU time of the whole
  * batch.  GDM_E_OOM if a structure does not fit; GDM_E_SINGULAR on an exactly
@@ -212,7 +258,7 @@ gdm_status gdm_adjoint(gdm_ctx* ctx, int64_t n_rhs, const double* khat, const do
 gdm_status gdm_batch_spectra(gdm_ctx* ctx, int64_t n_struct, const int64_t* cell_offset, const double* r_cell,
                              const double* step_nm, int64_t n_wl, const double* wavelengths, const double* eps,
                              int64_t n_pw, const double* khat, const double* e0, gdm_precision prec, int32_t ir_iters,
-                             gdm_selfterm selfterm, double* cs_out, double* be_out, gdm_info* info);
+                             double tol, gdm_selfterm selfterm, double* cs_out, double* be_out, gdm_info* info);
 
 /* The batch configurations measured so far by gdm_batch_spectra on this context:
  * returns their number; if out is not NULL, writes up to max_entries triples
@@ -244,12 +290,12 @@ gdm_status gdm_sync(gdm_ctx* ctx);
  * clears the counters and starts recording; 0 stops. */
 gdm_status gdm_profile(gdm_ctx* ctx, int enable);
 /* The same for a subset of the tags listed under gdm_profile_read: launches of
- * tag t are timed iff bit t of mask is set (mask 0 stops; 2047 = all).  Timing
+ * tag t are timed iff bit t of mask is set (mask 0 stops; 4095 = all).  Timing
  * only the kernels one needs keeps the events off the critical path of the
  * rest.  GDM_E_ARG for a mask outside [0, 2048). */
 gdm_status gdm_profile_mask(gdm_ctx* ctx, int32_t mask);
 /* Counters accumulated since gdm_profile / gdm_profile_mask, written to the HOST array
- * out (n_out >= 33): out[3 t + 0..2] = (milliseconds, work, launches) for
+ * out (n_out >= 36): out[3 t + 0..2] = (milliseconds, work, launches) for
  * t = 0 LU trailing-update GEMM, bulk part (the columns after the next panel's;
  * work = real flops 8 m n k), 1 LU panel (work =
  * columns), 2 assembly (work = bytes written), 3 block triangular solve of the
@@ -259,7 +305,8 @@ gdm_status gdm_profile_mask(gdm_ctx* ctx, int32_t mask);
  * dipole-pair kernel (work = ordered pairs x n_rhs), 8 adjoint probe kernel
  * (work = probe-dipole pairs x n_rhs), 9 probe fields (work = probe-dipole
  * pairs x n_rhs), 10 LU trailing-update GEMM of the next panel's columns (the
- * look-ahead product; work = real flops). */
+ * look-ahead product; work = real flops), 11 matrix-free product of
+ * gdm_solve_iterative (work = dipole pairs x n_rhs). */
 gdm_status gdm_profile_read(gdm_ctx* ctx, double* out, int32_t n_out);
 
 #ifdef __cplusplus

@@ -15,23 +15,35 @@
 #include "gdm_misc.hpp"
 #include "gdm_adjoint.hpp"
 #include "gdm_batch.hpp"
+#include "gdm_iterative.hpp"
 
 using namespace gdm;
 
 namespace {
 
+// Device bytes held by one context's buffers, and the caller's limit on them
+// (gdm_set_memory_limit; 0: none).
+struct MemAccount {
+  size_t used = 0;
+  size_t limit = 0;
+};
+
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  MemAccount* acct = nullptr;  // the owning context's account (null: not counted)
   hipError_t ensure(size_t bytes) {
     if (bytes <= cap && p) return hipSuccess;
+    if (bytes == 0) bytes = 256;
+    // the limit counts what the context would hold after the call
+    if (acct && acct->limit > 0 && acct->used - cap + bytes > acct->limit) return hipErrorOutOfMemory;
     if (p) {
       hipError_t e = hipFree(p);
       if (e != hipSuccess) return e;
+      if (acct) acct->used -= cap;
       p = nullptr;
       cap = 0;
     }
-    if (bytes == 0) bytes = 256;
     hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) {
       p = nullptr;
@@ -39,10 +51,12 @@ struct DevBuf {
       return e;
     }
     cap = bytes;
+    if (acct) acct->used += cap;
     return hipSuccess;
   }
   void release() {
     if (p) (void)hipFree(p);
+    if (p && acct) acct->used -= cap;
     p = nullptr;
     cap = 0;
   }
@@ -87,6 +101,7 @@ struct gdm_ctx {
   DevBuf X, Rr, C32, small, scratch, flag;
   DevBuf Lam, adj;  // adjoint field and adjoint workspace
   DevBuf part;      // split-k partial sums of the small-RHS refinement residual
+  DevBuf iter;      // workspace of gdm_solve_iterative
   // batched spectra: workspaces and the measured batch configuration per size class
   DevBuf bM64, bM32, bipiv, bws, bvec, bpart, bsmall, bpos, bwl;
   std::map<int64_t, std::pair<int, int>> batch_tune;  // n / 256 -> (items per group, nb)
@@ -96,6 +111,12 @@ struct gdm_ctx {
   Prof prof;
   bool lookahead = true;
   std::vector<hipEvent_t> lu_events;
+  int pivot_pb = 0;  // panel columns per pivot exchange (gdm_set_pivoting; 0: the library default)
+  MemAccount mem;    // device bytes of the buffers below and the caller's limit
+  std::vector<DevBuf*> buffers() {
+    return {&pos, &eps,  &alpha_c, &alpha6, &M,     &M64,  &ipiv,  &luws, &rows,   &ext_ws, &X,   &Rr,   &C32, &small,
+            &scratch, &flag, &Lam,  &adj,   &part, &bM64, &bM32, &bipiv, &bws, &bvec, &bpart, &bsmall, &bpos, &bwl, &iter};
+  }
 };
 
 #define FAIL(ctx, code, ...)                                     \
@@ -155,10 +176,16 @@ static gdm_status check_wavelength(gdm_ctx* c, double wl) {
   return GDM_OK;
 }
 
+// Panel columns per pivot exchange of the next factorisations: the caller's
+// choice (gdm_set_pivoting), else partial pivoting.  Measured at n = 12 000
+// (FP32+IR step, panels beside the look-ahead update): 5.14 us per column with
+// partial pivoting, 7.1-7.9 with tournaments over 2, 4 or 8 columns.
+static int panel_pb(const gdm_ctx* c) { return c->pivot_pb > 0 ? c->pivot_pb : 1; }
+
 template <typename T>
 static gdm_status run_lu(gdm_ctx* c, void* A, int64_t n, int64_t ld, LUPlan& plan, DevBuf& ws, DevBuf& ipiv,
                          int32_t* ipiv_out, gdm_info* info) {
-  plan = lu_plan(n, (int)sizeof(T), c->num_cu, c->lds_bytes);
+  plan = lu_plan(n, (int)sizeof(T), c->num_cu, c->lds_bytes, 1, 128, panel_pb(c));
   const size_t wsb = lu_workspace_bytes(plan, (int)sizeof(T), c->num_cu);
   HIPCHK(c, ws.ensure(wsb));
   LUWork w;
@@ -391,7 +418,7 @@ static bool batch_shape_for(gdm_ctx* c, int64_t n, int B, int nb_max, bool ir, B
   const int eb = ir ? 4 : 8;
   sh.n = n;
   sh.B = B;
-  sh.plan = lu_plan(n, eb, c->num_cu, c->lds_bytes, B, nb_max);
+  sh.plan = lu_plan(n, eb, c->num_cu, c->lds_bytes, B, nb_max, panel_pb(c));
   sh.nb = sh.plan.nb;
   return sh.plan.nb >= 32 && lu_plan_fits(sh.plan) && sh.plan.max_wg * B <= c->num_cu;
 }
@@ -504,8 +531,8 @@ extern "C" int32_t gdm_batch_tuning(const gdm_ctx* c, int32_t* out, int32_t max_
 extern "C" gdm_status gdm_batch_spectra(gdm_ctx* c, int64_t n_struct, const int64_t* cell_offset,
                                         const double* r_cell, const double* step_nm, int64_t n_wl,
                                         const double* wavelengths, const double* eps, int64_t n_pw, const double* khat,
-                                        const double* e0, gdm_precision prec, int32_t ir_iters, gdm_selfterm selfterm,
-                                        double* cs_out, double* be_out, gdm_info* info) {
+                                        const double* e0, gdm_precision prec, int32_t ir_iters, double tol,
+                                        gdm_selfterm selfterm, double* cs_out, double* be_out, gdm_info* info) {
   if (!c) return GDM_E_ARG;
   if (n_struct <= 0 || !cell_offset || !r_cell || !step_nm || n_wl <= 0 || !wavelengths || !eps || n_pw <= 0 ||
       !khat || !e0 || !cs_out)
@@ -526,12 +553,14 @@ extern "C" gdm_status gdm_batch_spectra(gdm_ctx* c, int64_t n_struct, const int6
     if (!(wavelengths[l] > 0.0) || !std::isfinite(wavelengths[l])) FAIL(c, GDM_E_ARG, "wavelengths must be > 0");
   if (ir_iters < 0) ir_iters = 2;
   if (ir_iters > 20) FAIL(c, GDM_E_ARG, "at most 20 refinement corrections");
+  if (!(tol >= 0.0) || !std::isfinite(tol)) FAIL(c, GDM_E_ARG, "tol must be finite and >= 0");
   const bool ir = prec == GDM_PREC_FP32_IR;
   const int radiative = selfterm == GDM_SELF_RADIATIVE ? 1 : 0;
   HIPCHK(c, hipSetDevice(c->device));
   size_t free_b = 0, total_b = 0;
   HIPCHK(c, hipMemGetInfo(&free_b, &total_b));
-  const size_t budget = std::min<size_t>(free_b / 2, (size_t)64 << 30);
+  size_t budget = std::min<size_t>(free_b / 2, (size_t)64 << 30);
+  if (c->mem.limit > 0) budget = std::min(budget, c->mem.limit > c->mem.used ? (c->mem.limit - c->mem.used) / 2 : 0);
 
   // largest feasible group per structure size: panels of all items co-resident,
   // matrices within the memory budget, at most 32 items and n_wl
@@ -718,6 +747,9 @@ extern "C" gdm_status gdm_batch_spectra(gdm_ctx* c, int64_t n_struct, const int6
     if (info) info->bad_index = sticky[1];
     FAIL(c, GDM_E_SINGULAR, "exactly zero pivot in column %d of a batched system", sticky[1]);
   }
+  if (ir && tol > 0.0 && !(be_max <= tol))
+    FAIL(c, GDM_E_NOCONV, "a batched system ends at backward error %.3e > tol %.3e after %d corrections", be_max,
+         tol, ir_iters);
   return GDM_OK;
 }
 
@@ -764,6 +796,7 @@ gdm_status gdm_create(int device, void* hip_stream, gdm_ctx** out) {
   if (hipSetDevice(device) != hipSuccess) return GDM_E_DEVICE;
   gdm_ctx* c = new gdm_ctx();
   c->device = device;
+  for (DevBuf* b : c->buffers()) b->acct = &c->mem;
   hipDeviceProp_t prop;
   if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
     c->num_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
@@ -795,10 +828,7 @@ void gdm_destroy(gdm_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  for (DevBuf* b : {&c->pos, &c->eps, &c->alpha_c, &c->alpha6, &c->M, &c->M64, &c->ipiv, &c->luws, &c->rows,
-                    &c->ext_ws, &c->X, &c->Rr, &c->C32, &c->small, &c->scratch, &c->flag, &c->Lam, &c->adj, &c->part, &c->bM64, &c->bM32, &c->bipiv,
-                    &c->bws, &c->bvec, &c->bpart, &c->bsmall, &c->bpos, &c->bwl})
-    b->release();
+  for (DevBuf* b : c->buffers()) b->release();
   for (auto& e : c->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& e : c->sev)
@@ -817,6 +847,24 @@ const char* gdm_last_error(const gdm_ctx* c) { return c ? c->err.c_str() : "null
 gdm_status gdm_sync(gdm_ctx* c) {
   if (!c) return GDM_E_ARG;
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return GDM_OK;
+}
+
+gdm_status gdm_set_memory_limit(gdm_ctx* c, int64_t bytes) {
+  if (!c) return GDM_E_ARG;
+  if (bytes < 0) FAIL(c, GDM_E_ARG, "memory limit must be >= 0 (got %lld)", (long long)bytes);
+  c->mem.limit = (size_t)bytes;
+  return GDM_OK;
+}
+
+int64_t gdm_memory_used(const gdm_ctx* c) { return c ? (int64_t)c->mem.used : 0; }
+
+gdm_status gdm_set_pivoting(gdm_ctx* c, int32_t columns_per_exchange) {
+  if (!c) return GDM_E_ARG;
+  const int v = columns_per_exchange;
+  if (v != 0 && v != 1 && v != 2 && v != 4 && v != 8)
+    FAIL(c, GDM_E_ARG, "columns per pivot exchange must be 0, 1, 2, 4 or 8 (got %d)", v);
+  c->pivot_pb = v;
   return GDM_OK;
 }
 
@@ -933,6 +981,63 @@ gdm_status gdm_factorize(gdm_ctx* c, double wl, gdm_precision prec, gdm_info* in
   c->prec = prec;
   c->M1 = -1.0;
   c->factored = true;
+  return GDM_OK;
+}
+
+gdm_status gdm_set_wavelength(gdm_ctx* c, double wl) {
+  if (!c) return GDM_E_ARG;
+  gdm_status s = check_wavelength(c, wl);
+  if (s != GDM_OK) return s;
+  if (wl != c->wavelength) c->factored = false;
+  c->wavelength = wl;
+  return GDM_OK;
+}
+
+gdm_status gdm_solve_iterative(gdm_ctx* c, double wl, int64_t nrhs, const double* f0, double tol, int32_t max_iter,
+                               int32_t restart, double* q_out, double* f_out, gdm_info* info) {
+  if (!c) return GDM_E_ARG;
+  gdm_status s = check_wavelength(c, wl);
+  if (s != GDM_OK) return s;
+  if (nrhs <= 0 || !f0 || !q_out) FAIL(c, GDM_E_ARG, "need n_rhs > 0, f0 and q_out");
+  if (nrhs > 65535) FAIL(c, GDM_E_ARG, "at most 65535 right-hand sides per call");
+  if (restart <= 0) restart = 30;
+  if (restart > 1000) FAIL(c, GDM_E_ARG, "restart must be <= 1000");
+  if (max_iter <= 0) max_iter = 1000;
+  if (!(tol > 0.0)) tol = 1e-13;
+  HIPCHK(c, hipSetDevice(c->device));
+  if ((s = prepare_alpha(c)) != GDM_OK) return s;
+  if (wl != c->wavelength) c->factored = false;
+  c->wavelength = wl;
+  const int64_t n = c->n;
+  const Wave w = wave_of(c, wl);
+  const DipoleView d = view_of(c, self_term(c, w));
+  HIPCHK(c, c->iter.ensure(iter_workspace_bytes(c->N, n, nrhs, restart, c->num_cu)));
+  HIPCHK(c, c->X.ensure(sizeof(double2) * n * nrhs));
+  IterWork iw;
+  iter_workspace_carve(c->iter.p, c->N, n, nrhs, restart, c->num_cu, iw);
+  double2* X = c->X.as<double2>();
+  HIPCHK(c, hipEventRecord(c->ev[0], c->stream));
+  GmresStats gs;
+  HIPCHK(c, gmres_solve(d, w, iw, n, nrhs, reinterpret_cast<const double2*>(f0), X, tol, max_iter, restart, c->stream,
+                        gs, &c->prof));
+  HIPCHK(c, launch_apply_alpha(view_of(c, make_double2(0, 0)), X, n, reinterpret_cast<double2*>(q_out), n, nrhs,
+                               c->stream));
+  if (f_out) HIPCHK(c, launch_copy_d(X, n, reinterpret_cast<double2*>(f_out), n, n, nrhs, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev[3], c->stream));
+  HIPCHK(c, hipEventSynchronize(c->ev[3]));
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[3]);
+  c->prof.collect();
+  if (info) {
+    info->ir_iters = gs.iters;
+    info->backward_err = gs.relres;
+    info->bad_index = -1;
+    info->ms_solve = ms;
+    info->ms_ir = 0.f;
+  }
+  if (!(gs.relres <= tol))
+    FAIL(c, GDM_E_NOCONV, "GMRES stopped after %d products at relative residual %.3e > tol %.3e", gs.iters, gs.relres,
+         tol);
   return GDM_OK;
 }
 

@@ -43,59 +43,13 @@ __device__ inline void assemble_strip(const DipoleView& d, const Wave& w, double
   const int f = s < N ? 0 : 1;                    // field type of the row slot: E or H
   const int64_t dr = f == 0 ? s : nc + (s - N);   // row dipole
   double2 v[NC][3];  // v[column][row a] of this thread's block
-#pragma unroll
-  for (int c = 0; c < NC; ++c)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) v[c][a] = make_double2(0.0, 0.0);
   if (live) {
-    if (dr == j) {
-      // diagonal block I - S alpha (cells: scalar S^Ep and alpha; effective: S = 0)
-      if (!EFF) {
-        const double2 dg = csub(make_double2(1.0, 0.0), cmul(d.self_c, d.alpha_c[j]));
+    m_block<EFF>(d, w, dr, f, j, v);
+  } else {
 #pragma unroll
-        for (int a = 0; a < 3; ++a) v[a][a] = dg;
-      } else {
+    for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          v[a][a] = make_double2(f == 0 ? 1.0 : 0.0, 0.0);
-          v[(3 + a) % NC][a] = make_double2(f == 1 ? 1.0 : 0.0, 0.0);
-        }
-      }
-    } else {
-      const double Rx = d.pos[3 * dr + 0] - d.pos[3 * j + 0];
-      const double Ry = d.pos[3 * dr + 1] - d.pos[3 * j + 1];
-      const double Rz = d.pos[3 * dr + 2] - d.pos[3 * j + 2];
-      Green g;
-      green_eh(Rx, Ry, Rz, w, f == 1 || EFF, g);
-      if (!EFF) {
-        // -G^{f p} alpha_j : 3 x 3
-        const double2 al = d.alpha_c[j];
-        const double2 ma = make_double2(-al.x, -al.y);
-#pragma unroll
-        for (int c = 0; c < 3; ++c)
-#pragma unroll
-          for (int a = 0; a < 3; ++a) v[c][a] = cmul(f == 0 ? gep(g, a, c) : ghp(g, a, c), ma);
-      } else {
-        // -[G^{f p} G^{f m}] alpha6_j : 3 x 6
-        const double2* al = d.alpha6 + (j - nc) * 36;
-        double2 gr[3][6];
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-#pragma unroll
-          for (int b = 0; b < 6; ++b) gr[a][b] = f == 0 ? g6(g, w.eps_env, a, b) : g6(g, w.eps_env, 3 + a, b);
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-#pragma unroll
-          for (int b = 0; b < 6; ++b) {
-            const double2 ab = al[b * 6 + c];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) cfma(v[c][a], gr[a][b], ab);
-          }
-#pragma unroll
-          for (int a = 0; a < 3; ++a) v[c][a] = make_double2(-v[c][a].x, -v[c][a].y);
-        }
-      }
-    }
+      for (int a = 0; a < 3; ++a) v[c][a] = make_double2(0.0, 0.0);
   }
   // write the strip column by column through LDS (coalesced stores)
   const int64_t row0 = 3 * s0;

@@ -1,6 +1,7 @@
 // Host-side launch declarations shared by the kernel files and the C-ABI layer.
 #pragma once
 #include <hip/hip_runtime.h>
+#include "gdm_common.hpp"
 #include <cstdint>
 #include <vector>
 
@@ -14,6 +15,70 @@ struct DipoleView {
   int64_t N, nc, ne;
   double2 self_c;          // S^Ep of a cell (times I3)
 };
+
+// The 3 x NC block of M = I - G~ A at row dipole dr (field f: 0 electric, 1
+// magnetic) and column dipole j (NC = 3 columns for a cell, 6 for an effective
+// dipole: its electric then magnetic columns): v[column][row].  Diagonal blocks
+// I - S alpha (cells) or the identity rows (effective dipoles, S = 0);
+// off-diagonal blocks -G^{f.}(r_dr - r_j) alpha_j.  FP64, one sincos.
+template <bool EFF>
+__device__ inline void m_block(const DipoleView& d, const Wave& w, int64_t dr, int f, int64_t j,
+                               double2 (&v)[EFF ? 6 : 3][3]) {
+  constexpr int NC = EFF ? 6 : 3;
+  const int64_t nc = d.nc;
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) v[c][a] = make_double2(0.0, 0.0);
+  if (dr == j) {
+    // diagonal block I - S alpha (cells: scalar S^Ep and alpha; effective: S = 0)
+    if (!EFF) {
+      const double2 dg = csub(make_double2(1.0, 0.0), cmul(d.self_c, d.alpha_c[j]));
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v[a][a] = dg;
+    } else {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        v[a][a] = make_double2(f == 0 ? 1.0 : 0.0, 0.0);
+        v[(3 + a) % NC][a] = make_double2(f == 1 ? 1.0 : 0.0, 0.0);
+      }
+    }
+    return;
+  }
+  const double Rx = d.pos[3 * dr + 0] - d.pos[3 * j + 0];
+  const double Ry = d.pos[3 * dr + 1] - d.pos[3 * j + 1];
+  const double Rz = d.pos[3 * dr + 2] - d.pos[3 * j + 2];
+  Green g;
+  green_eh(Rx, Ry, Rz, w, f == 1 || EFF, g);
+  if (!EFF) {
+    // -G^{f p} alpha_j : 3 x 3
+    const double2 al = d.alpha_c[j];
+    const double2 ma = make_double2(-al.x, -al.y);
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v[c][a] = cmul(f == 0 ? gep(g, a, c) : ghp(g, a, c), ma);
+  } else {
+    // -[G^{f p} G^{f m}] alpha6_j : 3 x 6
+    const double2* al = d.alpha6 + (j - nc) * 36;
+    double2 gr[3][6];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 6; ++b) gr[a][b] = f == 0 ? g6(g, w.eps_env, a, b) : g6(g, w.eps_env, 3 + a, b);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+#pragma unroll
+      for (int b = 0; b < 6; ++b) {
+        const double2 ab = al[b * 6 + c];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) cfma(v[c][a], gr[a][b], ab);
+      }
+#pragma unroll
+      for (int a = 0; a < 3; ++a) v[c][a] = make_double2(-v[c][a].x, -v[c][a].y);
+    }
+  }
+}
 
 template <typename T>
 hipError_t launch_assemble(const DipoleView& d, const struct Wave& w, void* M, int64_t ld, hipStream_t st);
@@ -96,7 +161,8 @@ enum ProfTag {
   PROF_ADJ_PROBE = 8,
   PROF_FIELDS = 9,
   PROF_LOOKAHEAD = 10,
-  PROF_NTAGS = 11
+  PROF_ITER_MATVEC = 11,
+  PROF_NTAGS = 12
 };
 struct Prof {
   uint32_t mask = 0;  // bit t: record launches of tag t
@@ -130,6 +196,7 @@ struct LUPlan {
   int64_t n = 0;
   int nb = 0;
   int max_wg = 0;  // number of CUs: upper bound on panel workgroups
+  int pb = 1;      // panel columns per pivot exchange (1: partial pivoting; 2, 4, 8: tournament)
   std::vector<LUBlock> blocks;
 };
 
@@ -137,9 +204,12 @@ struct LUPlan {
 // batch of nbatch items every per-item field below holds nbatch copies, item z
 // at field + z * s_field (elements of the field's type).
 struct LUWork {
-  unsigned long long* cand;  // [2][gmax][KEY_STRIDE] epoch-tagged pivot keys (value, row)
-  unsigned long long* rows;  // [2][gmax][wwmax] epoch-tagged candidate rows
-  int gmax;                  // max panel workgroups (all items together)
+  unsigned long long* cand;  // [2][gitem][max(KEY_STRIDE, pb (1 + pb words per complex))] epoch-tagged
+                             // pivot keys / candidate records
+  unsigned long long* rows;  // [2][gitem][pb][wwmax] epoch-tagged candidate rows
+  int gmax;                  // number of CUs (max panel workgroups of all items together)
+  int gitem;                 // max panel workgroups of one item (the plan's max_wg)
+  int pb;                    // panel columns per pivot exchange the buffers are sized for
   int wwmax;                 // payload words per row (nb * words per complex)
   int32_t* err;              // [2] (shared): exchange timeout flag, first zero pivot (INT32_MAX if none)
   int32_t* pairs;            // [nblocks][2][2 nb]: destination rows then source rows
@@ -155,7 +225,10 @@ struct LUWork {
 
 // nbatch: number of same-size items factored together (their panels share one
 // launch, so each panel gets at most num_cu / nbatch workgroups).
-LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch = 1, int nb_max = 128);
+// pb: panel columns per pivot exchange (1: partial pivoting with LAPACK's
+// pivots; 2, 4 or 8: tournament pivoting, reduced when the candidates of the
+// widest panel would exceed 1024 or its rows would not fit the LDS).
+LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch = 1, int nb_max = 128, int pb = 1);
 // one-time host-side kernel settings for a plan (call before graph capture)
 template <typename T>
 hipError_t lu_prepare(const LUPlan& plan);

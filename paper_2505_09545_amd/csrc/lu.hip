@@ -25,7 +25,10 @@
 // 0-based global row indices (LAPACK semantics otherwise).
 #include <algorithm>
 #include <climits>
+#include <map>
+#include <mutex>
 #include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "gdm_common.hpp"
@@ -137,6 +140,66 @@ __device__ inline void ll_get_n(const u64* const (&p)[K], uint32_t epoch, uint32
   }
 #pragma unroll
   for (int i = 0; i < K; ++i) out[i] = (uint32_t)v[i];
+}
+
+// f(0), f(1), ..., f(N - 1) with compile-time indices (expanded whatever the
+// unroller decides, so register arrays indexed by them stay in registers)
+template <typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F& f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+// CPT records of KW consecutive words each (record u at base[u]), returned once
+// every word carries `epoch`; all loads in flight together.  While some word is
+// stale every word is loaded again (a word that already carries the epoch keeps
+// it until this reader is done, so reloading it is harmless).
+template <int KW, int CPT>
+__device__ inline void ll_get_rec(const u64* const (&base)[CPT], uint32_t epoch, uint32_t (&out)[CPT * KW], int* bad) {
+  u64 v[CPT * KW];
+  auto load_all = [&]() {
+    static_for<CPT * KW>([&](auto i) {
+      v[i] = __hip_atomic_load(base[i / KW] + i % KW, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    });
+  };
+  load_all();
+  uint32_t it = 0;
+  while (true) {
+    bool all = true;
+    static_for<CPT * KW>([&](auto i) { all = all && (uint32_t)(v[i] >> 32) == epoch; });
+    if (all) break;
+    if (++it > SPIN_LIMIT) {
+      *bad = 1;
+      break;
+    }
+    load_all();
+  }
+  static_for<CPT * KW>([&](auto i) { out[i] = (uint32_t)v[i]; });
+}
+
+// K words at p[i] (any addresses), as ll_get_rec.
+template <int K>
+__device__ inline void ll_get_sel(const u64* const (&p)[K], uint32_t epoch, uint32_t (&out)[K], int* bad) {
+  u64 v[K];
+  auto load_all = [&]() {
+    static_for<K>([&](auto i) { v[i] = __hip_atomic_load(p[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); });
+  };
+  load_all();
+  uint32_t it = 0;
+  while (true) {
+    bool all = true;
+    static_for<K>([&](auto i) { all = all && (uint32_t)(v[i] >> 32) == epoch; });
+    if (all) break;
+    if (++it > SPIN_LIMIT) {
+      *bad = 1;
+      break;
+    }
+    load_all();
+  }
+  static_for<K>([&](auto i) { out[i] = (uint32_t)v[i]; });
 }
 
 // complex values travel as their 32-bit words (2 for complex float, 4 for
@@ -283,8 +346,8 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
     const int64_t gj = k0 + j;
     const uint32_t E = epoch0 + (uint32_t)j;
     const int par = j & 1;
-    u64* cand = ws.cand + (size_t)par * ws.gmax * KEY_STRIDE;
-    u64* rows = ws.rows + (size_t)par * ws.gmax * ws.wwmax;
+    u64* cand = ws.cand + (size_t)par * ws.gitem * KEY_STRIDE;
+    u64* rows = ws.rows + (size_t)par * ws.gitem * ws.wwmax;
     // workgroup candidate over its active rows (labels >= gj); column j is final
     block_argmax(best, brow, skey1, sidx1);
     const u64 mybest = best;
@@ -415,6 +478,652 @@ __global__ void __launch_bounds__(256) panel_kernel(cplx<T>* __restrict__ A, int
   if (g == 0) {
     for (int j = tid; j < w; j += 256) ipiv[k0 + j] = pl[j];
     if (tid == 0 && zero_col >= 0) atomicMin(&ws.err[1], (int)(k0 + zero_col));
+  }
+  for (int lr = tid; lr < myR; lr += 256) {
+    const int32_t orig = (int32_t)(rbase + lr);
+    if (lab[lr] != orig) {
+      const int slot = __hip_atomic_fetch_add(mcount, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (slot < mcap) {
+        mdst[slot] = lab[lr];
+        msrc[slot] = orig;
+      }
+    }
+  }
+  for (int lr = tid; lr < myR; lr += 256) {
+    CT* dst = A + lab[lr] + k0 * ld;
+    for (int c0 = 0; c0 < wfull; c0 += LB) {
+      CT v[LB];
+#pragma unroll
+      for (int u = 0; u < LB; ++u) v[u] = tile[(c0 + u) * R + lr];
+#pragma unroll
+      for (int u = 0; u < LB; ++u) dst[(c0 + u) * ld] = v[u];
+    }
+    for (int c = wfull; c < w; ++c) dst[c * ld] = tile[c * R + lr];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// 1b. panel factorisation with tournament pivoting: one exchange per PB columns
+// ---------------------------------------------------------------------------
+// The columns of the panel are taken in inner steps of PB.  For the step's
+// columns [j0, j0 + pw) the pivots are chosen by a tournament of partial
+// pivotings, each on the original values of its candidates:
+//   * every row workgroup picks up to PB candidate rows among its active rows
+//     (one wave, partial pivoting on the step's columns) and publishes them:
+//     their labels and step values, and their remaining columns;
+//   * root workgroups (one per TP_ROOT_SPAN row workgroups, launched after
+//     them) hold one candidate per thread; each wave picks PB among its 64,
+//     then one wave PB among the 4 PB winners, and the root publishes them;
+//   * every row workgroup reads the roots' winners (one per lane of one wave)
+//     and picks the step's PB pivots among them.  The arithmetic is identical
+//     everywhere, so all row workgroups agree on the pivots and on the factored
+//     PB x PB pivot block (L11 strictly below the diagonal, U11 on and above).
+// Then the U rows of the step (a pivot row's remaining columns, fetched from
+// its owner, minus L11 times the earlier U rows) and, for every other active
+// row, the multipliers l = a U11^-1 and the rank-pw update of its remaining
+// columns: the next step's columns first (they decide its candidates), the
+// candidates' remaining columns next (they are published), the rest after the
+// publication, while the roots work.
+// This is the tree form of communication-avoiding LU (tournament pivoting);
+// with PB = 1 it would be plain partial pivoting, which panel_kernel
+// implements.  Pivot keys and ties follow panel_kernel (largest |re| + |im| in
+// FP32, lowest label); rows never move between workgroups, and interchanges
+// swap labels.
+//
+// Exchange buffers (per batch item, double-buffered by the parity of the inner
+// step; every 32-bit payload travels in an epoch-tagged 64-bit word):
+//   records ws.cand [2][gitem][PB][K], K = 1 + PB NW: label, PB step values
+//     (label 0xffffffff: no candidate);
+//   root results after them, [2][ceil(gitem / TP_ROOT_SPAN)][PB][KR],
+//     KR = 2 + PB NW: candidate index (workgroup PB + slot, 0xffffffff: none),
+//     label, PB step values;
+//   rows ws.rows [2][gitem][PB][wwmax]: a candidate's columns after the step.
+constexpr int TP_ROOT_SPAN = 32;
+
+template <typename CT>
+__device__ inline CT rdlane(CT v, int l) {
+  if constexpr (sizeof(CT) == 8) {
+    CT r;
+    r.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.x), l));
+    r.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v.y), l));
+    return r;
+  } else {
+    auto rd = [&](double d) {
+      const long long b = __double_as_longlong(d);
+      const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+      const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+      return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+    };
+    CT r;
+    r.x = rd(v.x);
+    r.y = rd(v.y);
+    return r;
+  }
+}
+
+// One step of partial pivoting inside a wave over the candidates its lanes hold
+// (RL per lane: values v[r][0..PB), labels lab[r], live flags alive[r]): the
+// live candidate with the largest |re| + |im| in column c (lowest label on ties)
+// is chosen; its values pv (multipliers of the earlier steps before column c,
+// its U row from c on) reach every lane; every other live candidate is
+// eliminated.  wl / wsl: lane and slot of the chosen one (wave-uniform); inv:
+// 1 / pv[c] (0 for a zero pivot).  Returns false if no live candidate is left.
+template <typename CT, int PB, int RL>
+__device__ __forceinline__ bool wave_pivot_step(int c, int pw, CT (&v)[RL][PB], const uint32_t (&lab)[RL], bool (&alive)[RL],
+                                       CT (&pv)[PB], CT& inv, int& wl, int& wsl) {
+  const int lane = threadIdx.x & 63;
+  u64 best = 0;
+  int bs = 0;
+#pragma unroll
+  for (int r = 0; r < RL; ++r)
+    if (alive[r]) {
+      const u64 k = pivot_key(v[r][c], lab[r]);
+      if (k > best) {
+        best = k;
+        bs = r;
+      }
+    }
+  const u64 wb = wave_max_u64(best);
+  if (wb == 0) return false;
+  const unsigned long long m = __ballot(best == wb);  // one lane: keys are unique
+  wl = __builtin_amdgcn_readfirstlane(__ffsll((unsigned long long)m) - 1);
+  wsl = __builtin_amdgcn_readlane(bs, wl);
+  // the lane's chosen slot by register selects (the empty asm keeps the
+  // compiler from turning the select chain into an indexed load from a stack
+  // copy of v)
+  CT mine[PB];
+#pragma unroll
+  for (int cc = 0; cc < PB; ++cc) {
+    mine[cc] = v[0][cc];
+#pragma unroll
+    for (int r = 1; r < RL; ++r) {
+      CT t = v[r][cc];
+      asm volatile("" : "+v"(t.x), "+v"(t.y));
+      mine[cc].x = bs == r ? t.x : mine[cc].x;
+      mine[cc].y = bs == r ? t.y : mine[cc].y;
+    }
+  }
+#pragma unroll
+  for (int cc = 0; cc < PB; ++cc) pv[cc] = rdlane(mine[cc], wl);
+  if (lane == wl)
+#pragma unroll
+    for (int r = 0; r < RL; ++r)
+      if (r == bs) alive[r] = false;
+  if (pv[c].x == 0 && pv[c].y == 0) {
+    inv.x = 0;
+    inv.y = 0;
+  } else {
+    inv = cinv_t(pv[c]);
+  }
+#pragma unroll
+  for (int r = 0; r < RL; ++r)
+    if (alive[r]) {
+      const CT l = cmul_t(v[r][c], inv);
+      v[r][c] = l;
+#pragma unroll
+      for (int cc = 0; cc < PB; ++cc)
+        if (cc > c && cc < pw) v[r][cc] = r1_upd(v[r][cc], l, pv[cc]);
+    }
+  return true;
+}
+
+template <typename T, int PB>
+__global__ void __launch_bounds__(256) panel_tp_kernel(cplx<T>* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
+                                                        int w, int R, int G, int32_t* __restrict__ ipiv, LUWork ws,
+                                                        uint32_t epoch0, int64_t sA, int64_t sipiv,
+                                                        int32_t* __restrict__ mdst, int32_t* __restrict__ msrc,
+                                                        int32_t* __restrict__ mcount, int mcap) {
+  using CT = cplx<T>;
+  constexpr int NW = sizeof(CT) / 4;
+  constexpr int K = 1 + PB * NW;   // words of a candidate record
+  constexpr int KR = 2 + PB * NW;  // words of a root's winner
+  A += (int64_t)blockIdx.y * sA;
+  ipiv += (int64_t)blockIdx.y * sipiv;
+  ws.cand += (int64_t)blockIdx.y * ws.s_cand;
+  ws.rows += (int64_t)blockIdx.y * ws.s_rows;
+  mdst += (int64_t)blockIdx.y * ws.s_pairs;
+  msrc += (int64_t)blockIdx.y * ws.s_pairs;
+  mcount += (int64_t)blockIdx.y * ws.s_npairs;
+  const int g = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // an earlier panel's exchange failed (flag set before this launch): the
+  // factorisation is lost, so do not wait out another exchange
+  if (__hip_atomic_load(&ws.err[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+  const int NR = (G + TP_ROOT_SPAN - 1) / TP_ROOT_SPAN;
+  const int nrmax = (ws.gitem + TP_ROOT_SPAN - 1) / TP_ROOT_SPAN;
+  const size_t rec_par = (size_t)ws.gitem * PB * K;
+  u64* const res_all = ws.cand + 2 * rec_par;
+  const size_t res_par = (size_t)nrmax * PB * KR;
+  const int nsteps = (w + PB - 1) / PB;
+  __shared__ int bad;
+  if (tid == 0) bad = 0;
+
+  // ------------------------------------------------------------------ roots
+  if (g >= G) {
+    __shared__ uint32_t l1ci[4][PB], l1lab[4][PB];
+    __shared__ CT l1v[4][PB][PB];
+    const int r = g - G;
+    const int cg = r * TP_ROOT_SPAN + tid / PB, cs = tid % PB;
+    const bool have = tid < TP_ROOT_SPAN * PB && cg < G;
+    __syncthreads();
+    for (int s = 0; s < nsteps; ++s) {
+      const int j0 = s * PB, pw = w - j0 < PB ? w - j0 : PB;
+      const uint32_t E = epoch0 + (uint32_t)s;
+      const int par = s & 1;
+      const u64* rec = ws.cand + par * rec_par;
+      const u64* base[1] = {rec + (size_t)(have ? cg * PB + cs : 0) * K};  // record 0 is always published
+      uint32_t wd[K];
+      ll_get_rec<K, 1>(base, E, wd, &bad);
+      CT v[1][PB], v0[PB];
+      uint32_t lb[1] = {wd[0]};
+      bool al[1] = {have && wd[0] != 0xffffffffu};
+#pragma unroll
+      for (int c = 0; c < PB; ++c) {
+        uint32_t* d = reinterpret_cast<uint32_t*>(&v0[c]);
+#pragma unroll
+        for (int q = 0; q < NW; ++q) d[q] = wd[1 + c * NW + q];
+        v[0][c] = v0[c];
+      }
+      // level 1: PB winners of each wave, with their original values
+      bool more = true;
+#pragma unroll
+      for (int c = 0; c < PB; ++c) {
+        CT pv[PB], inv;
+        int wl = 0, wsl = 0;
+        if (c < pw && more) more = wave_pivot_step<CT, PB, 1>(c, pw, v, lb, al, pv, inv, wl, wsl);
+        if (c < pw && more) {
+          if (lane == wl) {
+            l1ci[wv][c] = (uint32_t)(cg * PB + cs);
+            l1lab[wv][c] = lb[0];
+#pragma unroll
+            for (int cc = 0; cc < PB; ++cc) l1v[wv][c][cc] = v0[cc];
+          }
+        } else if (lane == 0) {
+          l1ci[wv][c] = 0xffffffffu;
+        }
+      }
+      __syncthreads();
+      // level 2 (wave 0): PB winners among the 4 PB, published with their original values
+      if (wv == 0) {
+        const int sw = lane / PB, sc = lane % PB;
+        const bool in = lane < 4 * PB;
+        uint32_t ci2 = in ? l1ci[sw][sc] : 0xffffffffu;
+        uint32_t lb2[1] = {in ? l1lab[sw][sc] : 0u};
+        bool al2[1] = {ci2 != 0xffffffffu};
+        CT u0[PB], u[1][PB];
+#pragma unroll
+        for (int cc = 0; cc < PB; ++cc) {
+          if (in) {
+            u0[cc] = l1v[sw][sc][cc];
+          } else {
+            u0[cc].x = 0;
+            u0[cc].y = 0;
+          }
+          u[0][cc] = u0[cc];
+        }
+        u64* res = res_all + par * res_par + (size_t)r * PB * KR;
+        bool more2 = true;
+#pragma unroll
+        for (int c = 0; c < PB; ++c) {
+          CT pv[PB], inv;
+          int wl = 0, wsl = 0;
+          if (c < pw && more2) more2 = wave_pivot_step<CT, PB, 1>(c, pw, u, lb2, al2, pv, inv, wl, wsl);
+          const bool got = c < pw && more2;
+          // the winner's lane (lane 0 for an empty slot) writes the slot's KR words
+          if ((got && lane == wl) || (!got && lane == 0)) {
+            u64* o = res + (size_t)c * KR;
+            ll_put(&o[0], E, got ? ci2 : 0xffffffffu);
+            ll_put(&o[1], E, got ? lb2[0] : 0u);
+#pragma unroll
+            for (int cc = 0; cc < PB; ++cc)
+#pragma unroll
+              for (int q = 0; q < NW; ++q) ll_put(&o[2 + cc * NW + q], E, got ? cword(u0[cc], q) : 0u);
+          }
+        }
+      }
+      __syncthreads();  // the level-1 slots are rewritten next step
+      if (bad) break;
+    }
+    if (bad && tid == 0) __hip_atomic_store(&ws.err[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return;
+  }
+
+  // ------------------------------------------------------------ row workgroups
+  extern __shared__ unsigned char smem_raw[];
+  CT* tile = reinterpret_cast<CT*>(smem_raw);                        // [w][R], column c at tile + c R
+  CT* prow = tile + (size_t)w * R;                                   // [PB][w] U rows of the step
+  CT* sel = prow + (size_t)PB * w;                                   // [PB][R] scratch of the local choice (R > 256)
+  int32_t* lab = reinterpret_cast<int32_t*>(sel + (size_t)PB * R);  // [R] row labels (final positions)
+  int32_t* pl = lab + R;                                             // [w] pivot positions of this panel
+  __shared__ CT blk[PB][PB];  // factored pivot block of the step
+  __shared__ CT binv[PB];     // 1 / U11[c][c] (0 for a zero pivot)
+  __shared__ int pci[PB];     // candidate index (workgroup PB + slot) of pivot c
+  __shared__ int32_t plab[PB];  // label of pivot c's row when the step starts
+  __shared__ int chosen[PB];  // local rows offered as candidates
+  __shared__ int nch;
+  __shared__ int zcol;        // first zero pivot column of this panel (-1: none)
+  const int64_t rbase = k0 + (int64_t)g * R;
+  const int myR = (int)(n - rbase < (int64_t)R ? (n - rbase > 0 ? n - rbase : 0) : R);
+  if (tid == 0) zcol = -1;
+  constexpr int LB = 128 / (int)sizeof(CT);
+  const int wfull = w - w % LB;
+  for (int lr = tid; lr < myR; lr += 256) {
+    const CT* src = A + (rbase + lr) + k0 * ld;
+    for (int c0 = 0; c0 < wfull; c0 += LB) {
+      CT v[LB];
+#pragma unroll
+      for (int u = 0; u < LB; ++u) v[u] = src[(c0 + u) * ld];
+#pragma unroll
+      for (int u = 0; u < LB; ++u) tile[(c0 + u) * R + lr] = v[u];
+    }
+    for (int c = wfull; c < w; ++c) tile[c * R + lr] = src[c * ld];
+  }
+  for (int lr = tid; lr < myR; lr += 256) lab[lr] = (int32_t)(rbase + lr);
+  // 2D mapping of the bulk update: RP rows x CG column groups
+  int RP = 1;
+  while (RP < myR && RP < 256) RP <<= 1;
+  const int CG = 256 / RP;
+  const int ulr0 = tid & (RP - 1), ucg = tid / RP;
+  __syncthreads();
+
+  // Local choice (wave 0): partial pivoting on columns [j1, j1 + pw1) of the
+  // active rows (labels >= k0 + j1).  Up to 128 rows the lanes keep their rows
+  // (lane, lane + 64) in registers; beyond that, in the LDS scratch.
+  // Writes chosen[] and nch.
+  auto local_choice = [&](int j1, int pw1) {
+    if (wv != 0) return;
+    const int32_t gj1 = (int32_t)(k0 + j1);
+    int cnt = 0;
+    if (myR <= 128) {
+      constexpr int RL = 2;
+      CT v[RL][PB];
+      uint32_t lb[RL];
+      bool al[RL];
+#pragma unroll
+      for (int i = 0; i < RL; ++i) {
+        const int lr = lane + 64 * i;
+        al[i] = lr < myR && lab[lr] >= gj1;
+        lb[i] = al[i] ? (uint32_t)lab[lr] : 0u;
+#pragma unroll
+        for (int c = 0; c < PB; ++c) {
+          v[i][c].x = 0;
+          v[i][c].y = 0;
+          if (al[i] && c < pw1) v[i][c] = tile[(j1 + c) * R + lr];
+        }
+      }
+      bool more = true;
+#pragma unroll
+      for (int c = 0; c < PB; ++c) {
+        CT pv[PB], inv;
+        int wl = 0, wsl = 0;
+        if (c < pw1 && more) more = wave_pivot_step<CT, PB, RL>(c, pw1, v, lb, al, pv, inv, wl, wsl);
+        if (c < pw1 && more) {
+          if (lane == 0) chosen[c] = wl + 64 * wsl;
+          cnt = c + 1;
+        }
+      }
+    } else {
+      for (int lr = lane; lr < myR; lr += 64)
+#pragma unroll
+        for (int c = 0; c < PB; ++c)
+          if (c < pw1) sel[c * R + lr] = tile[(j1 + c) * R + lr];
+      uint32_t taken = 0;  // bit i: row lane + 64 i already chosen
+      bool more = true;
+#pragma unroll
+      for (int c = 0; c < PB; ++c) {
+        if (c < pw1 && more) {
+          u64 best = 0;
+          int blr = -1;
+          for (int lr = lane, i = 0; lr < myR; lr += 64, ++i) {
+            if (lab[lr] < gj1 || ((taken >> i) & 1u)) continue;
+            const u64 kk = pivot_key(sel[c * R + lr], (uint32_t)lab[lr]);
+            if (kk > best) {
+              best = kk;
+              blr = lr;
+            }
+          }
+          const u64 wbest = wave_max_u64(best);
+          if (wbest == 0) {
+            more = false;  // no active row left
+          } else {
+            const int wl = __ffsll((unsigned long long)__ballot(best == wbest)) - 1;
+            const int wlr = __shfl(blr, wl);
+            if (lane == wl) taken |= 1u << ((wlr - lane) >> 6);
+            if (lane == 0) chosen[c] = wlr;
+            cnt = c + 1;
+            CT pv[PB];
+#pragma unroll
+            for (int cc = 0; cc < PB; ++cc) {
+              CT v = {0, 0};
+              if (lane == wl && cc >= c && cc < pw1) v = sel[cc * R + wlr];
+              pv[cc].x = __shfl(v.x, wl);
+              pv[cc].y = __shfl(v.y, wl);
+            }
+            CT inv;
+            if (pv[c].x == 0 && pv[c].y == 0) {
+              inv.x = 0;
+              inv.y = 0;
+            } else {
+              inv = cinv_t(pv[c]);
+            }
+            for (int lr = lane, i = 0; lr < myR; lr += 64, ++i) {
+              if (lab[lr] < gj1 || ((taken >> i) & 1u)) continue;
+              const CT l = cmul_t(sel[c * R + lr], inv);
+#pragma unroll
+              for (int cc = 0; cc < PB; ++cc)
+                if (cc > c && cc < pw1) sel[cc * R + lr] = r1_upd(sel[cc * R + lr], l, pv[cc]);
+            }
+          }
+        }
+      }
+    }
+    if (lane == 0) nch = cnt;
+  };
+  auto is_chosen = [&](int lr) {
+    bool r = false;
+#pragma unroll
+    for (int c = 0; c < PB; ++c) r = r || (c < nch && chosen[c] == lr);
+    return r;
+  };
+  // Publish the candidates of step s (columns [j1, j1 + pw1)): records, then
+  // the columns after the step.
+  auto publish = [&](int s, int j1, int pw1) {
+    const uint32_t E = epoch0 + (uint32_t)s;
+    const int par = s & 1;
+    u64* rec = ws.cand + par * rec_par + (size_t)g * PB * K;
+    u64* rws = ws.rows + (size_t)par * ws.gitem * PB * ws.wwmax + (size_t)g * PB * ws.wwmax;
+    for (int t = tid; t < PB * K; t += 256) {
+      const int c = t / K, k = t % K;
+      uint32_t v;
+      if (c >= nch) {
+        v = k == 0 ? 0xffffffffu : 0u;
+      } else {
+        const int lr = chosen[c];
+        if (k == 0) {
+          v = (uint32_t)lab[lr];
+        } else {
+          const int cc = (k - 1) / NW;
+          v = cc < pw1 ? cword(tile[(j1 + cc) * R + lr], (k - 1) % NW) : 0u;
+        }
+      }
+      ll_put(&rec[t], E, v);
+    }
+    const int WR = (w - j1 - pw1) * NW;
+    for (int t = tid; t < nch * WR; t += 256) {
+      const int c = t / WR, k = t % WR;
+      ll_put(&rws[(size_t)c * ws.wwmax + k], E, cword(tile[(j1 + pw1 + k / NW) * R + chosen[c]], k % NW));
+    }
+  };
+
+  local_choice(0, PB < w ? PB : w);
+  __syncthreads();
+  publish(0, 0, PB < w ? PB : w);
+  for (int s = 0; s < nsteps; ++s) {
+    const int j0 = s * PB, pw = w - j0 < PB ? w - j0 : PB;
+    const int j1 = j0 + pw, pw1 = w - j1 < PB ? w - j1 : PB;
+    const int32_t gj0 = (int32_t)(k0 + j0), gj1 = (int32_t)(k0 + j1);
+    const uint32_t E = epoch0 + (uint32_t)s;
+    const int par = s & 1;
+    // --- the step's pivots: wave 0 chooses among the roots' winners ---
+    if (wv == 0) {
+      const bool in = lane < NR * PB;
+      const u64* res = res_all + par * res_par;
+      const u64* base[1] = {res + (size_t)(in ? lane : 0) * KR};  // root 0's slot 0 is always published
+      uint32_t wd[KR];
+      ll_get_rec<KR, 1>(base, E, wd, &bad);
+      const uint32_t ci = in ? wd[0] : 0xffffffffu;
+      uint32_t lb[1] = {wd[1]};
+      bool al[1] = {ci != 0xffffffffu};
+      CT v[1][PB];
+#pragma unroll
+      for (int c = 0; c < PB; ++c) {
+        uint32_t* d = reinterpret_cast<uint32_t*>(&v[0][c]);
+#pragma unroll
+        for (int q = 0; q < NW; ++q) d[q] = wd[2 + c * NW + q];
+      }
+      bool more = true;
+#pragma unroll
+      for (int c = 0; c < PB; ++c) {
+        CT pv[PB], inv;
+        int wl = 0, wsl = 0;
+        const uint32_t cic = ci, lbc = lb[0];  // before the step retires the winner
+        if (c < pw && more) more = wave_pivot_step<CT, PB, 1>(c, pw, v, lb, al, pv, inv, wl, wsl);
+        if (c < pw) {
+          if (!more) {
+            if (lane == 0) bad = 1;  // fewer candidates than columns: cannot happen
+          } else {
+            const uint32_t wci = (uint32_t)__builtin_amdgcn_readlane((int)cic, wl);
+            const uint32_t wlb = (uint32_t)__builtin_amdgcn_readlane((int)lbc, wl);
+            if (lane == 0) {
+              pci[c] = (int)wci;
+              plab[c] = (int32_t)wlb;
+              binv[c] = inv;
+#pragma unroll
+              for (int cc = 0; cc < PB; ++cc) blk[c][cc] = pv[cc];
+              if (pv[c].x == 0 && pv[c].y == 0 && zcol < 0) zcol = j0 + c;
+            }
+          }
+        }
+      }
+    }
+    __syncthreads();
+    if (bad) {
+      if (tid == 0) __hip_atomic_store(&ws.err[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      return;
+    }
+    // --- positions of the pivots before their interchanges (LAPACK ipiv) ---
+    int32_t ppos[PB];
+#pragma unroll
+    for (int c = 0; c < PB; ++c) {
+      int32_t p = plab[c < pw ? c : 0];
+#pragma unroll
+      for (int cc = 0; cc < PB; ++cc)
+        if (cc < c && p == gj0 + cc) p = ppos[cc];
+      ppos[c] = p;
+    }
+    if (tid == 0)
+#pragma unroll
+      for (int c = 0; c < PB; ++c)
+        if (c < pw) pl[j0 + c] = ppos[c];
+    // which local row is pivot c (-1 if another workgroup owns it)
+    int own[PB];
+#pragma unroll
+    for (int c = 0; c < PB; ++c) own[c] = (c < pw && pci[c] / PB == g) ? chosen[pci[c] % PB] : -1;
+    // --- fetch the pivot rows' columns [j1, w) from their owners (at most 8
+    // words per thread, all in flight together) ---
+    {
+      const int WR = (w - j1) * NW;
+      const int tot = pw * WR;
+      if (tot > 0) {
+        const u64* rws = ws.rows + (size_t)par * ws.gitem * PB * ws.wwmax;
+        uint32_t* p32 = reinterpret_cast<uint32_t*>(prow);
+        constexpr int FB = 8;  // PB w NW <= 8 x 128 x 2 = 4 x 128 x 4 = 2048 = 8 x 256
+        const u64* pp[FB];
+#pragma unroll
+        for (int i = 0; i < FB; ++i) {
+          const int t = tid + 256 * i < tot ? tid + 256 * i : 0;
+          const int c = t / WR, k = t % WR;
+          const int ci = pci[c];
+          pp[i] = rws + (size_t)(ci / PB) * PB * ws.wwmax + (size_t)(ci % PB) * ws.wwmax + k;
+        }
+        uint32_t wd[FB];
+        ll_get_sel<FB>(pp, E, wd, &bad);
+#pragma unroll
+        for (int i = 0; i < FB; ++i) {
+          const int t = tid + 256 * i;
+          if (t < tot) p32[((size_t)(t / WR) * w + j1) * NW + t % WR] = wd[i];
+        }
+      }
+    }
+    // --- interchanges: labels of the pivot rows and of the rows they displace ---
+    for (int lr = tid; lr < myR; lr += 256) {
+      int32_t L = lab[lr];
+      if (L < gj0) continue;
+#pragma unroll
+      for (int c = 0; c < PB; ++c) {
+        if (c < pw) {
+          if (own[c] == lr) L = gj0 + c;
+          else if (L == gj0 + c) L = ppos[c];
+        }
+      }
+      lab[lr] = L;
+    }
+    __syncthreads();
+    // --- U rows: columns [j1, w) of pivot c minus L11[c][:c] times the earlier ones ---
+    for (int col = j1 + tid; col < w; col += 256)
+#pragma unroll
+      for (int c = 1; c < PB; ++c) {
+        if (c < pw) {
+          CT u = prow[c * w + col];
+#pragma unroll
+          for (int cc = 0; cc < PB; ++cc)
+            if (cc < c) u = r1_upd(u, blk[c][cc], prow[cc * w + col]);
+          prow[c * w + col] = u;
+        }
+      }
+    __syncthreads();
+    // --- the step's rows: pivot rows get their factored values, every other
+    // active row its multipliers and the update of the next step's columns ---
+    for (int t = tid; t < pw * (w - j0); t += 256) {
+      const int c = t / (w - j0), col = j0 + t % (w - j0);
+      int lr = -1;
+#pragma unroll
+      for (int cc = 0; cc < PB; ++cc)
+        if (cc == c) lr = own[cc];
+      if (lr >= 0) tile[col * R + lr] = col < j1 ? blk[c][col - j0] : prow[c * w + col];
+    }
+    for (int lr = tid; lr < myR; lr += 256) {
+      if (lab[lr] < gj1) continue;
+      CT l[PB];
+#pragma unroll
+      for (int c = 0; c < PB; ++c) {
+        l[c].x = 0;
+        l[c].y = 0;
+        if (c < pw) {
+          CT a = tile[(j0 + c) * R + lr];
+#pragma unroll
+          for (int cc = 0; cc < PB; ++cc)
+            if (cc < c) a = r1_upd(a, l[cc], blk[cc][c]);
+          l[c] = cmul_t(a, binv[c]);
+          tile[(j0 + c) * R + lr] = l[c];
+        }
+      }
+#pragma unroll
+      for (int cc = 0; cc < PB; ++cc) {
+        if (cc < pw1) {
+          CT a = tile[(j1 + cc) * R + lr];
+#pragma unroll
+          for (int c = 0; c < PB; ++c)
+            if (c < pw) a = r1_upd(a, l[c], prow[c * w + j1 + cc]);
+          tile[(j1 + cc) * R + lr] = a;
+        }
+      }
+    }
+    __syncthreads();
+    if (j1 >= w) break;
+    // --- candidates of the next step, their remaining columns, publication ---
+    local_choice(j1, pw1);
+    __syncthreads();
+    {
+      const int WC = w - j1 - pw1;
+      for (int t = tid; t < nch * WC; t += 256) {
+        const int c = t / WC, col = j1 + pw1 + t % WC;
+        const int lr = chosen[c];
+        CT a = tile[col * R + lr];
+#pragma unroll
+        for (int cc = 0; cc < PB; ++cc)
+          if (cc < pw) a = r1_upd(a, tile[(j0 + cc) * R + lr], prow[cc * w + col]);
+        tile[col * R + lr] = a;
+      }
+    }
+    __syncthreads();
+    publish(s + 1, j1, pw1);
+    // --- the rest of the update, while the roots choose ---
+    for (int lr = ulr0; lr < myR; lr += RP) {
+      if (lab[lr] < gj1 || is_chosen(lr)) continue;
+      CT l[PB];
+#pragma unroll
+      for (int c = 0; c < PB; ++c) {
+        if (c < pw) {
+          l[c] = tile[(j0 + c) * R + lr];
+        } else {
+          l[c].x = 0;
+          l[c].y = 0;
+        }
+      }
+      for (int col = j1 + pw1 + ucg; col < w; col += CG) {
+        CT a = tile[col * R + lr];
+#pragma unroll
+        for (int c = 0; c < PB; ++c)
+          if (c < pw) a = r1_upd(a, l[c], prow[c * w + col]);
+        tile[col * R + lr] = a;
+      }
+    }
+  }
+  __syncthreads();
+  if (bad && tid == 0) __hip_atomic_store(&ws.err[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (g == 0) {
+    for (int j = tid; j < w; j += 256) ipiv[k0 + j] = pl[j];
+    if (tid == 0 && zcol >= 0) atomicMin(&ws.err[1], (int)(k0 + zcol));
   }
   for (int lr = tid; lr < myR; lr += 256) {
     const int32_t orig = (int32_t)(rbase + lr);
@@ -839,25 +1548,45 @@ static hipError_t launch_block_trsm(const cplx<T>* A, int64_t ld, int64_t n, int
 // planning and workspace
 // ---------------------------------------------------------------------------
 static const int LDS_RESERVE = 2048;
+// the tournament panel's static LDS (pivot block, wave slots) is larger
+static const int LDS_RESERVE_TP = 4096;
+// rows per workgroup of the local choice (a 32-bit mask of each lane's rows)
+static const int TP_MAX_ROWS = 2048;
 
-
-// dynamic LDS of a panel workgroup: tile, pivot row, multipliers, labels, pivots
-static size_t panel_lds_bytes(int w, int R, size_t cbytes) {
-  return ((size_t)w * R + w) * cbytes + (size_t)(R + w) * 4;
+// dynamic LDS of a panel workgroup: tile, pivot row(s), scratch, labels, pivots
+static size_t panel_lds_bytes(int w, int R, size_t cbytes, int pb) {
+  if (pb <= 1) return ((size_t)w * R + w) * cbytes + (size_t)(R + w) * 4;
+  return ((size_t)w * R + (size_t)pb * w + (size_t)pb * R) * cbytes + (size_t)(R + w) * 4;
+}
+static int lds_reserve(int pb) { return pb <= 1 ? LDS_RESERVE : LDS_RESERVE_TP; }
+// most rows of one panel workgroup that fit its LDS
+static int64_t panel_rows_max(int w, int64_t lds_bytes, int cbytes, int pb) {
+  if (pb <= 1) return (lds_bytes - LDS_RESERVE - (int64_t)w * (cbytes + 4)) / ((int64_t)(w + 1) * cbytes + 4);
+  const int64_t r = (lds_bytes - LDS_RESERVE_TP - (int64_t)w * (pb * cbytes + 4)) / ((int64_t)(w + pb) * cbytes + 4);
+  return r < TP_MAX_ROWS ? r : TP_MAX_ROWS;
 }
 
-LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch, int nb_max) {
+// root workgroups of a tournament panel over G row workgroups
+static int tp_roots(int G) { return (G + 31) / 32; }
+
+LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch, int nb_max, int pb) {
   LUPlan p;
   p.n = n;
   if (nbatch < 1) nbatch = 1;
+  if (pb != 1 && pb != 2 && pb != 4 && pb != 8) pb = 1;
+  if (elem_bytes == 8 && pb > 4) pb = 4;  // FP64 candidates of 8 columns would need too many registers
+  p.pb = pb;
   // the panels of all items run in one launch and must all be resident
   p.max_wg = num_cu / nbatch > 0 ? num_cu / nbatch : 1;
+  // row workgroups of one panel: with tournament pivoting, one root workgroup
+  // per 32 of them must be resident too (G + ceil(G / 32) <= max_wg)
+  const int avail = pb > 1 ? std::max(1, 32 * p.max_wg / 33) : p.max_wg;
   const int cbytes = 2 * elem_bytes;
   int nb = nb_max >= 16 && nb_max <= 128 ? nb_max : 128;
-  // the panel must fit: ceil(n / max_wg) rows x nb columns in LDS
+  // the panel must fit: ceil(n / avail) rows x nb columns in LDS
   while (nb > 16) {
-    const int64_t R = (n + p.max_wg - 1) / p.max_wg;
-    if ((int64_t)panel_lds_bytes(nb, (int)R, cbytes) + LDS_RESERVE <= lds_bytes) break;
+    const int64_t R = (n + avail - 1) / avail;
+    if (R <= panel_rows_max(nb, lds_bytes, cbytes, pb)) break;
     nb /= 2;
   }
   p.nb = nb;
@@ -867,12 +1596,11 @@ LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch,
   // FP64 panel (twice the bytes per row) is fastest spread over every CU.  The
   // cap is raised when the panel's rows would not fit the LDS of fewer
   // workgroups.
-  int cap = p.max_wg;
+  int cap = avail;
   if (elem_bytes == 4 && nbatch == 1) {
-    const int64_t rmax = ((int64_t)lds_bytes - LDS_RESERVE - (int64_t)nb * (cbytes + 4)) /
-                         ((int64_t)(nb + 1) * cbytes + 4);
-    const int64_t need = rmax > 0 ? (n + rmax - 1) / rmax : p.max_wg;
-    cap = (int)std::min<int64_t>(p.max_wg, std::max<int64_t>(128, need));
+    const int64_t rmax = panel_rows_max(nb, lds_bytes, cbytes, pb);
+    const int64_t need = rmax > 0 ? (n + rmax - 1) / rmax : avail;
+    cap = (int)std::min<int64_t>(avail, std::max<int64_t>(128, need));
   }
   for (int64_t k0 = 0; k0 < n; k0 += nb) {
     LUBlock b;
@@ -881,7 +1609,7 @@ LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch,
     const int64_t m = n - k0;
     int64_t R = (m + cap - 1) / cap;
     if (R < 32) R = 32;
-    const int64_t Rmax = (lds_bytes - LDS_RESERVE - (int64_t)b.w * (cbytes + 4)) / ((int64_t)(b.w + 1) * cbytes + 4);
+    const int64_t Rmax = panel_rows_max(b.w, lds_bytes, cbytes, pb);
     if (R > Rmax) R = Rmax;
     b.R = (int)R;
     b.G = (int)((m + R - 1) / R);
@@ -892,7 +1620,7 @@ LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch,
 
 bool lu_plan_fits(const LUPlan& p) {
   for (const LUBlock& b : p.blocks)
-    if (b.G > p.max_wg || (int64_t)b.G * b.R < p.n - b.k0) return false;
+    if (b.G + (p.pb > 1 ? tp_roots(b.G) : 0) > p.max_wg || (int64_t)b.G * b.R < p.n - b.k0) return false;
   return true;
 }
 
@@ -923,9 +1651,18 @@ void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu,
   };
   w.nbatch = nbatch;
   w.gmax = num_cu;
+  w.gitem = p.max_wg > 0 ? p.max_wg : num_cu;
+  w.pb = p.pb;
   w.wwmax = (int)ww;
-  w.s_cand = (int64_t)(al256(2 * (size_t)num_cu * KEY_STRIDE * 8) / 8);
-  w.s_rows = (int64_t)(al256(2 * (size_t)num_cu * ww * 8) / 8);
+  const size_t pbz = (size_t)(p.pb > 1 ? p.pb : 1);
+  const size_t nwc = 2 * (size_t)elem_bytes / 4;  // 32-bit words per complex
+  // tournament: records [2][gitem][pb][1 + pb nwc], then the roots' winners
+  // [2][ceil(gitem / 32)][pb][2 + pb nwc]; partial pivoting: keys [2][gitem][KEY_STRIDE]
+  const size_t cand_words = p.pb > 1 ? 2 * (size_t)w.gitem * pbz * (1 + pbz * nwc) +
+                                           2 * (size_t)tp_roots(w.gitem) * pbz * (2 + pbz * nwc)
+                                     : 2 * (size_t)w.gitem * KEY_STRIDE;
+  w.s_cand = (int64_t)(al256(cand_words * 8) / 8);
+  w.s_rows = (int64_t)(al256(2 * (size_t)w.gitem * pbz * ww * 8) / 8);
   w.cand = reinterpret_cast<unsigned long long*>(take((size_t)nbatch * w.s_cand * 8));
   w.rows = reinterpret_cast<unsigned long long*>(take((size_t)nbatch * w.s_rows * 8));
   w.err = reinterpret_cast<int32_t*>(take(64));
@@ -942,20 +1679,57 @@ void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu,
   w.bytes = off + 256;
 }
 
-// Panels may need more than the default 64 KB of dynamic LDS: raise the
+// The panel kernel of a plan (pb columns per exchange).
+template <typename T>
+static const void* panel_fn(int pb) {
+  switch (pb) {
+    case 2: return reinterpret_cast<const void*>(&panel_tp_kernel<T, 2>);
+    case 4: return reinterpret_cast<const void*>(&panel_tp_kernel<T, 4>);
+    case 8:
+      if constexpr (sizeof(T) == 4) return reinterpret_cast<const void*>(&panel_tp_kernel<T, 8>);
+      return nullptr;
+    default: return reinterpret_cast<const void*>(&panel_kernel<T>);
+  }
+}
+
+// One panel launch: G row workgroups (plus the roots of a tournament panel) per item.
+template <typename T>
+static void launch_panel(int pb, const LUBlock& b, int NB, size_t lds, hipStream_t st, cplx<T>* A, int64_t ld,
+                         int64_t n, int32_t* ipiv, const LUWork& ws, uint32_t epoch, int64_t sA, int64_t sipiv,
+                         int32_t* dst, int32_t* src, int32_t* npr, int mcap) {
+  const dim3 grid(b.G + (pb > 1 ? tp_roots(b.G) : 0), NB);
+#define GDM_PANEL_ARGS A, ld, n, b.k0, b.w, b.R, b.G, ipiv, ws, epoch, sA, sipiv, dst, src, npr, mcap
+  switch (pb) {
+    case 2: hipLaunchKernelGGL((panel_tp_kernel<T, 2>), grid, dim3(256), lds, st, GDM_PANEL_ARGS); break;
+    case 4: hipLaunchKernelGGL((panel_tp_kernel<T, 4>), grid, dim3(256), lds, st, GDM_PANEL_ARGS); break;
+    case 8:
+      if constexpr (sizeof(T) == 4) {
+        hipLaunchKernelGGL((panel_tp_kernel<T, 8>), grid, dim3(256), lds, st, GDM_PANEL_ARGS);
+        break;
+      }
+      [[fallthrough]];
+    default: hipLaunchKernelGGL(panel_kernel<T>, grid, dim3(256), lds, st, GDM_PANEL_ARGS); break;
+  }
+#undef GDM_PANEL_ARGS
+}
+
+// Panels may need more than the default 64 KB of dynamic LDS: raise each panel
 // kernel's limit once (a host-side setting; done before any graph capture).
 template <typename T>
 hipError_t lu_prepare(const LUPlan& plan) {
-  size_t lds_need = 0;
-  for (const LUBlock& b : plan.blocks)
-    lds_need = std::max(lds_need, panel_lds_bytes(b.w, b.R, sizeof(cplx<T>)));
-  static size_t lds_set[2] = {0, 0};
-  size_t& cur = lds_set[sizeof(T) == 8 ? 0 : 1];
-  if (lds_need > 64 * 1024 && lds_need > cur) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&panel_kernel<T>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_need);
-    if (e != hipSuccess) return e;
-    cur = lds_need;
+  static std::map<const void*, size_t> lds_set;
+  static std::mutex mu;
+  std::lock_guard<std::mutex> lk(mu);
+  for (const LUBlock& b : plan.blocks) {
+    const size_t need = panel_lds_bytes(b.w, b.R, sizeof(cplx<T>), plan.pb);
+    const void* fn = panel_fn<T>(plan.pb);
+    if (!fn) return hipErrorInvalidValue;
+    size_t& cur = lds_set[fn];
+    if (need > 64 * 1024 && need > cur) {
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+      if (e != hipSuccess) return e;
+      cur = need;
+    }
   }
   return hipSuccess;
 }
@@ -975,7 +1749,9 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
   const int NB = ws.nbatch;
   const double fb = (double)NB;
   hipError_t e;
-  if (NB < 1 || NB > 65535 || !lu_plan_fits(plan) || plan.max_wg * NB > ws.gmax) return hipErrorInvalidValue;
+  if (NB < 1 || NB > 65535 || !lu_plan_fits(plan) || plan.max_wg * NB > ws.gmax || plan.max_wg > ws.gitem ||
+      plan.pb > ws.pb)
+    return hipErrorInvalidValue;
   hipLaunchKernelGGL(init_err_kernel, dim3(1), dim3(64), 0, st, ws.err);
   // exchange buffers start from zero (epoch 0 is never used), so epochs 1, 2, ...
   // of this factorisation are unique
@@ -1044,13 +1820,12 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
     const LUBlock& b = plan.blocks[bi];
     const int64_t k0 = b.k0;
     const int w = b.w;
-    const size_t lds = panel_lds_bytes(w, b.R, sizeof(CT));
+    const size_t lds = panel_lds_bytes(w, b.R, sizeof(CT), plan.pb);
     LUCHK(P.begin(st, PROF_PANEL, (double)w * fb));
     int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;  // moved rows: destinations, then sources 2 nb later
     int32_t* src = dst + 2 * nb;
     int32_t* npr = ws.npairs + bi;
-    hipLaunchKernelGGL(panel_kernel<T>, dim3(b.G, NB), dim3(256), lds, st, A, ld, n, k0, w, b.R, b.G, ipiv, ws, epoch,
-                       sA, sipiv, dst, src, npr, 2 * nb);
+    launch_panel<T>(plan.pb, b, NB, lds, st, A, ld, n, ipiv, ws, epoch, sA, sipiv, dst, src, npr, 2 * nb);
     epoch += (uint32_t)w;
     LUCHK(hipGetLastError());
     LUCHK(P.end(st));

@@ -27,8 +27,9 @@ STATUS_NAMES = ["OK", "E_ARG", "E_OOM", "E_DEVICE", "E_SINGULAR", "E_NOCONV", "E
 PREC_FP64, PREC_FP32_IR = 0, 1
 SELF_STATIC, SELF_RADIATIVE = 0, 1
 
-EXPORTED = ["gdm_create", "gdm_destroy", "gdm_last_error", "gdm_set_environment", "gdm_set_structure",
-            "gdm_num_unknowns", "gdm_assemble", "gdm_factorize", "gdm_incident_planewave", "gdm_solve",
+EXPORTED = ["gdm_create", "gdm_destroy", "gdm_last_error", "gdm_set_memory_limit", "gdm_memory_used", "gdm_set_pivoting",
+            "gdm_set_environment", "gdm_set_structure",
+            "gdm_num_unknowns", "gdm_assemble", "gdm_factorize", "gdm_set_wavelength", "gdm_solve_iterative", "gdm_incident_planewave", "gdm_solve",
             "gdm_planewave", "gdm_fields", "gdm_fields_noalloc", "gdm_cross_sections", "gdm_adjoint", "gdm_batch_spectra", "gdm_batch_tuning", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
             "gdm_profile", "gdm_profile_mask", "gdm_profile_read"]
 
@@ -61,11 +62,16 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gdm_create": ([ctypes.c_int, P, ctypes.POINTER(P)], ctypes.c_int),
         "gdm_destroy": ([P], None),
         "gdm_last_error": ([P], ctypes.c_char_p),
+        "gdm_set_memory_limit": ([P, I64], ctypes.c_int),
+        "gdm_memory_used": ([P], I64),
+        "gdm_set_pivoting": ([P, I32], ctypes.c_int),
         "gdm_set_environment": ([P, D], ctypes.c_int),
         "gdm_set_structure": ([P, I64, P, D, P, I64, P, P, ctypes.c_int], ctypes.c_int),
         "gdm_num_unknowns": ([P], I64),
         "gdm_assemble": ([P, D, ctypes.c_int, P, I64], ctypes.c_int),
         "gdm_factorize": ([P, D, ctypes.c_int, ctypes.POINTER(GDMInfo)], ctypes.c_int),
+        "gdm_set_wavelength": ([P, D], ctypes.c_int),
+        "gdm_solve_iterative": ([P, D, I64, P, D, I32, I32, P, P, ctypes.POINTER(GDMInfo)], ctypes.c_int),
         "gdm_incident_planewave": ([P, I64, P, P, P], ctypes.c_int),
         "gdm_solve": ([P, I64, P, D, I32, P, P, ctypes.POINTER(GDMInfo)], ctypes.c_int),
         "gdm_planewave": ([P, I64, P, P, I64, P, P, P], ctypes.c_int),
@@ -74,7 +80,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gdm_cross_sections": ([P, I64, P, P, P, P, I32, P], ctypes.c_int),
         "gdm_adjoint": ([P, I64, P, P, P, P, P, P, I64, P, P, D, I32, P, P, P, ctypes.POINTER(GDMInfo)],
                         ctypes.c_int),
-        "gdm_batch_spectra": ([P, I64, P, P, P, I64, P, P, I64, P, P, ctypes.c_int, I32, ctypes.c_int, P, P,
+        "gdm_batch_spectra": ([P, I64, P, P, P, I64, P, P, I64, P, P, ctypes.c_int, I32, D, ctypes.c_int, P, P,
                                ctypes.POINTER(GDMInfo)], ctypes.c_int),
         "gdm_batch_tuning": ([P, P, I32], I32),
         "gdm_getrf": ([P, ctypes.c_int, I64, P, I64, P, ctypes.POINTER(GDMInfo)], ctypes.c_int),
@@ -168,6 +174,20 @@ class Context:
             raise ValueError(f"{name}: expected shape {tuple(shape)}, got {tuple(t.shape)}")
         return t
 
+    def set_memory_limit(self, nbytes: int = 0):
+        """Limit on the device bytes of this context's buffers (0: none); calls
+        that would exceed it fail with GDM_E_OOM (include/gdm.h)."""
+        self._check(self._call("gdm_set_memory_limit", self.h, int(nbytes)))
+
+    def memory_used(self) -> int:
+        return int(self.lib.gdm_memory_used(self.h))
+
+    def set_pivoting(self, columns_per_exchange: int = 0):
+        """Panel columns per pivot exchange of the next factorisations
+        (include/gdm.h, gdm_set_pivoting): 1 partial pivoting, 2/4/8 tournament,
+        0 the library default."""
+        self._check(self._call("gdm_set_pivoting", self.h, int(columns_per_exchange)))
+
     # -- structure / environment ------------------------------------------------
     def set_environment(self, n_env: float):
         self.state_id += 1
@@ -203,6 +223,24 @@ class Context:
         self._check(self._call("gdm_factorize", self.h, float(wavelength), int(prec), ctypes.byref(self.info)))
         return self.info
 
+    def set_wavelength(self, wavelength):
+        self.state_id += 1
+        self._check(self._call("gdm_set_wavelength", self.h, float(wavelength)))
+
+    def solve_iterative(self, wavelength, f0, tol=0.0, max_iter=0, restart=0, want_field=True):
+        """Matrix-free GMRES solve at `wavelength` (include/gdm.h,
+        gdm_solve_iterative): returns (q, F); self.info.ir_iters = products with
+        M, self.info.backward_err = largest relative residual."""
+        f0 = self._dev(f0, torch.complex128, None, "f0")
+        if f0.dim() != 2 or f0.shape[1] != self.n:
+            raise ValueError(f"f0 must be [n_rhs, {self.n}]")
+        q = torch.empty_like(f0)
+        f = torch.empty_like(f0) if want_field else None
+        self.state_id += 1
+        self._check(self._call("gdm_solve_iterative", self.h, float(wavelength), f0.shape[0], _ptr(f0), float(tol),
+                               int(max_iter), int(restart), _ptr(q), _ptr(f), ctypes.byref(self.info)))
+        return q, f
+
     def incident_planewave(self, khat, e0):
         k = self._dev(khat, torch.float64, None, "khat").reshape(-1, 3)
         e = self._dev(e0, torch.complex128, None, "e0").reshape(-1, 3)
@@ -213,13 +251,30 @@ class Context:
         return f0
 
     def solve(self, f0, tol=0.0, max_iter=-1, want_field=True):
+        """Moments q (and fields F) of the right-hand sides f0 [n_rhs, n].  If the
+        library runs out of device memory, the right-hand sides are solved in two
+        halves, recursively down to one at a time (the paper's restart with a
+        smaller batch after an out-of-memory error); self.info then holds the
+        largest backward error and correction count over the parts."""
         f0 = self._dev(f0, torch.complex128, None, "f0")
         if f0.dim() != 2 or f0.shape[1] != self.n:
             raise ValueError(f"f0 must be [n_rhs, {self.n}]")
+        return self._solve_parts(f0, tol, max_iter, want_field)
+
+    def _solve_parts(self, f0, tol, max_iter, want_field):
         q = torch.empty_like(f0)
         f = torch.empty_like(f0) if want_field else None
         st = self._call("gdm_solve", self.h, f0.shape[0], _ptr(f0), float(tol), int(max_iter), _ptr(q), _ptr(f),
-                                ctypes.byref(self.info))
+                        ctypes.byref(self.info))
+        if st == GDM_E_OOM and f0.shape[0] > 1:
+            del q, f
+            h = f0.shape[0] // 2
+            q1, f1 = self._solve_parts(f0[:h], tol, max_iter, want_field)
+            it1, be1 = self.info.ir_iters, self.info.backward_err
+            q2, f2 = self._solve_parts(f0[h:], tol, max_iter, want_field)
+            self.info.ir_iters = max(it1, self.info.ir_iters)
+            self.info.backward_err = max(be1, self.info.backward_err)
+            return torch.cat([q1, q2]), (torch.cat([f1, f2]) if want_field else None)
         self._check(st)
         return q, f
 
@@ -233,11 +288,24 @@ class Context:
         return E, H
 
     def fields(self, q, r_probe, want_h=True):
+        """Scattered fields E, H [n_rhs, P, 3] of the moments q at r_probe [P, 3].
+        If the library runs out of device memory, the probes are evaluated in
+        two halves, recursively down to one probe at a time."""
         q = self._dev(q, torch.complex128, None, "q")
         r = self._dev(r_probe, torch.float64, None, "r_probe").reshape(-1, 3)
+        return self._fields_parts(q, r, want_h)
+
+    def _fields_parts(self, q, r, want_h):
         E = torch.empty((q.shape[0], len(r), 3), dtype=torch.complex128, device=self.device)
         H = torch.empty_like(E) if want_h else None
-        self._check(self._call("gdm_fields", self.h, q.shape[0], _ptr(q), len(r), _ptr(r), _ptr(E), _ptr(H)))
+        st = self._call("gdm_fields", self.h, q.shape[0], _ptr(q), len(r), _ptr(r), _ptr(E), _ptr(H))
+        if st == GDM_E_OOM and len(r) > 1:
+            del E, H
+            h = len(r) // 2
+            E1, H1 = self._fields_parts(q, r[:h], want_h)
+            E2, H2 = self._fields_parts(q, r[h:], want_h)
+            return torch.cat([E1, E2], dim=1), (torch.cat([H1, H2], dim=1) if want_h else None)
+        self._check(st)
         return E, H
 
     def fields_noalloc(self, q, r_probe, E, H=None):
@@ -295,7 +363,7 @@ class Context:
         self._check(st)
         return grad_r, grad_eps[: self.n_cell], grad_wl
 
-    def batch_spectra(self, r_cells, step, wavelengths, eps, khat, e0, prec=PREC_FP32_IR, ir_iters=-1,
+    def batch_spectra(self, r_cells, step, wavelengths, eps, khat, e0, prec=PREC_FP32_IR, ir_iters=-1, tol=0.0,
                       selfterm=SELF_STATIC, want_be=True):
         """Cross sections of many structures x wavelengths (include/gdm.h,
         gdm_batch_spectra).  r_cells: list of [N_s, 3] cell positions; step: one
@@ -321,7 +389,7 @@ class Context:
         host = ctypes.c_void_p  # host arrays: cell offsets, steps, wavelengths
         st = self._call("gdm_batch_spectra", self.h, ns, host(off.ctypes.data), _ptr(rc), host(steps.ctypes.data),
                         len(wl), host(wl.ctypes.data), _ptr(ep), len(k), _ptr(k), _ptr(e), int(prec), int(ir_iters),
-                        int(selfterm), _ptr(cs), _ptr(be), ctypes.byref(self.info))
+                        float(tol), int(selfterm), _ptr(cs), _ptr(be), ctypes.byref(self.info))
         self._check(st)
         return cs, (be if prec == PREC_FP32_IR else None)
 
@@ -361,7 +429,7 @@ class Context:
         self._check(self._call("gdm_sync", self.h))
 
     PROF_TAGS = ("update", "panel", "assemble", "trsm", "perm", "solve", "resid", "adj_pair", "adj_probe", "fields",
-                 "lookahead")
+                 "lookahead", "iter_matvec")
 
     def profile(self, enable: bool, tags=None):
         """Start (clearing the counters) or stop per-launch event timing; `tags`

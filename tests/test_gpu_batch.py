@@ -67,12 +67,18 @@ def oracle_cs(r, step, eps, wl, khat, e0, mode="static"):
     return _CACHE[key]
 
 
+@pytest.mark.parametrize("pivoting", [1, 4])
 @pytest.mark.parametrize("prec", [1, 0])
-def test_batch_matches_oracle(ctx, prec):
-    say("batch vs oracle prec", prec)
+def test_batch_matches_oracle(ctx, prec, pivoting):
+    """Partial pivoting (the default) and tournament pivoting over 4 columns."""
+    say("batch vs oracle prec", prec, "pivoting", pivoting)
     structs, wl, eps, khat, e0 = small_batch()
     ctx.set_environment(1.0)
-    cs, be = ctx.batch_spectra(structs, 10.0, wl, eps, khat, e0, prec=prec)
+    ctx.set_pivoting(pivoting)
+    try:
+        cs, be = ctx.batch_spectra(structs, 10.0, wl, eps, khat, e0, prec=prec)
+    finally:
+        ctx.set_pivoting(0)
     cs = cs.cpu().numpy()
     print("  cells", [len(r) for r in structs], "info ms", ctx.info.ms_factor, flush=True)
     for s, r in enumerate(structs):

@@ -121,10 +121,77 @@ def test_getrf_pivots_match_lapack(ctx):
     rng = np.random.default_rng(5)
     A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
     tA = torch.from_numpy(np.ascontiguousarray(A.T)).cuda()
-    piv = ctx.getrf(tA).cpu().numpy()
+    ctx.set_pivoting(1)  # partial pivoting (also the default)
+    try:
+        piv = ctx.getrf(tA).cpu().numpy()
+    finally:
+        ctx.set_pivoting(0)
     _, lp = sla.lu_factor(A)
     # LAPACK's izamax uses |re| + |im| as well
     assert np.array_equal(piv, lp)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("pb", [1, 2, 4, 8])
+@pytest.mark.parametrize("n", [3, 131, 1000, 2601])
+def test_getrf_pivoting_widths(ctx, dtype, pb, n):
+    """Every pivoting mode (columns per exchange 1: partial pivoting; 2, 4, 8:
+    tournament; FP64 caps it at 4) on random matrices: ragged last panel (n not
+    a multiple of the 128-column panel nor of the inner width), panels over
+    one to ~80 workgroups.  P A = L U is checked through the solves of both
+    op(A): the normwise backward error ||A x - b|| / (||A|| ||x|| + ||b||) of
+    every column within a small multiple of the precision's unit roundoff."""
+    say("getrf pivoting", dtype, pb, n)
+    rng = np.random.default_rng(1000 + n)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    Bm = rng.standard_normal((n, 3)) + 1j * rng.standard_normal((n, 3))
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    u = 1.1e-16 if dtype == "c128" else 6e-8
+    tA = torch.from_numpy(np.ascontiguousarray(A.T)).to(tdt).cuda()
+    ctx.set_pivoting(pb)
+    try:
+        ipiv = ctx.getrf(tA).cpu().numpy()
+    finally:
+        ctx.set_pivoting(0)
+    assert np.all(ipiv >= np.arange(n)) and np.all(ipiv < n)
+    ndt = np.complex128 if dtype == "c128" else np.complex64
+    As = A.astype(ndt).astype(np.complex128)  # the matrix and RHS as stored
+    Bs = Bm.astype(ndt).astype(np.complex128)
+    for trans in (0, 1):
+        tB = torch.from_numpy(np.ascontiguousarray(Bm.T)).to(tdt).cuda()
+        ctx.getrs(tA, tB, trans)
+        torch.cuda.synchronize()
+        X = tB.cpu().numpy().T.astype(np.complex128)
+        op = As.T if trans else As
+        r = op @ X - Bs
+        norm_op = np.abs(op).sum(axis=1).max()
+        be = np.max(np.abs(r).max(axis=0) / (norm_op * np.abs(X).max(axis=0) + np.abs(Bs).max(axis=0)))
+        assert be < 30 * u * np.sqrt(n), (trans, be)
+
+
+@pytest.mark.parametrize("dtype", ["c128", "c64"])
+@pytest.mark.parametrize("pb", [1, 4, 8])
+def test_getrf_zero_column_reports_its_index(ctx, dtype, pb):
+    """An exactly zero column makes that column's pivot zero whatever the row
+    interchanges: GDM_E_SINGULAR with bad_index = the column (here 37 and 200,
+    the first reported)."""
+    from paper_2505_09545_amd import gdm
+    say("getrf zero column", dtype, pb)
+    n = 300
+    rng = np.random.default_rng(77)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    A[:, 37] = 0
+    A[:, 200] = 0
+    tdt = torch.complex128 if dtype == "c128" else torch.complex64
+    tA = torch.from_numpy(np.ascontiguousarray(A.T)).to(tdt).cuda()
+    ctx.set_pivoting(pb)
+    try:
+        with pytest.raises(gdm.GDMError) as ei:
+            ctx.getrf(tA)
+    finally:
+        ctx.set_pivoting(0)
+    assert ei.value.status == gdm.GDM_E_SINGULAR
+    assert ctx.info.bad_index == 37
 
 
 # ---------------------------------------------------------------------------
@@ -251,7 +318,7 @@ def test_argument_errors(ctx):
 def test_profile_tag_mask(ctx):
     """gdm_profile_mask times only the launches of the tags it is given (the
     benchmark's timed region keeps events on the update GEMM only);
-    gdm_profile(ctx, 1) times every tag; a mask outside [0, 2048) is an
+    gdm_profile(ctx, 1) times every tag; a mask outside [0, 4096) is an
     argument error."""
     say("profile tag mask")
     from paper_2505_09545_amd import gdm
@@ -269,25 +336,31 @@ def test_profile_tag_mask(ctx):
     for t in ("update", "lookahead", "panel", "assemble", "trsm", "solve", "resid"):
         assert p[t]["launches"] > 0 and p[t]["ms"] > 0, (t, p[t])
     with pytest.raises(gdm.GDMError) as e:
-        ctx._check(ctx._call("gdm_profile_mask", ctx.h, 1 << 11))
+        ctx._check(ctx._call("gdm_profile_mask", ctx.h, 1 << 12))
     assert e.value.status == gdm.GDM_E_ARG
 
 
 # ---------------------------------------------------------------------------
 # full size: the 12 000-unknown benchmark workload against stored oracle values
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("pivoting", [1, 4])
 @pytest.mark.parametrize("prec", [1, 0])
-def test_full_config2_vs_golden(ctx, prec):
-    """n = 12 000, 66 RHS, in the launch configuration bench.py times: every
-    cross section, the 2-norm of every column of q and F, and q, F at 97 seeded
-    sample unknowns of every RHS against tests/golden/config2_samples.npz (written
-    by tests/golden/make_golden.py from the oracle)."""
+def test_full_config2_vs_golden(ctx, prec, pivoting):
+    """n = 12 000, 66 RHS, in the launch configuration bench.py times (partial
+    pivoting), and with tournament pivoting over 4 columns: every cross
+    section, the 2-norm of every column of q and F, and q, F at 97 seeded sample
+    unknowns of every RHS against tests/golden/config2_samples.npz (written by
+    tests/golden/make_golden.py from the oracle)."""
     import os
-    say("full config2", "prec", prec)
+    say("full config2", "prec", prec, "pivoting", pivoting)
     ref = np.load(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "config2_samples.npz"))
     w = gi.config2()
     from paper_2505_09545_amd import gdm
-    out = gdm.run_forward(ctx, w, prec=prec, tol=1e-14 if prec == 1 else 0.0, probes=False)
+    ctx.set_pivoting(pivoting)
+    try:
+        out = gdm.run_forward(ctx, w, prec=prec, tol=1e-14 if prec == 1 else 0.0, probes=False)
+    finally:
+        ctx.set_pivoting(0)
     q = out["q"]
     f = out["f"]
     qn = torch.linalg.vector_norm(q, dim=1).cpu().numpy()
