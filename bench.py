@@ -99,6 +99,65 @@ def cpu_baseline(sample_cells: int, threads: int = 0) -> dict:
                        f"cross sections in FP64 NumPy/SciPy")
 
 
+def coupling_flops(n_cell: int, n_eff: int, nrhs: int) -> float:
+    """FP64 flops of one matrix-free product with M (every ordered pair of
+    distinct dipoles): the dyad (about 100) per pair, then per RHS G^Ep p (72),
+    and for an effective target h x p (48), for an effective source G^Em m (48),
+    for both eps G^Ep m (84)."""
+    N = n_cell + n_eff
+    pairs = float(N) * (N - 1)
+    per_rhs = 72.0 * pairs + 48.0 * n_eff * (N - 1) * 2 + 84.0 * n_eff * max(n_eff - 1, 0)
+    return FIELD_PAIR_FLOPS * pairs + nrhs * per_rhs
+
+
+def iterative_timing(gdm) -> dict:
+    """The matrix-free GMRES solve (gdm_solve_iterative, relative residual
+    1e-13): the n = 69 000 hybrid workload (no matrix stored) and the
+    n = 12 000 benchmark structure with its two normal-incidence plane waves.
+    Seconds of the solve call, products with M, and the FP64 VALU rate of the
+    products (HIP events on the product's launches, after one untimed solve)."""
+    import torch
+    import gdm_inputs as gi
+    out = {}
+    for tag, w in (("cfg5", gi.config5(probes=1)), ("cfg2_2rhs", None)):
+        if w is None:
+            w = gi.config2()
+            w = dict(w, khat=w["khat"][:2], e0=w["e0"][:2])
+        ctx = gdm.Context(0)
+        try:
+            r_eff = w.get("r_eff")
+            ne = 0 if r_eff is None else len(r_eff)
+            ctx.set_environment(w["n_env"])
+            ctx.set_structure(torch.as_tensor(w["r_cell"]), w["step"], torch.as_tensor(w["eps_cell"]),
+                              torch.as_tensor(r_eff) if ne else None,
+                              torch.as_tensor(w["alpha_eff"]) if ne else None)
+            ctx.set_wavelength(w["wavelength"])
+            khat, e0, e2 = gdm.plane_wave_inputs(w, ctx)
+            f0 = ctx.incident_planewave(khat, e0)
+            ctx.solve_iterative(w["wavelength"], f0, tol=1e-13)
+            torch.cuda.synchronize()
+            ctx.profile(True, tags=["iter_matvec"])
+            t0 = time.perf_counter()
+            ctx.solve_iterative(w["wavelength"], f0, tol=1e-13)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            pm = ctx.profile_read()["iter_matvec"]
+            ctx.profile(False)
+            nrhs = f0.shape[0]
+            fl = coupling_flops(len(w["r_cell"]), ne, nrhs) * pm["launches"]
+            out.update({f"iter_{tag}_n": ctx.n, f"iter_{tag}_nrhs": nrhs, f"iter_{tag}_s": dt,
+                        f"iter_{tag}_products": int(ctx.info.ir_iters),
+                        f"iter_{tag}_relres": float(ctx.info.backward_err),
+                        f"iter_{tag}_matvec_ms": pm["ms"] / max(pm["launches"], 1),
+                        f"iter_{tag}_matvec_frac_fp64_valu": fl / (pm["ms"] * 1e-3) / 1e12 / PEAK_FP64_VALU
+                        if pm["ms"] > 0 else None,
+                        f"iter_{tag}_device_bytes": int(ctx.memory_used())})
+        finally:
+            ctx.close()
+            torch.cuda.empty_cache()
+    return out
+
+
 def config1_timing(ctx, gdm, steps: int, warmup: int) -> dict:
     """The 257-cell sphere (gdm_inputs.config1) in plain FP64: assembly + LU,
     incident field, solve (2 plane waves), cross sections and the fields at 1000
@@ -108,7 +167,7 @@ def config1_timing(ctx, gdm, steps: int, warmup: int) -> dict:
     w = gi.config1()
     dev = ctx.device
     rp = torch.as_tensor(w["r_probe"], dtype=torch.float64, device=dev)
-    khat, e0, e2 = gdm.plane_wave_inputs(w, dev)
+    khat, e0, e2 = gdm.plane_wave_inputs(w, ctx)
     ctx.set_environment(w["n_env"])
     ctx.set_structure(torch.as_tensor(w["r_cell"]), w["step"], torch.as_tensor(w["eps_cell"]))
 
@@ -147,7 +206,7 @@ def config5_timing(gdm) -> dict:
         ctx.set_structure(torch.as_tensor(w["r_cell"]), w["step"], torch.as_tensor(w["eps_cell"]),
                           torch.as_tensor(w["r_eff"]), torch.as_tensor(w["alpha_eff"]))
         n = ctx.n
-        khat, e0, e2 = gdm.plane_wave_inputs(w, dev)
+        khat, e0, e2 = gdm.plane_wave_inputs(w, ctx)
         rp = torch.as_tensor(w["r_probe"], dtype=torch.float64, device=dev)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -306,7 +365,8 @@ def main() -> int:
     ap.add_argument("--batch-wavelengths", type=int, default=0, help="only the first L wavelengths (0: all)")
     ap.add_argument("--no-cfg1", action="store_true", help="skip the 257-cell sphere (config 1) timing")
     ap.add_argument("--no-cfg5", action="store_true", help="skip the n = 69 000 hybrid workload with 10^6 probes")
-    ap.add_argument("--cpu-1thread-cells", type=int, default=1500,
+    ap.add_argument("--no-iterative", action="store_true", help="skip the matrix-free GMRES timing")
+    ap.add_argument("--cpu-1thread-cells", type=int, default=2400,
                     help="cells of the single-thread oracle sample (0: skip)")
     ap.add_argument("--copy-calib-mb", type=int, default=0,
                     help="after the timed region, run one device copy of this many MiB (a known-size kernel "
@@ -327,7 +387,7 @@ def main() -> int:
     ctx.set_environment(w["n_env"])
     ctx.set_structure(torch.as_tensor(w["r_cell"]), w["step"], torch.as_tensor(w["eps_cell"]))
     n = ctx.n
-    khat, e0, e2 = gdm.plane_wave_inputs(w, dev)
+    khat, e0, e2 = gdm.plane_wave_inputs(w, ctx)
     nrhs = len(w["khat"])
     wl = w["wavelength"]
 
@@ -444,6 +504,8 @@ def main() -> int:
     ctx.close()
     if not args.no_cfg5:
         line.update(config5_timing(gdm))
+    if not args.no_iterative:
+        line.update(iterative_timing(gdm))
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_sample_cells)
         if args.cpu_1thread_cells > 0:

@@ -176,6 +176,16 @@ gdm_status gdm_planewave(gdm_ctx* ctx, int64_t n_pw, const double* khat, const d
 gdm_status gdm_fields(gdm_ctx* ctx, int64_t n_rhs, const double* q, int64_t n_probe, const double* r_probe,
                       double* E_sca, double* H_sca);
 
+/* Step (c), total field: E = E_inc + E_sca and H = H_inc + H_sca at the probes
+ * for moments q [n_rhs][n] of plane-wave illuminations khat [n_rhs][3], e0
+ * [n_rhs][3] complex (as in gdm_planewave); otherwise as gdm_fields. */
+gdm_status gdm_fields_total(gdm_ctx* ctx, int64_t n_rhs, const double* q, const double* khat, const double* e0,
+                            int64_t n_probe, const double* r_probe, double* E, double* H);
+
+/* Intensity |E0|^2 = sum_a |e0[r][a]|^2 of plane-wave amplitudes e0 [n_pw][3]
+ * complex, into out [n_pw] (device; the normalisation of gdm_cross_sections). */
+gdm_status gdm_planewave_intensity(gdm_ctx* ctx, int64_t n_pw, const double* e0, double* out);
+
 /* Step (c) for callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * computation, arguments, layouts and errors as gdm_fields, and the same result

@@ -48,12 +48,10 @@ def _forward(sim: GDMSetup, r_cell, eps_cell, wl: float, r_eff):
     e0 = c._dev(sim.e0, torch.complex128, None, "e0").reshape(-1, 3)
     f0 = c.incident_planewave(khat, e0)
     q, f = c.solve(f0, tol=sim.tol)
-    e2 = (e0.abs() ** 2).sum(dim=1)
+    e2 = c.planewave_intensity(e0)
     cs = c.cross_sections(f0, q, f, e2)[:, :3].contiguous()
     if sim.r_probe is not None and len(sim.r_probe):
-        E_inc, _ = c.planewave(khat, e0, sim.r_probe, want_h=False)
-        E_sca, _ = c.fields(q, sim.r_probe, want_h=False)
-        E = E_inc + E_sca
+        E, _ = c.fields_total(q, khat, e0, sim.r_probe, want_h=False)
     else:
         E = torch.zeros((len(khat), 0, 3), dtype=torch.complex128, device=c.device)
     return khat, e0, f0, q, f, cs, E

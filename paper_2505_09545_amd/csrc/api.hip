@@ -1197,7 +1197,8 @@ gdm_status gdm_adjoint(gdm_ctx* c, int64_t nrhs, const double* khat, const doubl
 // Probe fields of gdm_fields and gdm_fields_noalloc: partial sums of the dipole
 // splits in `part` (capacity part_cap bytes), the probe-on-dipole flag at `flag`.
 static gdm_status fields_core(gdm_ctx* c, int64_t nrhs, const double* q, int64_t P, const double* rp, double* E,
-                              double* H, void* part, size_t part_cap, int* flag_dev, int nsplit, bool prof) {
+                              double* H, void* part, size_t part_cap, int* flag_dev, int nsplit, bool prof,
+                              const double* khat = nullptr, const double* e0 = nullptr) {
   const Wave w = wave_of(c, c->wavelength);
   const DipoleView d = view_of(c, make_double2(0, 0));
   if (fields_scratch_bytes(nrhs, P, nsplit, H != nullptr) > part_cap)
@@ -1210,6 +1211,9 @@ static gdm_status fields_core(gdm_ctx* c, int64_t nrhs, const double* q, int64_t
                           reinterpret_cast<double2*>(H), static_cast<double2*>(part), nsplit, rmin * rmin, flag_dev,
                           c->stream));
   if (prof) HIPCHK(c, c->prof.end(c->stream));
+  if (khat)  // total field: add the incident plane waves
+    HIPCHK(c, launch_planewave_points(w, c->n_env, nrhs, khat, reinterpret_cast<const double2*>(e0), rp, P,
+                                      reinterpret_cast<double2*>(E), reinterpret_cast<double2*>(H), c->stream, true));
   int flag = 0;
   HIPCHK(c, hipMemcpyAsync(&flag, flag_dev, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1237,6 +1241,29 @@ gdm_status gdm_fields(gdm_ctx* c, int64_t nrhs, const double* q, int64_t P, cons
   if (need > 0) HIPCHK(c, c->scratch.ensure(need));
   HIPCHK(c, c->flag.ensure(sizeof(int) * 4));
   return fields_core(c, nrhs, q, P, rp, E, H, c->scratch.p, c->scratch.cap, c->flag.as<int>(), nsplit, true);
+}
+
+gdm_status gdm_fields_total(gdm_ctx* c, int64_t nrhs, const double* q, const double* khat, const double* e0,
+                            int64_t P, const double* rp, double* E, double* H) {
+  if (!c) return GDM_E_ARG;
+  gdm_status s = fields_check(c, nrhs, q, P, rp, E);
+  if (s != GDM_OK || P == 0) return s;
+  if (!khat || !e0) FAIL(c, GDM_E_ARG, "khat and e0 are required");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int nsplit = fields_num_splits(P, c->N, c->num_cu);
+  const size_t need = fields_scratch_bytes(nrhs, P, nsplit, H != nullptr);
+  if (need > 0) HIPCHK(c, c->scratch.ensure(need));
+  HIPCHK(c, c->flag.ensure(sizeof(int) * 4));
+  return fields_core(c, nrhs, q, P, rp, E, H, c->scratch.p, c->scratch.cap, c->flag.as<int>(), nsplit, true, khat,
+                     e0);
+}
+
+gdm_status gdm_planewave_intensity(gdm_ctx* c, int64_t n_pw, const double* e0, double* out) {
+  if (!c) return GDM_E_ARG;
+  if (n_pw <= 0 || !e0 || !out) FAIL(c, GDM_E_ARG, "need n_pw > 0, e0 and out");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, launch_pw_intensity(n_pw, reinterpret_cast<const double2*>(e0), out, c->stream));
+  return GDM_OK;
 }
 
 gdm_status gdm_fields_noalloc(gdm_ctx* c, int64_t nrhs, const double* q, int64_t P, const double* rp, double* E,

@@ -15,9 +15,13 @@ hipError_t launch_cell_alpha(const double2* eps, int64_t nc, double eps_env, dou
 hipError_t launch_incident(const DipoleView& d, const Wave& w, double n_env, int64_t n_pw, const double* khat,
                            const double2* e0, double2* f0, int64_t n, hipStream_t st);
 
-// Plane wave at arbitrary points: E, H [n_pw][P][3] (H nullable).
+// Plane wave at arbitrary points: E, H [n_pw][P][3] (H nullable); accumulate:
+// added to E, H instead of written.
 hipError_t launch_planewave_points(const Wave& w, double n_env, int64_t n_pw, const double* khat, const double2* e0,
-                                   const double* r, int64_t P, double2* E, double2* H, hipStream_t st);
+                                   const double* r, int64_t P, double2* E, double2* H, hipStream_t st,
+                                   bool accumulate = false);
+// out[r] = |e0[r]|^2 for n_pw plane-wave amplitudes e0 [n_pw][3]
+hipError_t launch_pw_intensity(int64_t n_pw, const double2* e0, double* out, hipStream_t st);
 
 // q = A F in the unknown layout (cells: alpha F; effective: alpha6 (E, H)).
 hipError_t launch_apply_alpha(const DipoleView& d, const double2* F, int64_t ldf, double2* q, int64_t ldq,

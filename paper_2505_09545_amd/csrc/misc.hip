@@ -71,6 +71,9 @@ hipError_t launch_incident(const DipoleView& d, const Wave& w, double n_env, int
   return hipGetLastError();
 }
 
+// ACC: add the plane wave to E (and H) instead of writing it (total field at
+// probes = incident + scattered).
+template <bool ACC>
 __global__ void planewave_points_kernel(Wave w, double n_env, int64_t n_pw, const double* khat, const double2* e0,
                                         const double* rp, int64_t P, double2* E, double2* H) {
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -81,22 +84,44 @@ __global__ void planewave_points_kernel(Wave w, double n_env, int64_t n_pw, cons
   const double2* e = e0 + 3 * r;
   const double2 ex = cmul(e[0], ph), ey = cmul(e[1], ph), ez = cmul(e[2], ph);
   double2* oe = E + (r * P + p) * 3;
-  oe[0] = ex;
-  oe[1] = ey;
-  oe[2] = ez;
+  oe[0] = ACC ? cadd(oe[0], ex) : ex;
+  oe[1] = ACC ? cadd(oe[1], ey) : ey;
+  oe[2] = ACC ? cadd(oe[2], ez) : ez;
   if (H) {
     double2* oh = H + (r * P + p) * 3;
-    oh[0] = cscale(csub(cscale(ez, ky), cscale(ey, kz)), n_env);
-    oh[1] = cscale(csub(cscale(ex, kz), cscale(ez, kx)), n_env);
-    oh[2] = cscale(csub(cscale(ey, kx), cscale(ex, ky)), n_env);
+    const double2 hx = cscale(csub(cscale(ez, ky), cscale(ey, kz)), n_env);
+    const double2 hy = cscale(csub(cscale(ex, kz), cscale(ez, kx)), n_env);
+    const double2 hz = cscale(csub(cscale(ey, kx), cscale(ex, ky)), n_env);
+    oh[0] = ACC ? cadd(oh[0], hx) : hx;
+    oh[1] = ACC ? cadd(oh[1], hy) : hy;
+    oh[2] = ACC ? cadd(oh[2], hz) : hz;
   }
 }
 
 hipError_t launch_planewave_points(const Wave& w, double n_env, int64_t n_pw, const double* khat, const double2* e0,
-                                   const double* r, int64_t P, double2* E, double2* H, hipStream_t st) {
+                                   const double* r, int64_t P, double2* E, double2* H, hipStream_t st,
+                                   bool accumulate) {
   if (n_pw <= 0 || P <= 0) return hipSuccess;
-  hipLaunchKernelGGL(planewave_points_kernel, dim3((unsigned)((P + 255) / 256), (unsigned)n_pw), dim3(256), 0, st, w,
-                     n_env, n_pw, khat, e0, r, P, E, H);
+  const dim3 grid((unsigned)((P + 255) / 256), (unsigned)n_pw);
+  if (accumulate)
+    hipLaunchKernelGGL(planewave_points_kernel<true>, grid, dim3(256), 0, st, w, n_env, n_pw, khat, e0, r, P, E, H);
+  else
+    hipLaunchKernelGGL(planewave_points_kernel<false>, grid, dim3(256), 0, st, w, n_env, n_pw, khat, e0, r, P, E, H);
+  return hipGetLastError();
+}
+
+// |E0|^2 = sum_a |e0[r][a]|^2 per plane wave
+__global__ void pw_intensity_kernel(int64_t n_pw, const double2* __restrict__ e0, double* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n_pw) return;
+  double s = 0;
+  for (int a = 0; a < 3; ++a) s += e0[3 * r + a].x * e0[3 * r + a].x + e0[3 * r + a].y * e0[3 * r + a].y;
+  out[r] = s;
+}
+
+hipError_t launch_pw_intensity(int64_t n_pw, const double2* e0, double* out, hipStream_t st) {
+  if (n_pw <= 0) return hipSuccess;
+  hipLaunchKernelGGL(pw_intensity_kernel, dim3((unsigned)((n_pw + 255) / 256)), dim3(256), 0, st, n_pw, e0, out);
   return hipGetLastError();
 }
 

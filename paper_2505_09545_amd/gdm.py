@@ -30,7 +30,7 @@ SELF_STATIC, SELF_RADIATIVE = 0, 1
 EXPORTED = ["gdm_create", "gdm_destroy", "gdm_last_error", "gdm_set_memory_limit", "gdm_memory_used", "gdm_set_pivoting",
             "gdm_set_environment", "gdm_set_structure",
             "gdm_num_unknowns", "gdm_assemble", "gdm_factorize", "gdm_set_wavelength", "gdm_solve_iterative", "gdm_incident_planewave", "gdm_solve",
-            "gdm_planewave", "gdm_fields", "gdm_fields_noalloc", "gdm_cross_sections", "gdm_adjoint", "gdm_batch_spectra", "gdm_batch_tuning", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
+            "gdm_planewave", "gdm_fields", "gdm_fields_total", "gdm_planewave_intensity", "gdm_fields_noalloc", "gdm_cross_sections", "gdm_adjoint", "gdm_batch_spectra", "gdm_batch_tuning", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
             "gdm_profile", "gdm_profile_mask", "gdm_profile_read"]
 
 
@@ -77,6 +77,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gdm_planewave": ([P, I64, P, P, I64, P, P, P], ctypes.c_int),
         "gdm_fields": ([P, I64, P, I64, P, P, P], ctypes.c_int),
         "gdm_fields_noalloc": ([P, I64, P, I64, P, P, P], ctypes.c_int),
+        "gdm_fields_total": ([P, I64, P, P, P, I64, P, P, P], ctypes.c_int),
+        "gdm_planewave_intensity": ([P, I64, P, P], ctypes.c_int),
         "gdm_cross_sections": ([P, I64, P, P, P, P, I32, P], ctypes.c_int),
         "gdm_adjoint": ([P, I64, P, P, P, P, P, P, I64, P, P, D, I32, P, P, P, ctypes.POINTER(GDMInfo)],
                         ctypes.c_int),
@@ -308,6 +310,27 @@ class Context:
         self._check(st)
         return E, H
 
+    def fields_total(self, q, khat, e0, r_probe, want_h=True):
+        """Total fields E = E_inc + E_sca (and H) [n_rhs, P, 3] at r_probe for the
+        moments q of plane waves khat [n_rhs, 3], e0 [n_rhs, 3] (include/gdm.h,
+        gdm_fields_total)."""
+        q = self._dev(q, torch.complex128, None, "q")
+        k = self._dev(khat, torch.float64, (q.shape[0], 3), "khat")
+        e = self._dev(e0, torch.complex128, (q.shape[0], 3), "e0")
+        r = self._dev(r_probe, torch.float64, None, "r_probe").reshape(-1, 3)
+        E = torch.empty((q.shape[0], len(r), 3), dtype=torch.complex128, device=self.device)
+        H = torch.empty_like(E) if want_h else None
+        self._check(self._call("gdm_fields_total", self.h, q.shape[0], _ptr(q), _ptr(k), _ptr(e), len(r), _ptr(r),
+                               _ptr(E), _ptr(H)))
+        return E, H
+
+    def planewave_intensity(self, e0):
+        """|E0|^2 per plane wave of amplitudes e0 [n_pw, 3] (gdm_planewave_intensity)."""
+        e = self._dev(e0, torch.complex128, None, "e0").reshape(-1, 3)
+        out = torch.empty(len(e), dtype=torch.float64, device=self.device)
+        self._check(self._call("gdm_planewave_intensity", self.h, len(e), _ptr(e), _ptr(out)))
+        return out
+
     def fields_noalloc(self, q, r_probe, E, H=None):
         """gdm_fields_noalloc into caller-allocated outputs E (and H), each
         [n_rhs, P, 3] complex128 on the context's device; allocates nothing on
@@ -450,11 +473,12 @@ class Context:
                 for i, t in enumerate(self.PROF_TAGS)}
 
 
-def plane_wave_inputs(workload: dict, device):
-    khat = torch.as_tensor(workload["khat"], dtype=torch.float64, device=device)
-    e0 = torch.as_tensor(workload["e0"], dtype=torch.complex128, device=device)
-    e2 = (e0.abs() ** 2).sum(dim=1)
-    return khat, e0, e2
+def plane_wave_inputs(workload: dict, ctx: "Context"):
+    """Plane-wave directions and amplitudes of a workload on the context's
+    device, and their intensities |E0|^2 (computed by the library)."""
+    khat = torch.as_tensor(workload["khat"], dtype=torch.float64, device=ctx.device)
+    e0 = torch.as_tensor(workload["e0"], dtype=torch.complex128, device=ctx.device)
+    return khat, e0, ctx.planewave_intensity(e0)
 
 
 def run_forward(ctx: Context, workload: dict, prec=PREC_FP64, tol=0.0, probes=True, want_ff=False):
@@ -468,7 +492,7 @@ def run_forward(ctx: Context, workload: dict, prec=PREC_FP64, tol=0.0, probes=Tr
                       torch.as_tensor(r_eff) if ne else None,
                       torch.as_tensor(workload["alpha_eff"]) if ne else None)
     ctx.factorize(workload["wavelength"], prec)
-    khat, e0, e2 = plane_wave_inputs(workload, dev)
+    khat, e0, e2 = plane_wave_inputs(workload, ctx)
     f0 = ctx.incident_planewave(khat, e0)
     q, f = ctx.solve(f0, tol=tol)
     out = dict(f0=f0, q=q, f=f, cs=ctx.cross_sections(f0, q, f, e2, want_ff=want_ff), info=ctx.info)

@@ -78,7 +78,7 @@ def test_config5_full_size_sampled(ctx):
                       torch.as_tensor(w["r_eff"]), torch.as_tensor(w["alpha_eff"]))
     assert ctx.n == 69000
     ctx.factorize(w["wavelength"], gdm.PREC_FP32_IR)
-    khat, e0, e2 = gdm.plane_wave_inputs(w, ctx.device)
+    khat, e0, e2 = gdm.plane_wave_inputs(w, ctx)
     f0 = ctx.incident_planewave(khat, e0)
     q, f = ctx.solve(f0, tol=1e-14)
     print("  backward error", ctx.info.backward_err, "corrections", ctx.info.ir_iters, flush=True)

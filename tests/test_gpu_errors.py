@@ -51,7 +51,7 @@ def setup(ctx, w, prec):
     ctx.set_structure(torch.as_tensor(w["r_cell"]), w["step"], torch.as_tensor(w["eps_cell"]))
     ctx.factorize(w["wavelength"], prec)
     from paper_2505_09545_amd import gdm as g
-    khat, e0, e2 = g.plane_wave_inputs(w, ctx.device)
+    khat, e0, e2 = g.plane_wave_inputs(w, ctx)
     return ctx.incident_planewave(khat, e0)
 
 

@@ -77,7 +77,7 @@ def test_iterative_matches_oracle(ctx, which):
     w = workload(which)
     say("iterative vs oracle", which)
     setup(ctx, w)
-    khat, e0, e2 = gdm.plane_wave_inputs(w, ctx.device)
+    khat, e0, e2 = gdm.plane_wave_inputs(w, ctx)
     f0 = ctx.incident_planewave(khat, e0)
     q, f = ctx.solve_iterative(w["wavelength"], f0, tol=1e-13)
     print("  n", ctx.n, "products", ctx.info.ir_iters, "relres", ctx.info.backward_err, flush=True)
@@ -105,7 +105,7 @@ def test_iterative_config2_vs_golden(ctx):
     w = dict(w, khat=w["khat"][:2], e0=w["e0"][:2])
     say("iterative config2, 2 RHS")
     setup(ctx, w)
-    khat, e0, e2 = gdm.plane_wave_inputs(w, ctx.device)
+    khat, e0, e2 = gdm.plane_wave_inputs(w, ctx)
     f0 = ctx.incident_planewave(khat, e0)
     q, f = ctx.solve_iterative(w["wavelength"], f0, tol=1e-13)
     print("  products", ctx.info.ir_iters, "relres", ctx.info.backward_err, flush=True)
@@ -128,7 +128,7 @@ def test_iterative_config5_full_size_residual_rows(ctx):
     say("iterative config5 n = 69000")
     setup(ctx, w)
     assert ctx.n == 69000
-    khat, e0, e2 = gdm.plane_wave_inputs(w, ctx.device)
+    khat, e0, e2 = gdm.plane_wave_inputs(w, ctx)
     f0 = ctx.incident_planewave(khat, e0)
     q, f = ctx.solve_iterative(w["wavelength"], f0, tol=1e-13)
     relres = ctx.info.backward_err
@@ -152,7 +152,7 @@ def test_iterative_stops_at_max_iter_with_noconv(ctx):
     from paper_2505_09545_amd import gdm
     w = workload("config1")
     setup(ctx, w)
-    khat, e0, e2 = gdm.plane_wave_inputs(w, ctx.device)
+    khat, e0, e2 = gdm.plane_wave_inputs(w, ctx)
     f0 = ctx.incident_planewave(khat, e0)
     say("iterative max_iter 3")
     with pytest.raises(gdm.GDMError) as ei:
