@@ -33,6 +33,13 @@ follows (sections / equations of the paper):
 * gradients of a scalar loss by a hand-written FP64 adjoint (the paper obtains
   them by automatic differentiation, Sec. "Example: Autograd for resonance
   search").
+* point-dipole sources, the scattered part of the structured environment's
+  Green's tensor and the electric / magnetic LDOS (Sec. "Observables";
+  Appendix, illumination classes), from the same linear system; the paper
+  defers their formulas to references, the normalisation used here follows
+  from the power a dipole emits and is pinned by energy conservation (LDOS
+  times the host's emitted power = far-field power of source plus structure,
+  lossless cells with the radiative self-term) and by reciprocity.
 
 Units: nm, nm^2.  Complex values are numpy complex128.
 """
@@ -441,6 +448,59 @@ def scattered_fields(D: Dipoles, q, r_probe: np.ndarray, chunk: int = 512):
         g6 = green6(R, D.k0, D.n_env)
         out[:, p0:p1, :] = np.einsum("pjab,jbr->rpa", g6, q6)
     return out[..., 0:3], out[..., 3:6]
+
+
+# ----------------------------------------------------------------------------
+# local dipole sources, Green's tensor and LDOS of the structured environment
+# (Sec. "Observables": electric and magnetic LDOS and Green's tensors in a
+# nano-structured environment; Appendix, illumination classes: electric and
+# magnetic point-dipole sources)
+# ----------------------------------------------------------------------------
+def dipole_source_at_dipoles(D: Dipoles, r_src, d_src) -> np.ndarray:
+    """F0 [n, n_src] of point dipole sources d_src = (p, m) [n_src, 6] at r_src
+    [n_src, 3]: the source's own field G6(r_i - r_s) d_s at every dipole, in the
+    reduced layout."""
+    R = D.pos[:, None, :] - np.asarray(r_src, dtype=np.float64)[None, :, :]
+    g6 = green6(R, D.k0, D.n_env)  # [N, S, 6, 6]
+    return D.from6(np.einsum("nsab,sb->nas", g6, np.asarray(d_src, dtype=np.complex128)))
+
+
+def green_scattered(wl: Dict, r_src, r_pts, mode: str = "static"):
+    """Scattered part of the 6x6 Green's tensor of the structured environment,
+    G_sca[s, p, row, c]: the field (row 0-2 E, 3-5 H) at r_pts[p] that the
+    structure scatters under the unit source component c (p_x, p_y, p_z, m_x,
+    m_y, m_z) at r_src[s] -- the solve of M F = G(., r_s) e_c, q = A F, then
+    re-propagation.  Returns (G_sca [S, P, 6, 6], D)."""
+    D = Dipoles(wl, mode=mode)
+    M = assemble(D)
+    r_src = np.asarray(r_src, dtype=np.float64).reshape(-1, 3)
+    S = len(r_src)
+    d = np.tile(np.eye(6, dtype=np.complex128), (S, 1))  # RHS 6 s + c
+    F0 = dipole_source_at_dipoles(D, np.repeat(r_src, 6, axis=0), d)
+    F, _ = solve(M, F0)
+    q = D.from6(np.einsum("dab,dbr->dar", D.alpha6, D.to6(F)))
+    r_pts = np.asarray(r_pts, dtype=np.float64).reshape(-1, 3)
+    E, H = scattered_fields(D, q, r_pts)  # [6 S, P, 3]
+    G = np.concatenate([E, H], axis=-1).reshape(S, 6, len(r_pts), 6)
+    return G.transpose(0, 2, 3, 1), D
+
+
+def ldos(wl: Dict, r_src, mode: str = "static") -> np.ndarray:
+    """Partial LDOS of electric and magnetic point dipoles at r_src along x, y,
+    z relative to the homogeneous host, [S, 2, 3]: a unit dipole d emits
+    (omega/2) Im(d^* . F(r_s)) with F its total field at itself; the host's part
+    is the radiation reaction Im G^Ep(0) = (2/3) k^3/eps_env I (Im G^Hm(0) =
+    (2/3) k^3 I), so rho_e,a/rho_0 = 1 + (3/2)(eps_env/k^3) Im G_sca^Ep_aa(r_s,
+    r_s) and rho_m,a/rho_0 = 1 + (3/2)(1/k^3) Im G_sca^Hm_aa(r_s, r_s)."""
+    G, D = green_scattered(wl, r_src, r_src, mode)
+    S = G.shape[0]
+    out = np.zeros((S, 2, 3))
+    k3 = D.k ** 3
+    for s in range(S):
+        for a in range(3):
+            out[s, 0, a] = 1.0 + 1.5 * D.eps_env / k3 * G[s, s, a, a].imag
+            out[s, 1, a] = 1.0 + 1.5 / k3 * G[s, s, 3 + a, 3 + a].imag
+    return out
 
 
 # ----------------------------------------------------------------------------

@@ -464,3 +464,89 @@ def test_matvec_rows_equals_assembled_product():
         got, scale = O.matvec_rows(D, rows, x)
         assert np.max(np.abs(got - full[rows]) / scale) < 1e-14
         assert np.all(scale >= np.abs(full[rows]) * (1 - 1e-12))
+
+
+def _lossless_cells():
+    """18 lossless cells (3 x 3 x 2, 20 nm, eps 9) in n_env 1.2 at 500 nm."""
+    w = dict(gi.config1())
+    w["r_cell"] = gi.cuboid_cells(3, 3, 2, 20.0)
+    w["step"] = 20.0
+    w["eps_cell"] = np.full(len(w["r_cell"]), 9.0 + 0j)
+    w["n_env"] = 1.2
+    w["wavelength"] = 500.0
+    return w
+
+
+def test_ldos_equals_radiated_power_ratio_when_lossless():
+    """Energy conservation pins the LDOS normalisation, the source fields and
+    the Green's tensor orientation: with lossless cells and the radiative
+    self-term (so the cells carry their radiation reaction), the power a unit
+    electric or magnetic dipole emits next to the structure, rho/rho_0 times its
+    power in the host, equals the far-field power of the source plus the induced
+    dipoles, computed by quadrature of the far-field amplitude (pinned above
+    against the exact double sum).  Every orientation, at 1e-12."""
+    w = _lossless_cells()
+    r0 = np.array([[30.0, -20.0, 65.0]])
+    L = O.ldos(w, r0, mode="radiative")
+    D = O.Dipoles(w, mode="radiative")
+    M = O.assemble(D)
+    wl2 = dict(w, r_eff=r0, alpha_eff=np.zeros((1, 6, 6), complex))
+    D2 = O.Dipoles(wl2, mode="radiative")  # the structure plus the source as a point dipole
+    for kind in (0, 1):
+        for a in range(3):
+            src = np.zeros(6, complex)
+            src[3 * kind + a] = 1.0
+            F0 = O.dipole_source_at_dipoles(D, r0, src[None, :])
+            F, _ = O.solve(M, F0)
+            q6 = np.zeros((D2.N, 6, 1), complex)
+            q6[:D.N] = np.einsum("dab,dbr->dar", D.alpha6, D.to6(F))
+            q6[D.N, :, 0] = src
+            P_tot = O.sca_farfield_quadrature(D2, D2.from6(q6), np.ones(1))[0]
+            q60 = np.zeros((D2.N, 6, 1), complex)
+            q60[D.N, :, 0] = src
+            P_0 = O.sca_farfield_quadrature(D2, D2.from6(q60), np.ones(1))[0]
+            assert abs(L[0, kind, a] - P_tot / P_0) < 1e-12, (kind, a)
+    # a lossless structure changes the LDOS (the pin is not trivially 1 = 1)
+    assert np.max(np.abs(L - 1.0)) > 0.02
+
+
+def test_green_tensor_of_structure_is_reciprocal():
+    """Reciprocity of the structured environment (isotropic cells):
+    G_sca(r1, r2) = P G_sca(r2, r1)^T P with P = diag(I, -I), for two points
+    outside the structure."""
+    w = _lossless_cells()
+    w["eps_cell"] = w["eps_cell"] + 0.7j
+    r1 = np.array([[30.0, -20.0, 65.0]])
+    r2 = np.array([[-40.0, 35.0, -55.0]])
+    G12, _ = O.green_scattered(w, r2, r1)  # source at r2, field at r1
+    G21, _ = O.green_scattered(w, r1, r2)
+    P = np.diag([1.0, 1.0, 1.0, -1.0, -1.0, -1.0])
+    assert np.max(np.abs(G12[0, 0] - P @ G21[0, 0].T @ P)) < 1e-14 * np.max(np.abs(G12))
+
+
+def test_ldos_is_one_without_a_structure():
+    """Cells with eps = eps_env have zero polarisability: nothing scatters, the
+    Green's tensor's scattered part vanishes and the LDOS is the host's."""
+    w = _lossless_cells()
+    w["eps_cell"] = np.full(len(w["r_cell"]), w["n_env"] ** 2 + 0j)
+    r0 = np.array([[30.0, -20.0, 65.0], [0.0, 0.0, -70.0]])
+    assert np.all(O.ldos(w, r0) == 1.0)
+    G, _ = O.green_scattered(w, r0, r0[::-1])
+    assert np.all(G == 0)
+
+
+def test_green_tensor_applied_to_a_source_gives_its_scattered_field():
+    """The tensor's layout (rows: field at the point, columns: source
+    components): G_sca(r, r_s) d equals the field scattered under the mixed
+    source d = (p, m) solved on its own (linearity of the solve), E and H."""
+    w = _lossless_cells()
+    w["eps_cell"] = w["eps_cell"] + 0.4j
+    r_s = np.array([[30.0, -20.0, 65.0]])
+    r_p = np.array([[-50.0, 10.0, 80.0], [5.0, 60.0, -40.0]])
+    d = np.array([0.3, -1.1j, 0.5 + 0.2j, 0.0, 0.7, -0.4j])
+    G, D = O.green_scattered(w, r_s, r_p)
+    F, _ = O.solve(O.assemble(D), O.dipole_source_at_dipoles(D, r_s, d[None, :]))
+    q = D.from6(np.einsum("dab,dbr->dar", D.alpha6, D.to6(F)))
+    E, H = O.scattered_fields(D, q, r_p)
+    ref = np.concatenate([E[0], H[0]], axis=-1)  # [P, 6]
+    assert np.max(np.abs(np.einsum("prc,c->pr", G[0], d) - ref)) < 1e-13 * np.max(np.abs(ref))
