@@ -213,6 +213,38 @@ gdm_status gdm_fields_noalloc(gdm_ctx* ctx, int64_t n_rhs, const double* q, int6
 gdm_status gdm_cross_sections(gdm_ctx* ctx, int64_t n_rhs, const double* f0, const double* q, const double* f,
                               const double* e0_norm2, int32_t want_ff, double* out);
 
+/* Point dipole sources as the illumination (Appendix, illumination classes:
+ * electric and magnetic dipole point sources): the incident field of sources
+ * d_src [n_src][6] complex (p then m) at r_src [n_src][3] on every dipole, in
+ * the unknown layout: f0 [n_src][n], F0_i = G(r_i, r_s) d_s with the dyad of Eq.
+ * superprop_G.  Uses the context wavelength.  GDM_E_PROBE_AT_DIPOLE if a
+ * source lies within 1e-9 step of a dipole. */
+gdm_status gdm_dipole_sources(gdm_ctx* ctx, int64_t n_src, const double* r_src, const double* d_src, double* f0);
+
+/* Partial LDOS of the structured environment (Sec. "Observables": electric and
+ * magnetic LDOS in a nano-structured environment) at r_src [n_src][3]
+ * (n_src <= 10922), relative to the homogeneous host: out [n_src][2][3] =
+ * (electric, magnetic) x (x, y, z),
+ *   rho_e,a / rho_0 = 1 + (3/2) (eps_env / k^3) Im G_sca^Ep_aa(r_s, r_s),
+ *   rho_m,a / rho_0 = 1 + (3/2) (1 / k^3)       Im G_sca^Hm_aa(r_s, r_s),
+ * the power a unit dipole emits there over its power in the host.  Solves the
+ * six unit sources of every point with the current factors (FP32 factors: FP64
+ * refinement to tol / max_iter as in gdm_solve; GDM_E_NOCONV if not reached,
+ * results written).  GDM_E_STATE without factors; GDM_E_PROBE_AT_DIPOLE for a
+ * point on a dipole.  info: refinement corrections and backward error. */
+gdm_status gdm_ldos(gdm_ctx* ctx, int64_t n_src, const double* r_src, double tol, int32_t max_iter, double* out,
+                    gdm_info* info);
+
+/* Scattered part of the structured environment's 6x6 Green's tensor (Sec.
+ * "The tg.Simulation class", Green's tensor of the environment defined by the
+ * structures): G [n_src][n_pts][6][6] complex, G[s][p][row][c] = field row
+ * (E_x, E_y, E_z, H_x, H_y, H_z) at r_pts[p] scattered by the structure under
+ * the unit source component c (p_x, p_y, p_z, m_x, m_y, m_z) at r_src[s]; the
+ * full tensor is the host's G(r_p, r_s) plus this part.  Solves as gdm_ldos;
+ * n_src <= 10922; GDM_E_PROBE_AT_DIPOLE for a source or point on a dipole. */
+gdm_status gdm_green_tensor(gdm_ctx* ctx, int64_t n_src, const double* r_src, int64_t n_pts, const double* r_pts,
+                            double tol, int32_t max_iter, double* G, gdm_info* info);
+
 /* Reverse mode (the paper differentiates the solver with automatic
  * differentiation, Sec. "Example: Autograd for resonance search"; here the
  * adjoint is written out).  For a real loss L that depends on the cross sections

@@ -102,6 +102,7 @@ struct gdm_ctx {
   DevBuf Lam, adj;  // adjoint field and adjoint workspace
   DevBuf part;      // split-k partial sums of the small-RHS refinement residual
   DevBuf iter;      // workspace of gdm_solve_iterative
+  DevBuf src;       // unit point sources of gdm_ldos / gdm_green_tensor: positions, moments, F0, q, fields
   // batched spectra: workspaces and the measured batch configuration per size class
   DevBuf bM64, bM32, bipiv, bws, bvec, bpart, bsmall, bpos, bwl;
   std::map<int64_t, std::pair<int, int>> batch_tune;  // n / 256 -> (items per group, nb)
@@ -115,7 +116,7 @@ struct gdm_ctx {
   MemAccount mem;    // device bytes of the buffers below and the caller's limit
   std::vector<DevBuf*> buffers() {
     return {&pos, &eps,  &alpha_c, &alpha6, &M,     &M64,  &ipiv,  &luws, &rows,   &ext_ws, &X,   &Rr,   &C32, &small,
-            &scratch, &flag, &Lam,  &adj,   &part, &bM64, &bM32, &bipiv, &bws, &bvec, &bpart, &bsmall, &bpos, &bwl, &iter};
+            &scratch, &flag, &Lam,  &adj,   &part, &bM64, &bM32, &bipiv, &bws, &bvec, &bpart, &bsmall, &bpos, &bwl, &iter, &src};
   }
 };
 
@@ -1330,6 +1331,129 @@ gdm_status gdm_cross_sections(gdm_ctx* c, int64_t nrhs, const double* f0, const 
   }
   HIPCHK(c, hipMemcpyAsync(out, o.data(), sizeof(double) * o.size(), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  return GDM_OK;
+}
+
+gdm_status gdm_dipole_sources(gdm_ctx* c, int64_t n_src, const double* r_src, const double* d_src, double* f0) {
+  if (!c) return GDM_E_ARG;
+  if (c->wavelength <= 0) FAIL(c, GDM_E_STATE, "no wavelength set (gdm_factorize or gdm_set_wavelength first)");
+  if (n_src <= 0 || !r_src || !d_src || !f0) FAIL(c, GDM_E_ARG, "need n_src > 0, r_src, d_src and f0");
+  if (n_src > 65535) FAIL(c, GDM_E_ARG, "at most 65535 sources per call");
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, c->flag.ensure(sizeof(int) * 4));
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, c->stream, c->flag.as<int>(), 1, 0);
+  const Wave w = wave_of(c, c->wavelength);
+  const double rmin = 1e-9 * c->step;
+  HIPCHK(c, launch_dipole_sources(view_of(c, make_double2(0, 0)), w, c->n, n_src, r_src,
+                                  reinterpret_cast<const double2*>(d_src), reinterpret_cast<double2*>(f0), rmin * rmin,
+                                  c->flag.as<int>(), c->stream));
+  int flag = 0;
+  HIPCHK(c, hipMemcpyAsync(&flag, c->flag.p, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (flag) FAIL(c, GDM_E_PROBE_AT_DIPOLE, "a source point lies on a dipole (|R| < 1e-9 step)");
+  return GDM_OK;
+}
+
+}  // extern "C"
+
+// The six unit sources (p_x, p_y, p_z, m_x, m_y, m_z) at each of n_src points:
+// their incident fields, the solve with the context's factors, q = A F.  On
+// return *Q points to the moments [6 n_src][n] (inside c->src; *extra bytes
+// after them are free for the caller).
+static gdm_status unit_source_moments(gdm_ctx* c, int64_t S, const double* r_src, double tol, int32_t max_iter,
+                                      size_t extra, double2** Q, char** extra_p, SolveStats& ss) {
+  const int64_t n = c->n, nr = 6 * S;
+  const size_t b_pos = (size_t)nr * 3 * sizeof(double), b_d = (size_t)nr * 6 * sizeof(double2);
+  const size_t b_vec = (size_t)nr * n * sizeof(double2);
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  HIPCHK(c, c->src.ensure(al(b_pos) + al(b_d) + 2 * al(b_vec) + al(extra)));
+  char* base = static_cast<char*>(c->src.p);
+  double* dpos = reinterpret_cast<double*>(base);
+  double2* dvec = reinterpret_cast<double2*>(base + al(b_pos));
+  double2* F0 = reinterpret_cast<double2*>(base + al(b_pos) + al(b_d));
+  *Q = reinterpret_cast<double2*>(base + al(b_pos) + al(b_d) + al(b_vec));
+  *extra_p = base + al(b_pos) + al(b_d) + 2 * al(b_vec);
+  // positions repeated six times and unit moments (the identity), set up on the host
+  std::vector<double> hpos((size_t)nr * 3);
+  std::vector<double2> hd((size_t)nr * 6, make_double2(0, 0));
+  std::vector<double> rs((size_t)S * 3);
+  HIPCHK(c, hipMemcpyAsync(rs.data(), r_src, sizeof(double) * 3 * S, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (int64_t r = 0; r < nr; ++r) {
+    for (int a = 0; a < 3; ++a) hpos[3 * r + a] = rs[3 * (r / 6) + a];
+    hd[6 * r + r % 6] = make_double2(1.0, 0.0);
+  }
+  HIPCHK(c, hipMemcpyAsync(dpos, hpos.data(), b_pos, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(dvec, hd.data(), b_d, hipMemcpyHostToDevice, c->stream));
+  gdm_status s = gdm_dipole_sources(c, nr, dpos, reinterpret_cast<const double*>(dvec), reinterpret_cast<double*>(F0));
+  if (s != GDM_OK) return s;
+  HIPCHK(c, c->X.ensure(sizeof(double2) * n * nr));
+  double2* X = c->X.as<double2>();
+  s = solve_core(c, 0, nr, F0, X, tol, max_iter, ss);
+  if (s != GDM_OK && s != GDM_E_NOCONV) return s;
+  HIPCHK(c, launch_apply_alpha(view_of(c, make_double2(0, 0)), X, n, *Q, n, nr, c->stream));
+  return s;
+}
+
+extern "C" {
+
+gdm_status gdm_ldos(gdm_ctx* c, int64_t n_src, const double* r_src, double tol, int32_t max_iter, double* out,
+                    gdm_info* info) {
+  if (!c) return GDM_E_ARG;
+  if (!c->factored) FAIL(c, GDM_E_STATE, "gdm_ldos before gdm_factorize");
+  if (n_src <= 0 || !r_src || !out) FAIL(c, GDM_E_ARG, "need n_src > 0, r_src and out");
+  if (n_src > 10922) FAIL(c, GDM_E_ARG, "at most 10922 source points per call");
+  HIPCHK(c, hipSetDevice(c->device));
+  double2* Q = nullptr;
+  char* ex = nullptr;
+  SolveStats ss;
+  const gdm_status s = unit_source_moments(c, n_src, r_src, tol, max_iter, 0, &Q, &ex, ss);
+  if (s != GDM_OK && s != GDM_E_NOCONV) return s;
+  HIPCHK(c, launch_ldos(view_of(c, make_double2(0, 0)), wave_of(c, c->wavelength), Q, c->n, n_src, r_src, out,
+                        c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (info) {
+    info->ir_iters = ss.iters;
+    info->backward_err = ss.be;
+    info->bad_index = -1;
+  }
+  if (s == GDM_E_NOCONV) FAIL(c, GDM_E_NOCONV, "refinement stopped at backward error %.3e > tol %.3e", ss.be, ss.tol);
+  return GDM_OK;
+}
+
+gdm_status gdm_green_tensor(gdm_ctx* c, int64_t n_src, const double* r_src, int64_t n_pts, const double* r_pts,
+                            double tol, int32_t max_iter, double* G, gdm_info* info) {
+  if (!c) return GDM_E_ARG;
+  if (!c->factored) FAIL(c, GDM_E_STATE, "gdm_green_tensor before gdm_factorize");
+  if (n_src <= 0 || n_pts <= 0 || !r_src || !r_pts || !G) FAIL(c, GDM_E_ARG, "bad Green's tensor arguments");
+  if (n_src > 10922) FAIL(c, GDM_E_ARG, "at most 10922 source points per call");
+  if ((n_src * n_pts * 36 + 255) / 256 > (int64_t)INT32_MAX) FAIL(c, GDM_E_ARG, "too many source-point pairs");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int64_t nr = 6 * n_src;
+  const int nsplit = fields_num_splits(n_pts, c->N, c->num_cu);
+  const size_t b_f = sizeof(double2) * (size_t)nr * n_pts * 3;
+  const size_t part = fields_scratch_bytes(nr, n_pts, nsplit, true);
+  double2* Q = nullptr;
+  char* ex = nullptr;
+  SolveStats ss;
+  const gdm_status s = unit_source_moments(c, n_src, r_src, tol, max_iter, 2 * b_f + part + 256, &Q, &ex, ss);
+  if (s != GDM_OK && s != GDM_E_NOCONV) return s;
+  double2* E = reinterpret_cast<double2*>(ex);
+  double2* H = E + (size_t)nr * n_pts * 3;
+  void* pbuf = reinterpret_cast<char*>(H + (size_t)nr * n_pts * 3);
+  HIPCHK(c, c->flag.ensure(sizeof(int) * 4));
+  const gdm_status sf = fields_core(c, nr, reinterpret_cast<const double*>(Q), n_pts, r_pts,
+                                    reinterpret_cast<double*>(E), reinterpret_cast<double*>(H), pbuf, part + 256,
+                                    c->flag.as<int>(), nsplit, true);
+  if (sf != GDM_OK) return sf;
+  HIPCHK(c, launch_green_gather(E, H, n_src, n_pts, reinterpret_cast<double2*>(G), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (info) {
+    info->ir_iters = ss.iters;
+    info->backward_err = ss.be;
+    info->bad_index = -1;
+  }
+  if (s == GDM_E_NOCONV) FAIL(c, GDM_E_NOCONV, "refinement stopped at backward error %.3e > tol %.3e", ss.be, ss.tol);
   return GDM_OK;
 }
 

@@ -53,6 +53,18 @@ hipError_t launch_rowsum_abs(const double2* M, int64_t ld, int64_t n, double* ro
 // column sums of |M| (1-norm = max column sum), out[n]
 hipError_t launch_colsum_abs(const double2* M, int64_t ld, int64_t n, double* cols, hipStream_t st);
 
+// Point dipole sources (sources.hip): F0 [n_src][n] of sources d [n_src][6]
+// (p, m) at rs [n_src][3]; a source within sqrt(min_r2) of a dipole sets *flag.
+hipError_t launch_dipole_sources(const DipoleView& d, const Wave& w, int64_t n, int64_t n_src, const double* rs,
+                                 const double2* ds, double2* f0, double min_r2, int* flag, hipStream_t st);
+// LDOS out [n_src][2][3] from the moments q [6 n_src][n] of the unit sources
+// (RHS 6 s + c: component c of (p, m) at rs[s]).
+hipError_t launch_ldos(const DipoleView& d, const Wave& w, const double2* q, int64_t n, int64_t n_src,
+                       const double* rs, double* out, hipStream_t st);
+// G [n_src][P][6][6] from the fields E, H [6 n_src][P][3] of the unit sources.
+hipError_t launch_green_gather(const double2* E, const double2* H, int64_t n_src, int64_t P, double2* G,
+                               hipStream_t st);
+
 int fields_num_splits(int64_t P, int64_t N, int num_cu);
 size_t fields_scratch_bytes(int64_t nrhs, int64_t P, int nsplit, bool want_h);
 hipError_t launch_fields(const DipoleView& d, const Wave& w, const double2* q, int64_t ldq, int64_t nrhs,

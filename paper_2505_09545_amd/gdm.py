@@ -30,7 +30,7 @@ SELF_STATIC, SELF_RADIATIVE = 0, 1
 EXPORTED = ["gdm_create", "gdm_destroy", "gdm_last_error", "gdm_set_memory_limit", "gdm_memory_used", "gdm_set_pivoting",
             "gdm_set_environment", "gdm_set_structure",
             "gdm_num_unknowns", "gdm_assemble", "gdm_factorize", "gdm_set_wavelength", "gdm_solve_iterative", "gdm_incident_planewave", "gdm_solve",
-            "gdm_planewave", "gdm_fields", "gdm_fields_total", "gdm_planewave_intensity", "gdm_fields_noalloc", "gdm_cross_sections", "gdm_adjoint", "gdm_batch_spectra", "gdm_batch_tuning", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
+            "gdm_planewave", "gdm_fields", "gdm_fields_total", "gdm_planewave_intensity", "gdm_fields_noalloc", "gdm_cross_sections", "gdm_dipole_sources", "gdm_ldos", "gdm_green_tensor", "gdm_adjoint", "gdm_batch_spectra", "gdm_batch_tuning", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
             "gdm_profile", "gdm_profile_mask", "gdm_profile_read"]
 
 
@@ -80,6 +80,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gdm_fields_total": ([P, I64, P, P, P, I64, P, P, P], ctypes.c_int),
         "gdm_planewave_intensity": ([P, I64, P, P], ctypes.c_int),
         "gdm_cross_sections": ([P, I64, P, P, P, P, I32, P], ctypes.c_int),
+        "gdm_dipole_sources": ([P, I64, P, P, P], ctypes.c_int),
+        "gdm_ldos": ([P, I64, P, D, I32, P, ctypes.POINTER(GDMInfo)], ctypes.c_int),
+        "gdm_green_tensor": ([P, I64, P, I64, P, D, I32, P, ctypes.POINTER(GDMInfo)], ctypes.c_int),
         "gdm_adjoint": ([P, I64, P, P, P, P, P, P, I64, P, P, D, I32, P, P, P, ctypes.POINTER(GDMInfo)],
                         ctypes.c_int),
         "gdm_batch_spectra": ([P, I64, P, P, P, I64, P, P, I64, P, P, ctypes.c_int, I32, D, ctypes.c_int, P, P,
@@ -355,6 +358,44 @@ class Context:
         self._check(self._call("gdm_cross_sections", self.h, f0.shape[0], _ptr(f0), _ptr(q), _ptr(f), _ptr(e2),
                                                 int(bool(want_ff)), _ptr(out)))
         return out
+
+    def dipole_sources(self, r_src, d_src):
+        """Incident field [n_src, n] of point dipoles d_src [n_src, 6] = (p, m) at
+        r_src [n_src, 3] on every dipole (gdm_dipole_sources)."""
+        r = self._dev(r_src, torch.float64, None, "r_src").reshape(-1, 3)
+        d = self._dev(d_src, torch.complex128, (len(r), 6), "d_src")
+        f0 = torch.empty((len(r), self.n), dtype=torch.complex128, device=self.device)
+        self._check(self._call("gdm_dipole_sources", self.h, len(r), _ptr(r), _ptr(d), _ptr(f0)))
+        return f0
+
+    def ldos(self, r_src, tol=0.0, max_iter=-1):
+        """Partial electric and magnetic LDOS [n_src, 2, 3] at r_src relative to
+        the host (gdm_ldos; needs factors).  After an out-of-memory error the
+        points are evaluated in halves."""
+        r = self._dev(r_src, torch.float64, None, "r_src").reshape(-1, 3)
+        out = torch.empty((len(r), 2, 3), dtype=torch.float64, device=self.device)
+        st = self._call("gdm_ldos", self.h, len(r), _ptr(r), float(tol), int(max_iter), _ptr(out),
+                        ctypes.byref(self.info))
+        if st == GDM_E_OOM and len(r) > 1:
+            h = len(r) // 2
+            return torch.cat([self.ldos(r[:h], tol, max_iter), self.ldos(r[h:], tol, max_iter)])
+        self._check(st)
+        return out
+
+    def green_tensor(self, r_src, r_pts, tol=0.0, max_iter=-1):
+        """Scattered 6x6 Green's tensor [n_src, n_pts, 6, 6] of the structured
+        environment (gdm_green_tensor; needs factors); halves the source points
+        after an out-of-memory error."""
+        r = self._dev(r_src, torch.float64, None, "r_src").reshape(-1, 3)
+        p = self._dev(r_pts, torch.float64, None, "r_pts").reshape(-1, 3)
+        G = torch.empty((len(r), len(p), 6, 6), dtype=torch.complex128, device=self.device)
+        st = self._call("gdm_green_tensor", self.h, len(r), _ptr(r), len(p), _ptr(p), float(tol), int(max_iter),
+                        _ptr(G), ctypes.byref(self.info))
+        if st == GDM_E_OOM and len(r) > 1:
+            h = len(r) // 2
+            return torch.cat([self.green_tensor(r[:h], p, tol, max_iter), self.green_tensor(r[h:], p, tol, max_iter)])
+        self._check(st)
+        return G
 
     def adjoint(self, khat, e0, f0, q, f, g_sigma=None, r_probe=None, g_e=None, tol=0.0, max_iter=-1):
         """Reverse pass (include/gdm.h, gdm_adjoint): returns (grad_r [N, 3],
