@@ -86,17 +86,27 @@ int64_t gdm_memory_used(const gdm_ctx* ctx);
 
 /* Pivoting of the next LU factorisations of this context (gdm_factorize,
  * gdm_getrf, gdm_batch_spectra); the paper factors by LU with partial
- * pivoting (Sec. "Numerical solution").  columns_per_exchange = 1: partial
- * pivoting, the largest |re| + |im| in each column (compared in FP32), lowest
- * row on ties -- LAPACK's pivot sequence up to such near-ties; 2, 4 or 8:
- * tournament pivoting, where the LU panel's workgroups each pick that many
- * candidate rows for that many columns by partial pivoting on their own rows,
- * and the pivots are chosen by partial pivoting among all candidates (one
- * device-wide exchange per that many columns instead of one per column; FP64
- * factorisations use at most 4); 0: the library default (1).  The factors
- * satisfy P M = L U either way; the row interchanges may differ.  GDM_E_ARG for
- * other values. */
+ * pivoting (Sec. "Numerical solution").  Every mode yields P M = L U.
+ *   1: partial pivoting, the largest |re| + |im| in each column (compared in
+ *      FP32), lowest row on ties -- LAPACK's pivot sequence up to such
+ *      near-ties -- searched column by column across the device;
+ *   2, 4 or 8: tournament pivoting, where the LU panel's workgroups each pick
+ *      that many candidate rows for that many columns by partial pivoting on
+ *      their own rows, and the pivots are chosen by partial pivoting among all
+ *      candidates (one device-wide exchange per that many columns; FP64
+ *      factorisations use at most 4); the row interchanges may differ;
+ *   0 (the default): speculative partial pivoting in gdm_factorize -- the
+ *      diagonal is taken as the pivot of every column without a search, and
+ *      every entry that partial pivoting would compare it with is checked
+ *      against it by the same rule; if any check fails (or a pivot is zero or
+ *      not finite) the matrix is assembled again and factored with mode 1, so
+ *      the pivots are partial pivoting's either way (near-ties aside);
+ *      gdm_getrf and gdm_batch_spectra use mode 1.
+ * GDM_E_ARG for other values. */
 gdm_status gdm_set_pivoting(gdm_ctx* ctx, int32_t columns_per_exchange);
+/* Factorisations of this context (since gdm_create) whose speculative panels
+ * failed their check and were repeated with the pivot search; -1 for NULL. */
+int64_t gdm_pivot_fallbacks(const gdm_ctx* ctx);
 
 /* Real refractive index of the lossless homogeneous host (Appendix, tg.env
  * EnvHomogeneous3D).  Must be > 0.  Invalidates the factors. */

@@ -1,6 +1,7 @@
 // C-ABI of libgdm (declared in include/gdm.h): context, device buffers, argument
 // validation and the host drivers that chain the kernels of the hot path.
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <cmath>
@@ -113,6 +114,8 @@ struct gdm_ctx {
   bool lookahead = true;
   std::vector<hipEvent_t> lu_events;
   int pivot_pb = 0;  // panel columns per pivot exchange (gdm_set_pivoting; 0: the library default)
+  int64_t pivot_fallbacks = 0;         // speculative factorisations repeated with the pivot search
+  int32_t spec_first_failed_block = -1;  // of the last such repetition
   MemAccount mem;    // device bytes of the buffers below and the caller's limit
   std::vector<DevBuf*> buffers() {
     return {&pos, &eps,  &alpha_c, &alpha6, &M,     &M64,  &ipiv,  &luws, &rows,   &ext_ws, &X,   &Rr,   &C32, &small,
@@ -181,12 +184,19 @@ static gdm_status check_wavelength(gdm_ctx* c, double wl) {
 // choice (gdm_set_pivoting), else partial pivoting.  Measured at n = 12 000
 // (FP32+IR step, panels beside the look-ahead update): 5.14 us per column with
 // partial pivoting, 7.1-7.9 with tournaments over 2, 4 or 8 columns.
-static int panel_pb(const gdm_ctx* c) { return c->pivot_pb > 0 ? c->pivot_pb : 1; }
+// Panel mode of a factorisation (lu_plan's pb): by default speculative panels
+// (0) where the caller can rebuild the matrix after a failed check, else the
+// pivot search in every column (1); otherwise what gdm_set_pivoting chose.
+static int panel_pb(const gdm_ctx* c, bool can_rebuild) {
+  return c->pivot_pb > 0 ? c->pivot_pb : (can_rebuild ? 0 : 1);
+}
 
+// rebuild (may be null): writes the matrix into A again, so that a speculative
+// factorisation whose check failed can be repeated with the pivot search.
 template <typename T>
 static gdm_status run_lu(gdm_ctx* c, void* A, int64_t n, int64_t ld, LUPlan& plan, DevBuf& ws, DevBuf& ipiv,
-                         int32_t* ipiv_out, gdm_info* info) {
-  plan = lu_plan(n, (int)sizeof(T), c->num_cu, c->lds_bytes, 1, 128, panel_pb(c));
+                         int32_t* ipiv_out, gdm_info* info, const std::function<hipError_t()>& rebuild = nullptr) {
+  plan = lu_plan(n, (int)sizeof(T), c->num_cu, c->lds_bytes, 1, 128, panel_pb(c, (bool)rebuild));
   const size_t wsb = lu_workspace_bytes(plan, (int)sizeof(T), c->num_cu);
   HIPCHK(c, ws.ensure(wsb));
   LUWork w;
@@ -200,8 +210,25 @@ static gdm_status run_lu(gdm_ctx* c, void* A, int64_t n, int64_t ld, LUPlan& pla
   HIPCHK(c, lu_factor<T>(A, ld, plan, w, piv, c->stream, &c->prof, c->lookahead ? c->side : nullptr));
   int32_t err[2] = {0, 0};
   HIPCHK(c, hipMemcpyAsync(err, w.err, sizeof(err), hipMemcpyDeviceToHost, c->stream));
+  std::vector<int32_t> flags;
+  if (plan.spec) {
+    flags.resize(plan.blocks.size());
+    HIPCHK(c, hipMemcpyAsync(flags.data(), w.spec, sizeof(int32_t) * flags.size(), hipMemcpyDeviceToHost, c->stream));
+  }
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->prof.collect();
+  const auto failed = std::find_if(flags.begin(), flags.end(), [](int32_t f) { return f != 0; });
+  if (failed != flags.end()) {
+    // a diagonal pivot is not partial pivoting's: again, with the pivot search
+    c->spec_first_failed_block = (int32_t)(failed - flags.begin());
+    ++c->pivot_fallbacks;
+    HIPCHK(c, rebuild());
+    plan.spec = false;
+    HIPCHK(c, lu_factor<T>(A, ld, plan, w, piv, c->stream, &c->prof, c->lookahead ? c->side : nullptr));
+    HIPCHK(c, hipMemcpyAsync(err, w.err, sizeof(err), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->prof.collect();
+  }
   if (info) info->bad_index = -1;
   if (err[0] != 0) FAIL(c, GDM_E_DEVICE, "LU panel barrier timed out (workgroups not co-resident?)");
   if (err[1] != INT32_MAX) {
@@ -419,7 +446,7 @@ static bool batch_shape_for(gdm_ctx* c, int64_t n, int B, int nb_max, bool ir, B
   const int eb = ir ? 4 : 8;
   sh.n = n;
   sh.B = B;
-  sh.plan = lu_plan(n, eb, c->num_cu, c->lds_bytes, B, nb_max, panel_pb(c));
+  sh.plan = lu_plan(n, eb, c->num_cu, c->lds_bytes, B, nb_max, panel_pb(c, false));
   sh.nb = sh.plan.nb;
   return sh.plan.nb >= 32 && lu_plan_fits(sh.plan) && sh.plan.max_wg * B <= c->num_cu;
 }
@@ -869,6 +896,8 @@ gdm_status gdm_set_pivoting(gdm_ctx* c, int32_t columns_per_exchange) {
   return GDM_OK;
 }
 
+int64_t gdm_pivot_fallbacks(const gdm_ctx* c) { return c ? c->pivot_fallbacks : -1; }
+
 gdm_status gdm_set_environment(gdm_ctx* c, double n_env) {
   if (!c) return GDM_E_ARG;
   if (!(n_env > 0.0) || !std::isfinite(n_env)) FAIL(c, GDM_E_ARG, "n_env must be finite and > 0 (got %g)", n_env);
@@ -961,8 +990,15 @@ gdm_status gdm_factorize(gdm_ctx* c, double wl, gdm_precision prec, gdm_info* in
     HIPCHK(c, launch_rowsum_abs(c->M64.as<double2>(), n, n, c->rows.as<double>(), c->stream));
   }
   HIPCHK(c, hipEventRecord(c->ev[1], c->stream));
-  if (prec == GDM_PREC_FP64) s = run_lu<double>(c, c->M.p, n, n, c->plan, c->luws, c->ipiv, nullptr, info);
-  else s = run_lu<float>(c, c->M.p, n, n, c->plan, c->luws, c->ipiv, nullptr, info);
+  // a failed speculative panel needs the matrix again: assembled anew (FP64), or
+  // both copies assembled anew (FP32 + IR; the FP64 copy is unchanged by then,
+  // and assembling is as fast as converting it)
+  auto rebuild = [&]() -> hipError_t {
+    if (prec == GDM_PREC_FP64) return launch_assemble<double>(d, w, c->M.p, n, c->stream);
+    return launch_assemble_dual(d, w, c->M64.as<double2>(), c->M.as<float2>(), n, c->stream);
+  };
+  if (prec == GDM_PREC_FP64) s = run_lu<double>(c, c->M.p, n, n, c->plan, c->luws, c->ipiv, nullptr, info, rebuild);
+  else s = run_lu<float>(c, c->M.p, n, n, c->plan, c->luws, c->ipiv, nullptr, info, rebuild);
   if (s != GDM_OK) return s;
   HIPCHK(c, hipEventRecord(c->ev[2], c->stream));
   HIPCHK(c, hipEventSynchronize(c->ev[2]));

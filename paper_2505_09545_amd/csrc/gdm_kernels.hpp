@@ -197,6 +197,7 @@ struct LUPlan {
   int nb = 0;
   int max_wg = 0;  // number of CUs: upper bound on panel workgroups
   int pb = 1;      // panel columns per pivot exchange (1: partial pivoting; 2, 4, 8: tournament)
+  bool spec = false;  // speculative panels (diagonal pivots checked against partial pivoting; pb = 1 plan)
   std::vector<LUBlock> blocks;
 };
 
@@ -214,12 +215,14 @@ struct LUWork {
   int32_t* err;              // [2] (shared): exchange timeout flag, first zero pivot (INT32_MAX if none)
   int32_t* pairs;            // [nblocks][2][2 nb]: destination rows then source rows
   int32_t* npairs;           // [nblocks]
+  int32_t* spec;             // [nblocks] speculative panel failed its check (after npairs, same item stride)
   void* tmp;                 // [tmp_elems] complex scratch (operand copies, split-k partials, solve sweeps)
   void* dinv;                // [nblocks][nb][nb] complex inverses of the diagonal triangles
+  void* upk;                 // speculative panels: packed U11 of the current block and its pivots' reciprocals
   std::vector<hipEvent_t>* events;  // host-side pool of reusable events (look-ahead)
   int64_t tmp_elems;         // capacity of tmp per item in complex elements
   int nbatch = 1;
-  int64_t s_cand = 0, s_rows = 0, s_pairs = 0, s_npairs = 0, s_tmp = 0, s_dinv = 0;
+  int64_t s_cand = 0, s_rows = 0, s_pairs = 0, s_npairs = 0, s_tmp = 0, s_dinv = 0, s_upk = 0;
   size_t bytes = 0;          // total size (set by lu_workspace_carve)
 };
 
@@ -227,7 +230,8 @@ struct LUWork {
 // launch, so each panel gets at most num_cu / nbatch workgroups).
 // pb: panel columns per pivot exchange (1: partial pivoting with LAPACK's
 // pivots; 2, 4 or 8: tournament pivoting, reduced when the candidates of the
-// widest panel would exceed 1024 or its rows would not fit the LDS).
+// widest panel would exceed 1024 or its rows would not fit the LDS; 0:
+// speculative panels, a partial-pivoting plan with `spec` set).
 LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch = 1, int nb_max = 128, int pb = 1);
 // one-time host-side kernel settings for a plan (call before graph capture)
 template <typename T>

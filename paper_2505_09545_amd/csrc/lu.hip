@@ -1545,6 +1545,246 @@ static hipError_t launch_block_trsm(const cplx<T>* A, int64_t ld, int64_t n, int
 }
 
 // ---------------------------------------------------------------------------
+// 1c. speculative panel: diagonal pivots, checked against partial pivoting
+// ---------------------------------------------------------------------------
+// Partial pivoting keeps the diagonal entry of column j as its pivot exactly
+// when no entry below it is larger in |re| + |im| (compared in FP32, lowest row
+// on ties: the rule of panel_kernel).  The coupling matrices of dielectric
+// structures are diagonally dominant enough for that to hold in every column,
+// and then the panel needs no pivot search at all: one workgroup factors the
+// diagonal block, and the rows below follow from L21 = A21 U11^-1, a
+// triangular solve per row.  The entries partial pivoting would have compared
+// in column j are a_ij = l_ij u_jj (the column after the eliminations of the
+// earlier columns), so each kernel checks |a_ij| <= |u_jj| for its rows; a
+// failure, a zero pivot or a NaN sets the block's flag, and the caller repeats
+// the factorisation with the pivot search (panel_kernel).  When no flag is set
+// the factors are those of partial pivoting, up to the rounding order of the
+// entries compared (near-ties within FP32 rounding may resolve either way).
+template <typename CT>
+__device__ inline float cabs1_f(const CT& v) {
+  return (float)(fabs(v.x) + fabs(v.y));
+}
+
+// Packed form of U11 for the row solves: row j of the strict upper triangle
+// (entries j + 1 .. w - 1) at offset j w - j (j + 1) / 2, after the w
+// reciprocals of the diagonal (SPEC_DINV slots).
+constexpr int SPEC_DINV = 128;
+__host__ __device__ constexpr int spec_upk_off(int j, int w) { return SPEC_DINV + j * w - j * (j + 1) / 2; }
+__host__ __device__ constexpr int spec_upk_size(int w) { return SPEC_DINV + w * (w - 1) / 2; }
+
+// Diagonal block (w x w at (k0, k0)) of batch item blockIdx.y, NT threads:
+// thread (tx, ty) = (tid % 32, tid / 32) holds rows tx + 32 p (p < 4) and
+// columns ty + TY q (q < 128 / TY, TY = NT / 32) in registers.  Per column j
+// the pivot row and the pivot column go through LDS (double-buffered by the
+// parity of j, one barrier per column); each thread reads all the entries it
+// needs at once and forms the multipliers of its rows itself.  Row and column
+// groups wholly at or before j are skipped (uniform branches), groups wholly
+// after it take a plain update and only the groups holding row or column j a
+// masked one, so the work per column follows the shrinking triangle (the VALU
+// of one CU sets the time: 64 lanes per cycle).  NT = 512: 32 entries per
+// thread, two waves per SIMD.  On exit U11 is also written, packed, to upk
+// (see spec_upk_off).
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) spec_diag_kernel(cplx<T>* __restrict__ A, int64_t ld, int64_t k0, int w,
+                                                        int32_t* __restrict__ ipiv, int32_t* __restrict__ flag,
+                                                        cplx<T>* __restrict__ upk, int64_t sA, int64_t sipiv,
+                                                        int64_t sflag, int64_t supk) {
+  using CT = cplx<T>;
+  constexpr int TY = NT / 32, Q = 128 / TY;
+  A += (int64_t)blockIdx.y * sA;  // batch item blockIdx.y
+  ipiv += (int64_t)blockIdx.y * sipiv;
+  flag += (int64_t)blockIdx.y * sflag;
+  upk += (int64_t)blockIdx.y * supk;
+  __shared__ CT rowb[2][128], colb[2][128];
+  const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
+  CT* D = A + k0 + k0 * ld;
+  CT a[4][Q];
+  static_for<4>([&](auto p) {
+    static_for<Q>([&](auto q) {
+      const int r = tx + 32 * p, c = ty + TY * q;
+      a[p][q].x = 0;
+      a[p][q].y = 0;
+      if (r < w && c < w) a[p][q] = D[r + (int64_t)c * ld];
+    });
+  });
+  bool bad = false;
+  for (int j = 0; j < w; ++j) {
+    const int par = j & 1;
+    const int jp = j >> 5, jr = j & 31;  // row group and lane index of row j
+    const int jq = j / TY, jc = j % TY;  // column group and index of column j
+    if (tx == jr) {
+      static_for<4>([&](auto p) {
+        if (p == jp) static_for<Q>([&](auto q) { rowb[par][ty + TY * q] = a[p][q]; });
+      });
+    }
+    if (ty == jc) {
+      static_for<Q>([&](auto q) {
+        if (q == jq) static_for<4>([&](auto p) { colb[par][tx + 32 * p] = a[p][q]; });
+      });
+    }
+    __syncthreads();
+    CT u[Q], v[4];
+    static_for<Q>([&](auto q) { u[q] = rowb[par][ty + TY * q]; });
+    static_for<4>([&](auto p) { v[p] = colb[par][tx + 32 * p]; });
+    const CT piv = rowb[par][j];
+    const float pk = cabs1_f(piv);
+    if (!(pk > 0.f)) bad = true;  // zero or NaN pivot
+    const CT inv = cinv_t(piv);
+    // groups wholly below / right of j take the plain update; the group holding
+    // row j (p == jp) or column j (q == jq) the masked one
+    static_for<4>([&](auto p) {
+      if (p < jp) return;
+      const bool pfull = p > jp;
+      const bool below = pfull || tx > jr;
+      const CT l = cmul_t(v[p], inv);
+      if (below && ty == jc && !(cabs1_f(v[p]) <= pk)) bad = true;
+      static_for<Q>([&](auto q) {
+        if (q < jq) return;
+        if (pfull && q > jq) {
+          a[p][q] = r1_upd(a[p][q], l, u[q]);
+          return;
+        }
+        const int c = ty + TY * q;
+        const CT t = r1_upd(a[p][q], l, u[q]);
+        const bool upd = below && c > j;
+        const bool mul = below && c == j;
+        a[p][q].x = upd ? t.x : (mul ? l.x : a[p][q].x);
+        a[p][q].y = upd ? t.y : (mul ? l.y : a[p][q].y);
+      });
+    });
+  }
+  static_for<4>([&](auto p) {
+    static_for<Q>([&](auto q) {
+      const int r = tx + 32 * p, c = ty + TY * q;
+      if (r < w && c < w) {
+        D[r + (int64_t)c * ld] = a[p][q];
+        if (r < c) upk[spec_upk_off(r, w) + (c - r - 1)] = a[p][q];
+        if (r == c) upk[r] = cinv_t(a[p][q]);
+      }
+    });
+  });
+  if (tid < w) ipiv[k0 + tid] = (int32_t)(k0 + tid);
+  if (__syncthreads_or(bad) && tid == 0) atomicOr(flag, 1);
+}
+
+// Rows below the diagonal block, x U11 = a for each row a of A21.  The packed
+// U11 and the reciprocals of its diagonal (written by spec_diag_kernel) are
+// staged once per workgroup in LDS, so the sweep over j needs no barrier.  Each
+// wave takes CPW rows at a time (lane l holds columns l and l + 64 of them) and
+// the workgroup loops over groups of 4 CPW rows.  Check: |x_j u_jj| <= |u_jj|
+// in |re| + |im| (FP32).
+template <typename T, int CPW>
+__global__ void __launch_bounds__(256) spec_l21_kernel(cplx<T>* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
+                                                        int w, const cplx<T>* __restrict__ upk,
+                                                        int32_t* __restrict__ flag, int64_t sA, int64_t supk,
+                                                        int64_t sflag) {
+  using CT = cplx<T>;
+  A += (int64_t)blockIdx.z * sA;  // batch item blockIdx.z
+  upk += (int64_t)blockIdx.z * supk;
+  flag += (int64_t)blockIdx.z * sflag;
+  extern __shared__ unsigned char smem_raw[];
+  CT* Up = reinterpret_cast<CT*>(smem_raw);  // spec_upk_size(w) entries
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  {
+    const int tot = spec_upk_size(w);
+    constexpr int SB = 8;
+    int e = tid;
+    for (; e + 256 * (SB - 1) < tot; e += 256 * SB) {
+      CT v[SB];
+#pragma unroll
+      for (int u = 0; u < SB; ++u) v[u] = upk[e + 256 * u];
+#pragma unroll
+      for (int u = 0; u < SB; ++u) Up[e + 256 * u] = v[u];
+    }
+    for (; e < tot; e += 256) Up[e] = upk[e];
+  }
+  __syncthreads();
+  const CT* U = A + k0 + k0 * ld;
+  CT dg[2];  // this lane's pivots u_ll, u_(l+64)(l+64) for the check
+  float pk[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i = lane + 64 * h;
+    dg[h].x = 0;
+    dg[h].y = 0;
+    if (i < w) dg[h] = U[i + (int64_t)i * ld];
+    pk[h] = cabs1_f(dg[h]);
+  }
+  bool bad = false;
+  const int64_t rows = n - k0 - w;
+  for (int64_t g0 = (int64_t)blockIdx.x * 4 * CPW; g0 < rows; g0 += (int64_t)gridDim.x * 4 * CPW) {
+    const int64_t r0 = k0 + w + g0 + (int64_t)wave * CPW;
+    CT b[2][CPW];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        const int i = lane + 64 * h;
+        b[h][c].x = 0;
+        b[h][c].y = 0;
+        if (i < w && r0 + c < n) b[h][c] = A[(r0 + c) + (k0 + i) * ld];
+      }
+    // x_j = b_j / u_jj (lane j % 64 of half j / 64), then b_i -= x_j u_ji for i > j
+    auto sweep = [&](auto half, int ja, int jz) __attribute__((always_inline)) {
+      constexpr int H = decltype(half)::value;
+      for (int j = ja; j < jz; ++j) {
+        const CT di = Up[j];
+        const int off = spec_upk_off(j, w) - (j + 1);  // Up + off + i = u_ji
+        const int i0 = lane, i1 = lane + 64;
+        CT u0, u1;
+        u0.x = 0; u0.y = 0; u1.x = 0; u1.y = 0;
+        if (i0 > j && i0 < w) u0 = Up[off + i0];
+        if (i1 > j && i1 < w) u1 = Up[off + i1];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+          const CT x = cmul_t(readlane_c(b[H][c], j & 63), di);
+          if (lane == (j & 63)) b[H][c] = x;
+          b[0][c] = r1_upd(b[0][c], x, u0);
+          b[1][c] = r1_upd(b[1][c], x, u1);
+        }
+      }
+    };
+    sweep(std::integral_constant<int, 0>{}, 0, w < 64 ? w : 64);
+    if (w > 64) sweep(std::integral_constant<int, 1>{}, 64, w);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int i = lane + 64 * h;
+      if (i >= w) continue;
+#pragma unroll
+      for (int c = 0; c < CPW; ++c) {
+        if (r0 + c >= n) continue;
+        if (!(cabs1_f(cmul_t(b[h][c], dg[h])) <= pk[h])) bad = true;
+        A[(r0 + c) + (k0 + i) * ld] = b[h][c];
+      }
+    }
+  }
+  if (__ballot(bad) != 0 && lane == 0) atomicOr(flag, 1);
+}
+
+template <typename T>
+static hipError_t launch_spec_panel(cplx<T>* A, int64_t ld, int64_t n, int64_t k0, int w, int32_t* ipiv,
+                                    int32_t* flag, cplx<T>* upk, hipStream_t st, int nbatch, int64_t sA, int64_t sipiv,
+                                    int64_t sflag, int64_t supk, int ncu) {
+  if (w > 128) return hipErrorInvalidValue;
+  constexpr int NT = 512;
+  hipLaunchKernelGGL((spec_diag_kernel<T, NT>), dim3(1, (unsigned)nbatch), dim3(NT), 0, st, A, ld, k0, w, ipiv, flag,
+                     upk, sA, sipiv, sflag, supk);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t nr = n - k0 - w;
+  if (nr <= 0) return hipSuccess;
+  constexpr int CPW = 8;
+  // packed triangle + reciprocals: FP64 132 KB (one workgroup per CU), FP32 66 KB
+  const size_t lds = (size_t)spec_upk_size(w) * sizeof(cplx<T>);
+  const int64_t groups = (nr + 4 * CPW - 1) / (4 * CPW);
+  const int per_cu = sizeof(T) == 4 ? 2 : 1;
+  const int64_t gx = std::min<int64_t>(groups, std::max<int64_t>(1, (int64_t)per_cu * ncu / std::max(1, nbatch)));
+  hipLaunchKernelGGL((spec_l21_kernel<T, CPW>), dim3((unsigned)gx, 1, (unsigned)nbatch), dim3(256), lds, st, A, ld, n,
+                     k0, w, upk, flag, sA, supk, sflag);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // planning and workspace
 // ---------------------------------------------------------------------------
 static const int LDS_RESERVE = 2048;
@@ -1573,6 +1813,7 @@ LUPlan lu_plan(int64_t n, int elem_bytes, int num_cu, int lds_bytes, int nbatch,
   LUPlan p;
   p.n = n;
   if (nbatch < 1) nbatch = 1;
+  p.spec = pb == 0;
   if (pb != 1 && pb != 2 && pb != 4 && pb != 8) pb = 1;
   if (elem_bytes == 8 && pb > 4) pb = 4;  // FP64 candidates of 8 columns would need too many registers
   p.pb = pb;
@@ -1667,14 +1908,17 @@ void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu,
   w.rows = reinterpret_cast<unsigned long long*>(take((size_t)nbatch * w.s_rows * 8));
   w.err = reinterpret_cast<int32_t*>(take(64));
   w.s_pairs = (int64_t)(al256(nblk * 2 * 2 * nb * 4) / 4);
-  w.s_npairs = (int64_t)(al256(nblk * 4) / 4);
+  w.s_npairs = (int64_t)(al256(2 * nblk * 4) / 4);  // moved-row counts, then the speculative panels' flags
   w.pairs = reinterpret_cast<int32_t*>(take((size_t)nbatch * w.s_pairs * 4));
   w.npairs = reinterpret_cast<int32_t*>(take((size_t)nbatch * w.s_npairs * 4));
+  w.spec = w.npairs ? w.npairs + nblk : nullptr;
   w.tmp_elems = tmp_rows(p) * (int64_t)nb;
   w.s_tmp = (int64_t)(al256((size_t)w.tmp_elems * cb) / cb);
   w.tmp = take((size_t)nbatch * w.s_tmp * cb);
   w.s_dinv = (int64_t)(al256(nblk * nb * nb * cb) / cb);
   w.dinv = take((size_t)nbatch * w.s_dinv * cb);
+  w.s_upk = p.spec ? (int64_t)(al256((size_t)spec_upk_size(128) * cb) / cb) : 0;
+  w.upk = p.spec ? take((size_t)nbatch * w.s_upk * cb) : nullptr;
   w.events = nullptr;
   w.bytes = off + 256;
 }
@@ -1720,6 +1964,16 @@ hipError_t lu_prepare(const LUPlan& plan) {
   static std::map<const void*, size_t> lds_set;
   static std::mutex mu;
   std::lock_guard<std::mutex> lk(mu);
+  if (plan.spec) {
+    const void* fn = reinterpret_cast<const void*>(&spec_l21_kernel<T, 8>);
+    const size_t need = (size_t)spec_upk_size(128) * sizeof(cplx<T>);
+    size_t& cur = lds_set[fn];
+    if (need > cur) {
+      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
+      if (e != hipSuccess) return e;
+      cur = need;
+    }
+  }
   for (const LUBlock& b : plan.blocks) {
     const size_t need = panel_lds_bytes(b.w, b.R, sizeof(cplx<T>), plan.pb);
     const void* fn = panel_fn<T>(plan.pb);
@@ -1825,9 +2079,14 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
     int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;  // moved rows: destinations, then sources 2 nb later
     int32_t* src = dst + 2 * nb;
     int32_t* npr = ws.npairs + bi;
-    launch_panel<T>(plan.pb, b, NB, lds, st, A, ld, n, ipiv, ws, epoch, sA, sipiv, dst, src, npr, 2 * nb);
-    epoch += (uint32_t)w;
-    LUCHK(hipGetLastError());
+    if (plan.spec) {
+      LUCHK(launch_spec_panel<T>(A, ld, n, k0, w, ipiv, ws.spec + bi, static_cast<CT*>(ws.upk), st, NB, sA, sipiv,
+                                   ws.s_npairs, ws.s_upk, ws.gmax));
+    } else {
+      launch_panel<T>(plan.pb, b, NB, lds, st, A, ld, n, ipiv, ws, epoch, sA, sipiv, dst, src, npr, 2 * nb);
+      epoch += (uint32_t)w;
+      LUCHK(hipGetLastError());
+    }
     LUCHK(P.end(st));
     const int64_t c1 = k0 + w;
     const int64_t nr = n - c1;

@@ -28,6 +28,7 @@ PREC_FP64, PREC_FP32_IR = 0, 1
 SELF_STATIC, SELF_RADIATIVE = 0, 1
 
 EXPORTED = ["gdm_create", "gdm_destroy", "gdm_last_error", "gdm_set_memory_limit", "gdm_memory_used", "gdm_set_pivoting",
+            "gdm_pivot_fallbacks",
             "gdm_set_environment", "gdm_set_structure",
             "gdm_num_unknowns", "gdm_assemble", "gdm_factorize", "gdm_set_wavelength", "gdm_solve_iterative", "gdm_incident_planewave", "gdm_solve",
             "gdm_planewave", "gdm_fields", "gdm_fields_total", "gdm_planewave_intensity", "gdm_fields_noalloc", "gdm_cross_sections", "gdm_dipole_sources", "gdm_ldos", "gdm_green_tensor", "gdm_adjoint", "gdm_batch_spectra", "gdm_batch_tuning", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
@@ -65,6 +66,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gdm_set_memory_limit": ([P, I64], ctypes.c_int),
         "gdm_memory_used": ([P], I64),
         "gdm_set_pivoting": ([P, I32], ctypes.c_int),
+        "gdm_pivot_fallbacks": ([P], I64),
         "gdm_set_environment": ([P, D], ctypes.c_int),
         "gdm_set_structure": ([P, I64, P, D, P, I64, P, P, ctypes.c_int], ctypes.c_int),
         "gdm_num_unknowns": ([P], I64),
@@ -189,9 +191,15 @@ class Context:
 
     def set_pivoting(self, columns_per_exchange: int = 0):
         """Panel columns per pivot exchange of the next factorisations
-        (include/gdm.h, gdm_set_pivoting): 1 partial pivoting, 2/4/8 tournament,
-        0 the library default."""
+        (include/gdm.h, gdm_set_pivoting): 1 partial pivoting with the search in
+        every column, 2/4/8 tournament, 0 the default (speculative partial
+        pivoting in factorize)."""
         self._check(self._call("gdm_set_pivoting", self.h, int(columns_per_exchange)))
+
+    def pivot_fallbacks(self) -> int:
+        """Factorisations whose speculative pivots failed their check and were
+        repeated with the pivot search (gdm_pivot_fallbacks)."""
+        return int(self.lib.gdm_pivot_fallbacks(self.h))
 
     # -- structure / environment ------------------------------------------------
     def set_environment(self, n_env: float):

@@ -550,3 +550,20 @@ def test_green_tensor_applied_to_a_source_gives_its_scattered_field():
     E, H = O.scattered_fields(D, q, r_p)
     ref = np.concatenate([E[0], H[0]], axis=-1)  # [P, 6]
     assert np.max(np.abs(np.einsum("prc,c->pr", G[0], d) - ref)) < 1e-13 * np.max(np.abs(ref))
+
+
+def test_partial_pivoting_keeps_the_diagonal_of_dielectric_matrices():
+    """LAPACK's partial pivoting (FP32, as the GPU factors) keeps the diagonal
+    of the coupling matrix of a dielectric sphere and of the mixed cells +
+    6x6-dipole system in every column, and leaves it for a plasmonic sphere
+    near its dipole resonance (eps = -2 + 0.1i): the premise under which the
+    GPU's speculative diagonal pivots are partial pivoting's, and the case in
+    which they must not be."""
+    import scipy.linalg as sl
+    w1 = gi.config1()
+    cases = (("dielectric sphere", w1, True), ("mixed", gi.small_mixed(), True),
+             ("plasmonic sphere", dict(w1, eps_cell=np.full(len(w1["r_cell"]), -2.0 + 0.1j)), False))
+    for name, w, keeps in cases:
+        M = O.assemble(O.Dipoles(w))
+        _, piv = sl.lu_factor(M.astype(np.complex64))
+        assert bool(np.all(piv == np.arange(len(piv)))) == keeps, name
