@@ -40,6 +40,12 @@ follows (sections / equations of the paper):
   from the power a dipole emits and is pinned by energy conservation (LDOS
   times the host's emitted power = far-field power of source plus structure,
   lossless cells with the radiative self-term) and by reciprocity.
+* exact multipole moments (electric and magnetic dipoles and quadrupoles) of
+  the cells' polarisation and their scattering and extinction cross sections
+  (Sec. "Observables"); the paper names the exact-moment construction by
+  reference only, the forms used here are pinned by projecting the far field on
+  the l = 1, 2 electric / magnetic multipole subspaces (scattering) and by the
+  optical theorem on those projections (extinction).
 
 Units: nm, nm^2.  Complex values are numpy complex128.
 """
@@ -50,6 +56,7 @@ from typing import Dict
 
 import numpy as np
 import scipy.linalg as sla
+import scipy.special as sps
 
 FOUR_PI = 4.0 * math.pi
 
@@ -500,6 +507,107 @@ def ldos(wl: Dict, r_src, mode: str = "static") -> np.ndarray:
         for a in range(3):
             out[s, 0, a] = 1.0 + 1.5 * D.eps_env / k3 * G[s, s, a, a].imag
             out[s, 1, a] = 1.0 + 1.5 / k3 * G[s, s, 3 + a, 3 + a].imag
+    return out
+
+
+# ----------------------------------------------------------------------------
+# exact multipole decomposition up to quadrupoles (Sec. "Observables": exact
+# multipole decomposition of the polarisation inside a discretised structure and
+# of the scattering and extinction cross sections; Sec. "Implementation
+# technical details", which names the exact-moment and extinction references)
+# ----------------------------------------------------------------------------
+def multipole_center(D: Dipoles) -> np.ndarray:
+    """Default expansion point: the mean position of the mesh cells."""
+    return np.mean(D.pos[:D.nc], axis=0)
+
+
+def multipole_moments(D: Dipoles, q, r0=None) -> Dict:
+    """Exact electric / magnetic dipole and quadrupole moments of the mesh
+    cells' polarisation (their electric dipoles p_j at r_j; effective dipoles
+    are not part of the discretised structure and are left out), about r0.
+
+    With R = r_j - r0, x = k|R| and spherical Bessel functions j_n(x) (SciPy),
+    summed over cells, in the Gaussian convention of farfield_amplitude:
+      p   = p_j j0 + (k^2/2) [3 (R.p_j) R - R^2 p_j] j2/x^2
+      m   = -i k0 (3/2) (R x p_j) j1/x
+      Qe  = 3 { [3 (R p_j^T + p_j R^T) - 2 (R.p_j) I] j1/x
+                + 2 k^2 [5 (R.p_j) R R^T - R^2 (R p_j^T + p_j R^T) - R^2 (R.p_j) I] j3/x^3 }
+      Qm  = -i k0 15 [R (R x p_j)^T + (R x p_j) R^T] j2/x^2
+    (the current of a dipole is -i omega p; at x -> 0 these become the
+    long-wavelength moments: p, m = -(i k0/2) sum R x p, the traceless
+    quadrupoles).  Returns dict p [rhs,3], m [rhs,3], Qe [rhs,3,3], Qm [rhs,3,3]
+    and r0."""
+    r0 = multipole_center(D) if r0 is None else np.asarray(r0, dtype=np.float64)
+    q = np.asarray(q, dtype=np.complex128)
+    if q.ndim == 1:
+        q = q[:, None]
+    nc = D.nc
+    P = q[:3 * nc].reshape(nc, 3, -1)  # [nc, 3, rhs]
+    R = D.pos[:nc] - r0[None, :]
+    rr = np.linalg.norm(R, axis=1)
+    x = D.k * rr
+    xs = np.where(x > 0, x, 1.0)
+    j0 = sps.spherical_jn(0, x)
+    # j_n(x)/x^n at x = 0: 1 / (2n+1)!!
+    w1 = np.where(x > 0, sps.spherical_jn(1, xs) / xs, 1.0 / 3.0)
+    w2 = np.where(x > 0, sps.spherical_jn(2, xs) / xs ** 2, 1.0 / 15.0)
+    w3 = np.where(x > 0, sps.spherical_jn(3, xs) / xs ** 3, 1.0 / 105.0)
+    k, k0 = D.k, D.k0
+    Rp = np.einsum("ja,jar->jr", R, P)  # R.p
+    R2 = rr ** 2
+    I3 = np.eye(3)
+    p = np.einsum("j,jar->ra", j0, P) + (k ** 2 / 2) * np.einsum(
+        "j,jar->ra", w2, 3 * Rp[:, None, :] * R[:, :, None] - R2[:, None, None] * P)
+    RxP = np.cross(R[:, :, None], P, axis=1)  # [nc, 3, rhs]
+    m = -1j * k0 * 1.5 * np.einsum("j,jar->ra", w1, RxP)
+    RPt = np.einsum("ja,jbr->jabr", R, P)
+    sym = RPt + RPt.transpose(0, 2, 1, 3)  # R p^T + p R^T
+    RR = np.einsum("ja,jb->jab", R, R)
+    t1 = 3 * sym - 2 * Rp[:, None, None, :] * I3[None, :, :, None]
+    t3 = (5 * Rp[:, None, None, :] * RR[:, :, :, None] - R2[:, None, None, None] * sym
+          - (R2[:, None] * Rp)[:, None, None, :] * I3[None, :, :, None])
+    Qe = 3 * (np.einsum("j,jabr->rab", w1, t1) + 2 * k ** 2 * np.einsum("j,jabr->rab", w3, t3))
+    RXt = np.einsum("ja,jbr->jabr", R, RxP)
+    Qm = -1j * k0 * 15 * np.einsum("j,jabr->rab", w2, RXt + RXt.transpose(0, 2, 1, 3))
+    return dict(p=p, m=m, Qe=Qe, Qm=Qm, r0=r0)
+
+
+def multipole_cross_sections(D: Dipoles, q, khat=None, e0=None, r0=None) -> Dict:
+    """Scattering cross sections of the four multipoles (exact moments above):
+      ED (8 pi/3) k^4/eps^2 |p|^2, MD (8 pi/3) k0^2 k^2 |m|^2,
+      EQ (pi/45) k^6/eps^2 sum|Qe_ab|^2, MQ (pi/45) k0^2 k^4 sum|Qm_ab|^2,
+    each over |E0|^2 -- the powers of the far-field patterns
+    (k^2/eps)(n x p) x n, -k0 k n x m, -(i k^3/(6 eps))(n x Qe n) x n and
+    (i k0 k^2/6) n x (Qm n) (farfield_amplitude's convention).  With a plane
+    wave (khat, e0) also the extinction of each: C Im(E0*(r0).p),
+    C Im(H0*(r0).m), (C/6) Im(sum_ab d_a E0*_b(r0) Qe_ab),
+    (C/6) Im(sum_ab d_a H0*_b(r0) Qm_ab), C = 4 pi k0/(n_env |E0|^2) (the
+    incident field and its gradient at r0 against each moment).
+    Returns dict sca [rhs, 4] and, with a plane wave, ext [rhs, 4]
+    (order ED, MD, EQ, MQ)."""
+    mo = multipole_moments(D, q, r0)
+    k, k0, eps = D.k, D.k0, D.eps_env
+    sca = np.stack([(8 * math.pi / 3) * k ** 4 / eps ** 2 * np.sum(np.abs(mo["p"]) ** 2, axis=1),
+                    (8 * math.pi / 3) * k0 ** 2 * k ** 2 * np.sum(np.abs(mo["m"]) ** 2, axis=1),
+                    (math.pi / 45) * k ** 6 / eps ** 2 * np.sum(np.abs(mo["Qe"]) ** 2, axis=(1, 2)),
+                    (math.pi / 45) * k0 ** 2 * k ** 4 * np.sum(np.abs(mo["Qm"]) ** 2, axis=(1, 2))], axis=1)
+    out = dict(sca=None, ext=None, moments=mo)
+    if khat is None:
+        out["sca"] = sca
+        return out
+    khat = np.atleast_2d(np.asarray(khat, dtype=np.float64))
+    e0 = np.atleast_2d(np.asarray(e0, dtype=np.complex128))
+    e2 = np.sum(np.abs(e0) ** 2, axis=1)
+    out["sca"] = sca / e2[:, None]
+    E, H = planewave(mo["r0"][None, :], khat, e0, k0, D.n_env)  # [rhs, 1, 3]
+    Es, Hs = np.conj(E[:, 0]), np.conj(H[:, 0])
+    gE = -1j * k * khat[:, :, None] * Es[:, None, :]  # d_a E0*_b
+    gH = -1j * k * khat[:, :, None] * Hs[:, None, :]
+    C = FOUR_PI * k0 / (D.n_env * e2)
+    out["ext"] = np.stack([C * np.imag(np.sum(Es * mo["p"], axis=1)),
+                           C * np.imag(np.sum(Hs * mo["m"], axis=1)),
+                           C / 6 * np.imag(np.sum(gE * mo["Qe"], axis=(1, 2))),
+                           C / 6 * np.imag(np.sum(gH * mo["Qm"], axis=(1, 2)))], axis=1)
     return out
 
 

@@ -567,3 +567,106 @@ def test_partial_pivoting_keeps_the_diagonal_of_dielectric_matrices():
         M = O.assemble(O.Dipoles(w))
         _, piv = sl.lu_factor(M.astype(np.complex64))
         assert bool(np.all(piv == np.arange(len(piv)))) == keeps, name
+
+
+# ---------------------------------------------------------------------------
+# exact multipole decomposition: pinned by the far field itself
+# ---------------------------------------------------------------------------
+def _multipole_subspace_parts(D, q, khat_fwd=None, n_theta=40, n_phi=80):
+    """Least-squares projection of the oracle's far-field amplitude A(n) (one
+    RHS) on the four subspaces spanned by the patterns of an electric dipole
+    (n x a) x n, a magnetic dipole n x a, an electric quadrupole
+    (n x (M n)) x n and a magnetic quadrupole n x (M n) (a in C^3, M real
+    symmetric traceless): returns each part's power (the integral of |.|^2
+    over the sphere) and, if khat_fwd is given, its value in that direction."""
+    x, wx = np.polynomial.legendre.leggauss(n_theta)
+    phi = 2 * math.pi * np.arange(n_phi) / n_phi
+    ct, ph = np.meshgrid(x, phi, indexing="ij")
+    st = np.sqrt(1 - ct ** 2)
+    nh = np.stack([st * np.cos(ph), st * np.sin(ph), ct], axis=-1).reshape(-1, 3)
+    w = (wx[:, None] * np.full(n_phi, 2 * math.pi / n_phi)[None, :]).reshape(-1)
+    A = O.farfield_amplitude(D, q, nh)[:, :, 0]
+    E3 = np.eye(3)
+    Ms = []
+    for i, j in ((0, 1), (0, 2), (1, 2)):
+        M = np.zeros((3, 3))
+        M[i, j] = M[j, i] = 1.0
+        Ms.append(M)
+    Ms += [np.diag([1.0, -1.0, 0.0]), np.diag([1.0, 1.0, -2.0])]
+    pats = {
+        "ED": lambda n: [np.cross(np.cross(n, np.broadcast_to(a, n.shape)), n) for a in E3],
+        "MD": lambda n: [np.cross(n, np.broadcast_to(a, n.shape)) for a in E3],
+        "EQ": lambda n: [np.cross(np.cross(n, n @ M.T), n) for M in Ms],
+        "MQ": lambda n: [np.cross(n, n @ M.T) for M in Ms],
+    }
+    power, fwd = {}, {}
+    W = np.repeat(w, 3)
+    for name, f in pats.items():
+        F = np.stack([b.reshape(-1) for b in f(nh)], axis=1)
+        G = F.conj().T @ (W[:, None] * F)
+        c = np.linalg.solve(G, F.conj().T @ (W * A.reshape(-1)))
+        power[name] = float(np.real(c.conj() @ G @ c))
+        if khat_fwd is not None:
+            fwd[name] = sum(ci * b[0] for ci, b in zip(c, f(np.asarray(khat_fwd, dtype=np.float64)[None, :])))
+    return power, fwd
+
+
+@pytest.mark.parametrize("case", ["sphere_offcenter", "cuboid_ka1_medium"])
+def test_multipole_cross_sections_match_farfield_projections(case):
+    """Each multipole's scattering cross section equals the power of the far
+    field's projection on that multipole's subspace, and each extinction term
+    equals the optical theorem applied to that projection's forward value,
+    (4 pi / k) Im(e0* . A_X(khat)) / |E0|^2.  Exact (not long-wavelength):
+    the l = 3, 4, ... parts are orthogonal to these subspaces."""
+    w = dict(gi.config1())
+    if case == "sphere_offcenter":
+        r0 = np.array([12.0, -7.0, 5.0])
+    else:  # ka ~ 1 in a medium
+        w["r_cell"] = gi.cuboid_cells(6, 4, 5, 20.0)
+        w["step"] = 20.0
+        w["eps_cell"] = np.full(len(w["r_cell"]), 6.0 + 0.3j)
+        w["n_env"] = 1.4
+        w["wavelength"] = 700.0
+        r0 = None
+    kh = np.array([0.3, -0.2, 0.932])
+    kh /= np.linalg.norm(kh)
+    e0 = np.cross(kh, [1.0, 0.0, 0.0])
+    e0 = e0 / np.linalg.norm(e0) * (1.0 + 0.5j)
+    w["khat"], w["e0"] = kh[None, :], e0[None, :]
+    sim = O.simulate(w)
+    D = sim["D"]
+    mp = O.multipole_cross_sections(D, sim["q"], w["khat"], w["e0"], r0=r0)
+    # the far field about the expansion point: shift the dipoles so that r0 is the origin
+    r0v = mp["moments"]["r0"]
+    Dsh = O.Dipoles(dict(w, r_cell=w["r_cell"] - r0v))
+    e2 = float(np.sum(np.abs(e0) ** 2))
+    power, fwd = _multipole_subspace_parts(Dsh, sim["q"][:, :1], kh)
+    # the incident wave about r0 carries the phase exp(i k khat.r0)
+    e0c = e0 * np.exp(1j * D.k * (kh @ r0v))
+    for i, name in enumerate(("ED", "MD", "EQ", "MQ")):
+        assert mp["sca"][0, i] == pytest.approx(power[name] / e2, rel=1e-10, abs=1e-14), name
+        ext = (4 * math.pi / D.k) * np.imag(np.conj(e0c) @ fwd[name]) / e2
+        assert mp["ext"][0, i] == pytest.approx(ext, rel=1e-9, abs=1e-12 * abs(mp["ext"][0, 0])), name
+    # the remainder (l >= 3) of the total far-field cross section is small and positive
+    ff = float(O.sca_farfield_quadrature(D, sim["q"][:, :1], [e2])[0])
+    rest = ff - float(np.sum(mp["sca"][0]))
+    assert 0 <= rest < 0.05 * ff
+
+
+def test_multipoles_of_one_dipole_at_the_center():
+    """One cell at the expansion point: the exact electric dipole is the cell's
+    own moment, every other multipole vanishes, and the dipole's cross
+    sections are the whole far-field ones."""
+    w = dict(gi.config1())
+    w["r_cell"] = np.array([[5.0, -3.0, 2.0]])
+    w["eps_cell"] = np.array([12.0 + 0.1j])
+    sim = O.simulate(w)
+    mp = O.multipole_moments(sim["D"], sim["q"])
+    assert np.allclose(mp["r0"], w["r_cell"][0])
+    assert np.max(np.abs(mp["p"] - sim["q"][:3].T)) == 0.0
+    assert np.max(np.abs(mp["m"])) == 0.0 and np.max(np.abs(mp["Qe"])) == 0.0 and np.max(np.abs(mp["Qm"])) == 0.0
+    cs = O.multipole_cross_sections(sim["D"], sim["q"], w["khat"], w["e0"])
+    e2 = np.sum(np.abs(w["e0"]) ** 2, axis=1)
+    ff = O.sca_farfield_quadrature(sim["D"], sim["q"], e2)
+    assert np.allclose(cs["sca"][:, 0], ff, rtol=1e-12)
+    assert np.allclose(cs["ext"][:, 0], sim["ext"], rtol=1e-12)
