@@ -223,6 +223,35 @@ gdm_status gdm_fields_noalloc(gdm_ctx* ctx, int64_t n_rhs, const double* q, int6
 gdm_status gdm_cross_sections(gdm_ctx* ctx, int64_t n_rhs, const double* f0, const double* q, const double* f,
                               const double* e0_norm2, int32_t want_ff, double* out);
 
+/* Exact multipole decomposition of the mesh cells' polarisation up to
+ * quadrupole order, and the scattering and extinction cross sections of each
+ * multipole (Sec. "Observables"; Sec. "Implementation technical details").
+ * Moments about r0 (host double[3], or NULL for the mean position of the mesh
+ * cells) of the cells' electric dipoles in q [n_rhs][n] (gdm_solve's q_out;
+ * effective dipoles are not part of the discretised structure and are left
+ * out), with R = r_j - r0, x = k|R| and spherical Bessel functions j_n:
+ *   p  = sum p_j j0 + (k^2/2) [3 (R.p_j) R - R^2 p_j] j2/x^2
+ *   m  = -i k0 (3/2) sum (R x p_j) j1/x
+ *   Qe = 3 sum [3 (R p_j^T + p_j R^T) - 2 (R.p_j) I] j1/x
+ *          + 2 k^2 [5 (R.p_j) R R^T - R^2 (R p_j^T + p_j R^T) - R^2 (R.p_j) I] j3/x^3
+ *   Qm = -i k0 15 sum [R (R x p_j)^T + (R x p_j) R^T] j2/x^2
+ * (Gaussian units, the far-field convention of gdm_fields; at x -> 0 the
+ * long-wavelength moments).  moments (device, may be NULL): complex [n_rhs][24]
+ * = p (3), m (3), Qe (3x3 row-major), Qm (3x3).  sigma (device, may be NULL):
+ * double [n_rhs][8] = scattering of ED, MD, EQ, MQ, then their extinction:
+ *   (8 pi/3) k^4/eps^2 |p|^2, (8 pi/3) k0^2 k^2 |m|^2, (pi/45) k^6/eps^2 |Qe|^2,
+ *   (pi/45) k0^2 k^4 |Qm|^2 over |E0|^2;  C Im(E0*(r0).p), C Im(H0*(r0).m),
+ *   (C/6) Im(sum d_a E0*_b(r0) Qe_ab), (C/6) Im(sum d_a H0*_b(r0) Qm_ab),
+ *   C = 4 pi k0 / (n_env |E0|^2),
+ * for the plane waves khat [n_rhs][3], e0 [n_rhs][3] complex (device, as in
+ * gdm_incident_planewave); with khat = e0 = NULL the scattering terms are for
+ * |E0| = 1 and the extinction slots hold NaN.  The extinction terms add up to
+ * the total extinction up to the octupole and higher orders (which can make
+ * single terms negative for non-spherical shapes).  FP64.  Uses the context
+ * wavelength.  GDM_E_ARG without mesh cells. */
+gdm_status gdm_multipoles(gdm_ctx* ctx, int64_t n_rhs, const double* q, const double* r0, const double* khat,
+                          const double* e0, double* moments, double* sigma);
+
 /* Point dipole sources as the illumination (Appendix, illumination classes:
  * electric and magnetic dipole point sources): the incident field of sources
  * d_src [n_src][6] complex (p then m) at r_src [n_src][3] on every dipole, in

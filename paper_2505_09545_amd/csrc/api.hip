@@ -1323,6 +1323,39 @@ gdm_status gdm_fields_noalloc(gdm_ctx* c, int64_t nrhs, const double* q, int64_t
                      reinterpret_cast<int*>(b), nsplit, false);
 }
 
+gdm_status gdm_multipoles(gdm_ctx* c, int64_t n_rhs, const double* q, const double* r0, const double* khat,
+                          const double* e0, double* moments, double* sigma) {
+  if (!c) return GDM_E_ARG;
+  if (c->N <= 0) FAIL(c, GDM_E_STATE, "gdm_multipoles before gdm_set_structure");
+  if (c->wavelength <= 0) FAIL(c, GDM_E_STATE, "no wavelength set (gdm_factorize or gdm_set_wavelength first)");
+  if (n_rhs <= 0 || !q || (!moments && !sigma)) FAIL(c, GDM_E_ARG, "need n_rhs > 0, q, and moments or sigma");
+  if (n_rhs > 65535) FAIL(c, GDM_E_ARG, "at most 65535 right-hand sides per call");
+  if ((khat == nullptr) != (e0 == nullptr)) FAIL(c, GDM_E_ARG, "khat and e0 are given together or not at all");
+  if (c->nc <= 0) FAIL(c, GDM_E_ARG, "the structure has no mesh cells (multipoles of the discretised part only)");
+  HIPCHK(c, hipSetDevice(c->device));
+  double rc[3] = {0.0, 0.0, 0.0};
+  if (r0) {
+    for (int a = 0; a < 3; ++a) rc[a] = r0[a];
+    if (!std::isfinite(rc[0]) || !std::isfinite(rc[1]) || !std::isfinite(rc[2])) FAIL(c, GDM_E_ARG, "r0 not finite");
+  } else {
+    // the mean position of the cells, summed in order on the host
+    std::vector<double> hp((size_t)3 * c->nc);
+    HIPCHK(c, hipMemcpyAsync(hp.data(), c->pos.p, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int64_t j = 0; j < c->nc; ++j)
+      for (int a = 0; a < 3; ++a) rc[a] += hp[3 * j + a];
+    for (int a = 0; a < 3; ++a) rc[a] /= (double)c->nc;
+  }
+  const Wave w = wave_of(c, c->wavelength);
+  const int ns = multipole_num_splits(c->nc, c->num_cu, n_rhs);
+  HIPCHK(c, c->part.ensure(multipole_scratch_bytes(n_rhs, ns)));
+  HIPCHK(c, launch_multipoles(c->pos.as<double>(), c->nc, reinterpret_cast<const double2*>(q), c->n, n_rhs, rc, w.k,
+                              w.k0, c->n_env, khat, reinterpret_cast<const double2*>(e0), ns, c->part.as<double>(),
+                              reinterpret_cast<double2*>(moments), sigma, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return GDM_OK;
+}
+
 gdm_status gdm_cross_sections(gdm_ctx* c, int64_t nrhs, const double* f0, const double* q, const double* f,
                               const double* e0_norm2, int32_t want_ff, double* out) {
   if (!c) return GDM_E_ARG;

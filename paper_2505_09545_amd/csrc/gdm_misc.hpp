@@ -65,6 +65,15 @@ hipError_t launch_ldos(const DipoleView& d, const Wave& w, const double2* q, int
 hipError_t launch_green_gather(const double2* E, const double2* H, int64_t n_src, int64_t P, double2* G,
                                hipStream_t st);
 
+// Exact multipoles (multipole.hip): moments [nrhs][24] and cross sections
+// [nrhs][8] (either may be null) of the first nc dipoles (the cells) of q.
+int multipole_num_splits(int64_t nc, int num_cu, int64_t nrhs);
+size_t multipole_scratch_bytes(int64_t nrhs, int nsplit);
+hipError_t launch_multipoles(const double* pos, int64_t nc, const double2* q, int64_t n, int64_t nrhs,
+                             const double r0[3], double k, double k0, double n_env, const double* khat,
+                             const double2* e0, int nsplit, double* part, double2* moments, double* sigma,
+                             hipStream_t st);
+
 int fields_num_splits(int64_t P, int64_t N, int num_cu);
 size_t fields_scratch_bytes(int64_t nrhs, int64_t P, int nsplit, bool want_h);
 hipError_t launch_fields(const DipoleView& d, const Wave& w, const double2* q, int64_t ldq, int64_t nrhs,

@@ -31,7 +31,7 @@ EXPORTED = ["gdm_create", "gdm_destroy", "gdm_last_error", "gdm_set_memory_limit
             "gdm_pivot_fallbacks",
             "gdm_set_environment", "gdm_set_structure",
             "gdm_num_unknowns", "gdm_assemble", "gdm_factorize", "gdm_set_wavelength", "gdm_solve_iterative", "gdm_incident_planewave", "gdm_solve",
-            "gdm_planewave", "gdm_fields", "gdm_fields_total", "gdm_planewave_intensity", "gdm_fields_noalloc", "gdm_cross_sections", "gdm_dipole_sources", "gdm_ldos", "gdm_green_tensor", "gdm_adjoint", "gdm_batch_spectra", "gdm_batch_tuning", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
+            "gdm_planewave", "gdm_fields", "gdm_fields_total", "gdm_planewave_intensity", "gdm_fields_noalloc", "gdm_cross_sections", "gdm_multipoles", "gdm_dipole_sources", "gdm_ldos", "gdm_green_tensor", "gdm_adjoint", "gdm_batch_spectra", "gdm_batch_tuning", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
             "gdm_profile", "gdm_profile_mask", "gdm_profile_read"]
 
 
@@ -82,6 +82,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gdm_fields_total": ([P, I64, P, P, P, I64, P, P, P], ctypes.c_int),
         "gdm_planewave_intensity": ([P, I64, P, P], ctypes.c_int),
         "gdm_cross_sections": ([P, I64, P, P, P, P, I32, P], ctypes.c_int),
+        "gdm_multipoles": ([P, I64, P, ctypes.POINTER(ctypes.c_double), P, P, P, P], ctypes.c_int),
         "gdm_dipole_sources": ([P, I64, P, P, P], ctypes.c_int),
         "gdm_ldos": ([P, I64, P, D, I32, P, ctypes.POINTER(GDMInfo)], ctypes.c_int),
         "gdm_green_tensor": ([P, I64, P, I64, P, D, I32, P, ctypes.POINTER(GDMInfo)], ctypes.c_int),
@@ -366,6 +367,31 @@ class Context:
         self._check(self._call("gdm_cross_sections", self.h, f0.shape[0], _ptr(f0), _ptr(q), _ptr(f), _ptr(e2),
                                                 int(bool(want_ff)), _ptr(out)))
         return out
+
+    def multipoles(self, q, r0=None, khat=None, e0=None):
+        """Exact multipole moments [n_rhs, 24] complex (p, m, Qe 3x3, Qm 3x3) of
+        the mesh cells' polarisation about r0 (default: the cells' mean
+        position) and the cross sections [n_rhs, 8] (scattering ED, MD, EQ, MQ,
+        then extinction; with plane waves khat, e0 of the RHS) (gdm_multipoles)."""
+        q = self._dev(q, torch.complex128, None, "q")
+        nr = q.shape[0]
+        k = e = None
+        if (khat is None) != (e0 is None):
+            raise ValueError("khat and e0 go together")
+        if khat is not None:
+            k = self._dev(khat, torch.float64, (nr, 3), "khat")
+            e = self._dev(e0, torch.complex128, (nr, 3), "e0")
+        rc = None
+        if r0 is not None:
+            r0 = [float(v) for v in r0]
+            if len(r0) != 3:
+                raise ValueError("r0 must have 3 components")
+            rc = (ctypes.c_double * 3)(*r0)
+        mom = torch.empty((nr, 24), dtype=torch.complex128, device=self.device)
+        sig = torch.empty((nr, 8), dtype=torch.float64, device=self.device)
+        self._check(self._call("gdm_multipoles", self.h, nr, _ptr(q), rc, _ptr(k) if k is not None else None,
+                               _ptr(e) if e is not None else None, _ptr(mom), _ptr(sig)))
+        return mom, sig
 
     def dipole_sources(self, r_src, d_src):
         """Incident field [n_src, n] of point dipoles d_src [n_src, 6] = (p, m) at
