@@ -46,6 +46,11 @@ follows (sections / equations of the paper):
   reference only, the forms used here are pinned by projecting the far field on
   the l = 1, 2 electric / magnetic multipole subspaces (scattering) and by the
   optical theorem on those projections (extinction).
+* extraction of an effective electric-magnetic dipole pair from a discretised
+  structure (Sec. "Extraction of effective models"): moments by the exact
+  multipole decomposition, alpha_eff = F0^+ P by least squares; pinned by the
+  one-cell case (the cell's dressed polarisability exactly) and by the
+  extracted model reproducing the full simulation of a small particle.
 
 Units: nm, nm^2.  Complex values are numpy complex128.
 """
@@ -609,6 +614,55 @@ def multipole_cross_sections(D: Dipoles, q, khat=None, e0=None, r0=None) -> Dict
                            C / 6 * np.imag(np.sum(gE * mo["Qe"], axis=(1, 2))),
                            C / 6 * np.imag(np.sum(gH * mo["Qm"], axis=(1, 2)))], axis=1)
     return out
+
+
+# ----------------------------------------------------------------------------
+# effective models: extraction of one effective electric-magnetic dipole pair
+# (Sec. "Extraction of effective models": illuminate, simulate, extract the
+# dipole moments -- for one pair in 3D by the exact multipole decomposition --
+# and fit alpha_eff by least squares, alpha_eff = F0^+ P)
+# ----------------------------------------------------------------------------
+def illumination_at_point(D: Dipoles, r0, khat, e0, r_src, d_src) -> np.ndarray:
+    """(E0, H0) at r0 of each illumination, [N, 6]: the plane waves (khat, e0)
+    first, then the point-dipole sources d_src [n_src, 6] at r_src (their own
+    field G6(r0 - r_s) d_s)."""
+    r0 = np.asarray(r0, dtype=np.float64)
+    rows = []
+    if khat is not None and len(np.atleast_2d(khat)):
+        E, H = planewave(r0[None, :], khat, e0, D.k0, D.n_env)
+        rows.append(np.concatenate([E[:, 0], H[:, 0]], axis=1))
+    if r_src is not None and len(np.atleast_2d(r_src)):
+        rs = np.atleast_2d(np.asarray(r_src, dtype=np.float64))
+        g = green6(r0[None, :] - rs, D.k0, D.n_env)  # [S, 6, 6]
+        rows.append(np.einsum("sab,sb->sa", g, np.atleast_2d(np.asarray(d_src, dtype=np.complex128))))
+    return np.concatenate(rows, axis=0)
+
+
+def extract_dipole_pair(wl: Dict, khat, e0, r_src=None, d_src=None, r0=None, mode: str = "static"):
+    """Effective 6x6 polarisability of the structure about r0 (default: the
+    cells' mean position): for every illumination the full system is solved,
+    the exact electric and magnetic dipole moments (p, m) about r0 are taken
+    (multipole_moments) and stacked as the rows of P [N, 6]; the rows of F0
+    [N, 6] are the illuminations' (E0, H0) at r0.  alpha_eff minimises
+    ||F0 alpha_eff^T - P|| (least squares, LAPACK through NumPy), so that
+    (p, m) ~ alpha_eff (E0, H0).  Returns (alpha_eff [6, 6], relative residual
+    ||F0 alpha_eff^T - P||_F / ||P||_F, r0)."""
+    D = Dipoles(wl, mode=mode)
+    M = assemble(D)
+    cols = []
+    if khat is not None and len(np.atleast_2d(khat)):
+        cols.append(incident_at_dipoles(D, khat, e0))
+    if r_src is not None and len(np.atleast_2d(r_src)):
+        cols.append(dipole_source_at_dipoles(D, r_src, d_src))
+    F0 = np.concatenate(cols, axis=1)
+    F, _ = solve(M, F0)
+    q = D.from6(np.einsum("dab,dbr->dar", D.alpha6, D.to6(F)))
+    mo = multipole_moments(D, q, r0)
+    P = np.concatenate([mo["p"], mo["m"]], axis=1)  # [N, 6]
+    A = illumination_at_point(D, mo["r0"], khat, e0, r_src, d_src)
+    X, *_ = np.linalg.lstsq(A, P, rcond=None)
+    res = np.linalg.norm(A @ X - P) / np.linalg.norm(P)
+    return X.T, float(res), mo["r0"]
 
 
 # ----------------------------------------------------------------------------
