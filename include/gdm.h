@@ -252,6 +252,26 @@ gdm_status gdm_cross_sections(gdm_ctx* ctx, int64_t n_rhs, const double* f0, con
 gdm_status gdm_multipoles(gdm_ctx* ctx, int64_t n_rhs, const double* q, const double* r0, const double* khat,
                           const double* e0, double* moments, double* sigma);
 
+/* Effective model of the structure as one electric-magnetic dipole pair at r0
+ * (Sec. "Extraction of effective models"; the paper's single-pair 3D case):
+ * the n_pw plane waves (khat [n_pw][3], e0 [n_pw][3] complex, device) and
+ * n_src point-dipole sources (r_src [n_src][3], d_src [n_src][6] complex (p, m),
+ * device, as in gdm_dipole_sources) are solved with the context's factors (tol,
+ * max_iter as in gdm_solve); the electric and magnetic dipole moments of each
+ * response about r0 (host double[3], or NULL for the cells' mean position) are
+ * the exact ones of gdm_multipoles (rows of P [N][6]); the rows of F0 [N][6]
+ * are each illumination's (E0, H0) at r0 (a source's own field there).
+ * alpha (device, complex [6][6] row-major) minimises ||F0 alpha^T - P||_F, so
+ * that (p, m) ~ alpha (E0, H0) -- an effective dipole's alpha_eff for
+ * gdm_set_structure; *resid (host, may be NULL) = ||F0 alpha^T - P||_F / ||P||_F
+ * (large values: the structure is too large for one dipole pair).  Needs 6 <=
+ * n_pw + n_src <= 4096 and mesh cells; GDM_E_ARG if the illuminations leave
+ * alpha undetermined; GDM_E_STATE without factors; GDM_E_PROBE_AT_DIPOLE for a
+ * source on a dipole. */
+gdm_status gdm_extract_dipole_pair(gdm_ctx* ctx, int64_t n_pw, const double* khat, const double* e0, int64_t n_src,
+                                   const double* r_src, const double* d_src, const double* r0, double tol,
+                                   int32_t max_iter, double* alpha, double* resid, gdm_info* info);
+
 /* Point dipole sources as the illumination (Appendix, illumination classes:
  * electric and magnetic dipole point sources): the incident field of sources
  * d_src [n_src][6] complex (p then m) at r_src [n_src][3] on every dipole, in

@@ -1526,6 +1526,80 @@ gdm_status gdm_green_tensor(gdm_ctx* c, int64_t n_src, const double* r_src, int6
   return GDM_OK;
 }
 
+gdm_status gdm_extract_dipole_pair(gdm_ctx* c, int64_t n_pw, const double* khat, const double* e0, int64_t n_src,
+                                   const double* r_src, const double* d_src, const double* r0, double tol,
+                                   int32_t max_iter, double* alpha, double* resid, gdm_info* info) {
+  if (!c) return GDM_E_ARG;
+  if (!c->factored) FAIL(c, GDM_E_STATE, "gdm_extract_dipole_pair before gdm_factorize");
+  if (c->nc <= 0) FAIL(c, GDM_E_ARG, "the structure has no mesh cells");
+  if (n_pw < 0 || n_src < 0 || (n_pw > 0 && (!khat || !e0)) || (n_src > 0 && (!r_src || !d_src)) || !alpha)
+    FAIL(c, GDM_E_ARG, "bad illumination or output arguments");
+  const int64_t N = n_pw + n_src;
+  if (N < 6 || N > 4096) FAIL(c, GDM_E_ARG, "need 6 to 4096 illuminations (got %lld)", (long long)N);
+  HIPCHK(c, hipSetDevice(c->device));
+  double rc[3] = {0.0, 0.0, 0.0};
+  if (r0) {
+    for (int a = 0; a < 3; ++a) rc[a] = r0[a];
+  } else {
+    std::vector<double> hp((size_t)3 * c->nc);
+    HIPCHK(c, hipMemcpyAsync(hp.data(), c->pos.p, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int64_t j = 0; j < c->nc; ++j)
+      for (int a = 0; a < 3; ++a) rc[a] += hp[3 * j + a];
+    for (int a = 0; a < 3; ++a) rc[a] /= (double)c->nc;
+  }
+  const int64_t n = c->n;
+  // F0 [N][n], Q [N][n], moments [N][24], F0 at r0 [N][6], work [N][6], residual
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t b_vec = sizeof(double2) * (size_t)N * n, b_mom = sizeof(double2) * (size_t)N * 24,
+               b_six = sizeof(double2) * (size_t)N * 6;
+  HIPCHK(c, c->src.ensure(2 * al(b_vec) + al(b_mom) + 2 * al(b_six) + 256));
+  char* base = static_cast<char*>(c->src.p);
+  double2* F0 = reinterpret_cast<double2*>(base);
+  double2* Q = reinterpret_cast<double2*>(base + al(b_vec));
+  double2* mom = reinterpret_cast<double2*>(base + 2 * al(b_vec));
+  double2* A6 = reinterpret_cast<double2*>(base + 2 * al(b_vec) + al(b_mom));
+  double2* B6 = reinterpret_cast<double2*>(base + 2 * al(b_vec) + al(b_mom) + al(b_six));
+  double* dres = reinterpret_cast<double*>(base + 2 * al(b_vec) + al(b_mom) + 2 * al(b_six));
+  const Wave w = wave_of(c, c->wavelength);
+  const DipoleView d = view_of(c, make_double2(0, 0));
+  if (n_pw > 0)
+    HIPCHK(c, launch_incident(d, w, c->n_env, n_pw, khat, reinterpret_cast<const double2*>(e0), F0, n, c->stream));
+  if (n_src > 0) {
+    gdm_status s = gdm_dipole_sources(c, n_src, r_src, d_src, reinterpret_cast<double*>(F0 + (size_t)n_pw * n));
+    if (s != GDM_OK) return s;
+  }
+  HIPCHK(c, c->X.ensure(sizeof(double2) * n * N));
+  double2* X = c->X.as<double2>();
+  SolveStats ss;
+  gdm_status s = solve_core(c, 0, N, F0, X, tol, max_iter, ss);
+  if (s != GDM_OK && s != GDM_E_NOCONV) return s;
+  HIPCHK(c, launch_apply_alpha(d, X, n, Q, n, N, c->stream));
+  const int ns = multipole_num_splits(c->nc, c->num_cu, N);
+  HIPCHK(c, c->part.ensure(multipole_scratch_bytes(N, ns)));
+  HIPCHK(c, launch_multipoles(c->pos.as<double>(), c->nc, Q, n, N, rc, w.k, w.k0, c->n_env, nullptr, nullptr, ns,
+                              c->part.as<double>(), mom, nullptr, c->stream));
+  HIPCHK(c, launch_pair_extract(w, c->n_env, rc, n_pw, khat, reinterpret_cast<const double2*>(e0), n_src, r_src,
+                                reinterpret_cast<const double2*>(d_src), mom, A6, B6,
+                                reinterpret_cast<double2*>(alpha), dres, c->stream));
+  double hres = 0.0;
+  double2 ha[36];
+  HIPCHK(c, hipMemcpyAsync(&hres, dres, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(ha, alpha, sizeof(ha), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (resid) *resid = hres;
+  if (info) {
+    info->ir_iters = ss.iters;
+    info->backward_err = ss.be;
+    info->bad_index = -1;
+  }
+  for (int i = 0; i < 36; ++i)
+    if (!std::isfinite(ha[i].x) || !std::isfinite(ha[i].y))
+      FAIL(c, GDM_E_ARG, "the illuminations do not determine the model (rank-deficient fields at r0)");
+  if (s == GDM_E_NOCONV) FAIL(c, GDM_E_NOCONV, "refinement stopped at backward error %.3e > tol %.3e", ss.be, ss.tol);
+  return GDM_OK;
+}
+
 gdm_status gdm_getrf(gdm_ctx* c, int dtype, int64_t n, void* A, int64_t lda, int32_t* ipiv, gdm_info* info) {
   if (!c) return GDM_E_ARG;
   if (dtype != 0 && dtype != 1) FAIL(c, GDM_E_ARG, "dtype must be 0 or 1");

@@ -74,6 +74,14 @@ hipError_t launch_multipoles(const double* pos, int64_t nc, const double2* q, in
                              const double2* e0, int nsplit, double* part, double2* moments, double* sigma,
                              hipStream_t st);
 
+// Effective dipole pair (effective.hip): F0 [N][6] = (E0, H0) at r0 of n_pw
+// plane waves then n_src point sources; least squares alpha [6][6] (row-major,
+// (p, m) = alpha (E0, H0)) from the moments [N][24]; B [N][6] work array.
+hipError_t launch_pair_extract(const Wave& w, double n_env, const double r0[3], int64_t n_pw, const double* khat,
+                               const double2* e0, int64_t n_src, const double* rs, const double2* ds,
+                               const double2* moments, double2* F0, double2* B, double2* alpha, double* resid,
+                               hipStream_t st);
+
 int fields_num_splits(int64_t P, int64_t N, int num_cu);
 size_t fields_scratch_bytes(int64_t nrhs, int64_t P, int nsplit, bool want_h);
 hipError_t launch_fields(const DipoleView& d, const Wave& w, const double2* q, int64_t ldq, int64_t nrhs,

@@ -31,7 +31,7 @@ EXPORTED = ["gdm_create", "gdm_destroy", "gdm_last_error", "gdm_set_memory_limit
             "gdm_pivot_fallbacks",
             "gdm_set_environment", "gdm_set_structure",
             "gdm_num_unknowns", "gdm_assemble", "gdm_factorize", "gdm_set_wavelength", "gdm_solve_iterative", "gdm_incident_planewave", "gdm_solve",
-            "gdm_planewave", "gdm_fields", "gdm_fields_total", "gdm_planewave_intensity", "gdm_fields_noalloc", "gdm_cross_sections", "gdm_multipoles", "gdm_dipole_sources", "gdm_ldos", "gdm_green_tensor", "gdm_adjoint", "gdm_batch_spectra", "gdm_batch_tuning", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
+            "gdm_planewave", "gdm_fields", "gdm_fields_total", "gdm_planewave_intensity", "gdm_fields_noalloc", "gdm_cross_sections", "gdm_multipoles", "gdm_extract_dipole_pair", "gdm_dipole_sources", "gdm_ldos", "gdm_green_tensor", "gdm_adjoint", "gdm_batch_spectra", "gdm_batch_tuning", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
             "gdm_profile", "gdm_profile_mask", "gdm_profile_read"]
 
 
@@ -83,6 +83,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gdm_planewave_intensity": ([P, I64, P, P], ctypes.c_int),
         "gdm_cross_sections": ([P, I64, P, P, P, P, I32, P], ctypes.c_int),
         "gdm_multipoles": ([P, I64, P, ctypes.POINTER(ctypes.c_double), P, P, P, P], ctypes.c_int),
+        "gdm_extract_dipole_pair": ([P, I64, P, P, I64, P, P, ctypes.POINTER(ctypes.c_double), D, I32, P,
+                                     ctypes.POINTER(ctypes.c_double), P], ctypes.c_int),
         "gdm_dipole_sources": ([P, I64, P, P, P], ctypes.c_int),
         "gdm_ldos": ([P, I64, P, D, I32, P, ctypes.POINTER(GDMInfo)], ctypes.c_int),
         "gdm_green_tensor": ([P, I64, P, I64, P, D, I32, P, ctypes.POINTER(GDMInfo)], ctypes.c_int),
@@ -392,6 +394,29 @@ class Context:
         self._check(self._call("gdm_multipoles", self.h, nr, _ptr(q), rc, _ptr(k) if k is not None else None,
                                _ptr(e) if e is not None else None, _ptr(mom), _ptr(sig)))
         return mom, sig
+
+    def extract_dipole_pair(self, khat=None, e0=None, r_src=None, d_src=None, r0=None, tol=0.0, max_iter=-1):
+        """Effective 6x6 polarisability of the structure as one dipole pair at r0
+        (default: the cells' mean position) from plane waves (khat, e0) and point
+        sources (r_src, d_src), by least squares over the exact dipole moments of
+        the responses (gdm_extract_dipole_pair; needs factors).  Returns
+        (alpha [6, 6] complex on the device, relative residual)."""
+        k = e = rs = ds = None
+        npw = nsrc = 0
+        if khat is not None:
+            k = self._dev(khat, torch.float64, None, "khat").reshape(-1, 3)
+            e = self._dev(e0, torch.complex128, (len(k), 3), "e0")
+            npw = len(k)
+        if r_src is not None:
+            rs = self._dev(r_src, torch.float64, None, "r_src").reshape(-1, 3)
+            ds = self._dev(d_src, torch.complex128, (len(rs), 6), "d_src")
+            nsrc = len(rs)
+        rc = None if r0 is None else (ctypes.c_double * 3)(*[float(v) for v in r0])
+        alpha = torch.empty((6, 6), dtype=torch.complex128, device=self.device)
+        res = ctypes.c_double(0.0)
+        self._check(self._call("gdm_extract_dipole_pair", self.h, npw, _ptr(k), _ptr(e), nsrc, _ptr(rs), _ptr(ds), rc,
+                               float(tol), int(max_iter), _ptr(alpha), ctypes.byref(res), ctypes.byref(self.info)))
+        return alpha, float(res.value)
 
     def dipole_sources(self, r_src, d_src):
         """Incident field [n_src, n] of point dipoles d_src [n_src, 6] = (p, m) at
