@@ -101,11 +101,14 @@ int64_t gdm_memory_used(const gdm_ctx* ctx);
  *      against it by the same rule; if any check fails (or a pivot is zero or
  *      not finite) the matrix is assembled again and factored with mode 1, so
  *      the pivots are partial pivoting's either way (near-ties aside);
- *      gdm_getrf and gdm_batch_spectra use mode 1.
+ *      gdm_batch_spectra does the same per system (a system whose check
+ *      fails is computed again on its own with mode 1, its outputs
+ *      overwritten); gdm_getrf uses mode 1.
  * GDM_E_ARG for other values. */
 gdm_status gdm_set_pivoting(gdm_ctx* ctx, int32_t columns_per_exchange);
-/* Factorisations of this context (since gdm_create) whose speculative panels
- * failed their check and were repeated with the pivot search; -1 for NULL. */
+/* Factorisations of this context (since gdm_create), single systems and
+ * batched ones, whose speculative panels failed their check and were repeated
+ * with the pivot search; -1 for NULL. */
 int64_t gdm_pivot_fallbacks(const gdm_ctx* ctx);
 
 /* Real refractive index of the lossless homogeneous host (Appendix, tg.env

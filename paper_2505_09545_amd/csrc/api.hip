@@ -432,6 +432,9 @@ struct BatchBufs {
   double *rmax, *xmax, *bmax, *cmax, *minf, *rows, *sums5, *k0, *cs, *be, *be_max;
   double2* alpha;
   int32_t* sticky;
+  int32_t* sfail;   // [B] speculative panels: item failed its pivot checks
+  int32_t* scount;  // failed items listed so far
+  int64_t* slist;   // their global indices (structure * n_wl + wavelength)
   double* pos;
   double* wl;
 };
@@ -446,7 +449,7 @@ static bool batch_shape_for(gdm_ctx* c, int64_t n, int B, int nb_max, bool ir, B
   const int eb = ir ? 4 : 8;
   sh.n = n;
   sh.B = B;
-  sh.plan = lu_plan(n, eb, c->num_cu, c->lds_bytes, B, nb_max, panel_pb(c, false));
+  sh.plan = lu_plan(n, eb, c->num_cu, c->lds_bytes, B, nb_max, panel_pb(c, true));
   sh.nb = sh.plan.nb;
   return sh.plan.nb >= 32 && lu_plan_fits(sh.plan) && sh.plan.max_wg * B <= c->num_cu;
 }
@@ -474,6 +477,8 @@ static gdm_status batch_enqueue_group(gdm_ctx* c, const BatchShape& sh, const Ba
   else
     HIPCHK(c, lu_factor<double>(b.M64, n, sh.plan, w, b.ipiv, st, nullptr, c->lookahead ? c->side : nullptr, nn, n));
   HIPCHK(c, launch_batch_err(w.err, b.sticky, st));
+  if (sh.plan.spec)
+    HIPCHK(c, launch_batch_spec_collect(w.spec, w.s_npairs, (int)sh.plan.blocks.size(), B, b.sfail, st));
   HIPCHK(c, launch_batch_incident(b.pos, n, b.k0, c->n_env, npw, khat, e0, b.F0, B, st));
   auto residual = [&]() -> hipError_t {
     // R = F0 - M X per item (FP64, stored FP64 matrix)
@@ -627,8 +632,9 @@ extern "C" gdm_status gdm_batch_spectra(gdm_ctx* c, int64_t n_struct, const int6
   HIPCHK(c, c->bvec.ensure(sizeof(double2) * 4 * vec_elems + sizeof(float2) * vec_elems + 256));
   HIPCHK(c, c->bpart.ensure(sizeof(double2) * std::max<size_t>(part_elems, 1)));
   const size_t ncol = (size_t)Bcap * n_pw;
+  const size_t n_items = (size_t)n_struct * n_wl;
   const size_t nsmall = 4 * ncol + 2 * (size_t)Bcap + (size_t)Bcap * nmax + 5 * ncol + (size_t)Bcap + 3 * ncol +
-                        (size_t)Bcap + 1 + 2 * (size_t)Bcap + 64;
+                        (size_t)Bcap + 1 + 2 * (size_t)Bcap + 64 + (size_t)Bcap + 1 + n_items;
   HIPCHK(c, c->bsmall.ensure(sizeof(double) * nsmall));
   HIPCHK(c, c->bpos.ensure(sizeof(double) * pos_elems));
   HIPCHK(c, c->bwl.ensure(sizeof(double) * n_wl));
@@ -658,10 +664,14 @@ extern "C" gdm_status gdm_batch_spectra(gdm_ctx* c, int64_t n_struct, const int6
   b.cs = sp; sp += 3 * ncol;
   b.be_max = sp; sp += 1;
   b.alpha = reinterpret_cast<double2*>(sp); sp += 2 * (size_t)Bcap;
-  b.sticky = reinterpret_cast<int32_t*>(sp);
+  b.sticky = reinterpret_cast<int32_t*>(sp); sp += 64;
+  b.sfail = reinterpret_cast<int32_t*>(sp); sp += Bcap;
+  b.scount = reinterpret_cast<int32_t*>(sp); sp += 1;
+  b.slist = reinterpret_cast<int64_t*>(sp);
   b.pos = c->bpos.as<double>();
   b.wl = c->bwl.as<double>();
   HIPCHK(c, launch_batch_err_init(b.sticky, c->stream));
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, c->stream, b.scount, 1, 0);
   hipLaunchKernelGGL(fill_i32_kernel, dim3(1), dim3(64), 0, c->stream, reinterpret_cast<int*>(b.be_max), 2, 0);
   const double2* E0 = reinterpret_cast<const double2*>(e0);
   const double2* EPS = reinterpret_cast<const double2*>(eps);
@@ -736,6 +746,9 @@ extern "C" gdm_status gdm_batch_spectra(gdm_ctx* c, int64_t n_struct, const int6
       HIPCHK(c, launch_batch_unstage(b.cs, ir ? b.be : nullptr, nvalid, n_pw, s * n_wl + l0, cs_out,
                                      ir ? be_out : nullptr, c->stream));
       if (ir) HIPCHK(c, launch_batch_bemax(b.be, nvalid, b.be_max, c->stream));
+      if (sh.plan.spec)
+        HIPCHK(c, launch_batch_spec_list(b.sfail, nvalid, s * n_wl + l0, b.slist, b.scount, (int64_t)n_items,
+                                         c->stream));
       if (tuning) {
         // the candidates run on real groups (results kept); rate = items per ms
         HIPCHK(c, hipEventSynchronize(t1));
@@ -759,11 +772,40 @@ extern "C" gdm_status gdm_batch_spectra(gdm_ctx* c, int64_t n_struct, const int6
   (void)hipEventElapsedTime(&ms_total, tstart, tend);
   int32_t sticky[2] = {0, 0};
   double be_max = 0.0;
+  int32_t nfail = 0;
   HIPCHK(c, hipMemcpy(sticky, b.sticky, sizeof(sticky), hipMemcpyDeviceToHost));
   HIPCHK(c, hipMemcpy(&be_max, b.be_max, sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(c, hipMemcpy(&nfail, b.scount, sizeof(int32_t), hipMemcpyDeviceToHost));
+  std::vector<int64_t> failed((size_t)std::min<int64_t>(nfail, (int64_t)n_items));
+  if (!failed.empty())
+    HIPCHK(c, hipMemcpy(failed.data(), b.slist, sizeof(int64_t) * failed.size(), hipMemcpyDeviceToHost));
   release();
   for (hipEvent_t ev : {t0, t1, tstart, tend}) (void)hipEventDestroy(ev);
   if (status != GDM_OK) return status;
+  // Items whose speculative pivots failed their check: each again on its own
+  // with the pivot search, overwriting its outputs (rare for dielectrics; the
+  // zero-pivot and refinement reports below then cover these runs too).
+  if (!failed.empty()) {
+    std::sort(failed.begin(), failed.end());
+    const int saved = c->pivot_pb;
+    c->pivot_pb = 1;
+    for (int64_t item : failed) {
+      const int64_t s = item / n_wl, l = item % n_wl;
+      const int64_t off[2] = {0, cell_offset[s + 1] - cell_offset[s]};
+      gdm_info sub{};
+      const gdm_status st2 = gdm_batch_spectra(
+          c, 1, off, r_cell + 3 * cell_offset[s], step_nm + s, 1, wavelengths + l, eps + 2 * item, n_pw, khat, e0,
+          prec, ir_iters, 0.0, selfterm, cs_out + item * n_pw * 3, be_out ? be_out + item : nullptr, &sub);
+      ++c->pivot_fallbacks;
+      if (st2 != GDM_OK) {
+        c->pivot_pb = saved;
+        if (info) info->bad_index = sub.bad_index;
+        return st2;
+      }
+      if (ir) be_max = std::max(be_max, sub.backward_err);
+    }
+    c->pivot_pb = saved;
+  }
   if (info) {
     info->ir_iters = ir ? ir_iters : 0;
     info->backward_err = ir ? be_max : 0.0;

@@ -183,6 +183,27 @@ __global__ void batch_err_kernel(const int32_t* __restrict__ err, int32_t* __res
   }
 }
 
+// Speculative panels of a group: failed[z] = OR over the blocks of item z's
+// flags (flags of item z at flags + z * sflag, nblk of them).
+__global__ void batch_spec_collect_kernel(const int32_t* __restrict__ flags, int64_t sflag, int nblk, int B,
+                                          int32_t* __restrict__ failed) {
+  const int z = blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= B) return;
+  int32_t f = 0;
+  for (int b = 0; b < nblk; ++b) f |= flags[(int64_t)z * sflag + b];
+  failed[z] = f;
+}
+
+// Append the global indices (base + z) of the group's failed items to list,
+// count[0] holding the number of entries (capacity cap).
+__global__ void batch_spec_list_kernel(const int32_t* __restrict__ failed, int64_t nvalid, int64_t base,
+                                       int64_t* __restrict__ list, int32_t* __restrict__ count, int64_t cap) {
+  const int64_t z = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (z >= nvalid || !failed[z]) return;
+  const int slot = atomicAdd(count, 1);
+  if (slot < cap) list[slot] = base + z;
+}
+
 // be_max[0] = max(be_max[0], be[z < nvalid])
 __global__ void batch_bemax_kernel(const double* __restrict__ be, int64_t nvalid, double* __restrict__ be_max) {
   if (threadIdx.x == 0) {
@@ -279,6 +300,25 @@ hipError_t launch_batch_bemax(const double* be, int64_t nvalid, double* be_max, 
 
 hipError_t launch_batch_err_init(int32_t* sticky, hipStream_t st) {
   hipLaunchKernelGGL(batch_err_init_kernel, dim3(1), dim3(64), 0, st, sticky);
+  return hipGetLastError();
+}
+
+}  // namespace gdm
+
+namespace gdm {
+
+hipError_t launch_batch_spec_collect(const int32_t* flags, int64_t sflag, int nblk, int B, int32_t* failed,
+                                     hipStream_t st) {
+  hipLaunchKernelGGL(batch_spec_collect_kernel, dim3((unsigned)((B + 63) / 64)), dim3(64), 0, st, flags, sflag, nblk, B,
+                     failed);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_spec_list(const int32_t* failed, int64_t nvalid, int64_t base, int64_t* list, int32_t* count,
+                                  int64_t cap, hipStream_t st) {
+  if (nvalid <= 0) return hipSuccess;
+  hipLaunchKernelGGL(batch_spec_list_kernel, dim3((unsigned)((nvalid + 63) / 64)), dim3(64), 0, st, failed, nvalid,
+                     base, list, count, cap);
   return hipGetLastError();
 }
 

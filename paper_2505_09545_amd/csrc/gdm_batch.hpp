@@ -27,6 +27,12 @@ hipError_t launch_batch_cs(const double* sums5, const double* k0s, double n_env,
 hipError_t launch_batch_unstage(const double* cs, const double* be, int64_t nvalid, int64_t npw, int64_t base,
                                 double* cs_out, double* be_out, hipStream_t st);
 hipError_t launch_batch_err(const int32_t* err, int32_t* sticky, hipStream_t st);
+// speculative panels: per-item failure flags of a group, and the list of failed
+// global item indices (count[0] entries, at most cap stored)
+hipError_t launch_batch_spec_collect(const int32_t* flags, int64_t sflag, int nblk, int B, int32_t* failed,
+                                     hipStream_t st);
+hipError_t launch_batch_spec_list(const int32_t* failed, int64_t nvalid, int64_t base, int64_t* list, int32_t* count,
+                                  int64_t cap, hipStream_t st);
 hipError_t launch_batch_err_init(int32_t* sticky, hipStream_t st);
 // be_max[0] = max(be_max[0], be[0..nvalid))
 hipError_t launch_batch_bemax(const double* be, int64_t nvalid, double* be_max, hipStream_t st);

@@ -67,10 +67,11 @@ def oracle_cs(r, step, eps, wl, khat, e0, mode="static"):
     return _CACHE[key]
 
 
-@pytest.mark.parametrize("pivoting", [1, 4])
+@pytest.mark.parametrize("pivoting", [0, 1, 4])
 @pytest.mark.parametrize("prec", [1, 0])
 def test_batch_matches_oracle(ctx, prec, pivoting):
-    """Partial pivoting (the default) and tournament pivoting over 4 columns."""
+    """Speculative partial pivoting (the default), partial pivoting with the
+    search in every column, and tournament pivoting over 4 columns."""
     say("batch vs oracle prec", prec, "pivoting", pivoting)
     structs, wl, eps, khat, e0 = small_batch()
     ctx.set_environment(1.0)
@@ -89,6 +90,33 @@ def test_batch_matches_oracle(ctx, prec, pivoting):
     if prec == 1:
         b = be.cpu().numpy()
         assert np.all(b <= 1e-14) and np.all(b > 0), b
+        assert ctx.info.backward_err == pytest.approx(float(b.max()))
+
+
+@pytest.mark.parametrize("prec", [1, 0])
+def test_batch_speculative_fallback_items(ctx, prec):
+    """Two plasmonic items (eps = -2 + 0.1i: the cells' diagonal (eps + 2)/3
+    nearly vanishes, partial pivoting must interchange rows) inside an
+    otherwise dielectric batch: exactly those two items are recomputed with
+    the pivot search, and every item matches the oracle."""
+    say("batch speculative fallback prec", prec)
+    structs, wl, eps, khat, e0 = small_batch(n_wl=7)
+    eps = eps.copy()
+    eps[1, 3] = -2.0 + 0.1j
+    eps[2, 5] = -2.0 + 0.1j
+    ctx.set_environment(1.0)
+    before = ctx.pivot_fallbacks()
+    cs, be = ctx.batch_spectra(structs, 10.0, wl, eps, khat, e0, prec=prec)
+    assert ctx.pivot_fallbacks() - before == 2
+    cs = cs.cpu().numpy()
+    for s, r in enumerate(structs):
+        for l in range(len(wl)):
+            ref = oracle_cs(r, 10.0, eps[s, l], wl[l], khat, e0)
+            err = np.max(np.abs(cs[s, l] - ref) / np.abs(ref))
+            assert err < 1e-10, (s, l, err)
+    if prec == 1:
+        b = be.cpu().numpy()
+        assert np.all(b <= 1e-14)
         assert ctx.info.backward_err == pytest.approx(float(b.max()))
 
 
