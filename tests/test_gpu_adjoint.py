@@ -233,7 +233,7 @@ def test_autograd_function(ctx):
 
 def test_adjoint_full_config4_vs_golden(ctx):
     """Full-size config 4 (2000 cells, 4096 probes, n = 6000) against the stored
-    oracle gradient (tests/golden/make_golden.py), plus FD on sampled coordinates."""
+    oracle gradient (tests/golden/make_golden.py), FP64 and FP32 + refinement."""
     say("adjoint full config4")
     path = os.path.join(GOLDEN, "config4_adjoint.npz")
     ref = dict(np.load(path))
@@ -244,20 +244,52 @@ def test_adjoint_full_config4_vs_golden(ctx):
     check_vs_oracle(g, ref, len(w["r_cell"]), 1e-9)
     L32, g32 = gpu_loss_and_grad(ctx, w, 1)
     check_vs_oracle(g32, ref, len(w["r_cell"]), 1e-9)
+
+
+def test_adjoint_full_config4_finite_differences(ctx):
+    """Full-size config 4 (n = 6000) in FP64: the GPU adjoint against central
+    differences of the GPU forward on a seeded sample -- 64 coordinates (every
+    axis, cells spread over the cuboid), Re and Im of the permittivity of 8
+    cells, and the wavelength; max |g - g_FD| / max |g_FD| <= 1e-6 per group
+    (h = 1e-4 nm or 1e-4, truncation error ~1e-8 of the loss' scale)."""
+    say("adjoint full config4: finite differences")
+    w = gi.config4()
+    L, g = gpu_loss_and_grad(ctx, w, 0)
     rng = np.random.default_rng(11)
     h = 1e-4
+
+    def fd_of(mod):
+        wp, wm = mod(+h), mod(-h)
+        return (gpu_loss_and_grad(ctx, wp, 0, want_grad=False)[0] -
+                gpu_loss_and_grad(ctx, wm, 0, want_grad=False)[0]) / (2 * h)
+
+    cells = rng.choice(len(w["r_cell"]), 64, replace=False)
     fd, ad = [], []
-    for c in rng.choice(len(w["r_cell"]), 4, replace=False):
-        a = int(rng.integers(3))
-        wp, wm = dict(w), dict(w)
-        wp["r_cell"] = w["r_cell"].copy()
-        wm["r_cell"] = w["r_cell"].copy()
-        wp["r_cell"][c, a] += h
-        wm["r_cell"][c, a] -= h
-        fd.append((gpu_loss_and_grad(ctx, wp, 0, want_grad=False)[0] -
-                   gpu_loss_and_grad(ctx, wm, 0, want_grad=False)[0]) / (2 * h))
+    for i, c in enumerate(cells):
+        a = i % 3
+
+        def mod(d, c=c, a=a):
+            r = w["r_cell"].copy()
+            r[c, a] += d
+            return dict(w, r_cell=r)
+        fd.append(fd_of(mod))
         ad.append(g["r"][c, a])
-    assert rel_group(ad, fd) <= 1e-6, (ad, fd)
+    print("  coordinates: max rel", rel_group(ad, fd), flush=True)
+    assert rel_group(ad, fd) <= 1e-6
+    for part, key in ((1.0, "eps_re"), (1j, "eps_im")):
+        fd, ad = [], []
+        for c in cells[:8]:
+            def mod(d, c=c):
+                e = np.array(w["eps_cell"], dtype=np.complex128, copy=True)
+                e[c] += part * d
+                return dict(w, eps_cell=e)
+            fd.append(fd_of(mod))
+            ad.append(g[key][c])
+        print(" ", key, "max rel", rel_group(ad, fd), flush=True)
+        assert rel_group(ad, fd) <= 1e-6
+    fdw = fd_of(lambda d: dict(w, wavelength=w["wavelength"] + d))
+    print("  wavelength", g["wavelength"], fdw, flush=True)
+    assert abs(g["wavelength"] - fdw) <= 1e-6 * abs(fdw)
 
 
 def test_adjoint_state_and_argument_errors(ctx):
