@@ -33,6 +33,12 @@
 
 namespace gdm {
 
+// FP32 trailing updates with the 64 x 64 tile by 3M products (1) or the
+// expanded 4M form (0)
+#ifndef GEMM_UPDATE_3M
+#define GEMM_UPDATE_3M 1
+#endif
+
 template <typename T> struct acc_of;
 template <> struct acc_of<double> { using type = v4d; };
 template <> struct acc_of<float> { using type = v4f; };
@@ -244,6 +250,163 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
     }
 }
 
+// FP32 trailing update C -= A B by the 3M form of the complex product: with
+// A = Ar + i Ai, B = Br + i Bi the three real products T1 = Ar Br, T2 = Ai Bi
+// and T3 = (Ar + Ai)(Br + Bi) give Re(AB) = T1 - T2 and Im(AB) = T3 - T1 - T2,
+// so 3 real MFMAs replace the 4 of the expanded form (12 instead of 16 16x16x4
+// MFMAs per wave per 4 complex k).  The staging writes each operand as three
+// real planes (re, im, re + im; A as [k][row], B as [k][column], rows padded by
+// 16 floats) and every wave of the 2 x 2 grid holds 3 x WMB x WNB accumulators.
+// The extra rounding of the sums is that of 3M (its error bound is a small
+// multiple of the 4M one); the factorisations that use it are FP32 ones
+// refined in FP64.  Tiles: BM = 32 WMB complex rows, BN = 32 WNB columns, BK
+// complex k per stage; the XCD remap of cgemm_kernel.
+template <int WMB, int WNB, int BK, bool CB>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const float2* __restrict__ A, int64_t lda,
+                      const float2* __restrict__ B, int64_t ldb, float2* __restrict__ C, int64_t ldc, int tiles_m,
+                      int tiles, int64_t sA, int64_t sB, int64_t sC) {
+  constexpr int BM = 32 * WMB, BN = 32 * WNB;
+  constexpr int AL = BM * BK / 256, BL = BK * BN / 256;
+  static_assert(AL * 256 == BM * BK && BL * 256 == BK * BN && BK % 4 == 0, "tile shape");
+  constexpr int AP = BM + 16, BP = BN + 16;
+  A += (int64_t)blockIdx.y * sA;
+  B += (int64_t)blockIdx.y * sB;
+  C += (int64_t)blockIdx.y * sC;
+  __shared__ float As[2][3][BK * AP];  // [plane][k][row]
+  __shared__ float Bs[2][3][BK * BP];  // [plane][k][column]
+  const int bid = blockIdx.x;
+  const int xcd = bid & 7, loc = bid >> 3;
+  const int per = tiles >> 3, rem = tiles & 7;
+  const int tile = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + loc;
+  const int tm = tile % tiles_m, tn = tile / tiles_m;
+  const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wrow = (wave & 1) * 16 * WMB;  // complex rows
+  const int wcol = (wave >> 1) * 16 * WNB;
+  const int lr = lane & 15, lk = lane >> 4;
+  v4f acc[3][WMB][WNB];
+#pragma unroll
+  for (int q = 0; q < 3; ++q)
+#pragma unroll
+    for (int i = 0; i < WMB; ++i)
+#pragma unroll
+      for (int j = 0; j < WNB; ++j) acc[q][i][j] = v4f{0, 0, 0, 0};
+  float2 ra[AL], rb[BL];
+  auto gload = [&](int64_t kb) {
+#pragma unroll
+    for (int i = 0; i < AL; ++i) {
+      const int idx = tid + 256 * i;
+      const int mc = idx % BM, kc = idx / BM;
+      const int64_t gm = m0 + mc, gk = kb + kc;
+      ra[i] = (gm < m && gk < k) ? A[gm + gk * lda] : make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int i = 0; i < BL; ++i) {
+      const int idx = tid + 256 * i;
+      const int kc = idx % BK, nc = idx / BK;
+      const int64_t gn = n0 + nc, gk = kb + kc;
+      rb[i] = (gn < n && gk < k) ? B[gk + gn * ldb] : make_float2(0.f, 0.f);
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < AL; ++i) {
+      const int idx = tid + 256 * i;
+      const int mc = idx % BM, kc = idx / BM;
+      As[buf][0][kc * AP + mc] = ra[i].x;
+      As[buf][1][kc * AP + mc] = ra[i].y;
+      As[buf][2][kc * AP + mc] = ra[i].x + ra[i].y;
+    }
+#pragma unroll
+    for (int i = 0; i < BL; ++i) {
+      const int idx = tid + 256 * i;
+      const int kc = idx % BK, nc = idx / BK;
+      Bs[buf][0][kc * BP + nc] = rb[i].x;
+      Bs[buf][1][kc * BP + nc] = rb[i].y;
+      Bs[buf][2][kc * BP + nc] = rb[i].x + rb[i].y;
+    }
+  };
+  const int64_t ktiles = (k + BK - 1) / BK;
+  gload(0);
+  sstore(0);
+  __syncthreads();
+  for (int64_t kt = 0; kt < ktiles; ++kt) {
+    const int buf = (int)(kt & 1);
+    if (kt + 1 < ktiles) gload((kt + 1) * BK);
+#pragma unroll
+    for (int k4 = 0; k4 < BK; k4 += 4) {
+      const int kr = k4 + lk;
+      float a[3][WMB], b[3][WNB];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+#pragma unroll
+        for (int i = 0; i < WMB; ++i) a[q][i] = As[buf][q][kr * AP + wrow + 16 * i + lr];
+#pragma unroll
+        for (int j = 0; j < WNB; ++j) b[q][j] = Bs[buf][q][kr * BP + wcol + 16 * j + lr];
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int i = 0; i < WMB; ++i)
+#pragma unroll
+          for (int j = 0; j < WNB; ++j) acc[q][i][j] = mfma16(a[q][i], b[q][j], acc[q][i][j]);
+    }
+    if (kt + 1 < ktiles) sstore(buf ^ 1);
+    __syncthreads();
+  }
+  // lane holds rows 4 lk + r (r < 4) of column lr of each 16 x 16 block
+  auto out = [&](int i, int j, int r, float& cr, float& ci) {
+    const float t1 = acc[0][i][j][r], t2 = acc[1][i][j][r], t3 = acc[2][i][j][r];
+    cr = t1 - t2;
+    ci = t3 - t1 - t2;
+  };
+  if constexpr (CB) {
+    // every C load before the first store (the batched products' epilogue)
+    float2 cold[WMB][WNB][4];
+#pragma unroll
+    for (int i = 0; i < WMB; ++i)
+#pragma unroll
+      for (int j = 0; j < WNB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = m0 + wrow + 16 * i + 4 * lk + r, col = n0 + wcol + 16 * j + lr;
+          cold[i][j][r] = (row < m && col < n) ? C[row + col * ldc] : make_float2(0.f, 0.f);
+        }
+#pragma unroll
+    for (int i = 0; i < WMB; ++i)
+#pragma unroll
+      for (int j = 0; j < WNB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = m0 + wrow + 16 * i + 4 * lk + r, col = n0 + wcol + 16 * j + lr;
+          if (row >= m || col >= n) continue;
+          float cr, ci;
+          out(i, j, r, cr, ci);
+          C[row + col * ldc] = make_float2(cold[i][j][r].x - cr, cold[i][j][r].y - ci);
+        }
+    return;
+  }
+#pragma unroll
+  for (int i = 0; i < WMB; ++i)
+#pragma unroll
+    for (int j = 0; j < WNB; ++j) {
+      const int64_t col = n0 + wcol + 16 * j + lr;
+      if (col >= n) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = m0 + wrow + 16 * i + 4 * lk + r;
+        if (row >= m) continue;
+        float cr, ci;
+        out(i, j, r, cr, ci);
+        float2 c = C[row + col * ldc];
+        c.x -= cr;
+        c.y -= ci;
+        C[row + col * ldc] = c;
+      }
+    }
+}
+
 // Compute units of the current device (queried once per device).
 static int gemm_num_cu() {
   static int cu[64] = {};
@@ -312,12 +475,33 @@ hipError_t launch_gemm(int mode, int transA, int64_t m, int64_t n, int64_t k, co
   return launch_cfg<T, 1, 1, 0>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
 }
 
+// The FP32 update with the 64 x 64 tile: 3M products (cgemm3m_update_kernel).
+static hipError_t launch_update_3m(int64_t m, int64_t n, int64_t k, const float2* a, int64_t lda, const float2* b,
+                                   int64_t ldb, float2* c, int64_t ldc, hipStream_t st, int nbatch, int64_t sA,
+                                   int64_t sB, int64_t sC) {
+  const int64_t tm = (m + 63) / 64, tn = (n + 63) / 64;
+  if (tm * tn > INT32_MAX) return hipErrorInvalidValue;
+  const int tiles = (int)(tm * tn);
+  if (nbatch > 1)
+    hipLaunchKernelGGL((cgemm3m_update_kernel<2, 2, 8, true>), dim3(tiles, nbatch), dim3(256), 0, st, m, n, k, a, lda,
+                       b, ldb, c, ldc, (int)tm, tiles, sA, sB, sC);
+  else
+    hipLaunchKernelGGL((cgemm3m_update_kernel<2, 2, 4, false>), dim3(tiles, nbatch), dim3(256), 0, st, m, n, k, a,
+                       lda, b, ldb, c, ldc, (int)tm, tiles, sA, sB, sC);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_gemm_update(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
                               int64_t ldb, void* C, int64_t ldc, hipStream_t st, int nbatch, int64_t sA, int64_t sB,
                               int64_t sC) {
   if (m <= 0 || n <= 0 || k <= 0 || nbatch <= 0) return hipSuccess;
   if (nbatch > 65535) return hipErrorInvalidValue;
+  if constexpr (sizeof(T) == 4) {
+    if (GEMM_UPDATE_3M && !use_small_tiles(m, n, nbatch))
+      return launch_update_3m(m, n, k, static_cast<const float2*>(A), lda, static_cast<const float2*>(B), ldb,
+                              static_cast<float2*>(C), ldc, st, nbatch, sA, sB, sC);
+  }
   return launch_cfg<T, 0, 0, 1>(m, n, k, static_cast<const cplx<T>*>(A), lda, static_cast<const cplx<T>*>(B), ldb,
                                 static_cast<cplx<T>*>(C), ldc, st, GemmMask{}, nbatch, sA, sB, sC);
 }
