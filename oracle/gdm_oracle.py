@@ -51,6 +51,16 @@ follows (sections / equations of the paper):
   multipole decomposition, alpha_eff = F0^+ P by least squares; pinned by the
   one-cell case (the cell's dressed polarisability exactly) and by the
   extracted model reproducing the full simulation of a small particle.
+* global polarisability matrices (Sec. "Extraction of effective models";
+  Fig. reference_system): M effective pairs whose moments are q_g = alpha_G F_g
+  with one non-local 6M x 6M alpha_G, not coupled among themselves; their
+  absorption also subtracts the group's mutual radiation (the paper's own code
+  leaves GPM absorption to ext minus the far-field integral, Sec.
+  "Implementation technical details"; the two agree exactly).  Extraction by
+  scattered-field matching at probes and alpha_G = F0^+ P.  Pinned by the
+  exact GPM of a cluster of coupled point dipoles (whole-system results
+  unchanged, extraction returns it) and by a rod whose near field needs
+  several pairs.
 
 Units: nm, nm^2.  Complex values are numpy complex128.
 """
@@ -236,17 +246,46 @@ class Dipoles:
         self.idx[self.nc:, 3:6] = 3 * self.N + 3 * np.arange(self.ne)[:, None] + np.arange(3)[None, :]
         self.n = 3 * self.N + 3 * self.ne
         self.rho = np.concatenate([np.zeros(self.nc), np.ones(self.ne)])  # radiative reaction in alpha
+        # GPM groups (Sec. "Extraction of effective models": a global polarisability
+        # matrix over M effective dipoles): wl["gpm"] = [(first, M, alpha [6M, 6M]), ...]
+        # with `first` an index among the effective dipoles; members' own alpha_eff is
+        # not used, their moments are q_g = alpha_G F_g (blocks ordered (dipole, p, m)),
+        # and members of one group do not couple through G~ (alpha_G holds that).
+        self.groups = []
+        self.gid = -np.ones(self.N, dtype=np.int64)
+        for g, (first, M, aG) in enumerate(wl.get("gpm", []) or []):
+            mem = self.nc + int(first) + np.arange(int(M))
+            aG = np.asarray(aG, dtype=np.complex128).reshape(6 * int(M), 6 * int(M))
+            assert np.all(self.gid[mem] < 0) and mem[-1] < self.N
+            self.gid[mem] = g
+            self.alpha6[mem] = 0.0
+            self.groups.append((mem, aG))
+
+    def group_cols(self, mem) -> np.ndarray:
+        """Reduced indices of a group's unknowns, ordered (dipole, component)."""
+        return self.idx[mem].reshape(-1)
+
+    def q_of(self, F: np.ndarray) -> np.ndarray:
+        """q = A F in the reduced layout (local blocks, then the GPM groups)."""
+        q = self.from6(np.einsum("dab,db...->da...", self.alpha6, self.to6(F)))
+        for mem, aG in self.groups:
+            cols = self.group_cols(mem)
+            q[cols] = np.tensordot(aG, F[cols], axes=(1, 0))
+        return q
 
     def comps(self, d: int):
         return np.arange(6) if d >= self.nc else np.arange(3)
 
     def alpha_matrix(self) -> np.ndarray:
-        """Block-diagonal A in the reduced layout (q = A F)."""
+        """A in the reduced layout (q = A F): block diagonal, plus the GPM blocks."""
         A = np.zeros((self.n, self.n), dtype=np.complex128)
         for d in range(self.N):
             c = self.comps(d)
             ii = self.idx[d, c]
             A[np.ix_(ii, ii)] = self.alpha6[d][np.ix_(c, c)]
+        for mem, aG in self.groups:
+            cols = self.group_cols(mem)
+            A[np.ix_(cols, cols)] = aG
         return A
 
     def to6(self, x: np.ndarray) -> np.ndarray:
@@ -295,6 +334,9 @@ def coupling_greens(D: Dipoles, chunk: int = 64) -> np.ndarray:
             if D.ne:
                 cm = rows_all[D.nc:, 3:6].reshape(-1)
                 G[np.ix_(rr, cm)] = blk[:, D.nc:, :, 3:6].transpose(0, 2, 1, 3).reshape(len(rr), 3 * D.ne)
+    for mem, _ in D.groups:  # no coupling inside a GPM group
+        cols = D.group_cols(mem)
+        G[np.ix_(cols, cols)] = 0.0
     return G
 
 
@@ -307,6 +349,9 @@ def apply_alpha_right(D: Dipoles, G: np.ndarray) -> np.ndarray:
     for d in range(D.nc, D.N):
         c = D.idx[d]
         out[:, c] = G[:, c] @ D.alpha6[d]
+    for mem, aG in D.groups:
+        cols = D.group_cols(mem)
+        out[:, cols] = G[:, cols] @ aG
     return out
 
 
@@ -325,7 +370,7 @@ def matvec_rows(D: Dipoles, rows: np.ndarray, x: np.ndarray):
     sum of the moduli of the terms, |x_u| + sum |G6_ij q_j|_c + |S6_i q_i|_c,
     a scale for round-off bounds.  x: [n] (one vector)."""
     rows = np.asarray(rows, dtype=np.int64)
-    q6 = np.einsum("dab,db->da", D.alpha6, D.to6(x))  # [N, 6]
+    q6 = D.to6(D.q_of(x))  # [N, 6]
     # (dipole, component) of every requested unknown
     where = {int(D.idx[d, c]): (d, c) for d in range(D.N) for c in range(6) if D.idx[d, c] >= 0}
     out = np.zeros(len(rows), dtype=np.complex128)
@@ -337,6 +382,8 @@ def matvec_rows(D: Dipoles, rows: np.ndarray, x: np.ndarray):
         g = green6(R, D.k0, D.n_env)[:, c, :]  # [N, 6]
         terms = np.einsum("jb,jb->j", g, q6)
         terms[i] = D.S6[i][c] @ q6[i]
+        if D.gid[i] >= 0:  # no coupling inside a GPM group
+            terms[(D.gid == D.gid[i]) & (np.arange(D.N) != i)] = 0.0
         out[t] = x[u] - np.sum(terms)
         scale[t] = abs(x[u]) + np.sum(np.abs(terms))
     return out, scale
@@ -378,7 +425,7 @@ def simulate(wl: Dict, mode: str = "static", wavelength: float = None, eps_cell=
     M = assemble(D)
     F0 = incident_at_dipoles(D, wl["khat"], wl["e0"])
     F, lu = solve(M, F0)
-    q = D.from6(np.einsum("dab,dbr->dar", D.alpha6, D.to6(F)))
+    q = D.q_of(F)
     out = dict(D=D, F0=F0, F=F, q=q, lu=lu)
     out.update(cross_sections(D, F0, F, q, np.sum(np.abs(np.atleast_2d(wl["e0"])) ** 2, axis=1)))
     if keep_matrix:
@@ -399,6 +446,15 @@ def cross_sections(D: Dipoles, F0, F, q, e0_norm2) -> Dict:
     prad = (2.0 / 3.0) * D.k ** 3 * np.einsum("c,dcr->dr", w, np.abs(q6) ** 2)  # [N, rhs]
     ext = C * np.sum(np.imag(np.conj(F0) * q), axis=0)
     absr = C * (np.sum(np.imag(np.conj(F) * q), axis=0) - np.sum(D.rho[:, None] * prad, axis=0))
+    # a GPM group radiates as a whole: also subtract its members' mutual terms
+    # Im sum_{i != j in g} q_i^H G6(r_i - r_j) q_j (the self terms are in prad)
+    for mem, _ in D.groups:
+        R = D.pos[mem][:, None, :] - D.pos[mem][None, :, :]
+        same = np.eye(len(mem), dtype=bool)
+        g6 = green6(np.where(same[..., None], 1.0, R), D.k0, D.n_env)
+        g6[same] = 0.0
+        qg = q6[mem]
+        absr = absr - C * np.imag(np.einsum("iar,ijab,jbr->r", np.conj(qg), g6, qg))
     rad = C * np.sum(prad, axis=0)
     return dict(ext=ext, abs=absr, sca=ext - absr, rad=rad)
 
@@ -490,7 +546,7 @@ def green_scattered(wl: Dict, r_src, r_pts, mode: str = "static"):
     d = np.tile(np.eye(6, dtype=np.complex128), (S, 1))  # RHS 6 s + c
     F0 = dipole_source_at_dipoles(D, np.repeat(r_src, 6, axis=0), d)
     F, _ = solve(M, F0)
-    q = D.from6(np.einsum("dab,dbr->dar", D.alpha6, D.to6(F)))
+    q = D.q_of(F)
     r_pts = np.asarray(r_pts, dtype=np.float64).reshape(-1, 3)
     E, H = scattered_fields(D, q, r_pts)  # [6 S, P, 3]
     G = np.concatenate([E, H], axis=-1).reshape(S, 6, len(r_pts), 6)
@@ -656,13 +712,49 @@ def extract_dipole_pair(wl: Dict, khat, e0, r_src=None, d_src=None, r0=None, mod
         cols.append(dipole_source_at_dipoles(D, r_src, d_src))
     F0 = np.concatenate(cols, axis=1)
     F, _ = solve(M, F0)
-    q = D.from6(np.einsum("dab,dbr->dar", D.alpha6, D.to6(F)))
+    q = D.q_of(F)
     mo = multipole_moments(D, q, r0)
     P = np.concatenate([mo["p"], mo["m"]], axis=1)  # [N, 6]
     A = illumination_at_point(D, mo["r0"], khat, e0, r_src, d_src)
     X, *_ = np.linalg.lstsq(A, P, rcond=None)
     res = np.linalg.norm(A @ X - P) / np.linalg.norm(P)
     return X.T, float(res), mo["r0"]
+
+
+def extract_gpm(wl: Dict, r_gpm, khat, e0, r_src=None, d_src=None, r_probe=None, mode: str = "static"):
+    """Global polarisability matrix (6M x 6M) of the structure for M dipole
+    pairs at r_gpm [M, 3] (Sec. "Extraction of effective models"): for every
+    illumination the full system is solved and the scattered (E, H) at the
+    probes r_probe [P, 3] is computed (scattered_fields); the moments
+    (p_j, m_j) of the M pairs are the least-squares fit of that field by
+    sum_j G6(r_p - r_j) (p_j, m_j) (both E and H matched); with the rows of
+    F0 [N, 6M] the illuminations' (E0, H0) at the M positions and the rows of
+    P [N, 6M] the fitted moments, alpha_G minimises ||F0 alpha_G^T - P||.
+    Returns (alpha_G [6M, 6M] ordered (pair, p then m), relative residual of
+    the field fit (all illuminations), relative residual of the alpha fit)."""
+    D = Dipoles(wl, mode=mode)
+    M = assemble(D)
+    cols = []
+    if khat is not None and len(np.atleast_2d(khat)):
+        cols.append(incident_at_dipoles(D, khat, e0))
+    if r_src is not None and len(np.atleast_2d(r_src)):
+        cols.append(dipole_source_at_dipoles(D, r_src, d_src))
+    F0 = np.concatenate(cols, axis=1)
+    F, _ = solve(M, F0)
+    q = D.q_of(F)
+    rp = np.asarray(r_probe, dtype=np.float64).reshape(-1, 3)
+    rg = np.asarray(r_gpm, dtype=np.float64).reshape(-1, 3)
+    Es, Hs = scattered_fields(D, q, rp)  # [N, P, 3] each
+    Y = np.concatenate([Es, Hs], axis=2).reshape(Es.shape[0], -1).T  # [6P, N]
+    G = green6(rp[:, None, :] - rg[None, :, :], D.k0, D.n_env)  # [P, M, 6, 6]
+    G = G.transpose(0, 2, 1, 3).reshape(6 * len(rp), 6 * len(rg))
+    Q, *_ = np.linalg.lstsq(G, Y, rcond=None)  # [6M, N]
+    res_field = np.linalg.norm(G @ Q - Y) / np.linalg.norm(Y)
+    A = np.concatenate([illumination_at_point(D, r, khat, e0, r_src, d_src) for r in rg], axis=1)
+    P = Q.T  # [N, 6M]
+    X, *_ = np.linalg.lstsq(A, P, rcond=None)
+    res_alpha = np.linalg.norm(A @ X - P) / np.linalg.norm(P)
+    return X.T, float(res_field), float(res_alpha)
 
 
 # ----------------------------------------------------------------------------
@@ -695,11 +787,12 @@ def adjoint_gradient(wl: Dict, w_sca: float = 1.0, w_nf: float = None, mode="sta
       dL = 2 Re[(lam + g_F0) . dF0 + lam . dG~ q + (lam^T G~ + g_qe) dA F
                 + g_Ep . (dE0_p + dG_p q)] + explicit dependence through C(k0)."""
     D = Dipoles(wl, None, mode)
+    assert not D.groups, "the gradient is written for local polarisabilities"
     M = assemble(D)
     Gt = coupling_greens(D)
     F0 = incident_at_dipoles(D, wl["khat"], wl["e0"])
     F, lu = solve(M, F0)
-    q = D.from6(np.einsum("dab,dbr->dar", D.alpha6, D.to6(F)))
+    q = D.q_of(F)
     e2 = np.sum(np.abs(np.atleast_2d(wl["e0"])) ** 2, axis=1)  # [rhs]
     C = FOUR_PI * D.k0 / (D.n_env * e2)  # [rhs]
     nrhs = F0.shape[1]
