@@ -130,6 +130,23 @@ gdm_status gdm_set_structure(gdm_ctx* ctx, int64_t n_cell, const double* r_cell,
 /* Number of unknowns n of the current structure (0 if none). */
 int64_t gdm_num_unknowns(const gdm_ctx* ctx);
 
+/* Global polarisability matrices (Sec. "Extraction of effective models"; Fig.
+ * reference_system (b)): group g joins the effective dipoles [first[g],
+ * first[g] + size[g]) of the current structure (host arrays, 1 <= size <= 32,
+ * no dipole in two groups) into one non-local model: their moments are
+ * q_g = alpha_G F_g with alpha_G the g-th complex matrix of `alpha` (device,
+ * the groups' (6 size)^2 matrices one after another, each row-major with rows
+ * and columns ordered (member, then p_x, p_y, p_z, m_x, m_y, m_z)), and they do
+ * not couple among themselves through G~ (alpha_G holds that).  The members'
+ * own alpha_eff is ignored while the groups are set.  Absorption of a group
+ * also removes the power its members radiate into each other's fields, so that
+ * sca = ext - abs is the power radiated by all dipoles.  n_groups = 0 removes
+ * the groups; gdm_set_structure removes them too.  `alpha` is copied.
+ * Invalidates the factors.  With groups set, gdm_solve_iterative and
+ * gdm_adjoint return GDM_E_ARG. */
+gdm_status gdm_set_gpm(gdm_ctx* ctx, int64_t n_groups, const int64_t* first, const int64_t* size,
+                       const double* alpha);
+
 /* Step (a) alone: write M = I - G~ A at `wavelength_nm` into the caller's
  * column-major buffer M_out (n x n, leading dimension ld >= n), as complex
  * double (dtype 0) or complex float (dtype 1; FP64 arithmetic, rounded once). */
@@ -274,6 +291,25 @@ gdm_status gdm_multipoles(gdm_ctx* ctx, int64_t n_rhs, const double* q, const do
 gdm_status gdm_extract_dipole_pair(gdm_ctx* ctx, int64_t n_pw, const double* khat, const double* e0, int64_t n_src,
                                    const double* r_src, const double* d_src, const double* r0, double tol,
                                    int32_t max_iter, double* alpha, double* resid, gdm_info* info);
+
+/* GPM of the structure for n_pairs (1..32) dipole pairs at r_gpm [n_pairs][3]
+ * (device) by scattered-field matching (Sec. "Extraction of effective
+ * models"): the illuminations (as in gdm_extract_dipole_pair) are solved with
+ * the context's factors; the scattered (E, H) of each response at the probes
+ * r_probe [n_probe][3] (device, n_pairs <= n_probe <= 2^20, off the dipoles and
+ * the pairs) is fitted in least squares by sum_j G6(r_p - r_j) (p_j, m_j);
+ * with F0 [N][6 n_pairs] the illuminations' (E0, H0) at the pairs and P
+ * [N][6 n_pairs] the fitted moments, alpha (device, complex (6 n_pairs)^2
+ * row-major, ordered as in gdm_set_gpm) minimises ||F0 alpha^T - P||_F.
+ * resid (host double[2], may be NULL) = relative residuals of the field fit
+ * and of the alpha fit.  Needs 6 n_pairs <= n_pw + n_src <= 4096.  GDM_E_ARG
+ * if the fit is rank-deficient (pairs or probes that do not determine the
+ * model); GDM_E_STATE without factors; GDM_E_PROBE_AT_DIPOLE for a source or
+ * probe on a dipole. */
+gdm_status gdm_extract_gpm(gdm_ctx* ctx, int64_t n_pw, const double* khat, const double* e0, int64_t n_src,
+                           const double* r_src, const double* d_src, int64_t n_pairs, const double* r_gpm,
+                           int64_t n_probe, const double* r_probe, double tol, int32_t max_iter, double* alpha,
+                           double* resid, gdm_info* info);
 
 /* Point dipole sources as the illumination (Appendix, illumination classes:
  * electric and magnetic dipole point sources): the incident field of sources

@@ -85,6 +85,10 @@ struct gdm_ctx {
   double step = 0.0;
   gdm_selfterm self_mode = GDM_SELF_STATIC;
   DevBuf pos, eps, alpha_c, alpha6;
+  // global polarisability matrices (gdm_set_gpm): group of each effective
+  // dipole (-1 local), table (first, size, offset) and the matrices
+  DevBuf gpm_gid, gpm_tab, gpm_alpha;
+  int64_t n_gpm = 0;
   // factorisation state
   double wavelength = 0.0;
   bool factored = false;
@@ -119,7 +123,8 @@ struct gdm_ctx {
   MemAccount mem;    // device bytes of the buffers below and the caller's limit
   std::vector<DevBuf*> buffers() {
     return {&pos, &eps,  &alpha_c, &alpha6, &M,     &M64,  &ipiv,  &luws, &rows,   &ext_ws, &X,   &Rr,   &C32, &small,
-            &scratch, &flag, &Lam,  &adj,   &part, &bM64, &bM32, &bipiv, &bws, &bvec, &bpart, &bsmall, &bpos, &bwl, &iter, &src};
+            &scratch, &flag, &Lam,  &adj,   &part, &bM64, &bM32, &bipiv, &bws, &bvec, &bpart, &bsmall, &bpos, &bwl, &iter, &src,
+            &gpm_gid, &gpm_tab, &gpm_alpha};
   }
 };
 
@@ -150,6 +155,12 @@ static DipoleView view_of(const gdm_ctx* c, double2 self_c) {
   d.nc = c->nc;
   d.ne = c->ne;
   d.self_c = self_c;
+  if (c->n_gpm > 0) {
+    d.gid = c->gpm_gid.as<int32_t>();
+    d.gtab = c->gpm_tab.as<int64_t>();
+    d.galpha = c->gpm_alpha.as<double2>();
+    d.ngroups = c->n_gpm;
+  }
   return d;
 }
 
@@ -979,6 +990,7 @@ gdm_status gdm_set_structure(gdm_ctx* c, int64_t n_cell, const double* r_cell, d
   c->ne = n_eff;
   c->N = N;
   c->n = 3 * N + 3 * n_eff;
+  c->n_gpm = 0;  // groups refer to the previous structure's effective dipoles
   c->step = n_cell > 0 ? step_nm : 1.0;
   c->self_mode = selfterm;
   c->factored = false;
@@ -986,6 +998,44 @@ gdm_status gdm_set_structure(gdm_ctx* c, int64_t n_cell, const double* r_cell, d
 }
 
 int64_t gdm_num_unknowns(const gdm_ctx* c) { return c ? c->n : 0; }
+
+gdm_status gdm_set_gpm(gdm_ctx* c, int64_t n_groups, const int64_t* first, const int64_t* size, const double* alpha) {
+  if (!c) return GDM_E_ARG;
+  if (n_groups < 0 || (n_groups > 0 && (!first || !size || !alpha)))
+    FAIL(c, GDM_E_ARG, "need n_groups >= 0 and, for groups, first, size and alpha");
+  if (n_groups > 0 && c->ne <= 0) FAIL(c, GDM_E_ARG, "the structure has no effective dipoles");
+  std::vector<int32_t> gid((size_t)std::max<int64_t>(c->ne, 1), -1);
+  std::vector<int64_t> tab((size_t)std::max<int64_t>(3 * n_groups, 1));
+  int64_t off = 0;
+  for (int64_t g = 0; g < n_groups; ++g) {
+    const int64_t f = first[g], m = size[g];
+    if (m < 1 || m > GPM_MAX_PAIRS) FAIL(c, GDM_E_ARG, "group %lld: size %lld not in [1, %d]", (long long)g, (long long)m, GPM_MAX_PAIRS);
+    if (f < 0 || f + m > c->ne)
+      FAIL(c, GDM_E_ARG, "group %lld: effective dipoles [%lld, %lld) outside [0, %lld)", (long long)g, (long long)f,
+           (long long)(f + m), (long long)c->ne);
+    for (int64_t e = f; e < f + m; ++e) {
+      if (gid[e] >= 0) FAIL(c, GDM_E_ARG, "effective dipole %lld is in two groups", (long long)e);
+      gid[e] = (int32_t)g;
+    }
+    tab[3 * g] = f;
+    tab[3 * g + 1] = m;
+    tab[3 * g + 2] = off;
+    off += 36 * m * m;
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  c->factored = false;
+  c->n_gpm = 0;
+  if (n_groups == 0) return GDM_OK;
+  HIPCHK(c, c->gpm_gid.ensure(sizeof(int32_t) * gid.size()));
+  HIPCHK(c, c->gpm_tab.ensure(sizeof(int64_t) * tab.size()));
+  HIPCHK(c, c->gpm_alpha.ensure(sizeof(double2) * off));
+  HIPCHK(c, hipMemcpyAsync(c->gpm_gid.p, gid.data(), sizeof(int32_t) * gid.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->gpm_tab.p, tab.data(), sizeof(int64_t) * tab.size(), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->gpm_alpha.p, alpha, sizeof(double2) * off, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));  // the host vectors go out of scope
+  c->n_gpm = n_groups;
+  return GDM_OK;
+}
 
 gdm_status gdm_assemble(gdm_ctx* c, double wl, int dtype, void* M_out, int64_t ld) {
   if (!c) return GDM_E_ARG;
@@ -1079,6 +1129,7 @@ gdm_status gdm_solve_iterative(gdm_ctx* c, double wl, int64_t nrhs, const double
   if (s != GDM_OK) return s;
   if (nrhs <= 0 || !f0 || !q_out) FAIL(c, GDM_E_ARG, "need n_rhs > 0, f0 and q_out");
   if (nrhs > 65535) FAIL(c, GDM_E_ARG, "at most 65535 right-hand sides per call");
+  if (c->n_gpm > 0) FAIL(c, GDM_E_ARG, "the matrix-free solver does not handle GPM groups (use gdm_factorize)");
   if (restart <= 0) restart = 30;
   if (restart > 1000) FAIL(c, GDM_E_ARG, "restart must be <= 1000");
   if (max_iter <= 0) max_iter = 1000;
@@ -1189,6 +1240,7 @@ gdm_status gdm_adjoint(gdm_ctx* c, int64_t nrhs, const double* khat, const doubl
                        double* grad_wl, gdm_info* info) {
   if (!c) return GDM_E_ARG;
   if (!c->factored) FAIL(c, GDM_E_STATE, "gdm_adjoint needs the factors of gdm_factorize");
+  if (c->n_gpm > 0) FAIL(c, GDM_E_ARG, "gdm_adjoint is written for local polarisabilities (GPM groups are set)");
   if (nrhs <= 0 || nrhs > 65535) FAIL(c, GDM_E_ARG, "need 0 < n_rhs <= 65535");
   if (!khat || !e0 || !f0 || !q || !f) FAIL(c, GDM_E_ARG, "khat, e0, f0, q and f are required");
   if (!grad_r || !grad_wl || (c->nc > 0 && !grad_eps)) FAIL(c, GDM_E_ARG, "grad_r, grad_eps and grad_wl are required");
@@ -1408,14 +1460,17 @@ gdm_status gdm_cross_sections(gdm_ctx* c, int64_t nrhs, const double* f0, const 
   const Wave w = wave_of(c, c->wavelength);
   const DipoleView d = view_of(c, make_double2(0, 0));
   const int64_t nblk = sca_ff_blocks(c->N);
-  HIPCHK(c, c->small.ensure(sizeof(double) * std::max<int64_t>(5 * nrhs + nrhs * nblk, 4 * nrhs)));
+  const int64_t ng = c->n_gpm;
+  HIPCHK(c, c->small.ensure(sizeof(double) * std::max<int64_t>(5 * nrhs + nrhs * (nblk + ng), 4 * nrhs)));
   double* sums = c->small.as<double>();
-  double* part = sums + 5 * nrhs;
+  double* mutual = sums + 5 * nrhs;  // [nrhs][ng], GPM groups only
+  double* part = mutual + nrhs * ng;
   HIPCHK(c, launch_cs_sums(d, reinterpret_cast<const double2*>(f0), reinterpret_cast<const double2*>(q),
                            reinterpret_cast<const double2*>(f), c->n, nrhs, sums, c->stream));
+  HIPCHK(c, launch_gpm_mutual(d, w, reinterpret_cast<const double2*>(q), c->n, nrhs, mutual, c->stream));
   if (want_ff)
     HIPCHK(c, launch_sca_ff(d, w, reinterpret_cast<const double2*>(q), c->n, nrhs, part, nblk, c->stream));
-  std::vector<double> h(5 * nrhs + (want_ff ? nrhs * nblk : 0)), e2(nrhs);
+  std::vector<double> h(5 * nrhs + nrhs * ng + (want_ff ? nrhs * nblk : 0)), e2(nrhs);
   HIPCHK(c, hipMemcpyAsync(h.data(), sums, sizeof(double) * h.size(), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(e2.data(), e0_norm2, sizeof(double) * nrhs, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1425,8 +1480,10 @@ gdm_status gdm_cross_sections(gdm_ctx* c, int64_t nrhs, const double* f0, const 
     if (!(e2[r] > 0)) FAIL(c, GDM_E_ARG, "|E0|^2 of RHS %lld is not > 0", (long long)r);
     const double C = 4.0 * M_PI * w.k0 / (c->n_env * e2[r]);
     const double* s = &h[5 * r];
+    double mg = 0.0;  // the GPM groups' mutual radiation
+    for (int64_t g = 0; g < ng; ++g) mg += h[5 * nrhs + r * ng + g];
     const double ext = C * s[0];
-    const double ab = C * (s[1] - k3 * (s[3] / w.eps_env + s[4]));
+    const double ab = C * (s[1] - k3 * (s[3] / w.eps_env + s[4]) - mg);
     const double rad = C * k3 * ((s[2] + s[3]) / w.eps_env + s[4]);
     o[5 * r + 0] = ext;
     o[5 * r + 1] = ext - ab;
@@ -1434,7 +1491,7 @@ gdm_status gdm_cross_sections(gdm_ctx* c, int64_t nrhs, const double* f0, const 
     o[5 * r + 3] = rad;
     if (want_ff) {
       double off = 0;
-      for (int64_t b = 0; b < nblk; ++b) off += h[5 * nrhs + r * nblk + b];
+      for (int64_t b = 0; b < nblk; ++b) off += h[5 * nrhs + nrhs * ng + r * nblk + b];
       o[5 * r + 4] = C * off + rad;
     } else {
       o[5 * r + 4] = NAN;
@@ -1638,6 +1695,97 @@ gdm_status gdm_extract_dipole_pair(gdm_ctx* c, int64_t n_pw, const double* khat,
   for (int i = 0; i < 36; ++i)
     if (!std::isfinite(ha[i].x) || !std::isfinite(ha[i].y))
       FAIL(c, GDM_E_ARG, "the illuminations do not determine the model (rank-deficient fields at r0)");
+  if (s == GDM_E_NOCONV) FAIL(c, GDM_E_NOCONV, "refinement stopped at backward error %.3e > tol %.3e", ss.be, ss.tol);
+  return GDM_OK;
+}
+
+gdm_status gdm_extract_gpm(gdm_ctx* c, int64_t n_pw, const double* khat, const double* e0, int64_t n_src,
+                           const double* r_src, const double* d_src, int64_t n_pairs, const double* r_gpm,
+                           int64_t n_probe, const double* r_probe, double tol, int32_t max_iter, double* alpha,
+                           double* resid, gdm_info* info) {
+  if (!c) return GDM_E_ARG;
+  if (!c->factored) FAIL(c, GDM_E_STATE, "gdm_extract_gpm before gdm_factorize");
+  if (n_pw < 0 || n_src < 0 || (n_pw > 0 && (!khat || !e0)) || (n_src > 0 && (!r_src || !d_src)) || !alpha ||
+      !r_gpm || !r_probe)
+    FAIL(c, GDM_E_ARG, "bad illumination, position or output arguments");
+  if (n_pairs < 1 || n_pairs > GPM_MAX_PAIRS) FAIL(c, GDM_E_ARG, "n_pairs must be in [1, %d]", GPM_MAX_PAIRS);
+  const int64_t N = n_pw + n_src, K = 6 * n_pairs, P = n_probe;
+  if (N < K || N > 4096) FAIL(c, GDM_E_ARG, "need 6 n_pairs (%lld) to 4096 illuminations (got %lld)", (long long)K, (long long)N);
+  if (P < n_pairs || P > (1 << 20)) FAIL(c, GDM_E_ARG, "need n_pairs to 2^20 probes (got %lld)", (long long)P);
+  HIPCHK(c, hipSetDevice(c->device));
+  const int64_t n = c->n, m1 = 6 * P;
+  // F0 [N][n], Q [N][n], E, H [N][P][3], Gf (m1 x K), Y (m1 x N), X1 (K x N),
+  // F0g (N x K), PB (N x K), rdiag [K], norms [2][N] and [2][K]
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const size_t z = sizeof(double2);
+  const size_t sizes[] = {z * N * n, z * N * n, z * N * P * 3, z * N * P * 3, z * m1 * K, z * m1 * N,
+                          z * K * N, z * N * K, z * N * K, z * K, sizeof(double) * 2 * N, sizeof(double) * 2 * K};
+  size_t offs[12], tot = 0;
+  for (int i = 0; i < 12; ++i) {
+    offs[i] = tot;
+    tot += al(sizes[i]);
+  }
+  HIPCHK(c, c->src.ensure(tot));
+  char* base = static_cast<char*>(c->src.p);
+  double2* F0 = reinterpret_cast<double2*>(base + offs[0]);
+  double2* Q = reinterpret_cast<double2*>(base + offs[1]);
+  double2* E = reinterpret_cast<double2*>(base + offs[2]);
+  double2* H = reinterpret_cast<double2*>(base + offs[3]);
+  double2* Gf = reinterpret_cast<double2*>(base + offs[4]);
+  double2* Y = reinterpret_cast<double2*>(base + offs[5]);
+  double2* X1 = reinterpret_cast<double2*>(base + offs[6]);
+  double2* F0g = reinterpret_cast<double2*>(base + offs[7]);
+  double2* PB = reinterpret_cast<double2*>(base + offs[8]);
+  double2* rdiag = reinterpret_cast<double2*>(base + offs[9]);
+  double* nrm1 = reinterpret_cast<double*>(base + offs[10]);
+  double* nrm2 = reinterpret_cast<double*>(base + offs[11]);
+  const Wave w = wave_of(c, c->wavelength);
+  const DipoleView d = view_of(c, make_double2(0, 0));
+  if (n_pw > 0)
+    HIPCHK(c, launch_incident(d, w, c->n_env, n_pw, khat, reinterpret_cast<const double2*>(e0), F0, n, c->stream));
+  if (n_src > 0) {
+    gdm_status s = gdm_dipole_sources(c, n_src, r_src, d_src, reinterpret_cast<double*>(F0 + (size_t)n_pw * n));
+    if (s != GDM_OK) return s;
+  }
+  HIPCHK(c, c->X.ensure(sizeof(double2) * n * N));
+  double2* X = c->X.as<double2>();
+  SolveStats ss;
+  gdm_status s = solve_core(c, 0, N, F0, X, tol, max_iter, ss);
+  if (s != GDM_OK && s != GDM_E_NOCONV) return s;
+  HIPCHK(c, launch_apply_alpha(d, X, n, Q, n, N, c->stream));
+  gdm_status sf = gdm_fields(c, N, reinterpret_cast<const double*>(Q), P, r_probe, reinterpret_cast<double*>(E),
+                             reinterpret_cast<double*>(H));
+  if (sf != GDM_OK) return sf;
+  // moments of the pairs: min || Gf X1 - Y || over all illuminations at once
+  HIPCHK(c, launch_gpm_pack_fields(E, H, N, P, Y, c->stream));
+  HIPCHK(c, launch_gpm_fit_matrix(w, r_probe, P, r_gpm, n_pairs, Gf, c->stream));
+  HIPCHK(c, launch_qr_lsq(Gf, m1, (int)K, Y, (int)N, X1, rdiag, nrm1, c->stream));
+  // alpha_G: min || F0g X2 - PB ||, PB = X1^T; X2 (column-major K x K) is alpha_G row-major
+  HIPCHK(c, launch_gpm_illumination(w, c->n_env, r_gpm, n_pairs, n_pw, khat, reinterpret_cast<const double2*>(e0),
+                                    n_src, r_src, reinterpret_cast<const double2*>(d_src), F0g, c->stream));
+  HIPCHK(c, launch_transpose(X1, K, N, PB, c->stream));
+  HIPCHK(c, launch_qr_lsq(F0g, N, (int)K, PB, (int)K, reinterpret_cast<double2*>(alpha), rdiag, nrm2, c->stream));
+  std::vector<double> h1(2 * N), h2(2 * K);
+  std::vector<double2> ha((size_t)K * K);
+  HIPCHK(c, hipMemcpyAsync(h1.data(), nrm1, sizeof(double) * h1.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(h2.data(), nrm2, sizeof(double) * h2.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(ha.data(), alpha, sizeof(double2) * ha.size(), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double b1 = 0, r1 = 0, b2 = 0, r2 = 0;
+  for (int64_t i = 0; i < N; ++i) b1 += h1[i], r1 += h1[N + i];
+  for (int64_t i = 0; i < K; ++i) b2 += h2[i], r2 += h2[K + i];
+  if (resid) {
+    resid[0] = b1 > 0 ? std::sqrt(r1 / b1) : 0.0;
+    resid[1] = b2 > 0 ? std::sqrt(r2 / b2) : 0.0;
+  }
+  if (info) {
+    info->ir_iters = ss.iters;
+    info->backward_err = ss.be;
+    info->bad_index = -1;
+  }
+  for (const double2& v : ha)
+    if (!std::isfinite(v.x) || !std::isfinite(v.y))
+      FAIL(c, GDM_E_ARG, "the probes or the illuminations do not determine the model (rank-deficient fit)");
   if (s == GDM_E_NOCONV) FAIL(c, GDM_E_NOCONV, "refinement stopped at backward error %.3e > tol %.3e", ss.be, ss.tol);
   return GDM_OK;
 }

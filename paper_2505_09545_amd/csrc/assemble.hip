@@ -23,9 +23,11 @@
 // in LDS and written with consecutive lanes on consecutive elements, so each
 // store instruction covers one contiguous span (full cache lines).  With both
 // outputs the FP64 evaluation is shared by the complex-double and the
-// complex-float matrix.
+// complex-float matrix.  Columns of GPM group members are finished by
+// launch_gpm_columns (gpm.hip).
 #include "gdm_common.hpp"
 #include "gdm_kernels.hpp"
+#include "gdm_misc.hpp"
 
 namespace gdm {
 
@@ -106,7 +108,9 @@ static hipError_t launch_assemble_impl(const DipoleView& d, const Wave& w, doubl
   if (M64 && M32) launch_assemble_cols<true, true>(d, w, M64, M32, ld, row_blocks, st);
   else if (M64) launch_assemble_cols<true, false>(d, w, M64, M32, ld, row_blocks, st);
   else launch_assemble_cols<false, true>(d, w, M64, M32, ld, row_blocks, st);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_gpm_columns(d, M64, M32, ld, 3 * slots, st);  // no-op without GPM groups
 }
 
 template <typename T>

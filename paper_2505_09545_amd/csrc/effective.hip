@@ -27,33 +27,9 @@ __global__ void illum_at_point_kernel(Wave w, double n_env, double r0x, double r
                                       double2* __restrict__ F0) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n_pw + n_src) return;
-  double2* o = F0 + 6 * i;
-  if (i < n_pw) {
-    const double kx = khat[3 * i], ky = khat[3 * i + 1], kz = khat[3 * i + 2];
-    double sn, cs;
-    sincos(w.k * (kx * r0x + ky * r0y + kz * r0z), &sn, &cs);
-    double2 E[3];
-    for (int a = 0; a < 3; ++a) {
-      const double2 v = e0[3 * i + a];
-      E[a] = make_double2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
-      o[a] = E[a];
-    }
-    const double kk[3] = {kx, ky, kz};
-    for (int a = 0; a < 3; ++a) {
-      const int b = (a + 1) % 3, c = (a + 2) % 3;
-      o[3 + a] = make_double2(n_env * (kk[b] * E[c].x - kk[c] * E[b].x), n_env * (kk[b] * E[c].y - kk[c] * E[b].y));
-    }
-    return;
-  }
-  const int64_t s = i - n_pw;
-  Green g;
-  green_eh(r0x - rs[3 * s], r0y - rs[3 * s + 1], r0z - rs[3 * s + 2], w, true, g);
-  const double2* d = ds + 6 * s;
-  for (int r = 0; r < 6; ++r) {
-    double2 acc = make_double2(0.0, 0.0);
-    for (int c = 0; c < 6; ++c) cfma(acc, g6(g, w.eps_env, r, c), d[c]);
-    o[r] = acc;
-  }
+  double2 o[6];
+  illumination_at(w, n_env, r0x, r0y, r0z, i, n_pw, khat, e0, rs, ds, o);
+  for (int a = 0; a < 6; ++a) F0[6 * i + a] = o[a];
 }
 
 // sum over the workgroup (256 threads) in a fixed order

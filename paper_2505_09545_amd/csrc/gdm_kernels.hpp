@@ -14,13 +14,28 @@ struct DipoleView {
   const double2* alpha6;   // [ne][6][6] row-major effective polarisability
   int64_t N, nc, ne;
   double2 self_c;          // S^Ep of a cell (times I3)
+  // Global polarisability matrices over runs of effective dipoles (ngroups 0:
+  // none).  gid [ne]: group of each effective dipole, -1 for a local one;
+  // gtab [ngroups][3]: (first effective index, size M, offset of the group's
+  // matrix in galpha); galpha: row-major 6M x 6M complex matrices, rows and
+  // columns ordered (member, then p_x..p_z, m_x..m_z).  A member's own alpha6
+  // is not used; members of one group do not couple through G~.
+  const int32_t* gid = nullptr;
+  const int64_t* gtab = nullptr;
+  const double2* galpha = nullptr;
+  int64_t ngroups = 0;
 };
+
+// largest number of dipole pairs in one GPM group
+constexpr int GPM_MAX_PAIRS = 32;
 
 // The 3 x NC block of M = I - G~ A at row dipole dr (field f: 0 electric, 1
 // magnetic) and column dipole j (NC = 3 columns for a cell, 6 for an effective
 // dipole: its electric then magnetic columns): v[column][row].  Diagonal blocks
 // I - S alpha (cells) or the identity rows (effective dipoles, S = 0);
 // off-diagonal blocks -G^{f.}(r_dr - r_j) alpha_j.  FP64, one sincos.
+// A GPM member column j takes alpha_j = I here (the group's matrix is applied
+// to its columns afterwards) and a zero block against the other members.
 template <bool EFF>
 __device__ inline void m_block(const DipoleView& d, const Wave& w, int64_t dr, int f, int64_t j,
                                double2 (&v)[EFF ? 6 : 3][3]) {
@@ -45,6 +60,14 @@ __device__ inline void m_block(const DipoleView& d, const Wave& w, int64_t dr, i
     }
     return;
   }
+  bool unit_alpha = false;
+  if (EFF && d.gid) {
+    const int32_t gj = d.gid[j - nc];
+    if (gj >= 0) {
+      if (dr >= nc && d.gid[dr - nc] == gj) return;  // same group: no coupling
+      unit_alpha = true;
+    }
+  }
   const double Rx = d.pos[3 * dr + 0] - d.pos[3 * j + 0];
   const double Ry = d.pos[3 * dr + 1] - d.pos[3 * j + 1];
   const double Rz = d.pos[3 * dr + 2] - d.pos[3 * j + 2];
@@ -66,6 +89,13 @@ __device__ inline void m_block(const DipoleView& d, const Wave& w, int64_t dr, i
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = 0; b < 6; ++b) gr[a][b] = f == 0 ? g6(g, w.eps_env, a, b) : g6(g, w.eps_env, 3 + a, b);
+    if (unit_alpha) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int a = 0; a < 3; ++a) v[c][a] = make_double2(-gr[a][c].x, -gr[a][c].y);
+      return;
+    }
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
 #pragma unroll

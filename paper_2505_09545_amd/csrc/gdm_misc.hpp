@@ -82,6 +82,73 @@ hipError_t launch_pair_extract(const Wave& w, double n_env, const double r0[3], 
                                const double2* moments, double2* F0, double2* B, double2* alpha, double* resid,
                                hipStream_t st);
 
+// (E0, H0) at the point (x, y, z) of illumination i: plane wave i (khat,
+// e0 [n_pw][3]) when i < n_pw, else the point source s = i - n_pw, whose field
+// there is G6(r - rs[s]) ds[s] (ds [n_src][6] = (p, m)).
+__device__ inline void illumination_at(const Wave& w, double n_env, double x, double y, double z, int64_t i,
+                                       int64_t n_pw, const double* khat, const double2* e0, const double* rs,
+                                       const double2* ds, double2 (&o)[6]) {
+  if (i < n_pw) {
+    const double kx = khat[3 * i], ky = khat[3 * i + 1], kz = khat[3 * i + 2];
+    double sn, cs;
+    sincos(w.k * (kx * x + ky * y + kz * z), &sn, &cs);
+    double2 E[3];
+    for (int a = 0; a < 3; ++a) {
+      const double2 v = e0[3 * i + a];
+      E[a] = make_double2(v.x * cs - v.y * sn, v.x * sn + v.y * cs);
+      o[a] = E[a];
+    }
+    const double kk[3] = {kx, ky, kz};
+    for (int a = 0; a < 3; ++a) {
+      const int b = (a + 1) % 3, c = (a + 2) % 3;
+      o[3 + a] = make_double2(n_env * (kk[b] * E[c].x - kk[c] * E[b].x), n_env * (kk[b] * E[c].y - kk[c] * E[b].y));
+    }
+    return;
+  }
+  const int64_t s = i - n_pw;
+  Green g;
+  green_eh(x - rs[3 * s], y - rs[3 * s + 1], z - rs[3 * s + 2], w, true, g);
+  const double2* d = ds + 6 * s;
+  for (int r = 0; r < 6; ++r) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int c = 0; c < 6; ++c) cfma(acc, g6(g, w.eps_env, r, c), d[c]);
+    o[r] = acc;
+  }
+}
+
+// Global polarisability matrices (gpm.hip).  All use the groups of the
+// DipoleView (gtab, galpha on the device) and do nothing without groups.
+// Columns of the group members in M (FP64 and/or FP32 copy, ld): from
+// M' = I - G~ (members' alpha taken as I, no intra-group coupling) to
+// I - G~ alpha_G, in place; the FP64 copy is the source when both are given.
+hipError_t launch_gpm_columns(const DipoleView& d, double2* M64, float2* M32, int64_t ld, int64_t n, hipStream_t st);
+// q[members] = alpha_G F[members] for every group (q != F).
+hipError_t launch_gpm_apply(const DipoleView& d, const double2* F, int64_t ldf, double2* q, int64_t ldq, int64_t nrhs,
+                            hipStream_t st);
+// out [nrhs][ngroups] = Im sum_{i != j in g} q_i^H G6(r_i - r_j) q_j
+hipError_t launch_gpm_mutual(const DipoleView& d, const Wave& w, const double2* q, int64_t ldq, int64_t nrhs,
+                             double* out, hipStream_t st);
+// Extraction by scattered-field matching:
+// Y [nrhs][6P] (column-major 6P x nrhs) from E, H [nrhs][P][3];
+hipError_t launch_gpm_pack_fields(const double2* E, const double2* H, int64_t nrhs, int64_t P, double2* Y,
+                                  hipStream_t st);
+// Gf (6P x 6M, column-major): rows (probe, E then H component), columns
+// (pair, p then m): G6(r_p - r_j);
+hipError_t launch_gpm_fit_matrix(const Wave& w, const double* rp, int64_t P, const double* rg, int64_t M,
+                                 double2* Gf, hipStream_t st);
+// F0g (N x 6M, column-major): (E0, H0) of illumination i at pair j;
+hipError_t launch_gpm_illumination(const Wave& w, double n_env, const double* rg, int64_t M, int64_t n_pw,
+                                   const double* khat, const double2* e0, int64_t n_src, const double* rs,
+                                   const double2* ds, double2* F0g, hipStream_t st);
+// B (n x m, column-major) = A^T for A (m x n, column-major);
+hipError_t launch_transpose(const double2* A, int64_t m, int64_t n, double2* B, hipStream_t st);
+// least squares min ||A X - B|| by Householder QR (A m x K, B m x R, both
+// column-major and overwritten; m >= K): X (K x R, column-major, ldx K),
+// NaN where the diagonal of R falls below 1e-12 of its largest entry;
+// norms [2][R] = (|B_r|^2 before, |residual_r|^2); rdiag [K] work array.
+hipError_t launch_qr_lsq(double2* A, int64_t m, int K, double2* B, int R, double2* X, double2* rdiag, double* norms,
+                         hipStream_t st);
+
 int fields_num_splits(int64_t P, int64_t N, int num_cu);
 size_t fields_scratch_bytes(int64_t nrhs, int64_t P, int nsplit, bool want_h);
 hipError_t launch_fields(const DipoleView& d, const Wave& w, const double2* q, int64_t ldq, int64_t nrhs,

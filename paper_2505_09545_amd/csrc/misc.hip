@@ -158,7 +158,9 @@ hipError_t launch_apply_alpha(const DipoleView& d, const double2* F, int64_t ldf
   if (d.N <= 0 || nrhs <= 0) return hipSuccess;
   hipLaunchKernelGGL(apply_alpha_kernel, dim3((unsigned)((d.N + 255) / 256), (unsigned)nrhs), dim3(256), 0, st, d, F,
                      ldf, q, ldq, nrhs);
-  return hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return launch_gpm_apply(d, F, ldf, q, ldq, nrhs, st);  // members of GPM groups (overwrites their q)
 }
 
 // one workgroup (1024 threads) per RHS, FP64 tree reduction in LDS

@@ -29,7 +29,7 @@ SELF_STATIC, SELF_RADIATIVE = 0, 1
 
 EXPORTED = ["gdm_create", "gdm_destroy", "gdm_last_error", "gdm_set_memory_limit", "gdm_memory_used", "gdm_set_pivoting",
             "gdm_pivot_fallbacks",
-            "gdm_set_environment", "gdm_set_structure",
+            "gdm_set_environment", "gdm_set_structure", "gdm_set_gpm", "gdm_extract_gpm",
             "gdm_num_unknowns", "gdm_assemble", "gdm_factorize", "gdm_set_wavelength", "gdm_solve_iterative", "gdm_incident_planewave", "gdm_solve",
             "gdm_planewave", "gdm_fields", "gdm_fields_total", "gdm_planewave_intensity", "gdm_fields_noalloc", "gdm_cross_sections", "gdm_multipoles", "gdm_extract_dipole_pair", "gdm_dipole_sources", "gdm_ldos", "gdm_green_tensor", "gdm_adjoint", "gdm_batch_spectra", "gdm_batch_tuning", "gdm_getrf", "gdm_getrs", "gdm_gemm", "gdm_sync",
             "gdm_profile", "gdm_profile_mask", "gdm_profile_read"]
@@ -70,6 +70,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
         "gdm_set_environment": ([P, D], ctypes.c_int),
         "gdm_set_structure": ([P, I64, P, D, P, I64, P, P, ctypes.c_int], ctypes.c_int),
         "gdm_num_unknowns": ([P], I64),
+        "gdm_set_gpm": ([P, I64, ctypes.POINTER(I64), ctypes.POINTER(I64), P], ctypes.c_int),
+        "gdm_extract_gpm": ([P, I64, P, P, I64, P, P, I64, P, I64, P, D, I32, P, ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(GDMInfo)], ctypes.c_int),
         "gdm_assemble": ([P, D, ctypes.c_int, P, I64], ctypes.c_int),
         "gdm_factorize": ([P, D, ctypes.c_int, ctypes.POINTER(GDMInfo)], ctypes.c_int),
         "gdm_set_wavelength": ([P, D], ctypes.c_int),
@@ -221,6 +224,51 @@ class Context:
         self._check(self._call("gdm_set_structure", self.h, nc, _ptr(rc), float(step), _ptr(ec), ne, _ptr(re), _ptr(ae),
                                                int(selfterm)))
         self.n_cell, self.n_eff = nc, ne
+
+    def set_gpm(self, groups):
+        """Global polarisability matrices (gdm_set_gpm): groups = [(first, alpha_G)]
+        with alpha_G [6M, 6M] complex for the effective dipoles [first, first + M);
+        an empty list removes the groups."""
+        firsts, sizes, mats = [], [], []
+        for first, aG in groups:
+            aG = self._dev(aG, torch.complex128, None, "alpha_G")
+            if aG.dim() != 2 or aG.shape[0] != aG.shape[1] or aG.shape[0] % 6:
+                raise ValueError("alpha_G must be [6M, 6M]")
+            firsts.append(int(first))
+            sizes.append(aG.shape[0] // 6)
+            mats.append(aG.reshape(-1))
+        ng = len(firsts)
+        alpha = torch.cat(mats) if ng else None
+        fa = (ctypes.c_int64 * max(ng, 1))(*firsts)
+        sa = (ctypes.c_int64 * max(ng, 1))(*sizes)
+        self._keep_gpm = alpha
+        self.state_id += 1
+        self._check(self._call("gdm_set_gpm", self.h, ng, fa, sa, _ptr(alpha)))
+
+    def extract_gpm(self, r_gpm, r_probe, khat=None, e0=None, r_src=None, d_src=None, tol=0.0, max_iter=-1):
+        """GPM of the structure for pairs at r_gpm [M, 3] by scattered-field
+        matching at r_probe [P, 3] under plane waves (khat, e0) and point sources
+        (r_src, d_src) (gdm_extract_gpm; needs factors).  Returns (alpha_G
+        [6M, 6M] complex on the device, (field-fit residual, alpha-fit residual))."""
+        k = e = rs = ds = None
+        npw = nsrc = 0
+        if khat is not None:
+            k = self._dev(khat, torch.float64, None, "khat").reshape(-1, 3)
+            e = self._dev(e0, torch.complex128, (len(k), 3), "e0")
+            npw = len(k)
+        if r_src is not None:
+            rs = self._dev(r_src, torch.float64, None, "r_src").reshape(-1, 3)
+            ds = self._dev(d_src, torch.complex128, (len(rs), 6), "d_src")
+            nsrc = len(rs)
+        rg = self._dev(r_gpm, torch.float64, None, "r_gpm").reshape(-1, 3)
+        rp = self._dev(r_probe, torch.float64, None, "r_probe").reshape(-1, 3)
+        M = len(rg)
+        alpha = torch.empty((6 * M, 6 * M), dtype=torch.complex128, device=self.device)
+        res = (ctypes.c_double * 2)(0.0, 0.0)
+        self._check(self._call("gdm_extract_gpm", self.h, npw, _ptr(k), _ptr(e), nsrc, _ptr(rs), _ptr(ds), M, _ptr(rg),
+                               len(rp), _ptr(rp), float(tol), int(max_iter), _ptr(alpha), res,
+                               ctypes.byref(self.info)))
+        return alpha, (float(res[0]), float(res[1]))
 
     @property
     def n(self) -> int:

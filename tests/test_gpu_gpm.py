@@ -1,0 +1,248 @@
+"""GPU parity of global polarisability matrices (gdm_set_gpm, gdm_extract_gpm
+through the C-ABI) against the FP64 oracle.
+
+* A cluster of three coupled 6x6 dipoles beside a block of cells, replaced by
+  its exact GPM: the assembled matrix within 1e-12 of its largest entry; the
+  moments within 1e-10 relative (FP64 factors, and FP32 factors refined to
+  1e-14); ext / sca / abs and the far-field double sum within 1e-10
+  relative; moments also equal to those of the coupled cluster (the two
+  systems are algebraically one); with the radiative cell self-term
+  sca = ext - abs equals the far-field double sum to rounding.
+* Extraction: from the coupled cluster itself the exact alpha_G within 1e-9
+  of its largest entry; from a 256-cell rod (3 pairs) alpha_G within 1e-8 of
+  its largest entry of the oracle's LAPACK least squares, and the residuals
+  within 1e-6 relative.
+* Error paths: bad groups, paths without GPM support, too few illuminations.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import gdm_inputs as gi
+from oracle import gdm_oracle as O
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2505_09545_amd import gdm
+    c = gdm.Context(0)
+    yield c
+    c.close()
+
+
+def exact_gpm(w, first, M):
+    """alpha_G = (I - A G)^-1 A of M coupled dipoles (q = A (F_ext + G q))."""
+    D = O.Dipoles(w)
+    mem = D.nc + first + np.arange(M)
+    R = D.pos[mem][:, None, :] - D.pos[mem][None, :, :]
+    same = np.eye(M, dtype=bool)
+    g6 = O.green6(np.where(same[..., None], 1.0, R), D.k0, D.n_env)
+    g6[same] = 0.0
+    G = g6.transpose(0, 2, 1, 3).reshape(6 * M, 6 * M)
+    A = np.zeros((6 * M, 6 * M), dtype=complex)
+    for i in range(M):
+        A[6 * i:6 * i + 6, 6 * i:6 * i + 6] = w["alpha_eff"][first + i]
+    return np.linalg.solve(np.eye(6 * M) - A @ G, A)
+
+
+def set_structure(ctx, w):
+    ne = len(w["r_eff"])
+    ctx.set_environment(w["n_env"])
+    ctx.set_structure(torch.as_tensor(w["r_cell"]), w["step"], torch.as_tensor(w["eps_cell"]),
+                      torch.as_tensor(w["r_eff"]) if ne else None, torch.as_tensor(w["alpha_eff"]) if ne else None)
+
+
+def cluster_case():
+    w = gi.small_mixed(n_eff=5)
+    aG = exact_gpm(w, 1, 3)
+    return w, aG, dict(w, gpm=[(1, 3, aG)])
+
+
+def test_gpm_assembly_matches_oracle(ctx):
+    w, aG, wg = cluster_case()
+    say("gpm assembly")
+    set_structure(ctx, w)
+    ctx.set_gpm([(1, torch.as_tensor(aG))])
+    M = ctx.assemble(w["wavelength"]).cpu().numpy()
+    Mo = O.assemble(O.Dipoles(wg))
+    assert np.max(np.abs(M - Mo)) <= 1e-12 * np.max(np.abs(Mo))
+    M32 = ctx.assemble(w["wavelength"], torch.complex64).cpu().numpy()
+    assert np.max(np.abs(M32 - Mo)) <= 1e-6 * np.max(np.abs(Mo))
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gpm_simulation_matches_oracle(ctx, prec):
+    w, aG, wg = cluster_case()
+    say("gpm simulation prec", prec)
+    set_structure(ctx, w)
+    ctx.set_gpm([(1, torch.as_tensor(aG))])
+    ctx.factorize(w["wavelength"], prec)
+    f0 = ctx.incident_planewave(torch.as_tensor(w["khat"]), torch.as_tensor(w["e0"]))
+    q, f = ctx.solve(f0, tol=1e-14 if prec == 1 else 0.0)
+    ref = O.simulate(wg)
+    full = O.simulate(w)
+    qn = q.cpu().numpy().T
+    assert np.max(np.abs(qn - ref["q"])) <= 1e-10 * np.max(np.abs(ref["q"]))
+    assert np.max(np.abs(qn - full["q"])) <= 1e-10 * np.max(np.abs(full["q"]))
+    e2 = torch.as_tensor(np.sum(np.abs(w["e0"]) ** 2, axis=1))
+    cs = ctx.cross_sections(f0, q, f, e2, want_ff=True).cpu().numpy()
+    for col, key in ((0, "ext"), (1, "sca"), (2, "abs")):
+        assert np.max(np.abs(cs[:, col] - ref[key]) / np.abs(ref[key])) < 1e-10, key
+    ff = O.sca_farfield_doublesum(ref["D"], ref["q"], np.sum(np.abs(w["e0"]) ** 2, axis=1))
+    assert np.max(np.abs(cs[:, 4] - ff) / ff) < 1e-10
+    E, H = ctx.fields(q, torch.as_tensor(w["r_probe"]))
+    Eo, Ho = O.scattered_fields(ref["D"], ref["q"], w["r_probe"])
+    assert np.max(np.abs(E.cpu().numpy() - Eo)) <= 1e-10 * np.max(np.abs(Eo))
+    assert np.max(np.abs(H.cpu().numpy() - Ho)) <= 1e-10 * np.max(np.abs(Ho))
+
+
+def test_gpm_energy_balance_with_radiative_cells(ctx):
+    """With the radiative cell self-term the system conserves energy: the GPU's
+    sca = ext - abs (with the groups' mutual term) equals its far-field double
+    sum to rounding, and both equal the oracle."""
+    from paper_2505_09545_amd import gdm
+    w, aG, wg = cluster_case()
+    say("gpm radiative energy balance")
+    ctx.set_environment(w["n_env"])
+    ctx.set_structure(torch.as_tensor(w["r_cell"]), w["step"], torch.as_tensor(w["eps_cell"]),
+                      torch.as_tensor(w["r_eff"]), torch.as_tensor(w["alpha_eff"]), selfterm=gdm.SELF_RADIATIVE)
+    ctx.set_gpm([(1, torch.as_tensor(aG))])
+    ctx.factorize(w["wavelength"], 0)
+    f0 = ctx.incident_planewave(torch.as_tensor(w["khat"]), torch.as_tensor(w["e0"]))
+    q, f = ctx.solve(f0)
+    e2 = torch.as_tensor(np.sum(np.abs(w["e0"]) ** 2, axis=1))
+    cs = ctx.cross_sections(f0, q, f, e2, want_ff=True).cpu().numpy()
+    assert np.max(np.abs(cs[:, 4] - cs[:, 1]) / cs[:, 1]) < 1e-10
+    ref = O.simulate(wg, mode="radiative")
+    assert np.max(np.abs(cs[:, 1] - ref["sca"]) / ref["sca"]) < 1e-10
+
+
+def test_gpm_two_groups_and_clearing(ctx):
+    """Two groups ((0, 2) and (3, 2)) against the oracle; then n_groups = 0
+    restores the local model and gdm_set_structure drops the groups."""
+    w = gi.small_mixed(n_eff=5)
+    a1, a2 = exact_gpm(w, 0, 2), exact_gpm(w, 3, 2)
+    wg = dict(w, gpm=[(0, 2, a1), (3, 2, a2)])
+    say("gpm two groups")
+    set_structure(ctx, w)
+    ctx.set_gpm([(0, torch.as_tensor(a1)), (3, torch.as_tensor(a2))])
+    ctx.factorize(w["wavelength"], 0)
+    f0 = ctx.incident_planewave(torch.as_tensor(w["khat"]), torch.as_tensor(w["e0"]))
+    q, f = ctx.solve(f0)
+    ref = O.simulate(wg)
+    assert np.max(np.abs(q.cpu().numpy().T - ref["q"])) <= 1e-10 * np.max(np.abs(ref["q"]))
+    e2 = torch.as_tensor(np.sum(np.abs(w["e0"]) ** 2, axis=1))
+    cs = ctx.cross_sections(f0, q, f, e2).cpu().numpy()
+    assert np.max(np.abs(cs[:, 2] - ref["abs"]) / np.abs(ref["abs"])) < 1e-10
+    # local model again
+    full = O.simulate(w)
+    for clear in ("groups", "structure"):
+        if clear == "groups":
+            ctx.set_gpm([])
+        else:
+            ctx.set_gpm([(0, torch.as_tensor(a1))])
+            set_structure(ctx, w)
+        ctx.factorize(w["wavelength"], 0)
+        q, f = ctx.solve(f0)
+        assert np.max(np.abs(q.cpu().numpy().T - full["q"])) <= 1e-10 * np.max(np.abs(full["q"])), clear
+
+
+def illuminations(n, radius, seed=4):
+    rng = np.random.default_rng(seed)
+    k, e = gi.random_planewaves(rng, n)
+    rs = gi.fibonacci_sphere(n, radius)
+    ds = rng.standard_normal((n, 6)) + 1j * rng.standard_normal((n, 6))
+    return k, e, rs, ds
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gpm_extraction_of_a_dipole_cluster_is_exact(ctx, prec):
+    w = gi.small_mixed(n_eff=5)
+    cl = dict(w, r_cell=np.zeros((0, 3)), eps_cell=np.zeros(0, complex),
+              r_eff=w["r_eff"][1:4], alpha_eff=w["alpha_eff"][1:4])
+    ref = exact_gpm(cl, 0, 3)
+    k, e, rs, ds = illuminations(12, 300.0)
+    rp = gi.fibonacci_sphere(40, 350.0)
+    say("gpm extraction cluster prec", prec)
+    set_structure(ctx, cl)
+    ctx.factorize(cl["wavelength"], prec)
+    a, (rf, ra) = ctx.extract_gpm(torch.as_tensor(cl["r_eff"]), torch.as_tensor(rp), k, e, rs, ds,
+                                  tol=1e-14 if prec == 1 else 0.0)
+    a = a.cpu().numpy()
+    print("  residuals", rf, ra, flush=True)
+    assert np.max(np.abs(a - ref)) <= 1e-9 * np.max(np.abs(ref))
+    assert rf < 1e-12 and ra < 1e-12
+
+
+def rod():
+    w = dict(gi.config1())
+    w["r_cell"] = gi.cuboid_cells(16, 4, 4, 5.0)
+    w["step"] = 5.0
+    w["eps_cell"] = np.full(len(w["r_cell"]), 12.0 + 0.1j)
+    w["r_eff"], w["alpha_eff"] = np.zeros((0, 3)), np.zeros((0, 6, 6), complex)
+    return w
+
+
+def test_gpm_extraction_of_a_rod_matches_oracle(ctx):
+    w = rod()
+    k, e, rs, ds = illuminations(16, 70.0)
+    rp = gi.fibonacci_sphere(300, 90.0)
+    rg = np.stack([np.linspace(-30.0, 30.0, 3), np.zeros(3), np.zeros(3)], 1) + w["r_cell"].mean(0)
+    say("gpm extraction rod")
+    set_structure(ctx, w)
+    ctx.factorize(w["wavelength"], 0)
+    a, (rf, ra) = ctx.extract_gpm(torch.as_tensor(rg), torch.as_tensor(rp), k, e, rs, ds)
+    a = a.cpu().numpy()
+    ao, rfo, rao = O.extract_gpm(w, rg, k, e, rs, ds, rp)
+    print("  residuals", rf, rfo, ra, rao, flush=True)
+    assert np.max(np.abs(a - ao)) <= 1e-8 * np.max(np.abs(ao))
+    assert abs(rf - rfo) <= 1e-6 * rfo and abs(ra - rao) <= 1e-6 * rao
+
+
+def test_gpm_errors(ctx):
+    from paper_2505_09545_amd import gdm
+    w = gi.small_mixed(n_eff=5)
+    aG = exact_gpm(w, 1, 3)
+    set_structure(ctx, w)
+    say("gpm errors")
+    bad = [
+        [(3, torch.as_tensor(aG))],                                 # runs past the last effective dipole
+        [(1, torch.as_tensor(aG)), (2, torch.as_tensor(aG[:6, :6]))],  # dipole 2 in two groups
+        [(-1, torch.as_tensor(aG[:6, :6]))],
+    ]
+    for groups in bad:
+        with pytest.raises(gdm.GDMError) as ei:
+            ctx.set_gpm(groups)
+        assert ei.value.status == gdm.GDM_E_ARG
+    ctx.set_gpm([(1, torch.as_tensor(aG))])
+    f0 = torch.zeros((1, ctx.n), dtype=torch.complex128, device="cuda")
+    with pytest.raises(gdm.GDMError) as ei:
+        ctx.solve_iterative(w["wavelength"], f0)
+    assert ei.value.status == gdm.GDM_E_ARG
+    ctx.factorize(w["wavelength"], 0)
+    k, e = gi.random_planewaves(np.random.default_rng(1), 2)
+    f0 = ctx.incident_planewave(torch.as_tensor(k), torch.as_tensor(e))
+    q, f = ctx.solve(f0)
+    with pytest.raises(gdm.GDMError) as ei:
+        ctx.adjoint(k, e, f0, q, f, g_sigma=torch.ones((2, 3), dtype=torch.float64))
+    assert ei.value.status == gdm.GDM_E_ARG
+    # extraction needs at least 6 illuminations per pair
+    cl = dict(w, r_cell=np.zeros((0, 3)), eps_cell=np.zeros(0, complex),
+              r_eff=w["r_eff"][1:4], alpha_eff=w["alpha_eff"][1:4])
+    set_structure(ctx, cl)
+    ctx.factorize(cl["wavelength"], 0)
+    kk, ee, rs, ds = illuminations(8, 300.0)
+    with pytest.raises(gdm.GDMError) as ei:
+        ctx.extract_gpm(torch.as_tensor(cl["r_eff"]), torch.as_tensor(gi.fibonacci_sphere(40, 350.0)), kk, ee, rs, ds)
+    assert ei.value.status == gdm.GDM_E_ARG
