@@ -461,8 +461,8 @@ def main() -> int:
         **res,
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": PEAK_FP32_MFMA, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_MFMA, "traffic": update_gemm_traffic(),
-                     "kernel": "cgemm_kernel<float,0,0,1> (LU trailing update, bulk: the columns after "
-                               "the next panel's, side stream)",
+                     "kernel": "cgemm3m_update_kernel (LU trailing update, bulk: the columns after the next "
+                               "panel's, side stream; the last launches with the small tile use cgemm_kernel)",
                      "launches_per_step": up["launches"] / args.steps,
                      "avg_launch_ms": up["ms"] / max(up["launches"], 1),
                      "flops_per_launch": up["work"] / max(up["launches"], 1)},

@@ -248,11 +248,11 @@ struct LUWork {
   int32_t* spec;             // [nblocks] speculative panel failed its check (after npairs, same item stride)
   void* tmp;                 // [tmp_elems] complex scratch (operand copies, split-k partials, solve sweeps)
   void* dinv;                // [nblocks][nb][nb] complex inverses of the diagonal triangles
-  void* upk;                 // speculative panels: packed U11 of the current block and its pivots' reciprocals
+  void* l21c;                // speculative panels: copy of the rows below the diagonal block (n x nb complex)
   std::vector<hipEvent_t>* events;  // host-side pool of reusable events (look-ahead)
   int64_t tmp_elems;         // capacity of tmp per item in complex elements
   int nbatch = 1;
-  int64_t s_cand = 0, s_rows = 0, s_pairs = 0, s_npairs = 0, s_tmp = 0, s_dinv = 0, s_upk = 0;
+  int64_t s_cand = 0, s_rows = 0, s_pairs = 0, s_npairs = 0, s_tmp = 0, s_dinv = 0, s_l21c = 0;
   size_t bytes = 0;          // total size (set by lu_workspace_carve)
 };
 

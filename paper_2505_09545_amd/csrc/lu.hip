@@ -1565,13 +1565,6 @@ __device__ inline float cabs1_f(const CT& v) {
   return (float)(fabs(v.x) + fabs(v.y));
 }
 
-// Packed form of U11 for the row solves: row j of the strict upper triangle
-// (entries j + 1 .. w - 1) at offset j w - j (j + 1) / 2, after the w
-// reciprocals of the diagonal (SPEC_DINV slots).
-constexpr int SPEC_DINV = 128;
-__host__ __device__ constexpr int spec_upk_off(int j, int w) { return SPEC_DINV + j * w - j * (j + 1) / 2; }
-__host__ __device__ constexpr int spec_upk_size(int w) { return SPEC_DINV + w * (w - 1) / 2; }
-
 // Diagonal block (w x w at (k0, k0)) of batch item blockIdx.y, NT threads:
 // thread (tx, ty) = (tid % 32, tid / 32) holds rows tx + 32 p (p < 4) and
 // columns ty + TY q (q < 128 / TY, TY = NT / 32) in registers.  Per column j
@@ -1582,19 +1575,16 @@ __host__ __device__ constexpr int spec_upk_size(int w) { return SPEC_DINV + w * 
 // after it take a plain update and only the groups holding row or column j a
 // masked one, so the work per column follows the shrinking triangle (the VALU
 // of one CU sets the time: 64 lanes per cycle).  NT = 512: 32 entries per
-// thread, two waves per SIMD.  On exit U11 is also written, packed, to upk
-// (see spec_upk_off).
+// thread, two waves per SIMD.
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) spec_diag_kernel(cplx<T>* __restrict__ A, int64_t ld, int64_t k0, int w,
                                                         int32_t* __restrict__ ipiv, int32_t* __restrict__ flag,
-                                                        cplx<T>* __restrict__ upk, int64_t sA, int64_t sipiv,
-                                                        int64_t sflag, int64_t supk) {
+                                                        int64_t sA, int64_t sipiv, int64_t sflag) {
   using CT = cplx<T>;
   constexpr int TY = NT / 32, Q = 128 / TY;
   A += (int64_t)blockIdx.y * sA;  // batch item blockIdx.y
   ipiv += (int64_t)blockIdx.y * sipiv;
   flag += (int64_t)blockIdx.y * sflag;
-  upk += (int64_t)blockIdx.y * supk;
   __shared__ CT rowb[2][128], colb[2][128];
   const int tid = threadIdx.x, tx = tid & 31, ty = tid >> 5;
   CT* D = A + k0 + k0 * ld;
@@ -1656,131 +1646,99 @@ __global__ void __launch_bounds__(NT) spec_diag_kernel(cplx<T>* __restrict__ A, 
   static_for<4>([&](auto p) {
     static_for<Q>([&](auto q) {
       const int r = tx + 32 * p, c = ty + TY * q;
-      if (r < w && c < w) {
-        D[r + (int64_t)c * ld] = a[p][q];
-        if (r < c) upk[spec_upk_off(r, w) + (c - r - 1)] = a[p][q];
-        if (r == c) upk[r] = cinv_t(a[p][q]);
-      }
+      if (r < w && c < w) D[r + (int64_t)c * ld] = a[p][q];
     });
   });
   if (tid < w) ipiv[k0 + tid] = (int32_t)(k0 + tid);
   if (__syncthreads_or(bad) && tid == 0) atomicOr(flag, 1);
 }
 
-// Rows below the diagonal block, x U11 = a for each row a of A21.  The packed
-// U11 and the reciprocals of its diagonal (written by spec_diag_kernel) are
-// staged once per workgroup in LDS, so the sweep over j needs no barrier.  Each
-// wave takes CPW rows at a time (lane l holds columns l and l + 64 of them) and
-// the workgroup loops over groups of 4 CPW rows.  Check: |x_j u_jj| <= |u_jj|
-// in |re| + |im| (FP32).
-template <typename T, int CPW>
-__global__ void __launch_bounds__(256) spec_l21_kernel(cplx<T>* __restrict__ A, int64_t ld, int64_t n, int64_t k0,
-                                                        int w, const cplx<T>* __restrict__ upk,
-                                                        int32_t* __restrict__ flag, int64_t sA, int64_t supk,
-                                                        int64_t sflag) {
+// The check of the rows below the diagonal block once L21 is formed:
+// |l_ij u_jj| <= |u_jj| in |re| + |im| (FP32): the entry partial pivoting
+// would compare with the pivot u_jj at step j is a_ij = l_ij u_jj, and the
+// diagonal keeps the pivot only if no such entry is larger (ties to the lower
+// row index).  Threads along the rows (coalesced), blockIdx.y over groups of
+// 16 columns.
+template <typename T>
+__global__ void __launch_bounds__(256) spec_check_kernel(const cplx<T>* __restrict__ A, int64_t ld, int64_t n,
+                                                          int64_t k0, int w, int32_t* __restrict__ flag, int64_t sA,
+                                                          int64_t sflag) {
   using CT = cplx<T>;
-  A += (int64_t)blockIdx.z * sA;  // batch item blockIdx.z
-  upk += (int64_t)blockIdx.z * supk;
+  A += (int64_t)blockIdx.z * sA;
   flag += (int64_t)blockIdx.z * sflag;
-  extern __shared__ unsigned char smem_raw[];
-  CT* Up = reinterpret_cast<CT*>(smem_raw);  // spec_upk_size(w) entries
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  {
-    const int tot = spec_upk_size(w);
-    constexpr int SB = 8;
-    int e = tid;
-    for (; e + 256 * (SB - 1) < tot; e += 256 * SB) {
-      CT v[SB];
-#pragma unroll
-      for (int u = 0; u < SB; ++u) v[u] = upk[e + 256 * u];
-#pragma unroll
-      for (int u = 0; u < SB; ++u) Up[e + 256 * u] = v[u];
-    }
-    for (; e < tot; e += 256) Up[e] = upk[e];
+  constexpr int CG = 16;
+  const int j0 = blockIdx.y * CG;
+  __shared__ CT dg[CG];
+  __shared__ float pk[CG];
+  if (threadIdx.x < CG) {
+    const int j = j0 + threadIdx.x;
+    CT d;
+    d.x = 0;
+    d.y = 0;
+    if (j < w) d = A[(k0 + j) + (k0 + j) * ld];
+    dg[threadIdx.x] = d;
+    pk[threadIdx.x] = cabs1_f(d);
   }
   __syncthreads();
-  const CT* U = A + k0 + k0 * ld;
-  CT dg[2];  // this lane's pivots u_ll, u_(l+64)(l+64) for the check
-  float pk[2];
-#pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int i = lane + 64 * h;
-    dg[h].x = 0;
-    dg[h].y = 0;
-    if (i < w) dg[h] = U[i + (int64_t)i * ld];
-    pk[h] = cabs1_f(dg[h]);
-  }
+  const int64_t r = k0 + w + (int64_t)blockIdx.x * 256 + threadIdx.x;
   bool bad = false;
-  const int64_t rows = n - k0 - w;
-  for (int64_t g0 = (int64_t)blockIdx.x * 4 * CPW; g0 < rows; g0 += (int64_t)gridDim.x * 4 * CPW) {
-    const int64_t r0 = k0 + w + g0 + (int64_t)wave * CPW;
-    CT b[2][CPW];
+  if (r < n) {
+    const int jn = w - j0 < CG ? w - j0 : CG;
+    CT x[CG];
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int c = 0; c < CG; ++c)
+      if (c < jn) x[c] = A[r + (k0 + j0 + c) * ld];
 #pragma unroll
-      for (int c = 0; c < CPW; ++c) {
-        const int i = lane + 64 * h;
-        b[h][c].x = 0;
-        b[h][c].y = 0;
-        if (i < w && r0 + c < n) b[h][c] = A[(r0 + c) + (k0 + i) * ld];
-      }
-    // x_j = b_j / u_jj (lane j % 64 of half j / 64), then b_i -= x_j u_ji for i > j
-    auto sweep = [&](auto half, int ja, int jz) __attribute__((always_inline)) {
-      constexpr int H = decltype(half)::value;
-      for (int j = ja; j < jz; ++j) {
-        const CT di = Up[j];
-        const int off = spec_upk_off(j, w) - (j + 1);  // Up + off + i = u_ji
-        const int i0 = lane, i1 = lane + 64;
-        CT u0, u1;
-        u0.x = 0; u0.y = 0; u1.x = 0; u1.y = 0;
-        if (i0 > j && i0 < w) u0 = Up[off + i0];
-        if (i1 > j && i1 < w) u1 = Up[off + i1];
-#pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-          const CT x = cmul_t(readlane_c(b[H][c], j & 63), di);
-          if (lane == (j & 63)) b[H][c] = x;
-          b[0][c] = r1_upd(b[0][c], x, u0);
-          b[1][c] = r1_upd(b[1][c], x, u1);
-        }
-      }
-    };
-    sweep(std::integral_constant<int, 0>{}, 0, w < 64 ? w : 64);
-    if (w > 64) sweep(std::integral_constant<int, 1>{}, 64, w);
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int i = lane + 64 * h;
-      if (i >= w) continue;
-#pragma unroll
-      for (int c = 0; c < CPW; ++c) {
-        if (r0 + c >= n) continue;
-        if (!(cabs1_f(cmul_t(b[h][c], dg[h])) <= pk[h])) bad = true;
-        A[(r0 + c) + (k0 + i) * ld] = b[h][c];
-      }
-    }
+    for (int c = 0; c < CG; ++c)
+      if (c < jn && !(cabs1_f(cmul_t(x[c], dg[c])) <= pk[c])) bad = true;
   }
-  if (__ballot(bad) != 0 && lane == 0) atomicOr(flag, 1);
+  if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
+// Speculative panel of block bi (columns [k0, k0 + w)): the diagonal block,
+// then L21 = A21 U11^-1 for the rows below as U11^-1 (into the block's inverse
+// slot, which later steps overwrite only after this panel) and one GEMM from a
+// copy of A21, then the check.  (A row-parallel substitution x U11 = a on the
+// VALUs, with U11 staged in LDS, took 115 us per early FP32 block beside the
+// bulk update and 590 us in FP64, where the staged triangle fills 132 KB of a
+// CU's LDS; the inverse + GEMM form: FP32 factorisation 59.5 -> 59.2 ms, FP64
+// 110.3 -> 108.7 ms at n = 12 000.)
 template <typename T>
-static hipError_t launch_spec_panel(cplx<T>* A, int64_t ld, int64_t n, int64_t k0, int w, int32_t* ipiv,
-                                    int32_t* flag, cplx<T>* upk, hipStream_t st, int nbatch, int64_t sA, int64_t sipiv,
-                                    int64_t sflag, int64_t supk, int ncu) {
-  if (w > 128) return hipErrorInvalidValue;
+static hipError_t launch_spec_panel(cplx<T>* A, int64_t ld, int64_t n, int nb, int bi, int64_t k0, int w,
+                                    int32_t* ipiv, const LUWork& ws, hipStream_t st, int nbatch, int64_t sA,
+                                    int64_t sipiv) {
+  if (w > 128 || !ws.l21c || k0 != (int64_t)bi * nb) return hipErrorInvalidValue;
+  using CT = cplx<T>;
+  int32_t* flag = ws.spec + bi;
+  const int64_t sflag = ws.s_npairs;
   constexpr int NT = 512;
   hipLaunchKernelGGL((spec_diag_kernel<T, NT>), dim3(1, (unsigned)nbatch), dim3(NT), 0, st, A, ld, k0, w, ipiv, flag,
-                     upk, sA, sipiv, sflag, supk);
+                     sA, sipiv, sflag);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   const int64_t nr = n - k0 - w;
   if (nr <= 0) return hipSuccess;
-  constexpr int CPW = 8;
-  // packed triangle + reciprocals: FP64 132 KB (one workgroup per CU), FP32 66 KB
-  const size_t lds = (size_t)spec_upk_size(w) * sizeof(cplx<T>);
-  const int64_t groups = (nr + 4 * CPW - 1) / (4 * CPW);
-  const int per_cu = sizeof(T) == 4 ? 2 : 1;
-  const int64_t gx = std::min<int64_t>(groups, std::max<int64_t>(1, (int64_t)per_cu * ncu / std::max(1, nbatch)));
-  hipLaunchKernelGGL((spec_l21_kernel<T, CPW>), dim3((unsigned)gx, 1, (unsigned)nbatch), dim3(256), lds, st, A, ld, n,
-                     k0, w, upk, flag, sA, supk, sflag);
+  CT* dinv = static_cast<CT*>(ws.dinv);
+  const int PW = trsm_pw(nb, (int)sizeof(T));
+  const size_t lds = (size_t)PW * nb * sizeof(CT);
+  const dim3 g1((unsigned)((nb + 3) / 4), 1, (unsigned)nbatch);
+  if ((int64_t)g1.x * nbatch <= ws.gmax) {
+    hipLaunchKernelGGL((block_inv_kernel<T, 1, 1>), g1, dim3(256), lds, st, A, ld, n, nb, bi, dinv, PW, sA, ws.s_dinv);
+  } else {
+    const dim3 g4((unsigned)((nb + 15) / 16), 1, (unsigned)nbatch);
+    hipLaunchKernelGGL((block_inv_kernel<T, 1, 4>), g4, dim3(256), lds, st, A, ld, n, nb, bi, dinv, PW, sA, ws.s_dinv);
+  }
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  CT* l21 = A + (k0 + w) + k0 * ld;
+  CT* cp = static_cast<CT*>(ws.l21c);
+  if ((e = launch_copy_block<T>(l21, ld, cp, nr, nr, w, st, nbatch, sA, ws.s_l21c)) != hipSuccess) return e;
+  GemmMask mk;
+  mk.bkind = GEMM_MASK_UPPER;
+  if ((e = launch_gemm<T>(1, 0, nr, w, w, cp, nr, dinv + (size_t)bi * nb * nb, nb, l21, ld, st, mk, nbatch, ws.s_l21c,
+                          ws.s_dinv, sA)) != hipSuccess)
+    return e;
+  const dim3 gc((unsigned)((nr + 255) / 256), (unsigned)((w + 15) / 16), (unsigned)nbatch);
+  hipLaunchKernelGGL((spec_check_kernel<T>), gc, dim3(256), 0, st, A, ld, n, k0, w, flag, sA, sflag);
   return hipGetLastError();
 }
 
@@ -1917,8 +1875,8 @@ void lu_workspace_carve(void* base, const LUPlan& p, int elem_bytes, int num_cu,
   w.tmp = take((size_t)nbatch * w.s_tmp * cb);
   w.s_dinv = (int64_t)(al256(nblk * nb * nb * cb) / cb);
   w.dinv = take((size_t)nbatch * w.s_dinv * cb);
-  w.s_upk = p.spec ? (int64_t)(al256((size_t)spec_upk_size(128) * cb) / cb) : 0;
-  w.upk = p.spec ? take((size_t)nbatch * w.s_upk * cb) : nullptr;
+  w.s_l21c = p.spec ? w.s_tmp : 0;
+  w.l21c = p.spec ? take((size_t)nbatch * w.s_l21c * cb) : nullptr;
   w.events = nullptr;
   w.bytes = off + 256;
 }
@@ -1964,16 +1922,6 @@ hipError_t lu_prepare(const LUPlan& plan) {
   static std::map<const void*, size_t> lds_set;
   static std::mutex mu;
   std::lock_guard<std::mutex> lk(mu);
-  if (plan.spec) {
-    const void* fn = reinterpret_cast<const void*>(&spec_l21_kernel<T, 8>);
-    const size_t need = (size_t)spec_upk_size(128) * sizeof(cplx<T>);
-    size_t& cur = lds_set[fn];
-    if (need > cur) {
-      hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)need);
-      if (e != hipSuccess) return e;
-      cur = need;
-    }
-  }
   for (const LUBlock& b : plan.blocks) {
     const size_t need = panel_lds_bytes(b.w, b.R, sizeof(cplx<T>), plan.pb);
     const void* fn = panel_fn<T>(plan.pb);
@@ -2080,8 +2028,7 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
     int32_t* src = dst + 2 * nb;
     int32_t* npr = ws.npairs + bi;
     if (plan.spec) {
-      LUCHK(launch_spec_panel<T>(A, ld, n, k0, w, ipiv, ws.spec + bi, static_cast<CT*>(ws.upk), st, NB, sA, sipiv,
-                                   ws.s_npairs, ws.s_upk, ws.gmax));
+      LUCHK(launch_spec_panel<T>(A, ld, n, nb, bi, k0, w, ipiv, ws, st, NB, sA, sipiv));
     } else {
       launch_panel<T>(plan.pb, b, NB, lds, st, A, ld, n, ipiv, ws, epoch, sA, sipiv, dst, src, npr, 2 * nb);
       epoch += (uint32_t)w;
