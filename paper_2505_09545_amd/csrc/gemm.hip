@@ -27,7 +27,8 @@
 // Per thread and stage the big tile loads one (4 k) or two (8 k) complex
 // elements of A and as many of B, the small one one of each.
 // Workgroups are remapped so that each of the 8 XCDs works on a contiguous
-// range of tiles (their operands then share that XCD's L2).
+// range of tiles (their operands then share that XCD's L2), taken in the
+// grouped order of grouped_tile.
 #include "gdm_common.hpp"
 #include "gdm_kernels.hpp"
 
@@ -58,6 +59,31 @@ __device__ inline bool mask_keep(int kind, int64_t r, int64_t c) {
   }
 }
 
+// Order of the output tiles: the tile columns are cut into NBLK blocks (8 or
+// 16: one or two per XCD range of the remap) and each block is walked by
+// groups of GM tile rows, a group covering all of the block's columns before
+// the next.  An XCD then keeps one block's B strips and the current group's A
+// strips in its L2 together (at k = 128 a 64-wide strip is 64 KB in FP32, 128
+// KB in FP64), so an A strip comes from memory about once per block instead of
+// once per tile column.  Measured on the n = 12 000 FP32 factorisation: HBM
+// fetch of the bulk update 598 -> 267 MiB per launch, factorisation 59.1 ->
+// 58.45 ms.
+template <int GM, int NBLK>
+__device__ inline void grouped_tile(int t, int tiles_m, int tiles, int& tm, int& tn) {
+  const int tiles_n = tiles / tiles_m;
+  const int cbw = (tiles_n + NBLK - 1) / NBLK;
+  const int per_blk = tiles_m * cbw;
+  const int blk = t / per_blk;
+  const int within = t - blk * per_blk;
+  const int cols = min(cbw, tiles_n - blk * cbw);
+  const int per_grp = GM * cols;
+  const int grp = within / per_grp;
+  const int w2 = within - grp * per_grp;
+  const int rows = min(GM, tiles_m - grp * GM);
+  tm = grp * GM + w2 % rows;
+  tn = blk * cbw + w2 / rows;
+}
+
 template <typename T, int MODE, int TRANSA, int ROLE, int WM, int WN, int BK, bool CB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) cgemm_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict__ A,
                                                      int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb,
@@ -86,7 +112,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
   const int xcd = bid & 7, loc = bid >> 3;
   const int per = tiles >> 3, rem = tiles & 7;
   const int tile = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + loc;
-  const int tm = tile % tiles_m, tn = tile / tiles_m;
+  int tm, tn;
+  grouped_tile<16, sizeof(T) == 8 ? 16 : 8>(tile, tiles_m, tiles, tm, tn);
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wrow = (wave & 1) * 16 * WM;  // real-row offset of the wave inside the tile
@@ -260,7 +287,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
 // The extra rounding of the sums is that of 3M (its error bound is a small
 // multiple of the 4M one); the factorisations that use it are FP32 ones
 // refined in FP64.  Tiles: BM = 32 WMB complex rows, BN = 32 WNB columns, BK
-// complex k per stage; the XCD remap of cgemm_kernel.
+// complex k per stage; the XCD remap of cgemm_kernel, then grouped_tile.
 template <int WMB, int WNB, int BK, bool CB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const float2* __restrict__ A, int64_t lda,
@@ -279,7 +306,8 @@ cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const float2* __restrict_
   const int xcd = bid & 7, loc = bid >> 3;
   const int per = tiles >> 3, rem = tiles & 7;
   const int tile = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + loc;
-  const int tm = tile % tiles_m, tn = tile / tiles_m;
+  int tm, tn;
+  grouped_tile<16, 8>(tile, tiles_m, tiles, tm, tn);
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wrow = (wave & 1) * 16 * WMB;  // complex rows
