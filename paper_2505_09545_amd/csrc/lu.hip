@@ -2074,10 +2074,12 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
                            int64_t lld, int64_t slop) -> hipError_t {
       hipError_t r;
       if (ncols <= 0) return hipSuccess;
-      if ((r = P.begin(s, PROF_PERM, 0.0)) != hipSuccess) return r;
-      hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)ncols, NB), dim3(256), 0, s, A, ld, cb, dst, src, npr,
-                         sA, ws.s_pairs, ws.s_npairs);
-      if ((r = P.end(s)) != hipSuccess) return r;
+      if (!plan.spec) {  // a speculative panel moves no rows
+        if ((r = P.begin(s, PROF_PERM, 0.0)) != hipSuccess) return r;
+        hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)ncols, NB), dim3(256), 0, s, A, ld, cb, dst, src, npr,
+                           sA, ws.s_pairs, ws.s_npairs);
+        if ((r = P.end(s)) != hipSuccess) return r;
+      }
       // U12 = L11^-1 A12 = A12 - (I - L11^-1) A12
       if ((r = P.begin(s, PROF_TRSM, 8.0 * w * w * (double)ncols * fb)) != hipSuccess) return r;
       if ((r = launch_copy_block<T>(A + k0 + cb * ld, ld, tmp, w, w, ncols, s, NB, sA, stmp)) != hipSuccess) return r;
@@ -2104,8 +2106,8 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
       // launch (one launch and its gap fewer per block on the panels' path),
       // then the update
       LUCHK(P.begin(st, PROF_TRSM, 8.0 * w * w * (double)wa * fb));
-      LUCHK(launch_block_trsm<T>(A, ld, n, nb, bi, A + k0 + c1 * ld, ld, wa, st, NB, sA, sA, dst, src, npr,
-                                 ws.s_pairs, ws.s_npairs));
+      LUCHK(launch_block_trsm<T>(A, ld, n, nb, bi, A + k0 + c1 * ld, ld, wa, st, NB, sA, sA, dst, src,
+                                 plan.spec ? nullptr : npr, ws.s_pairs, ws.s_npairs));
       LUCHK(P.end(st));
       LUCHK(P.begin(st, PROF_LOOKAHEAD, 8.0 * (double)nr * (double)wa * w * fb));
       LUCHK(launch_gemm_update<T>(nr, wa, w, A + c1 + k0 * ld, ld, A + k0 + c1 * ld, ld, A + c1 + c1 * ld, ld, st, NB,
@@ -2212,6 +2214,9 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
   const int64_t chunk = ws.tmp_elems / (trans ? skinny_t_chunks(n, nb) * nb : n);
   if (chunk < 1) return hipErrorInvalidValue;
   const int64_t part_elems = (int64_t)NB * sX;  // the transposed partial sums of all items
+  // factors left by a speculative plan have no interchanges (a failed check
+  // repeats the factorisation with a pivoting plan), so their lists are empty
+  const bool perm = !plan.spec;
   for (int64_t r0 = 0; r0 < nrhs; r0 += chunk) {
     const int64_t nr = nrhs - r0 < chunk ? nrhs - r0 : chunk;
     CT* B = Ball + r0 * ldb;
@@ -2228,9 +2233,11 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
         const int64_t k0 = b.k0;
         const int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;
         const int32_t* src = dst + 2 * nb;
-        hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)nr, NB), dim3(256), 0, st, B, ldb, (int64_t)0, dst,
-                           src, ws.npairs + bi, sB, ws.s_pairs, ws.s_npairs);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (perm) {
+          hipLaunchKernelGGL(row_permute_kernel<T>, dim3((unsigned)nr, NB), dim3(256), 0, st, B, ldb, (int64_t)0, dst,
+                             src, ws.npairs + bi, sB, ws.s_pairs, ws.s_npairs);
+          if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
         GemmMask m;
         m.akind = GEMM_MASK_STRICT_LOWER;
         m.ar0 = 0;
@@ -2280,8 +2287,9 @@ hipError_t lu_solve(int trans, const void* Av, int64_t ld, const LUPlan& plan, c
           return e;
         const int32_t* dst = ws.pairs + bi * 4 * (size_t)nb;
         const int32_t* src = dst + 2 * nb;
-        hipLaunchKernelGGL(row_permute_inv_kernel<T>, dim3((unsigned)nr, NB), dim3(256), 0, st, B, ldb, (int64_t)0, dst,
-                           src, ws.npairs + bi, sB, ws.s_pairs, ws.s_npairs);
+        if (perm)
+          hipLaunchKernelGGL(row_permute_inv_kernel<T>, dim3((unsigned)nr, NB), dim3(256), 0, st, B, ldb, (int64_t)0,
+                             dst, src, ws.npairs + bi, sB, ws.s_pairs, ws.s_npairs);
       }
     }
   }
