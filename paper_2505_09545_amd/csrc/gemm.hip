@@ -288,11 +288,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
 // multiple of the 4M one); the factorisations that use it are FP32 ones
 // refined in FP64.  Tiles: BM = 32 WMB complex rows, BN = 32 WNB columns, BK
 // complex k per stage; the XCD remap of cgemm_kernel, then grouped_tile.
-template <int WMB, int WNB, int BK, bool CB>
+template <typename T, int WMB, int WNB, int BK, bool CB>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const float2* __restrict__ A, int64_t lda,
-                      const float2* __restrict__ B, int64_t ldb, float2* __restrict__ C, int64_t ldc, int tiles_m,
+cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict__ A, int64_t lda,
+                      const cplx<T>* __restrict__ B, int64_t ldb, cplx<T>* __restrict__ C, int64_t ldc, int tiles_m,
                       int tiles, int64_t sA, int64_t sB, int64_t sC) {
+  using CT = cplx<T>;
+  using ACC = typename acc_of<T>::type;
+  const CT czero = CT{0, 0};
   constexpr int BM = 32 * WMB, BN = 32 * WNB;
   constexpr int AL = BM * BK / 256, BL = BK * BN / 256;
   static_assert(AL * 256 == BM * BK && BL * 256 == BK * BN && BK % 4 == 0, "tile shape");
@@ -300,41 +303,41 @@ cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const float2* __restrict_
   A += (int64_t)blockIdx.y * sA;
   B += (int64_t)blockIdx.y * sB;
   C += (int64_t)blockIdx.y * sC;
-  __shared__ float As[2][3][BK * AP];  // [plane][k][row]
-  __shared__ float Bs[2][3][BK * BP];  // [plane][k][column]
+  __shared__ T As[2][3][BK * AP];  // [plane][k][row]
+  __shared__ T Bs[2][3][BK * BP];  // [plane][k][column]
   const int bid = blockIdx.x;
   const int xcd = bid & 7, loc = bid >> 3;
   const int per = tiles >> 3, rem = tiles & 7;
   const int tile = (xcd < rem ? xcd * (per + 1) : rem * (per + 1) + (xcd - rem) * per) + loc;
   int tm, tn;
-  grouped_tile<16, 8>(tile, tiles_m, tiles, tm, tn);
+  grouped_tile<16, sizeof(T) == 8 ? 16 : 8>(tile, tiles_m, tiles, tm, tn);
   const int64_t m0 = (int64_t)tm * BM, n0 = (int64_t)tn * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wrow = (wave & 1) * 16 * WMB;  // complex rows
   const int wcol = (wave >> 1) * 16 * WNB;
   const int lr = lane & 15, lk = lane >> 4;
-  v4f acc[3][WMB][WNB];
+  ACC acc[3][WMB][WNB];
 #pragma unroll
   for (int q = 0; q < 3; ++q)
 #pragma unroll
     for (int i = 0; i < WMB; ++i)
 #pragma unroll
-      for (int j = 0; j < WNB; ++j) acc[q][i][j] = v4f{0, 0, 0, 0};
-  float2 ra[AL], rb[BL];
+      for (int j = 0; j < WNB; ++j) acc[q][i][j] = ACC{0, 0, 0, 0};
+  CT ra[AL], rb[BL];
   auto gload = [&](int64_t kb) {
 #pragma unroll
     for (int i = 0; i < AL; ++i) {
       const int idx = tid + 256 * i;
       const int mc = idx % BM, kc = idx / BM;
       const int64_t gm = m0 + mc, gk = kb + kc;
-      ra[i] = (gm < m && gk < k) ? A[gm + gk * lda] : make_float2(0.f, 0.f);
+      ra[i] = (gm < m && gk < k) ? A[gm + gk * lda] : czero;
     }
 #pragma unroll
     for (int i = 0; i < BL; ++i) {
       const int idx = tid + 256 * i;
       const int kc = idx % BK, nc = idx / BK;
       const int64_t gn = n0 + nc, gk = kb + kc;
-      rb[i] = (gn < n && gk < k) ? B[gk + gn * ldb] : make_float2(0.f, 0.f);
+      rb[i] = (gn < n && gk < k) ? B[gk + gn * ldb] : czero;
     }
   };
   auto sstore = [&](int buf) {
@@ -365,7 +368,7 @@ cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const float2* __restrict_
 #pragma unroll
     for (int k4 = 0; k4 < BK; k4 += 4) {
       const int kr = k4 + lk;
-      float a[3][WMB], b[3][WNB];
+      T a[3][WMB], b[3][WNB];
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
 #pragma unroll
@@ -383,23 +386,25 @@ cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const float2* __restrict_
     if (kt + 1 < ktiles) sstore(buf ^ 1);
     __syncthreads();
   }
-  // lane holds rows 4 lk + r (r < 4) of column lr of each 16 x 16 block
-  auto out = [&](int i, int j, int r, float& cr, float& ci) {
-    const float t1 = acc[0][i][j][r], t2 = acc[1][i][j][r], t3 = acc[2][i][j][r];
+  // lane holds rows 4 lk + r (r < 4) of column lr of each 16 x 16 block (FP32),
+  // rows lk + 4 r (FP64, the other result layout of the FP64 MFMA)
+  auto rof = [&](int r) { return sizeof(T) == 8 ? lk + 4 * r : 4 * lk + r; };
+  auto out = [&](int i, int j, int r, T& cr, T& ci) {
+    const T t1 = acc[0][i][j][r], t2 = acc[1][i][j][r], t3 = acc[2][i][j][r];
     cr = t1 - t2;
     ci = t3 - t1 - t2;
   };
   if constexpr (CB) {
     // every C load before the first store (the batched products' epilogue)
-    float2 cold[WMB][WNB][4];
+    CT cold[WMB][WNB][4];
 #pragma unroll
     for (int i = 0; i < WMB; ++i)
 #pragma unroll
       for (int j = 0; j < WNB; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t row = m0 + wrow + 16 * i + 4 * lk + r, col = n0 + wcol + 16 * j + lr;
-          cold[i][j][r] = (row < m && col < n) ? C[row + col * ldc] : make_float2(0.f, 0.f);
+          const int64_t row = m0 + wrow + 16 * i + rof(r), col = n0 + wcol + 16 * j + lr;
+          cold[i][j][r] = (row < m && col < n) ? C[row + col * ldc] : czero;
         }
 #pragma unroll
     for (int i = 0; i < WMB; ++i)
@@ -407,11 +412,11 @@ cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const float2* __restrict_
       for (int j = 0; j < WNB; ++j)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t row = m0 + wrow + 16 * i + 4 * lk + r, col = n0 + wcol + 16 * j + lr;
+          const int64_t row = m0 + wrow + 16 * i + rof(r), col = n0 + wcol + 16 * j + lr;
           if (row >= m || col >= n) continue;
-          float cr, ci;
+          T cr, ci;
           out(i, j, r, cr, ci);
-          C[row + col * ldc] = make_float2(cold[i][j][r].x - cr, cold[i][j][r].y - ci);
+          C[row + col * ldc] = CT{cold[i][j][r].x - cr, cold[i][j][r].y - ci};
         }
     return;
   }
@@ -423,11 +428,11 @@ cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const float2* __restrict_
       if (col >= n) continue;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t row = m0 + wrow + 16 * i + 4 * lk + r;
+        const int64_t row = m0 + wrow + 16 * i + rof(r);
         if (row >= m) continue;
-        float cr, ci;
+        T cr, ci;
         out(i, j, r, cr, ci);
-        float2 c = C[row + col * ldc];
+        CT c = C[row + col * ldc];
         c.x -= cr;
         c.y -= ci;
         C[row + col * ldc] = c;
@@ -504,17 +509,18 @@ hipError_t launch_gemm(int mode, int transA, int64_t m, int64_t n, int64_t k, co
 }
 
 // The FP32 update with the 64 x 64 tile: 3M products (cgemm3m_update_kernel).
-static hipError_t launch_update_3m(int64_t m, int64_t n, int64_t k, const float2* a, int64_t lda, const float2* b,
-                                   int64_t ldb, float2* c, int64_t ldc, hipStream_t st, int nbatch, int64_t sA,
+template <typename T>
+static hipError_t launch_update_3m(int64_t m, int64_t n, int64_t k, const cplx<T>* a, int64_t lda, const cplx<T>* b,
+                                   int64_t ldb, cplx<T>* c, int64_t ldc, hipStream_t st, int nbatch, int64_t sA,
                                    int64_t sB, int64_t sC) {
   const int64_t tm = (m + 63) / 64, tn = (n + 63) / 64;
   if (tm * tn > INT32_MAX) return hipErrorInvalidValue;
   const int tiles = (int)(tm * tn);
   if (nbatch > 1)
-    hipLaunchKernelGGL((cgemm3m_update_kernel<2, 2, 8, true>), dim3(tiles, nbatch), dim3(256), 0, st, m, n, k, a, lda,
-                       b, ldb, c, ldc, (int)tm, tiles, sA, sB, sC);
+    hipLaunchKernelGGL((cgemm3m_update_kernel<T, 2, 2, 8, true>), dim3(tiles, nbatch), dim3(256), 0, st, m, n, k, a,
+                       lda, b, ldb, c, ldc, (int)tm, tiles, sA, sB, sC);
   else
-    hipLaunchKernelGGL((cgemm3m_update_kernel<2, 2, 4, false>), dim3(tiles, nbatch), dim3(256), 0, st, m, n, k, a,
+    hipLaunchKernelGGL((cgemm3m_update_kernel<T, 2, 2, 4, false>), dim3(tiles, nbatch), dim3(256), 0, st, m, n, k, a,
                        lda, b, ldb, c, ldc, (int)tm, tiles, sA, sB, sC);
   return hipGetLastError();
 }
@@ -525,11 +531,9 @@ hipError_t launch_gemm_update(int64_t m, int64_t n, int64_t k, const void* A, in
                               int64_t sC) {
   if (m <= 0 || n <= 0 || k <= 0 || nbatch <= 0) return hipSuccess;
   if (nbatch > 65535) return hipErrorInvalidValue;
-  if constexpr (sizeof(T) == 4) {
-    if (GEMM_UPDATE_3M && !use_small_tiles(m, n, nbatch))
-      return launch_update_3m(m, n, k, static_cast<const float2*>(A), lda, static_cast<const float2*>(B), ldb,
-                              static_cast<float2*>(C), ldc, st, nbatch, sA, sB, sC);
-  }
+  if (GEMM_UPDATE_3M && !use_small_tiles(m, n, nbatch))
+    return launch_update_3m<T>(m, n, k, static_cast<const cplx<T>*>(A), lda, static_cast<const cplx<T>*>(B), ldb,
+                               static_cast<cplx<T>*>(C), ldc, st, nbatch, sA, sB, sC);
   return launch_cfg<T, 0, 0, 1>(m, n, k, static_cast<const cplx<T>*>(A), lda, static_cast<const cplx<T>*>(B), ldb,
                                 static_cast<cplx<T>*>(C), ldc, st, GemmMask{}, nbatch, sA, sB, sC);
 }
