@@ -517,8 +517,9 @@ static hipError_t launch_update_3m(int64_t m, int64_t n, int64_t k, const cplx<T
   if (tm * tn > INT32_MAX) return hipErrorInvalidValue;
   const int tiles = (int)(tm * tn);
   if (nbatch > 1)
-    hipLaunchKernelGGL((cgemm3m_update_kernel<T, 2, 2, 8, true>), dim3(tiles, nbatch), dim3(256), 0, st, m, n, k, a,
-                       lda, b, ldb, c, ldc, (int)tm, tiles, sA, sB, sC);
+    // (FP64: 4 complex k per stage, 8 would leave one wave per SIMD)
+    hipLaunchKernelGGL((cgemm3m_update_kernel<T, 2, 2, sizeof(T) == 8 ? 4 : 8, true>), dim3(tiles, nbatch), dim3(256), 0,
+                       st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, sA, sB, sC);
   else
     hipLaunchKernelGGL((cgemm3m_update_kernel<T, 2, 2, 4, false>), dim3(tiles, nbatch), dim3(256), 0, st, m, n, k, a,
                        lda, b, ldb, c, ldc, (int)tm, tiles, sA, sB, sC);

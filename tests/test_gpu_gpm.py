@@ -246,3 +246,38 @@ def test_gpm_errors(ctx):
     with pytest.raises(gdm.GDMError) as ei:
         ctx.extract_gpm(torch.as_tensor(cl["r_eff"]), torch.as_tensor(gi.fibonacci_sphere(40, 350.0)), kk, ee, rs, ds)
     assert ei.value.status == gdm.GDM_E_ARG
+
+
+def larger_case():
+    """1000 cells (10^3 cube, 6 nm, eps 6+0.2i) and six 6x6 dipoles around it,
+    joined into two groups of three by their exact GPMs: n = 3036, so the
+    group column transform, the speculative panels and the solves run over
+    many tiles."""
+    rng = np.random.default_rng(21)
+    r = gi.cuboid_cells(10, 10, 10, 6.0)
+    ang = np.arange(6) * (2 * np.pi / 6)
+    r_eff = np.stack([110 * np.cos(ang), 110 * np.sin(ang), 15.0 * (np.arange(6) - 2.5)], axis=1)
+    k, e = gi.random_planewaves(rng, 4)
+    w = dict(name="cube1000_6eff", r_cell=r, step=6.0, eps_cell=np.full(len(r), 6.0 + 0.2j), n_env=1.0,
+             wavelength=650.0, khat=k, e0=e, r_probe=gi.fibonacci_sphere(64, 300.0), r_eff=r_eff,
+             alpha_eff=gi.mie_like_alpha6(rng, 6, 650.0, 1.0, a_nm=30.0))
+    groups = [(0, 3, exact_gpm(w, 0, 3)), (3, 3, exact_gpm(w, 3, 3))]
+    return w, groups
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_gpm_larger_system_matches_oracle(ctx, prec):
+    w, groups = larger_case()
+    say("gpm n = 3036, prec", prec)
+    set_structure(ctx, w)
+    ctx.set_gpm([(f, torch.as_tensor(a)) for f, _, a in groups])
+    ctx.factorize(w["wavelength"], prec)
+    f0 = ctx.incident_planewave(torch.as_tensor(w["khat"]), torch.as_tensor(w["e0"]))
+    q, f = ctx.solve(f0, tol=1e-14 if prec == 1 else 0.0)
+    ref = O.simulate(dict(w, gpm=groups))
+    qn = q.cpu().numpy().T
+    assert np.max(np.abs(qn - ref["q"])) <= 1e-10 * np.max(np.abs(ref["q"]))
+    e2 = torch.as_tensor(np.sum(np.abs(w["e0"]) ** 2, axis=1))
+    cs = ctx.cross_sections(f0, q, f, e2).cpu().numpy()
+    for col, key in ((0, "ext"), (1, "sca"), (2, "abs")):
+        assert np.max(np.abs(cs[:, col] - ref[key]) / np.abs(ref[key])) < 1e-10, key
