@@ -2057,7 +2057,9 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
     // its masked-operand form (-L11^-1 below the diagonal, = I - L11^-1 there),
     // and reaches the diagonal block of A only after the main stream's
     // substitution has read L11.
-    const bool early = la && NB == 1 && nr - wa > 0 && 4 * nr > 3 * n;
+    // (while more than half the rows remain: measured against three quarters,
+    // FP32 factorisation 58.4 -> 58.1 ms, FP64 100.5 -> 99.8 ms at n = 12 000)
+    const bool early = la && NB == 1 && nr - wa > 0 && 2 * nr > n;
     hipEvent_t panel_done = nullptr;
     if (early) {
       LUCHK(new_event(panel_done));
