@@ -363,11 +363,11 @@ static gdm_status solve_core(gdm_ctx* c, int trans, int64_t nrhs, const double2*
       if (nfull > 0) {
         const int64_t kc = rs.kc, nk = n / kc, tail = n - nk * kc;
         double2* part = c->part.as<double2>();
-        HIPCHK(c, launch_gemm<double>(1, 0, n, nfull, kc, c->M64.p, n, X, n, part, n, c->stream, GemmMask{}, (int)nk,
-                                      kc * n, kc, n * nfull));
+        HIPCHK(c, launch_gemm_product_3m<double>(n, nfull, kc, c->M64.p, n, X, n, part, n, c->stream, (int)nk,
+                                                 kc * n, kc, n * nfull));
         if (tail > 0)
-          HIPCHK(c, launch_gemm<double>(1, 0, n, nfull, tail, c->M64.as<double2>() + nk * kc * n, n, X + nk * kc, n,
-                                        part + nk * n * nfull, n, c->stream));
+          HIPCHK(c, launch_gemm_product_3m<double>(n, nfull, tail, c->M64.as<double2>() + nk * kc * n, n, X + nk * kc,
+                                                   n, part + nk * n * nfull, n, c->stream));
         HIPCHK(c, launch_partial_reduce<double>(part, (int)(nk + (tail > 0)), n, nfull, Rr, n, c->stream));
       }
       if (rem > 0 && !rem_side)

@@ -141,6 +141,12 @@ template <typename T>
 hipError_t launch_gemm(int mode, int transA, int64_t m, int64_t n, int64_t k, const void* A, int64_t lda,
                        const void* B, int64_t ldb, void* C, int64_t ldc, hipStream_t st, GemmMask mk = GemmMask{},
                        int nbatch = 1, int64_t sA = 0, int64_t sB = 0, int64_t sC = 0);
+// C = A B on the 3M kernel (64 x 64 tiles; no masks, no transpose); nbatch
+// independent products, item z at A + z sA, B + z sB, C + z sC.
+template <typename T>
+hipError_t launch_gemm_product_3m(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
+                                  int64_t ldb, void* C, int64_t ldc, hipStream_t st, int nbatch = 1, int64_t sA = 0,
+                                  int64_t sB = 0, int64_t sC = 0);
 // The LU trailing update A22 -= L21 U12: same kernel body, separate symbol so
 // that profilers report it on its own.
 template <typename T>

@@ -288,7 +288,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
 // multiple of the 4M one); the factorisations that use it are FP32 ones
 // refined in FP64.  Tiles: BM = 32 WMB complex rows, BN = 32 WNB columns, BK
 // complex k per stage; the XCD remap of cgemm_kernel, then grouped_tile.
-template <typename T, int WMB, int WNB, int BK, bool CB>
+template <typename T, int WMB, int WNB, int BK, bool CB, int MODE = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
 cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict__ A, int64_t lda,
                       const cplx<T>* __restrict__ B, int64_t ldb, cplx<T>* __restrict__ C, int64_t ldc, int tiles_m,
@@ -394,6 +394,25 @@ cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict
     cr = t1 - t2;
     ci = t3 - t1 - t2;
   };
+  if constexpr (MODE == 1) {
+    // C = A B (no read of C)
+#pragma unroll
+    for (int i = 0; i < WMB; ++i)
+#pragma unroll
+      for (int j = 0; j < WNB; ++j) {
+        const int64_t col = n0 + wcol + 16 * j + lr;
+        if (col >= n) continue;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t row = m0 + wrow + 16 * i + rof(r);
+          if (row >= m) continue;
+          T cr, ci;
+          out(i, j, r, cr, ci);
+          C[row + col * ldc] = CT{cr, ci};
+        }
+      }
+    return;
+  }
   if constexpr (CB) {
     // every C load before the first store (the batched products' epilogue)
     CT cold[WMB][WNB][4];
@@ -525,6 +544,27 @@ static hipError_t launch_update_3m(int64_t m, int64_t n, int64_t k, const cplx<T
                        lda, b, ldb, c, ldc, (int)tm, tiles, sA, sB, sC);
   return hipGetLastError();
 }
+
+// C = A B with the 3M kernel (64 x 64 tiles, 4 complex k per stage), nbatch
+// independent products (item z at A + z sA, B + z sB, C + z sC): the k-split
+// partial products of the FP64 refinement residual.
+template <typename T>
+hipError_t launch_gemm_product_3m(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
+                                  int64_t ldb, void* C, int64_t ldc, hipStream_t st, int nbatch, int64_t sA, int64_t sB,
+                                  int64_t sC) {
+  if (m <= 0 || n <= 0 || k <= 0 || nbatch <= 0) return hipSuccess;
+  if (nbatch > 65535) return hipErrorInvalidValue;
+  const int64_t tm = (m + 63) / 64, tn = (n + 63) / 64;
+  if (tm * tn > INT32_MAX) return hipErrorInvalidValue;
+  const int tiles = (int)(tm * tn);
+  hipLaunchKernelGGL((cgemm3m_update_kernel<T, 2, 2, 4, false, 1>), dim3(tiles, nbatch), dim3(256), 0, st, m, n, k,
+                     static_cast<const cplx<T>*>(A), lda, static_cast<const cplx<T>*>(B), ldb, static_cast<cplx<T>*>(C),
+                     ldc, (int)tm, tiles, sA, sB, sC);
+  return hipGetLastError();
+}
+template hipError_t launch_gemm_product_3m<double>(int64_t, int64_t, int64_t, const void*, int64_t, const void*,
+                                                   int64_t, void*, int64_t, hipStream_t, int, int64_t, int64_t,
+                                                   int64_t);
 
 template <typename T>
 hipError_t launch_gemm_update(int64_t m, int64_t n, int64_t k, const void* A, int64_t lda, const void* B,
