@@ -501,8 +501,15 @@ template <typename T, int MODE, int TRANSA, int ROLE>
 static hipError_t launch_cfg(int64_t m, int64_t n, int64_t k, const cplx<T>* a, int64_t lda, const cplx<T>* b,
                              int64_t ldb, cplx<T>* c, int64_t ldc, hipStream_t st, GemmMask mk, int nbatch, int64_t sA,
                              int64_t sB, int64_t sC) {
-  if (use_small_tiles(m, n, nbatch))
+  if (use_small_tiles(m, n, nbatch)) {
+    // one system's products over k >= 64 (the solve steps, L21 and U12 blocks,
+    // the look-ahead columns) with 16 complex k per stage: half the stages of
+    // their latency-bound k loop (FP32+IR step 72.9 -> 72.2 ms; 32 measured
+    // the same); the batched launches keep 8
+    if (nbatch == 1 && k >= 64)
+      return launch_tiles<T, MODE, TRANSA, ROLE, 2, 1, 16>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
     return launch_tiles<T, MODE, TRANSA, ROLE, 2, 1, 8>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
+  }
   // 4 complex k per stage for the products of one system (update GEMM: FP32
   // 87.5 -> 90, FP64 40 -> 45 TFLOP/s; FP64 step 158.6 -> 148.8 ms), 8 for
   // batched launches (83 vs 78 systems/s on the batched spectra)
