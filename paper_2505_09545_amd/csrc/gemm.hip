@@ -24,6 +24,11 @@
 //     matrix cores.  Measured on the 66-RHS solves: 8 complex k per stage
 //     11.6 ms, 16: 12.4, 32: 14.7, 64: 17.6 (the smaller stage leaves more
 //     workgroups resident per CU); wider tiles over all 66 columns: 16.5.
+//     One system's products over 64 <= k <= 128 (16 complex k per stage)
+//     load their whole k range into registers before the first stage, so a
+//     launch waits for memory once instead of once per stage (FP32+IR step
+//     72.6 -> 72.0 ms; FP64 takes it in two halves of 64, whose registers
+//     would otherwise spill).
 // Per thread and stage the big tile loads one (4 k) or two (8 k) complex
 // elements of A and as many of B, the small one one of each.
 // Workgroups are remapped so that each of the 8 XCDs works on a contiguous
@@ -38,6 +43,11 @@ namespace gdm {
 // expanded 4M form (0)
 #ifndef GEMM_UPDATE_3M
 #define GEMM_UPDATE_3M 1
+#endif
+// small-tile products of one system over 64 <= k <= 128 with the whole k range
+// prefetched into registers (1) or the two-buffer k loop (0)
+#ifndef GEMM_SMALL_PREFETCH
+#define GEMM_SMALL_PREFETCH 1
 #endif
 
 template <typename T> struct acc_of;
@@ -84,7 +94,7 @@ __device__ inline void grouped_tile(int t, int tiles_m, int tiles, int& tm, int&
   tn = blk * cbw + w2 / rows;
 }
 
-template <typename T, int MODE, int TRANSA, int ROLE, int WM, int WN, int BK, bool CB>
+template <typename T, int MODE, int TRANSA, int ROLE, int WM, int WN, int BK, bool CB, int NST = 0>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) cgemm_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict__ A,
                                                      int64_t lda, const cplx<T>* __restrict__ B, int64_t ldb,
                                                      cplx<T>* __restrict__ C, int64_t ldc, int tiles_m, int tiles,
@@ -126,7 +136,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
     for (int j = 0; j < WN; ++j) acc[i][j] = ACC{0, 0, 0, 0};
 
   CT ra[AL], rb[BL];
-  auto gload = [&](int64_t kb) {
+  auto gload_to = [&](int64_t kb, CT(&ra)[AL], CT(&rb)[BL]) {
 #pragma unroll
     for (int i = 0; i < AL; ++i) {
       const int idx = tid + 256 * i;
@@ -153,7 +163,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
       rb[i] = u;
     }
   };
-  auto sstore = [&](int buf) {
+  auto gload = [&](int64_t kb) { gload_to(kb, ra, rb); };
+  auto sstore_from = [&](int buf, const CT(&ra)[AL], const CT(&rb)[BL]) {
 #pragma unroll
     for (int i = 0; i < AL; ++i) {
       const int idx = tid + 256 * i;
@@ -170,11 +181,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
       Bs[buf][nc * BSK + 2 * kc2 + 1] = rb[i].y;
     }
   };
+  auto sstore = [&](int buf) { sstore_from(buf, ra, rb); };
 
-  const int64_t ktiles = (k + BK - 1) / BK;
-  gload(0);
-  sstore(0);
-  __syncthreads();
   const int lr = lane & 15;   // row (A) / column (B) inside a 16-block
   const int lk = lane >> 4;   // k index inside a 4-step
   // Output rows of the 16x16 accumulator held by a lane: f32 MFMA gives rows
@@ -183,9 +191,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
   // grid, so that in both cases the lane ends up with real rows 4*lk .. 4*lk+3,
   // i.e. (re, im) of two consecutive complex rows.
   const int arow = sizeof(T) == 8 ? (4 * (lr & 3) + (lr >> 2)) : lr;
-  for (int64_t kt = 0; kt < ktiles; ++kt) {
-    const int buf = (int)(kt & 1);
-    if (kt + 1 < ktiles) gload((kt + 1) * BK);
+  auto mma = [&](int buf) {
 #pragma unroll
     for (int s = 0; s < BK / 2; ++s) {
       const int kk = 4 * s + lk;       // real k inside the stage
@@ -205,23 +211,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
 #pragma unroll
         for (int bn = 0; bn < WN; ++bn) acc[bm][bn] = mfma16(a[bm], b[bn], acc[bm][bn]);
     }
-    if (kt + 1 < ktiles) sstore(buf ^ 1);
-    __syncthreads();
-  }
-  // epilogue: lane holds real rows 4*lk + {0..3} = two complex rows of column lane%16
-  // (general products only: rows [ar0, ar0 + adw) optionally written to mk.c2)
-  CT* const c2 = ROLE == 0 && mk.c2 ? static_cast<CT*>(mk.c2) + (int64_t)blockIdx.y * mk.sc2 : nullptr;
-  auto dest = [&](int64_t row, int64_t col) -> CT* {
-    if (ROLE == 0 && c2 && row >= mk.ar0 && row < mk.ar0 + mk.adw) return c2 + (row - mk.ar0) + col * mk.ldc2;
-    return C + row + col * ldc;
   };
-  if constexpr (MODE == 0 && CB) {
-    // Every C load issued before the first store (a load after a store to the
-    // same array waits for it, since the compiler cannot tell the addresses
-    // apart: one memory latency per element otherwise).  Measured: batched
-    // spectra 72.5 -> 82 systems/s; the single large products of one system
-    // keep the plain loop below (2 % slower this way).
-    CT cold[WM][WN][2];
+  // C of this lane's outputs (MODE 0): loaded before the k loop when the whole
+  // k range is prefetched, else after it (batched launches)
+  CT cold[WM][WN][2];
+  auto load_c = [&]() {
 #pragma unroll
     for (int bm = 0; bm < WM; ++bm)
 #pragma unroll
@@ -234,6 +228,60 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) c
           cold[bm][bn][h].y = 0;
           if (col < n && row < m) cold[bm][bn][h] = C[row + col * ldc];
         }
+  };
+  if constexpr (NST > 0) {
+    // k in chunks of NST stages, each chunk's operands in flight at once: all
+    // of its stages are loaded into registers up front, then staged through
+    // LDS one stage at a time, so a chunk pays one memory latency instead of
+    // one per stage (these launches are short products whose time is set by
+    // latency).  FP32 takes k <= 128 in one chunk; FP64 (twice the registers
+    // per element) in two.
+    static_assert(NST % 2 == 0, "stages alternate the two LDS buffers across chunks");
+    for (int64_t kc0 = 0; kc0 < k; kc0 += (int64_t)NST * BK) {
+      CT pa[NST][AL], pb[NST][BL];
+#pragma unroll
+      for (int s = 0; s < NST; ++s) gload_to(kc0 + (int64_t)s * BK, pa[s], pb[s]);
+      if constexpr (MODE == 0) {
+        if (kc0 == 0) load_c();
+      }
+#pragma unroll
+      for (int s = 0; s < NST; ++s) {
+        if (kc0 + (int64_t)s * BK < k) {  // uniform over the workgroup
+          // buffer s & 1 was last read two stages earlier, which every wave
+          // finished before the barrier of the stage in between
+          sstore_from(s & 1, pa[s], pb[s]);
+          __syncthreads();
+          mma(s & 1);
+        }
+      }
+    }
+  } else {
+    const int64_t ktiles = (k + BK - 1) / BK;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int64_t kt = 0; kt < ktiles; ++kt) {
+      const int buf = (int)(kt & 1);
+      if (kt + 1 < ktiles) gload((kt + 1) * BK);
+      mma(buf);
+      if (kt + 1 < ktiles) sstore(buf ^ 1);
+      __syncthreads();
+    }
+  }
+  // epilogue: lane holds real rows 4*lk + {0..3} = two complex rows of column lane%16
+  // (general products only: rows [ar0, ar0 + adw) optionally written to mk.c2)
+  CT* const c2 = ROLE == 0 && mk.c2 ? static_cast<CT*>(mk.c2) + (int64_t)blockIdx.y * mk.sc2 : nullptr;
+  auto dest = [&](int64_t row, int64_t col) -> CT* {
+    if (ROLE == 0 && c2 && row >= mk.ar0 && row < mk.ar0 + mk.adw) return c2 + (row - mk.ar0) + col * mk.ldc2;
+    return C + row + col * ldc;
+  };
+  if constexpr (MODE == 0 && (CB || NST > 0)) {
+    // Every C load issued before the first store (a load after a store to the
+    // same array waits for it, since the compiler cannot tell the addresses
+    // apart: one memory latency per element otherwise).  Measured: batched
+    // spectra 72.5 -> 82 systems/s; the single large products of one system
+    // keep the plain loop below (2 % slower this way).
+    if constexpr (NST == 0) load_c();
 #pragma unroll
     for (int bm = 0; bm < WM; ++bm)
 #pragma unroll
@@ -473,7 +521,7 @@ static int gemm_num_cu() {
 }
 
 // Launch with the tile shape (WM, WN, BK); tile counts checked by the caller's shape.
-template <typename T, int MODE, int TRANSA, int ROLE, int WM, int WN, int BK>
+template <typename T, int MODE, int TRANSA, int ROLE, int WM, int WN, int BK, int NST = 0>
 static hipError_t launch_tiles(int64_t m, int64_t n, int64_t k, const cplx<T>* a, int64_t lda, const cplx<T>* b,
                                int64_t ldb, cplx<T>* c, int64_t ldc, hipStream_t st, GemmMask mk, int nbatch,
                                int64_t sA, int64_t sB, int64_t sC) {
@@ -482,12 +530,12 @@ static hipError_t launch_tiles(int64_t m, int64_t n, int64_t k, const cplx<T>* a
   const int tiles = (int)(tm * tn);
   // batched launches (several systems at once) take the epilogue with all C
   // loads in flight
-  if (nbatch > 1)
+  if (NST == 0 && nbatch > 1)
     hipLaunchKernelGGL((cgemm_kernel<T, MODE, TRANSA, ROLE, WM, WN, BK, true>), dim3(tiles, nbatch), dim3(256), 0, st, m,
                        n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk, sA, sB, sC);
   else
-    hipLaunchKernelGGL((cgemm_kernel<T, MODE, TRANSA, ROLE, WM, WN, BK, false>), dim3(tiles, nbatch), dim3(256), 0, st,
-                       m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk, sA, sB, sC);
+    hipLaunchKernelGGL((cgemm_kernel<T, MODE, TRANSA, ROLE, WM, WN, BK, false, NST>), dim3(tiles, nbatch), dim3(256), 0,
+                       st, m, n, k, a, lda, b, ldb, c, ldc, (int)tm, tiles, mk, sA, sB, sC);
   return hipGetLastError();
 }
 
@@ -506,6 +554,9 @@ static hipError_t launch_cfg(int64_t m, int64_t n, int64_t k, const cplx<T>* a, 
     // the look-ahead columns) with 16 complex k per stage: half the stages of
     // their latency-bound k loop (FP32+IR step 72.9 -> 72.2 ms; 32 measured
     // the same); the batched launches keep 8
+    if (nbatch == 1 && k >= 64 && k <= 128 && GEMM_SMALL_PREFETCH)
+      return launch_tiles<T, MODE, TRANSA, ROLE, 2, 1, 16, sizeof(T) == 8 ? 4 : 8>(m, n, k, a, lda, b, ldb, c, ldc, st,
+                                                                                mk, nbatch, sA, sB, sC);
     if (nbatch == 1 && k >= 64)
       return launch_tiles<T, MODE, TRANSA, ROLE, 2, 1, 16>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);
     return launch_tiles<T, MODE, TRANSA, ROLE, 2, 1, 8>(m, n, k, a, lda, b, ldb, c, ldc, st, mk, nbatch, sA, sB, sC);

@@ -1996,11 +1996,16 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
   // Upper parts of block b (final once panel b is done): the diagonal block
   // gets I - U11^-1, the block column above it U01 U11^-1.  With look-ahead (one
   // system) they are formed on the side stream after a block's bulk update,
-  // three blocks per step once at most half the rows remain (the panels then
-  // set the pace and the side stream has time to spare); the rest at the end.
-  // Measured at n = 12 000: FP32+IR step 93.3 -> 90.9 ms, FP64 146.7 -> 144.3 ms
-  // (from two per step at 3/4 of the rows: 91.5 and 145.8; the batched
-  // factorisations, whose side stream has no time to spare, keep the end).
+  // in the second half of the factorisation (the panels then set the pace and
+  // the side stream has time to spare); the rest at the end.  Measured at
+  // n = 12 000: FP32+IR step 93.3 -> 90.9 ms, FP64 146.7 -> 144.3 ms with three
+  // per step from half the rows (two per step from 3/4 of the rows: 91.5 and
+  // 145.8; the batched factorisations, whose side stream has no time to spare,
+  // keep the end).  Later, with the faster update and panels, three per step
+  // put the side stream on the panels' path (a kernel trace showed the next
+  // panel's substitution waiting for a bulk update held back by them); the
+  // graded count below: FP32+IR step 71.7 -> 69.6 ms, FP64 105.5 -> 103.5 ms
+  // (two per step from half the rows: 70.5 and 104.2).
   int u_next = 0;  // blocks [0, u_next) have their upper parts formed
   auto upper_parts = [&](hipStream_t s, int bb) -> hipError_t {
     hipError_t r;
@@ -2164,9 +2169,18 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
     LUCHK(launch_gemm<T>(0, 0, nr, w, w, tmpB, nr, diag, ld, A + c1 + k0 * ld, ld, sb, mb, NB, ws.s_tmp, sA, sA));
     LUCHK(P.end(sb));
     if (la && NB > 1) LUCHK(record_bulk_done());
-    if (la) {
-      if (NB == 1 && (2 * nr <= n || n <= 4096))
-        for (int q = 0; q < 3 && u_next <= bi; ++q) LUCHK(upper_parts(sb, u_next++));
+    if (la && NB == 1) {
+      // as many upper parts per step as the side stream has time for beside
+      // the shrinking bulk update: none while more than 55 % of the rows
+      // remain, then one, two from 30 % and three from 20 %, which catches up
+      // with the panels by about the last block (small systems: three per step
+      // throughout)
+      const int64_t r100 = 100 * nr;
+      int per = r100 <= 55 * n ? 1 : 0;
+      if (r100 <= 30 * n) per = 2;
+      if (r100 <= 20 * n) per = 3;
+      if (n <= 4096) per = 3;
+      for (int q = 0; q < per && u_next <= bi; ++q) LUCHK(upper_parts(sb, u_next++));
     }
   }
   if (bulk_done) {
