@@ -55,7 +55,11 @@ def oracle_q_rhs_major(sim):
                                               # >= 2 tiles of 64 x 64 per CU: the large tile, k not a
                                               # multiple of its 4 complex k per stage
                                               (1500, 1430, 130, 0, 0), (1430, 1500, 131, 1, 0),
-                                              (1500, 1400, 66, 0, 1)])
+                                              (1500, 1400, 66, 0, 1),
+                                              # small tiles with the whole k range (64 <= k <= 128) loaded
+                                              # up front: exact, ragged and chunked (FP64: two halves) k
+                                              (256, 66, 128, 0, 0), (300, 40, 64, 1, 1), (190, 97, 100, 1, 0),
+                                              (130, 66, 96, 0, 1)])
 def test_gemm_matches_numpy(ctx, dtype, m, n, k, mode, trans):
     say("gemm", dtype, m, n, k, mode, trans)
     rng = np.random.default_rng(m * 7 + n * 3 + k)
