@@ -335,6 +335,7 @@ def batch_timing(ctx, gdm, runs: int, n_struct: int = 0, n_wl: int = 0) -> dict:
     tune_s = time.perf_counter() - t0
     best = None
     be = 0.0
+    fb0 = ctx.pivot_fallbacks()
     for _ in range(max(runs, 1)):
         t0 = time.perf_counter()
         _, b = ctx.batch_spectra(r_cells, w["step"], w["wavelengths"], eps, khat, e0)
@@ -348,6 +349,7 @@ def batch_timing(ctx, gdm, runs: int, n_struct: int = 0, n_wl: int = 0) -> dict:
             "batch_systems": ns * nw, "batch_s": best, "batch_systems_per_s": ns * nw / best,
             "batch_tflops": flops / best / 1e12, "batch_frac_fp32_mfma": flops / best / 1e12 / PEAK_FP32_MFMA,
             "batch_tuning_s": tune_s, "batch_tuning_systems": ns * n_tune, "batch_max_backward_err": be,
+            "batch_pivot_fallbacks": ctx.pivot_fallbacks() - fb0,
             "batch_group_config": {str(k): v for k, v in sorted(ctx.batch_config().items())}}
 
 
