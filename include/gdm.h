@@ -430,15 +430,15 @@ gdm_status gdm_sync(gdm_ctx* ctx);
  * clears the counters and starts recording; 0 stops. */
 gdm_status gdm_profile(gdm_ctx* ctx, int enable);
 /* The same for a subset of the tags listed under gdm_profile_read: launches of
- * tag t are timed iff bit t of mask is set (mask 0 stops; 4095 = all).  Timing
+ * tag t are timed iff bit t of mask is set (mask 0 stops; 8191 = all).  Timing
  * only the kernels one needs keeps the events off the critical path of the
- * rest.  GDM_E_ARG for a mask outside [0, 2048). */
+ * rest.  GDM_E_ARG for a mask outside [0, 8192). */
 gdm_status gdm_profile_mask(gdm_ctx* ctx, int32_t mask);
 /* Counters accumulated since gdm_profile / gdm_profile_mask, written to the HOST array
- * out (n_out >= 36): out[3 t + 0..2] = (milliseconds, work, launches) for
+ * out (n_out >= 39): out[3 t + 0..2] = (milliseconds, work, launches) for
  * t = 0 LU trailing-update GEMM, bulk part (the columns after the next panel's;
- * work = real flops 8 m n k), 1 LU panel (work =
- * columns), 2 assembly (work = bytes written), 3 block triangular solve of the
+ * work = real flops 8 m n k), 1 LU panel: the pivot search, or the diagonal
+ * block's kernel of a speculative panel (work = columns), 2 assembly (work = bytes written), 3 block triangular solve of the
  * factorisation (work = real flops), 4 row permutation of the trailing columns,
  * 5 forward + backward substitution of gdm_solve / gdm_adjoint (work =
  * 8 n^2 n_rhs), 6 FP64 refinement residual (work = 8 n^2 n_rhs), 7 adjoint
@@ -446,7 +446,10 @@ gdm_status gdm_profile_mask(gdm_ctx* ctx, int32_t mask);
  * (work = probe-dipole pairs x n_rhs), 9 probe fields (work = probe-dipole
  * pairs x n_rhs), 10 LU trailing-update GEMM of the next panel's columns (the
  * look-ahead product; work = real flops), 11 matrix-free product of
- * gdm_solve_iterative (work = dipole pairs x n_rhs). */
+ * gdm_solve_iterative (work = dipole pairs x n_rhs), 12 the rest of a
+ * speculative panel: L21 = A21 U11^-1 (the triangle's inverse and the
+ * product) and the pivot check (work = real flops 8 (n - k) w^2 of the
+ * product). */
 gdm_status gdm_profile_read(gdm_ctx* ctx, double* out, int32_t n_out);
 
 #ifdef __cplusplus

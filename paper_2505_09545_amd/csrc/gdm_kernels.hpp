@@ -198,7 +198,8 @@ enum ProfTag {
   PROF_FIELDS = 9,
   PROF_LOOKAHEAD = 10,
   PROF_ITER_MATVEC = 11,
-  PROF_NTAGS = 12
+  PROF_PANEL_L21 = 12,
+  PROF_NTAGS = 13
 };
 struct Prof {
   uint32_t mask = 0;  // bit t: record launches of tag t

@@ -1695,20 +1695,18 @@ __global__ void __launch_bounds__(256) spec_check_kernel(const cplx<T>* __restri
   if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(flag, 1);
 }
 
-// Speculative panel of block bi (columns [k0, k0 + w)): the diagonal block,
-// then L21 = A21 U11^-1 for the rows below as U11^-1 (into the block's inverse
-// slot, which later steps overwrite only after this panel) and one GEMM from a
-// copy of A21, then the check.  (A row-parallel substitution x U11 = a on the
+// Speculative panel of block bi (columns [k0, k0 + w)): the diagonal block
+// (launch_spec_diag), then (launch_spec_l21) L21 = A21 U11^-1 for the rows below
+// as U11^-1 (into the block's inverse slot, which later steps overwrite only
+// after this panel) and one GEMM from a copy of A21, then the check.  (A row-parallel substitution x U11 = a on the
 // VALUs, with U11 staged in LDS, took 115 us per early FP32 block beside the
 // bulk update and 590 us in FP64, where the staged triangle fills 132 KB of a
 // CU's LDS; the inverse + GEMM form: FP32 factorisation 59.5 -> 59.2 ms, FP64
 // 110.3 -> 108.7 ms at n = 12 000.)
 template <typename T>
-static hipError_t launch_spec_panel(cplx<T>* A, int64_t ld, int64_t n, int nb, int bi, int64_t k0, int w,
-                                    int32_t* ipiv, const LUWork& ws, hipStream_t st, int nbatch, int64_t sA,
-                                    int64_t sipiv) {
+static hipError_t launch_spec_diag(cplx<T>* A, int64_t ld, int nb, int bi, int64_t k0, int w, int32_t* ipiv,
+                                   const LUWork& ws, hipStream_t st, int nbatch, int64_t sA, int64_t sipiv) {
   if (w > 128 || !ws.l21c || k0 != (int64_t)bi * nb) return hipErrorInvalidValue;
-  using CT = cplx<T>;
   int32_t* flag = ws.spec + bi;
   const int64_t sflag = ws.s_npairs;
   constexpr int NT = 512;
@@ -1743,8 +1741,18 @@ static hipError_t launch_spec_panel(cplx<T>* A, int64_t ld, int64_t n, int nb, i
   }
   hipLaunchKernelGGL((spec_diag_kernel<T, NT>), dim3(1, (unsigned)nbatch), dim3(NT), reserve, st, A, ld, k0, w, ipiv,
                      flag, sA, sipiv, sflag);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+// The rest of the speculative panel of block bi: L21 (w columns below the
+// diagonal block) and the check of its entries against the pivots.
+template <typename T>
+static hipError_t launch_spec_l21(cplx<T>* A, int64_t ld, int64_t n, int nb, int bi, int64_t k0, int w,
+                                  const LUWork& ws, hipStream_t st, int nbatch, int64_t sA) {
+  using CT = cplx<T>;
+  int32_t* flag = ws.spec + bi;
+  const int64_t sflag = ws.s_npairs;
+  hipError_t e;
   const int64_t nr = n - k0 - w;
   if (nr <= 0) return hipSuccess;
   CT* dinv = static_cast<CT*>(ws.dinv);
@@ -2062,7 +2070,10 @@ hipError_t lu_factor(void* Av, int64_t ld, const LUPlan& plan, const LUWork& ws,
     int32_t* src = dst + 2 * nb;
     int32_t* npr = ws.npairs + bi;
     if (plan.spec) {
-      LUCHK(launch_spec_panel<T>(A, ld, n, nb, bi, k0, w, ipiv, ws, st, NB, sA, sipiv));
+      LUCHK(launch_spec_diag<T>(A, ld, nb, bi, k0, w, ipiv, ws, st, NB, sA, sipiv));
+      LUCHK(P.end(st));
+      LUCHK(P.begin(st, PROF_PANEL_L21, 8.0 * (double)(n - k0 - w) * w * w * fb));
+      LUCHK(launch_spec_l21<T>(A, ld, n, nb, bi, k0, w, ws, st, NB, sA));
     } else {
       launch_panel<T>(plan.pb, b, NB, lds, st, A, ld, n, ipiv, ws, epoch, sA, sipiv, dst, src, npr, 2 * nb);
       epoch += (uint32_t)w;

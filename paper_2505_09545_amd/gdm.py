@@ -600,7 +600,7 @@ class Context:
         self._check(self._call("gdm_sync", self.h))
 
     PROF_TAGS = ("update", "panel", "assemble", "trsm", "perm", "solve", "resid", "adj_pair", "adj_probe", "fields",
-                 "lookahead", "iter_matvec")
+                 "lookahead", "iter_matvec", "panel_l21")
 
     def profile(self, enable: bool, tags=None):
         """Start (clearing the counters) or stop per-launch event timing; `tags`

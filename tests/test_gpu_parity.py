@@ -344,7 +344,7 @@ def test_argument_errors(ctx):
 def test_profile_tag_mask(ctx):
     """gdm_profile_mask times only the launches of the tags it is given (the
     benchmark's timed region keeps events on the update GEMM only);
-    gdm_profile(ctx, 1) times every tag; a mask outside [0, 4096) is an
+    gdm_profile(ctx, 1) times every tag; a mask outside [0, 2^tags) is an
     argument error."""
     say("profile tag mask")
     from paper_2505_09545_amd import gdm
@@ -359,10 +359,10 @@ def test_profile_tag_mask(ctx):
     gdm.run_forward(ctx, w, prec=gdm.PREC_FP32_IR, tol=1e-14, probes=False)
     p = ctx.profile_read()
     ctx.profile(False)
-    for t in ("update", "lookahead", "panel", "assemble", "trsm", "solve", "resid"):
+    for t in ("update", "lookahead", "panel", "panel_l21", "assemble", "trsm", "solve", "resid"):
         assert p[t]["launches"] > 0 and p[t]["ms"] > 0, (t, p[t])
     with pytest.raises(gdm.GDMError) as e:
-        ctx._check(ctx._call("gdm_profile_mask", ctx.h, 1 << 12))
+        ctx._check(ctx._call("gdm_profile_mask", ctx.h, 1 << len(gdm.Context.PROF_TAGS)))
     assert e.value.status == gdm.GDM_E_ARG
 
 
