@@ -46,6 +46,10 @@ namespace gdm {
 #endif
 // small-tile products of one system over 64 <= k <= 128 with the whole k range
 // prefetched into registers (1) or the two-buffer k loop (0)
+// B tile of the 3M update stored with a column swizzle (1) or plainly (0)
+#ifndef GEMM3M_BSWZ
+#define GEMM3M_BSWZ 1
+#endif
 #ifndef GEMM_SMALL_PREFETCH
 #define GEMM_SMALL_PREFETCH 1
 #endif
@@ -364,6 +368,12 @@ cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict
   const int wrow = (wave & 1) * 16 * WMB;  // complex rows
   const int wcol = (wave >> 1) * 16 * WNB;
   const int lr = lane & 15, lk = lane >> 4;
+  // B columns of k rows 4..7 (mod 8) stored with column bit 3 flipped: a wave
+  // stores 8 k x 8 columns, and with the row stride BP (16 banks apart mod 64)
+  // rows kc and kc + 4 would otherwise put the same column on the same bank;
+  // an MFMA operand read covers 4 k rows of one half, so its 16-column groups
+  // only permute
+  auto bswz = [](int kc, int nc) { return GEMM3M_BSWZ ? nc ^ (((kc >> 2) & 1) << 3) : nc; };
   ACC acc[3][WMB][WNB];
 #pragma unroll
   for (int q = 0; q < 3; ++q)
@@ -401,9 +411,10 @@ cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict
     for (int i = 0; i < BL; ++i) {
       const int idx = tid + 256 * i;
       const int kc = idx % BK, nc = idx / BK;
-      Bs[buf][0][kc * BP + nc] = rb[i].x;
-      Bs[buf][1][kc * BP + nc] = rb[i].y;
-      Bs[buf][2][kc * BP + nc] = rb[i].x + rb[i].y;
+      const int o = kc * BP + bswz(kc, nc);
+      Bs[buf][0][o] = rb[i].x;
+      Bs[buf][1][o] = rb[i].y;
+      Bs[buf][2][o] = rb[i].x + rb[i].y;
     }
   };
   const int64_t ktiles = (k + BK - 1) / BK;
@@ -422,7 +433,7 @@ cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict
 #pragma unroll
         for (int i = 0; i < WMB; ++i) a[q][i] = As[buf][q][kr * AP + wrow + 16 * i + lr];
 #pragma unroll
-        for (int j = 0; j < WNB; ++j) b[q][j] = Bs[buf][q][kr * BP + wcol + 16 * j + lr];
+        for (int j = 0; j < WNB; ++j) b[q][j] = Bs[buf][q][kr * BP + bswz(kr, wcol + 16 * j + lr)];
       }
 #pragma unroll
       for (int q = 0; q < 3; ++q)
