@@ -368,12 +368,13 @@ cgemm3m_update_kernel(int64_t m, int64_t n, int64_t k, const cplx<T>* __restrict
   const int wrow = (wave & 1) * 16 * WMB;  // complex rows
   const int wcol = (wave >> 1) * 16 * WNB;
   const int lr = lane & 15, lk = lane >> 4;
-  // B columns of k rows 4..7 (mod 8) stored with column bit 3 flipped: a wave
-  // stores 8 k x 8 columns, and with the row stride BP (16 banks apart mod 64)
-  // rows kc and kc + 4 would otherwise put the same column on the same bank;
-  // an MFMA operand read covers 4 k rows of one half, so its 16-column groups
-  // only permute
-  auto bswz = [](int kc, int nc) { return GEMM3M_BSWZ ? nc ^ (((kc >> 2) & 1) << 3) : nc; };
+  // B columns of k rows 4..7 (mod 8; FP64: 2..3 mod 4) stored with column bit 3
+  // flipped: a wave stores 8 k x 8 columns (FP64: 4 k x 16), and with the row
+  // stride BP (16 banks apart mod 64; FP64: 32) rows kc and kc + 4 (kc + 2)
+  // would otherwise put the same column on the same bank; an MFMA operand read
+  // covers 4 k rows, so its 16-column groups only permute
+  constexpr int SWK = sizeof(T) == 8 ? 2 : 4;
+  auto bswz = [](int kc, int nc) { return GEMM3M_BSWZ && (kc & SWK) ? nc ^ 8 : nc; };
   ACC acc[3][WMB][WNB];
 #pragma unroll
   for (int q = 0; q < 3; ++q)
